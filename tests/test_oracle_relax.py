@@ -1,0 +1,112 @@
+"""Oracle relaxation and V-cycle semantics against properties the method fixes."""
+import numpy as np
+import pytest
+
+from oracle import kkt, relax
+from oracle import grid as G
+from oracle import timebasis as tb
+
+
+def _setup(shape=(32,), h=0.25, n_t=4, dt=0.05, seed=0, field=None, t0=0.0, periodic=False):
+    g = G.Grid(shape, h, periodic=periodic)
+    rng = np.random.default_rng(seed)
+    r2 = sum(c ** 2 for c in g.coords()).ravel()
+    v0 = -1.0 / np.sqrt(r2 + 1.0)
+    psi0 = (np.exp(-r2 / 4) * np.exp(1j * rng.uniform(0, 2 * np.pi, g.npts)))
+    sysm = kkt.StepSystem(g, v0, n_t, dt, t0, field)
+    return g, v0, psi0, sysm
+
+
+def test_whole_domain_block_is_direct_solve():
+    g, v0, psi0, sysm = _setup((16,))
+    b = kkt.rhs(sysm, psi0)
+    x0 = kkt.initial_guess(sysm, psi0)
+    bl = G.blocks(g, (16,))
+    x1 = relax.reference_sweep_colour(sysm.K, b, x0, bl, 0, g.npts, 4)
+    np.testing.assert_allclose(x1, kkt.solve_direct(sysm.K, b), atol=1e-13)
+
+
+@pytest.mark.parametrize("shape,block", [((32,), (8,)), ((8, 8), (4, 4)), ((4, 4, 8), (2, 2, 4))])
+def test_block_annihilation_and_untouched_exterior(shape, block):
+    g, v0, psi0, sysm = _setup(shape, field=tb.pulse_sin2_cos(0.1, 0.5, 3.0), t0=0.7)
+    b = kkt.rhs(sysm, psi0)
+    x0 = kkt.initial_guess(sysm, psi0)
+    bl = G.blocks(g, block)
+    x1 = relax.reference_sweep_colour(sysm.K, b, x0, bl, 0, g.npts, 4)
+    r1 = b - sysm.K @ x1
+    moved = np.zeros(x0.size, bool)
+    for col, pts in bl:
+        if col == 0:
+            rows = relax.block_rows(pts, g.npts, 4)
+            assert np.abs(r1[rows]).max() < 1e-13
+            moved[rows] = True
+    assert np.all(x1[~moved] == x0[~moved])
+
+
+def test_fixed_point():
+    g, v0, psi0, sysm = _setup((8, 8))
+    b = kkt.rhs(sysm, psi0)
+    xd = kkt.solve_direct(sysm.K, b)
+    xs = relax.reference_sweep(sysm.K, b, xd, G.blocks(g, (4, 4)), g.npts, 4)
+    np.testing.assert_allclose(xs, xd, atol=1e-14)
+
+
+def test_colour_order_invariance():
+    g, v0, psi0, sysm = _setup((16, 8))
+    b = kkt.rhs(sysm, psi0)
+    x0 = kkt.initial_guess(sysm, psi0)
+    bl = G.blocks(g, (4, 4))
+    xa = relax.reference_sweep_colour(sysm.K, b, x0, bl, 1, g.npts, 4)
+    n1 = sum(1 for c, _ in bl if c == 1)
+    order = np.random.default_rng(1).permutation(n1)
+    xb = relax.reference_sweep_colour_sequential(sysm.K, b, x0, bl, 1, g.npts, 4, order)
+    np.testing.assert_allclose(xa, xb, atol=1e-15)
+
+
+def test_residual_norm_non_increasing_per_sweep_in_regime():
+    # 1D, h = 40/256, dt = 0.05: kappa = dt / (2 h^2) ~ 1.0, the configs' regime.
+    g = G.Grid((256,), 40.0 / 256)
+    x = g.coords()[0].ravel()
+    sysm = kkt.StepSystem(g, 0.5 * x ** 2, 8, 0.05)
+    psi0 = np.exp(-(x + 5) ** 2 / 2 + 1j * x)
+    b = kkt.rhs(sysm, psi0)
+    xk = kkt.initial_guess(sysm, psi0)
+    bl = G.blocks(g, (8,))
+    N0 = kkt.residual_norm(sysm, b - sysm.K @ xk)
+    hist = [N0]
+    for _ in range(8):
+        xk = relax.reference_sweep(sysm.K, b, xk, bl, g.npts, 8)
+        hist.append(kkt.residual_norm(sysm, b - sysm.K @ xk))
+    for a, c in zip(hist, hist[1:]):
+        assert c <= a + 1e-26 * N0
+    assert hist[-1] < 1e-20 * N0
+
+
+@pytest.mark.parametrize("levels,interp", [(2, "linear"), (3, "constant"), (3, "linear")])
+def test_vcycles_converge_to_direct_solution(levels, interp):
+    g, v0, psi0, sysm = _setup((32, 32), h=0.2, n_t=4, field=tb.pulse_sin2_cos(0.05, 0.057, 5.0), t0=1.0)
+    H = relax.build_hierarchy(g, v0, 4, 0.05, (4, 4), levels, t0=1.0,
+                              field=tb.pulse_sin2_cos(0.05, 0.057, 5.0), interp=interp)
+    b = kkt.rhs(H[0].system, psi0)
+    xs, hist = relax.solve_by_vcycles(H, kkt.initial_guess(H[0].system, psi0), b, tol=1e-12)
+    xd = kkt.solve_direct(H[0].system.K, b)
+    assert np.abs(xs - xd).max() <= 1e-10 * np.abs(xd).max()
+    assert hist[-1] <= 1e-12
+
+
+def test_adjoint_vcycles_converge_to_direct_adjoint():
+    g, v0, psi0, sysm = _setup((16, 16), h=0.2, n_t=4)
+    H = relax.build_hierarchy(g, v0, 4, 0.05, (4, 4), 2)
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=H[0].system.size) + 1j * rng.normal(size=H[0].system.size)
+    xs, hist = relax.solve_by_vcycles(H, np.zeros_like(b), b, tol=1e-12, adjoint=True)
+    xd = kkt.solve_direct(H[0].system.K.conj().T.tocsr(), b)
+    assert np.abs(xs - xd).max() <= 1e-10 * np.abs(xd).max()
+
+
+def test_coarse_operator_is_rediscretisation():
+    g, v0, psi0, sysm = _setup((8, 8), h=0.2, n_t=3)
+    H = relax.build_hierarchy(g, v0, 3, 0.05, (2, 2), 2)
+    gc = H[1].grid
+    assert gc.n == (4, 4) and abs(gc.h - 0.4) < 1e-15
+    np.testing.assert_allclose(H[1].v0, G.restriction(g) @ v0, atol=1e-15)
