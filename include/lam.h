@@ -1,0 +1,240 @@
+/*
+ * lam.h -- C ABI of the least-action TDSE relaxation library (liblam.so).
+ *
+ * Method: Z. B. Walters, "An efficient parallel method for relaxing to the
+ * minimum action wavefunction".  One propagation step expands the
+ * wavefunction as phi(x,t) = sum_{i,n} C_in chi_i(x) T_n(t) (Sec. "Review of
+ * the Least Action Principle") and solves the stationarity conditions of the
+ * action, Eq. (stationaryphase), with one Lagrange multiplier per spatial
+ * function imposing the initial condition.  Instead of a direct solve, the
+ * library relaxes many small independent subvolume problems (Sec. "Iterative
+ * relaxation to the least action solution", correction form
+ * Eq. (leastaction_correction)) inside a multigrid V-cycle (Sec. "Multigrid
+ * Relaxation", Eqs. (residual_rough), (correction_fine)).
+ *
+ * Discretisation used by this library:
+ *   - chi_i: one function per point of a 1D/2D/3D finite-difference grid,
+ *     overlap O = identity, H0 = -(1/2m) Lap_h with the (2d+1)-point
+ *     Laplacian; values one spacing outside the grid are zero, or the grid
+ *     is periodic.  Point coordinates are cell centred,
+ *     x_a(i) = (i - (n_a - 1)/2) h.
+ *   - T_n: Legendre polynomial P_n mapped onto [t0, t0 + dt], n < n_t
+ *     (Sec. "Implementation with Legendre Polynomials"), so that
+ *     U = diag(dt/(2n+1)), Q_nm = 2 for n > m with n - m odd, T_n(t0) = (-1)^n
+ *     and T_n(t0 + dt) = 1.
+ *   - V(x,t) = V0(x) + z E(t), z the coordinate along field_axis.
+ *
+ * Unknowns of one step, per grid point j: c_j0 .. c_j,n_t-1 and lambda_j.
+ * Row (j,m):  i sum_n Q_nm c_jn - U_mm ((T+V0) c)_jm - z_j sum_n W_mn c_jn
+ *             + (-1)^m lambda_j = rhs_jm     (rhs = 0 for a forward step),
+ * row j:      sum_n (-1)^n c_jn = psi0_j,
+ * with W_nm = int T_n T_m E(t) dt over the step.
+ *
+ * Conventions for every call:
+ *   - Device arrays are on the GPU the context was created on and are
+ *     accessed on the context's stream only.  Complex arrays are interleaved
+ *     (re, im) FP64 ("lam_c64"), i.e. the memory of a torch.complex128 tensor.
+ *   - A grid array has one entry per point in C order over the axes (axis
+ *     dim-1 contiguous).  A coefficient array c has n_t consecutive entries
+ *     per point: c[j * n_t + n].
+ *   - Caller memory is never freed or retained by the library.  The context
+ *     owns all of its internal device buffers.
+ *   - Calls that return a host scalar (a norm, statistics) synchronise the
+ *     stream.  Other calls are asynchronous with respect to the host.
+ *   - Return value: LAM_OK (0) or a negative LAM_E* code; lam_strerror()
+ *     names it.  On error no output is guaranteed to be written.
+ *   - A context is not thread safe; calls on one context must not overlap.
+ */
+#ifndef LAM_H
+#define LAM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LAM_OK          0
+#define LAM_EINVAL     -1   /* invalid argument: shape, block, level count, n_t, null pointer */
+#define LAM_ENOMEM     -2   /* device allocation failed */
+#define LAM_EHIP       -3   /* a HIP runtime call failed */
+#define LAM_ENOCONV    -4   /* tolerance not reached within max_cycles (outputs still written) */
+#define LAM_EDIVERGED  -5   /* residual norm non-finite or grew by more than 1e6 */
+#define LAM_ESTATE     -6   /* call needs a state that was never set (lam_set_state) */
+
+#define LAM_MAX_NT     8    /* largest number of Legendre time functions */
+#define LAM_MAX_BLOCK  64   /* largest number of grid points in one subvolume */
+
+#define LAM_PULSE_NONE          0
+#define LAM_PULSE_SIN2          1  /* E = e0 sin^2(pi t/T) cos(omega t) on [0,T] */
+#define LAM_PULSE_FOURIER       2  /* E = sum_q coef[q-1] sin(q pi t/T) on [0,T] */
+#define LAM_PULSE_SIN2_FOURIER  3  /* sum of the two */
+
+#define LAM_FP64   0   /* every kernel in FP64 */
+#define LAM_MIXED  1   /* subvolume solves in FP32, residuals/transfers/state in FP64 */
+
+typedef struct lam_ctx lam_ctx;
+typedef double lam_c64;   /* interleaved complex: element k is (p[2k], p[2k+1]) */
+
+typedef struct {
+    int dim;          /* 1, 2 or 3 */
+    int n[3];         /* points per axis (entries >= dim ignored) */
+    double h;         /* grid spacing of the finest level */
+    int periodic;     /* 0: zero values outside the grid; 1: periodic wrap */
+    int block[3];     /* subvolume points per axis; must divide n/2^l at every level l,
+                         product <= LAM_MAX_BLOCK */
+    int levels;       /* multigrid levels, >= 1 (1 = relaxation only); every axis
+                         must be even at all levels but the coarsest */
+    int nu_pre;       /* full sweeps before the coarse correction */
+    int nu_post;      /* full sweeps after it */
+    int nu_coarse;    /* full sweeps that make the coarsest-level solve */
+    int interp;       /* 0: cell-centred tensor-linear interpolation,
+                         1: piecewise constant (projection * interpolation = identity) */
+} lam_grid;
+
+typedef struct {
+    int n_t;          /* Legendre time functions per step, 1..LAM_MAX_NT */
+    double dt;        /* step length */
+} lam_time;
+
+typedef struct {
+    double mass;          /* particle mass (T = -(1/2m) Lap) */
+    const double* v0;     /* device, one FP64 per finest grid point; copied at create */
+    int field_axis;       /* axis of the dipole coordinate z (0..dim-1) */
+    int pulse_kind;       /* LAM_PULSE_* */
+    double e0, omega;     /* sin^2 pulse amplitude and carrier frequency */
+    double t_total;       /* pulse length T */
+    int n_coef;           /* Fourier sine amplitudes (may be 0) */
+    const double* coef;   /* host, n_coef values; copied at create */
+} lam_ham;
+
+typedef struct {
+    int precision;    /* LAM_FP64 or LAM_MIXED */
+    double tol;       /* stop when sqrt(N / N0) <= tol (N: residual norm, N0: at the start) */
+    int max_cycles;   /* V-cycle limit per solve */
+    int n_inner;      /* inner corrections of each subvolume solve when E(t) != 0;
+                         -1 = automatic (3 when the step has a field, else 0) */
+} lam_solver;
+
+typedef struct {
+    int cycles;           /* V-cycles done */
+    int sweeps_fine;      /* full sweeps (both colours) on the finest level */
+    double resid0;        /* sqrt(N) of the initial guess */
+    double resid;         /* sqrt(N) at the end */
+    double t_factor_ms;   /* time spent refactoring subvolume time blocks this call */
+    double t_solve_ms;    /* wall time of the call */
+} lam_stats;
+
+/* Create a propagator context: builds the level hierarchy (coarse grids with
+ * doubled spacing and the potential averaged over children) and factors every
+ * subvolume operator of every level.  hip_stream: a hipStream_t (NULL = the
+ * null stream).  Sec. "Review of the Least Action Principle" (problem
+ * statement), Sec. "Multigrid Relaxation" (hierarchy).
+ * Errors: LAM_EINVAL (shapes, blocks, levels, n_t, mass, h, dt, pointers),
+ * LAM_ENOMEM, LAM_EHIP. */
+int lam_create(const lam_grid* grid, const lam_time* time, const lam_ham* ham,
+               const lam_solver* solver, void* hip_stream, lam_ctx** out);
+
+/* Release every device buffer of the context.  Accepts NULL. */
+int lam_destroy(lam_ctx* ctx);
+
+/* Replace the Fourier pulse amplitudes (host array of n_coef values, n_coef
+ * must equal the count given at create). */
+int lam_set_pulse(lam_ctx* ctx, int n_coef, const double* coef);
+
+/* Replace V0 (device, one FP64 per finest point) and refactor every level. */
+int lam_set_potential(lam_ctx* ctx, const double* v0);
+
+/* Action residual of a forward step at time t0, Eq. (actionresidual) extended
+ * by the multiplier rows: rho = rhs - (stationarity rows applied to (c, lam)),
+ * sigma = psi0 - sum_n (-1)^n c_n.  norm (host, may be NULL) receives
+ * N = sum_jm U_mm |rho_jm|^2 + sum_j |sigma_j|^2 (Eq. (residnorm) with O = I).
+ * psi0, c, lam: device inputs (P, P*n_t, P complex).  rho (P*n_t) and
+ * sigma (P) are device outputs and may be NULL. */
+int lam_residual_action(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c,
+                        const lam_c64* lam, lam_c64* rho, lam_c64* sigma, double* norm);
+
+/* Same for the adjoint system K^H mu = E^H g of a step at t0 (E: end-of-step
+ * evaluation psi_j = sum_n c_jn, so E^H g puts g_j on every row (j, n)).
+ * g: device (P); mu_c (P*n_t), mu_lam (P): device inputs. */
+int lam_residual_adjoint(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c,
+                         const lam_c64* mu_lam, lam_c64* rho, lam_c64* sigma, double* norm);
+
+/* Load a forward state into the context: step time t0, initial wavefunction
+ * psi0 (P), coefficients c (P*n_t) and multipliers lam (P), all device.
+ * Subsequent lam_relax_sweep / lam_vcycle act on the system K x = (0, psi0). */
+int lam_set_state(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c,
+                  const lam_c64* lam);
+
+/* Load an adjoint state: subsequent sweeps / V-cycles act on K^H mu = E^H g. */
+int lam_set_adjoint_state(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c,
+                          const lam_c64* mu_lam);
+
+/* Copy the finest-level state (c: P*n_t, lam: P; device) out of the context. */
+int lam_get_state(lam_ctx* ctx, lam_c64* c, lam_c64* lam);
+
+/* One colour of subvolume relaxation on level `level` (0 = finest) of the
+ * context state: every subvolume of that colour (parity of the sum of its box
+ * coordinates) is replaced by x_U + K_UU^{-1} (b - K x)_U with the exterior
+ * held fixed (Sec. "Iterative relaxation to the least action solution").
+ * Subvolumes of one colour do not share a face, so they run in parallel. */
+int lam_relax_sweep(lam_ctx* ctx, int level, int colour);
+
+/* One V-cycle on the context state (Eqs. (residual_rough), (correction_fine)):
+ * nu_pre sweeps, residual, projection, recursive coarse correction (the
+ * coarsest level does nu_coarse sweeps), interpolation, nu_post sweeps.
+ * norm (host, may be NULL) receives N of the finest level afterwards. */
+int lam_vcycle(lam_ctx* ctx, double* norm);
+
+/* Propagate one step from t0: psi_in (device, P) -> psi_out (device, P,
+ * psi_out_j = sum_n c_jn).  V-cycles from the initial guess c_j0 = psi_in_j,
+ * c_jn = 0 (n >= 1), lambda = 0 until sqrt(N/N0) <= tol.  stats may be NULL.
+ * Returns LAM_ENOCONV (psi_out written) if max_cycles is reached,
+ * LAM_EDIVERGED if the norm becomes non-finite or grows by more than 1e6. */
+int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_out,
+                   lam_stats* stats);
+
+/* Backward pass of one step for a real loss L.  psi_in: the step's initial
+ * wavefunction (device checkpoint; the forward solve is recomputed from it).
+ * g_out = dL/dpsi_out^* (device, P).  Solves K^H mu = E^H g_out with the same
+ * relaxation and multigrid machinery, then
+ *   g_in   = dL/dpsi_in^* = mu on the initial-condition rows (device, P, written),
+ *   dL_dv0 += 2 Re sum_m conj(mu_jm) U_mm c_jm           (device, P, accumulated),
+ *   dL_dcoef[q] += 2 Re sum_j z_j sum_mn conj(mu_jm) W^(q)_mn c_jn
+ *                                            (host, n_coef, accumulated; may be NULL),
+ * with W^(q) the time matrix of the q-th Fourier sine function.
+ * stats (may be NULL) describe the adjoint solve. */
+int lam_adjoint_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, const lam_c64* g_out,
+                     lam_c64* g_in, double* dL_dv0, double* dL_dcoef, lam_stats* stats);
+
+/* Grid transfers on caller buffers; `level` is the fine level (0..levels-2).
+ * lam_restrict: coarse (rho, sigma) = average of the 2^d children of the fine
+ * (rho, sigma) (projection of Eq. (residual_rough)).
+ * lam_prolong_add: fine (c, lam) += interpolation of coarse (c, lam)
+ * (Eq. (correction_fine)).  All pointers device; sizes follow each level's
+ * point count (lam_level_shape). */
+int lam_restrict(lam_ctx* ctx, int level, const lam_c64* rho_f, const lam_c64* sigma_f,
+                 lam_c64* rho_c, lam_c64* sigma_c);
+int lam_prolong_add(lam_ctx* ctx, int level, const lam_c64* c_c, const lam_c64* lam_c,
+                    lam_c64* c_f, lam_c64* lam_f);
+
+/* Points per axis of a level (n[3], host). */
+int lam_level_shape(const lam_ctx* ctx, int level, int* n);
+
+/* Subvolume factor of block `block` on `level`: eigenvectors (host, bpts*bpts,
+ * row-major [point][mode]) and eigenvalues (host, bpts) of the real symmetric
+ * spatial block operator T_U + diag(V0_U).  For tests of the block factor. */
+int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, double* vals);
+
+/* Timing of finest-level sweep launches with HIP events on the context
+ * stream.  enable = 1 starts recording (clearing previous records),
+ * 0 stops.  lam_profile_read returns the launch count and summed kernel time
+ * (ms) recorded since the last enable; it synchronises the stream. */
+int lam_profile(lam_ctx* ctx, int enable);
+int lam_profile_read(lam_ctx* ctx, int* launches, double* total_ms);
+
+const char* lam_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAM_H */

@@ -75,13 +75,13 @@ class StepSystem:
         return self.grid.npts * (self.n_t + 1)
 
 
-def assemble(grid, v0, U, Q, s, W):
-    """Sparse K of the step (see module docstring)."""
+def assemble(grid, v0, U, Q, s, W, z=None):
+    """Sparse K of the step (see module docstring); z overrides the dipole coordinate."""
     P = grid.npts
     n_t = U.shape[0]
     I = sp.identity(P, format="csr")
     H = hamiltonian(grid, v0)
-    Z = sp.diags(grid.z())
+    Z = sp.diags(grid.z() if z is None else np.asarray(z, float).ravel())
     A = (sp.kron(I, 1j * Q.T) - sp.kron(H, U) - sp.kron(Z, W)).tocsr()
     B = sp.kron(I, s.reshape(-1, 1)).tocsr()          # multiplier columns
     C = sp.kron(I, s.reshape(1, -1)).tocsr()          # constraint rows
@@ -151,3 +151,78 @@ def propagate(grid, v0, psi0, n_t, dt, n_steps, field=None, t_start=0.0):
         psi, _, _ = step(grid, v0, psis[-1], n_t, dt, t_start + k * dt, field)
         psis.append(psi)
     return psis
+
+
+def residual_at_points(grid, v0, n_t, dt, t0, field, c, lam, psi0, points, stat_rhs=None, adjoint=False):
+    """Residual rows of the points ``points`` only, from the definition.
+
+    For every requested point j: rho_jm = rhs_jm - [ i (Q^T c_j)_m - (U ((T + V0) c)_j)_m
+    - z_j (W c_j)_m + s_m lambda_j ] and sigma_j = psi0_j - sum_n s_n c_jn, with the
+    neighbours of j gathered explicitly; usable on grids too large to assemble.
+    For adjoint=True the time block is (iQ^T)^H = -iQ and the right-hand side is
+    g_j on every row (pass g as stat_rhs, one value per point) with psi0 = 0.
+    c: (P, n_t), lam: (P,), psi0: (P,), points: iterable of point indices.
+    Returns rho (len(points), n_t) and sigma (len(points),).
+    """
+    U = tb.overlap_U(n_t, dt)
+    Q = tb.derivative_Q(n_t, dt)
+    s = tb.start_values(n_t)
+    W = np.zeros((n_t, n_t)) if field is None else tb.field_matrix(n_t, t0, dt, field)
+    shape = grid.n
+    z_axis = grid.field_axis % grid.dim
+    kin = 0.5 / grid.mass / grid.h ** 2
+    pts = np.asarray(points, dtype=np.int64)
+    rho = np.zeros((len(pts), n_t), complex)
+    sig = np.zeros(len(pts), complex)
+    tmat = (-1j * Q) if adjoint else (1j * Q.T)
+    for k, j in enumerate(pts):
+        idx = np.unravel_index(int(j), shape)
+        lap = -2.0 * grid.dim * c[j]
+        for a in range(grid.dim):
+            for d in (-1, 1):
+                nb = list(idx)
+                nb[a] += d
+                if grid.periodic:
+                    nb[a] %= shape[a]
+                elif not 0 <= nb[a] < shape[a]:
+                    continue
+                lap = lap + c[np.ravel_multi_index(tuple(nb), shape)]
+        Hc = -kin * lap + v0[j] * c[j]
+        z = (idx[z_axis] - 0.5 * (shape[z_axis] - 1)) * grid.h
+        row = tmat @ c[j] - U @ Hc - z * (W @ c[j]) + s * lam[j]
+        rhs = np.zeros(n_t, complex) if stat_rhs is None else stat_rhs[j]
+        rho[k] = rhs - row
+        sig[k] = psi0[j] - s @ c[j]
+    return rho, sig
+
+
+def block_system(grid, v0, n_t, dt, t0, field, points):
+    """Dense K restricted to the rows and columns of one box of points.
+
+    The box's own kinetic stencil with everything outside held at zero, its
+    V0 and z, and the time operators of the step: exactly the block of K on
+    those rows and columns (Dirichlet grids).
+    """
+    pts = np.asarray(points)
+    coords = np.array(np.unravel_index(pts, grid.n)).T
+    lo = coords.min(axis=0)
+    bshape = tuple(int(x) for x in coords.max(axis=0) - lo + 1)
+    order = np.ravel_multi_index(tuple((coords - lo).T), bshape)
+    if not np.array_equal(np.sort(order), np.arange(len(pts))):
+        raise ValueError("points must form a box")
+    sub = Grid(bshape, grid.h, False, grid.mass, grid.field_axis)
+    z_axis = grid.field_axis % grid.dim
+    zfull = (coords[:, z_axis] - 0.5 * (grid.n[z_axis] - 1)) * grid.h
+    inv = np.empty(len(pts), int)
+    inv[order] = np.arange(len(pts))
+    v_sub = np.asarray(v0)[pts][inv]
+    z_sub = zfull[inv]
+    U = tb.overlap_U(n_t, dt)
+    Q = tb.derivative_Q(n_t, dt)
+    s = tb.start_values(n_t)
+    W = np.zeros((n_t, n_t)) if field is None else tb.field_matrix(n_t, t0, dt, field)
+    K = assemble(sub, v_sub, U, Q, s, W, z=z_sub).toarray()
+    # rows/cols of ``sub`` are in box C order; entry k of ``points`` is box point order[k]
+    rows = np.concatenate([(order[:, None] * n_t + np.arange(n_t)[None, :]).ravel(),
+                           len(pts) * n_t + order])
+    return K[np.ix_(rows, rows)]

@@ -1,0 +1,794 @@
+// Host side of liblam: context, level hierarchy, factorisation, V-cycle,
+// step solve and adjoint step.  Every numerical step runs in the kernels of
+// lam_kernels.hip; this file only sizes, orders and launches them.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lam_internal.h"
+
+using namespace lam;
+
+namespace {
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return LAM_EHIP;      \
+    } while (0)
+
+#define LAMCHK(x)                                   \
+    do {                                            \
+        int r_ = (x);                               \
+        if (r_ != LAM_OK) return r_;                \
+    } while (0)
+
+struct Level {
+    LevelGeom g{};
+    int nblocks = 0;
+    int ncol[2] = {0, 0};
+    int* d_blocks[2] = {nullptr, nullptr};
+    double* d_v0 = nullptr;
+    double2* d_c = nullptr;     // state x = (c, lambda)
+    double2* d_lam = nullptr;
+    double2* d_bc = nullptr;    // right-hand side (coarse levels)
+    double2* d_bs = nullptr;
+    double2* d_rc = nullptr;    // residual scratch
+    double2* d_rs = nullptr;
+    double* d_V = nullptr;      // block eigenvectors (FP64)
+    double* d_e = nullptr;      // block eigenvalues
+    float* d_Vf = nullptr;      // FP32 copy (mixed path)
+    double2* d_Minv = nullptr;  // per-mode time-system inverses
+    float2* d_Minvf = nullptr;
+    double* d_shift = nullptr;  // per-block eigenvalue shift (frozen field)
+    std::vector<double> zc;     // block centre coordinate along the field axis
+    double factored_field = NAN;
+    bool fp32 = false;
+};
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_N.
+void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(N, 0.0);
+    w.assign(N, 0.0);
+    for (int i = 0; i < N; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (N + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= N; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = N * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= N; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = N * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+void legendre_values(int nt, double y, double* P) {
+    P[0] = 1.0;
+    if (nt > 1) P[1] = y;
+    for (int k = 1; k + 1 < nt; ++k) P[k + 1] = ((2.0 * k + 1.0) * y * P[k] - k * P[k - 1]) / (k + 1.0);
+}
+
+}  // namespace
+
+struct lam_ctx {
+    lam_grid grid{};
+    lam_time time{};
+    lam_ham ham{};
+    lam_solver solver{};
+    hipStream_t st = nullptr;
+    int nt = 0;
+    int L = 0;
+    std::vector<Level> lv;
+    std::vector<double> coef;
+    double U[kMaxNT] = {};
+    // current step
+    double t0 = NAN;
+    double W[kMaxNT * kMaxNT] = {};
+    double Ebar = 0.0;
+    int field_on = 0;
+    int n_inner = 0;
+    int have_state = 0;
+    int adjoint = 0;
+    double2* d_g = nullptr;       // adjoint: dL/dpsi_out^* (broadcast right-hand side)
+    // reductions
+    double* d_partial = nullptr;
+    int max_parts = 0;
+    double* d_red = nullptr;
+    double* h_red = nullptr;      // pinned
+    double2* d_Gpart = nullptr;
+    double2* d_G = nullptr;
+    double2* h_G = nullptr;       // pinned
+    double2* d_cf = nullptr;      // forward coefficients kept for the gradients
+    // profiling of finest-level sweeps
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    int nev = 0;
+    int sweeps_fine = 0;
+    double t_factor_ms = 0.0;
+};
+
+namespace {
+
+double field_value(const lam_ctx* c, double t) {
+    const lam_ham& h = c->ham;
+    if (h.pulse_kind == LAM_PULSE_NONE) return 0.0;
+    if (t < 0.0 || t > h.t_total) return 0.0;
+    double e = 0.0;
+    if (h.pulse_kind == LAM_PULSE_SIN2 || h.pulse_kind == LAM_PULSE_SIN2_FOURIER) {
+        const double s = std::sin(M_PI * t / h.t_total);
+        e += h.e0 * s * s * std::cos(h.omega * t);
+    }
+    if (h.pulse_kind == LAM_PULSE_FOURIER || h.pulse_kind == LAM_PULSE_SIN2_FOURIER) {
+        for (size_t q = 0; q < c->coef.size(); ++q) e += c->coef[q] * std::sin((q + 1) * M_PI * t / h.t_total);
+    }
+    return e;
+}
+
+// W_nm = int_{t0}^{t0+dt} T_n T_m f(t) dt for f = E (q < 0) or the q-th sine.
+void time_matrix(const lam_ctx* c, double t0, int q, double* W) {
+    const int nt = c->nt;
+    const double dt = c->time.dt;
+    std::vector<double> x, w;
+    gauss_legendre(48, x, w);
+    for (int k = 0; k < nt * nt; ++k) W[k] = 0.0;
+    double P[kMaxNT];
+    for (size_t k = 0; k < x.size(); ++k) {
+        const double t = t0 + 0.5 * dt * (x[k] + 1.0);
+        double f;
+        if (q < 0) {
+            f = field_value(c, t);
+        } else {
+            f = (t < 0.0 || t > c->ham.t_total) ? 0.0 : std::sin((q + 1) * M_PI * t / c->ham.t_total);
+        }
+        if (f == 0.0) continue;
+        legendre_values(nt, x[k], P);
+        const double wk = 0.5 * dt * w[k] * f;
+        for (int n = 0; n < nt; ++n)
+            for (int m = 0; m < nt; ++m) W[n * nt + m] += wk * P[n] * P[m];
+    }
+}
+
+int refactor_modes(lam_ctx* c, Level& L) {
+    if (L.factored_field == c->Ebar) return LAM_OK;
+    std::vector<double> sh(L.nblocks);
+    for (int b = 0; b < L.nblocks; ++b) sh[b] = c->Ebar * L.zc[b];
+    HIPCHK(hipMemcpyAsync(L.d_shift, sh.data(), sizeof(double) * L.nblocks, hipMemcpyHostToDevice, c->st));
+    HIPCHK(launch_mode_factor(c->nt, L.nblocks, L.g.bpts, c->U, L.d_e, L.d_shift, L.d_Minv,
+                              L.fp32 ? L.d_Minvf : nullptr, c->st));
+    // the shift array must stay valid until the kernel has read it
+    HIPCHK(hipStreamSynchronize(c->st));
+    L.factored_field = c->Ebar;
+    return LAM_OK;
+}
+
+// Select the step starting at t0: field matrix, mean field, inner-pass count.
+int set_step(lam_ctx* c, double t0) {
+    if (!(c->t0 == t0)) {
+        time_matrix(c, t0, -1, c->W);
+        c->t0 = t0;
+    }
+    const int nt = c->nt;
+    int on = 0;
+    for (int k = 0; k < nt * nt; ++k) on |= (c->W[k] != 0.0);
+    c->field_on = on;
+    c->Ebar = c->W[0] / c->U[0];
+    c->n_inner = c->solver.n_inner >= 0 ? c->solver.n_inner : (on ? 3 : 0);
+    auto t_a = std::chrono::steady_clock::now();
+    for (auto& L : c->lv) LAMCHK(refactor_modes(c, L));
+    c->t_factor_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
+    return LAM_OK;
+}
+
+int factor_level(lam_ctx* c, Level& L) {
+    HIPCHK(launch_block_eig(L.g, L.d_v0, L.d_V, L.d_e, L.fp32 ? L.d_Vf : nullptr, c->st));
+    L.factored_field = NAN;
+    return refactor_modes(c, L);
+}
+
+int sweep(lam_ctx* c, int l, int colour) {
+    Level& L = c->lv[l];
+    SweepArgs a{};
+    a.g = L.g;
+    a.blocks = L.d_blocks[colour];
+    a.c = L.d_c;
+    a.lam = L.d_lam;
+    a.v0 = L.d_v0;
+    if (l == 0) {
+        a.bc = nullptr;
+        a.bg = c->adjoint ? c->d_g : nullptr;
+        a.bs = c->adjoint ? nullptr : L.d_bs;
+    } else {
+        a.bc = L.d_bc;
+        a.bg = nullptr;
+        a.bs = L.d_bs;
+    }
+    a.V = L.fp32 ? static_cast<const void*>(L.d_Vf) : static_cast<const void*>(L.d_V);
+    a.Minv = L.fp32 ? static_cast<const void*>(L.d_Minvf) : static_cast<const void*>(L.d_Minv);
+    a.adjoint = c->adjoint;
+    a.n_inner = c->n_inner;
+    const bool rec = c->prof && l == 0;
+    if (rec) {
+        while ((int)c->ev.size() < c->nev + 2) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+        HIPCHK(hipEventRecord(c->ev[c->nev], c->st));
+    }
+    HIPCHK(launch_sweep(c->nt, L.fp32 ? 1 : 0, a, c->U, c->W, L.ncol[colour], c->st));
+    if (rec) {
+        HIPCHK(hipEventRecord(c->ev[c->nev + 1], c->st));
+        c->nev += 2;
+    }
+    return LAM_OK;
+}
+
+int full_sweep(lam_ctx* c, int l) {
+    LAMCHK(sweep(c, l, 0));
+    LAMCHK(sweep(c, l, 1));
+    if (l == 0) c->sweeps_fine++;
+    return LAM_OK;
+}
+
+// Residual of level l into its scratch (rc, rs).
+int level_residual(lam_ctx* c, int l) {
+    Level& L = c->lv[l];
+    const double2* bc = l == 0 ? nullptr : L.d_bc;
+    const double2* bg = (l == 0 && c->adjoint) ? c->d_g : nullptr;
+    const double2* bs = (l == 0 && c->adjoint) ? nullptr : L.d_bs;
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, L.d_c, L.d_lam, L.d_v0, bc, bg, bs, L.d_rc,
+                           L.d_rs, nullptr, nullptr, c->st));
+    return LAM_OK;
+}
+
+// N of the finest level for the context state (synchronises).
+int norm0(lam_ctx* c, double* out) {
+    Level& L = c->lv[0];
+    const double2* bg = c->adjoint ? c->d_g : nullptr;
+    const double2* bs = c->adjoint ? nullptr : L.d_bs;
+    int np = 0;
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, L.d_c, L.d_lam, L.d_v0, nullptr, bg, bs, nullptr,
+                           nullptr, c->d_partial, &np, c->st));
+    HIPCHK(launch_reduce(c->d_partial, np, 1, c->d_red, c->st));
+    HIPCHK(hipMemcpyAsync(c->h_red, c->d_red, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    *out = c->h_red[0];
+    return LAM_OK;
+}
+
+int vcycle(lam_ctx* c, int l) {
+    if (l == c->L - 1) {
+        for (int s = 0; s < c->grid.nu_coarse; ++s) LAMCHK(full_sweep(c, l));
+        return LAM_OK;
+    }
+    for (int s = 0; s < c->grid.nu_pre; ++s) LAMCHK(full_sweep(c, l));
+    LAMCHK(level_residual(c, l));
+    Level& F = c->lv[l];
+    Level& C = c->lv[l + 1];
+    HIPCHK(launch_restrict(c->nt, F.g, C.g, F.d_rc, F.d_rs, C.d_bc, C.d_bs, C.d_c, C.d_lam, c->st));
+    LAMCHK(vcycle(c, l + 1));
+    HIPCHK(launch_prolong(c->nt, F.g, C.g, c->grid.interp, C.d_c, C.d_lam, F.d_c, F.d_lam, c->st));
+    for (int s = 0; s < c->grid.nu_post; ++s) LAMCHK(full_sweep(c, l));
+    return LAM_OK;
+}
+
+// V-cycles on the context state until sqrt(N/N0) <= tol.
+int solve_loop(lam_ctx* c, lam_stats* stats) {
+    double N0 = 0.0, N = 0.0;
+    LAMCHK(norm0(c, &N0));
+    N = N0;
+    int cycles = 0;
+    int rc = LAM_OK;
+    if (N0 > 0.0) {
+        rc = LAM_ENOCONV;
+        for (cycles = 0; cycles < c->solver.max_cycles;) {
+            LAMCHK(vcycle(c, 0));
+            ++cycles;
+            LAMCHK(norm0(c, &N));
+            if (!std::isfinite(N) || N > 1e12 * N0) {
+                rc = LAM_EDIVERGED;
+                break;
+            }
+            if (std::sqrt(N / N0) <= c->solver.tol) {
+                rc = LAM_OK;
+                break;
+            }
+        }
+    }
+    if (stats) {
+        stats->cycles = cycles;
+        stats->resid0 = std::sqrt(N0);
+        stats->resid = std::sqrt(N);
+    }
+    return rc;
+}
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+int validate(const lam_grid* g, const lam_time* t, const lam_ham* h, const lam_solver* s) {
+    if (!g || !t || !h || !s) return LAM_EINVAL;
+    if (g->dim < 1 || g->dim > 3) return LAM_EINVAL;
+    if (!(g->h > 0.0) || !(t->dt > 0.0) || !(h->mass > 0.0)) return LAM_EINVAL;
+    if (t->n_t < 1 || t->n_t > LAM_MAX_NT) return LAM_EINVAL;
+    if (g->levels < 1 || g->levels > 16) return LAM_EINVAL;
+    if (g->nu_pre < 0 || g->nu_post < 0 || g->nu_coarse < 0) return LAM_EINVAL;
+    if (g->interp != 0 && g->interp != 1) return LAM_EINVAL;
+    if (h->field_axis < 0 || h->field_axis >= g->dim) return LAM_EINVAL;
+    if (h->pulse_kind < LAM_PULSE_NONE || h->pulse_kind > LAM_PULSE_SIN2_FOURIER) return LAM_EINVAL;
+    if (h->pulse_kind != LAM_PULSE_NONE && !(h->t_total > 0.0)) return LAM_EINVAL;
+    if (h->n_coef < 0 || (h->n_coef > 0 && !h->coef)) return LAM_EINVAL;
+    if (!h->v0) return LAM_EINVAL;
+    if (s->precision != LAM_FP64 && s->precision != LAM_MIXED) return LAM_EINVAL;
+    if (s->max_cycles < 0 || !(s->tol >= 0.0) || s->n_inner < -1) return LAM_EINVAL;
+    long bpts = 1;
+    for (int a = 0; a < g->dim; ++a) {
+        if (g->n[a] < 1 || g->block[a] < 1) return LAM_EINVAL;
+        bpts *= g->block[a];
+        long n = g->n[a];
+        for (int l = 0; l < g->levels; ++l) {
+            if (n % g->block[a]) return LAM_EINVAL;
+            const long nb = n / g->block[a];
+            if (g->periodic && nb > 1 && (nb & 1)) return LAM_EINVAL;
+            if (l + 1 < g->levels) {
+                if (n & 1) return LAM_EINVAL;
+                n /= 2;
+            }
+        }
+    }
+    if (bpts > LAM_MAX_BLOCK) return LAM_EINVAL;
+    long P = 1;
+    for (int a = 0; a < g->dim; ++a) {
+        P *= g->n[a];
+        if (P > (1L << 30)) return LAM_EINVAL;
+    }
+    return LAM_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return LAM_OK;
+    if (hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * count) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return LAM_ENOMEM;
+    }
+    return LAM_OK;
+}
+
+void free_ctx(lam_ctx* c) {
+    if (!c) return;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    for (auto& L : c->lv) {
+        for (int k = 0; k < 2; ++k) (void)hipFree(L.d_blocks[k]);
+        (void)hipFree(L.d_v0);
+        (void)hipFree(L.d_c);
+        (void)hipFree(L.d_lam);
+        (void)hipFree(L.d_bc);
+        (void)hipFree(L.d_bs);
+        (void)hipFree(L.d_rc);
+        (void)hipFree(L.d_rs);
+        (void)hipFree(L.d_V);
+        (void)hipFree(L.d_e);
+        (void)hipFree(L.d_Vf);
+        (void)hipFree(L.d_Minv);
+        (void)hipFree(L.d_Minvf);
+        (void)hipFree(L.d_shift);
+    }
+    (void)hipFree(c->d_g);
+    (void)hipFree(c->d_partial);
+    (void)hipFree(c->d_red);
+    (void)hipFree(c->d_Gpart);
+    (void)hipFree(c->d_G);
+    (void)hipFree(c->d_cf);
+    if (c->h_red) (void)hipHostFree(c->h_red);
+    if (c->h_G) (void)hipHostFree(c->h_G);
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int build(lam_ctx* c, const double* v0_dev) {
+    const lam_grid& gr = c->grid;
+    const int nt = c->nt;
+    c->lv.resize(gr.levels);
+    for (int l = 0; l < gr.levels; ++l) {
+        Level& L = c->lv[l];
+        LevelGeom& g = L.g;
+        g.dim = gr.dim;
+        g.P = 1;
+        g.nblk[0] = g.nblk[1] = g.nblk[2] = 1;
+        g.bdim[0] = g.bdim[1] = g.bdim[2] = 1;
+        g.n[0] = g.n[1] = g.n[2] = 1;
+        for (int a = 0; a < gr.dim; ++a) {
+            g.n[a] = gr.n[a] >> l;
+            g.bdim[a] = gr.block[a];
+            g.nblk[a] = g.n[a] / g.bdim[a];
+            g.P *= g.n[a];
+        }
+        g.h = gr.h * std::ldexp(1.0, l);
+        g.periodic = gr.periodic;
+        g.fax = c->ham.field_axis;
+        g.kin = 1.0 / (2.0 * c->ham.mass * g.h * g.h);
+        g.bpts = g.bdim[0] * g.bdim[1] * g.bdim[2];
+        L.nblocks = g.nblk[0] * g.nblk[1] * g.nblk[2];
+        L.fp32 = c->solver.precision == LAM_MIXED && (l < gr.levels - 1 || gr.levels == 1);
+        // colour lists and block centres along the field axis
+        std::vector<int> col[2];
+        L.zc.resize(L.nblocks);
+        for (int b = 0; b < L.nblocks; ++b) {
+            int bc[3] = {0, 0, 0}, t = b;
+            for (int a = gr.dim - 1; a >= 0; --a) {
+                bc[a] = t % g.nblk[a];
+                t /= g.nblk[a];
+            }
+            col[(bc[0] + bc[1] + bc[2]) & 1].push_back(b);
+            const int a = g.fax;
+            const double centre_index = bc[a] * g.bdim[a] + 0.5 * (g.bdim[a] - 1);
+            L.zc[b] = (centre_index - 0.5 * (g.n[a] - 1)) * g.h;
+        }
+        for (int k = 0; k < 2; ++k) {
+            L.ncol[k] = (int)col[k].size();
+            LAMCHK(dalloc(&L.d_blocks[k], col[k].size()));
+            if (!col[k].empty())
+                HIPCHK(hipMemcpy(L.d_blocks[k], col[k].data(), sizeof(int) * col[k].size(),
+                                 hipMemcpyHostToDevice));
+        }
+        const size_t P = g.P;
+        const size_t B = g.bpts;
+        LAMCHK(dalloc(&L.d_v0, P));
+        LAMCHK(dalloc(&L.d_c, P * nt));
+        LAMCHK(dalloc(&L.d_lam, P));
+        LAMCHK(dalloc(&L.d_rc, P * nt));
+        LAMCHK(dalloc(&L.d_rs, P));
+        LAMCHK(dalloc(&L.d_bs, P));
+        if (l > 0) LAMCHK(dalloc(&L.d_bc, P * nt));
+        LAMCHK(dalloc(&L.d_V, L.nblocks * B * B));
+        LAMCHK(dalloc(&L.d_e, L.nblocks * B));
+        LAMCHK(dalloc(&L.d_Minv, L.nblocks * B * (nt + 1) * (nt + 1)));
+        LAMCHK(dalloc(&L.d_shift, (size_t)L.nblocks));
+        if (L.fp32) {
+            LAMCHK(dalloc(&L.d_Vf, L.nblocks * B * B));
+            LAMCHK(dalloc(&L.d_Minvf, L.nblocks * B * (nt + 1) * (nt + 1)));
+        }
+    }
+    HIPCHK(hipMemcpyAsync(c->lv[0].d_v0, v0_dev, sizeof(double) * c->lv[0].g.P, hipMemcpyDeviceToDevice, c->st));
+    for (int l = 1; l < gr.levels; ++l)
+        HIPCHK(launch_average_potential(c->lv[l - 1].g, c->lv[l].g, c->lv[l - 1].d_v0, c->lv[l].d_v0, c->st));
+    const int P0 = c->lv[0].g.P;
+    c->max_parts = (P0 + kThreads - 1) / kThreads;
+    LAMCHK(dalloc(&c->d_partial, (size_t)c->max_parts));
+    LAMCHK(dalloc(&c->d_red, 1));
+    LAMCHK(dalloc(&c->d_g, (size_t)P0));
+    LAMCHK(dalloc(&c->d_cf, (size_t)P0 * nt));
+    LAMCHK(dalloc(&c->d_Gpart, (size_t)c->max_parts * nt * nt));
+    LAMCHK(dalloc(&c->d_G, (size_t)nt * nt));
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_red), sizeof(double)) != hipSuccess) return LAM_ENOMEM;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
+        return LAM_ENOMEM;
+    c->Ebar = 0.0;
+    for (auto& L : c->lv) LAMCHK(factor_level(c, L));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return LAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lam_create(const lam_grid* grid, const lam_time* time, const lam_ham* ham, const lam_solver* solver,
+               void* hip_stream, lam_ctx** out) {
+    if (!out) return LAM_EINVAL;
+    *out = nullptr;
+    LAMCHK(validate(grid, time, ham, solver));
+    lam_ctx* c = new (std::nothrow) lam_ctx();
+    if (!c) return LAM_ENOMEM;
+    c->grid = *grid;
+    c->time = *time;
+    c->ham = *ham;
+    c->solver = *solver;
+    c->st = static_cast<hipStream_t>(hip_stream);
+    c->nt = time->n_t;
+    c->L = grid->levels;
+    c->coef.assign(ham->coef, ham->coef + ham->n_coef);
+    c->ham.coef = nullptr;
+    c->ham.v0 = nullptr;
+    for (int m = 0; m < c->nt; ++m) c->U[m] = time->dt / (2.0 * m + 1.0);
+    const int r = build(c, ham->v0);
+    if (r != LAM_OK) {
+        free_ctx(c);
+        return r;
+    }
+    *out = c;
+    return LAM_OK;
+}
+
+int lam_destroy(lam_ctx* ctx) {
+    free_ctx(ctx);
+    return LAM_OK;
+}
+
+int lam_set_pulse(lam_ctx* ctx, int n_coef, const double* coef) {
+    if (!ctx || n_coef != (int)ctx->coef.size() || (n_coef > 0 && !coef)) return LAM_EINVAL;
+    ctx->coef.assign(coef, coef + n_coef);
+    ctx->t0 = NAN;  // field matrices must be recomputed
+    return LAM_OK;
+}
+
+int lam_set_potential(lam_ctx* ctx, const double* v0) {
+    if (!ctx || !v0) return LAM_EINVAL;
+    HIPCHK(hipMemcpyAsync(ctx->lv[0].d_v0, v0, sizeof(double) * ctx->lv[0].g.P, hipMemcpyDeviceToDevice, ctx->st));
+    for (int l = 1; l < ctx->L; ++l)
+        HIPCHK(launch_average_potential(ctx->lv[l - 1].g, ctx->lv[l].g, ctx->lv[l - 1].d_v0, ctx->lv[l].d_v0,
+                                        ctx->st));
+    for (auto& L : ctx->lv) LAMCHK(factor_level(ctx, L));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    return LAM_OK;
+}
+
+int lam_residual_action(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c, const lam_c64* lam,
+                        lam_c64* rho, lam_c64* sigma, double* norm) {
+    if (!ctx || bad_ptr(psi0) || bad_ptr(c) || bad_ptr(lam)) return LAM_EINVAL;
+    LAMCHK(set_step(ctx, t0));
+    Level& L = ctx->lv[0];
+    int np = 0;
+    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, ctx->W, 0, reinterpret_cast<const double2*>(c),
+                           reinterpret_cast<const double2*>(lam), L.d_v0, nullptr, nullptr,
+                           reinterpret_cast<const double2*>(psi0), reinterpret_cast<double2*>(rho),
+                           reinterpret_cast<double2*>(sigma), norm ? ctx->d_partial : nullptr, &np, ctx->st));
+    if (norm) {
+        HIPCHK(launch_reduce(ctx->d_partial, np, 1, ctx->d_red, ctx->st));
+        HIPCHK(hipMemcpyAsync(ctx->h_red, ctx->d_red, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        *norm = ctx->h_red[0];
+    }
+    return LAM_OK;
+}
+
+int lam_residual_adjoint(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c, const lam_c64* mu_lam,
+                         lam_c64* rho, lam_c64* sigma, double* norm) {
+    if (!ctx || bad_ptr(g) || bad_ptr(mu_c) || bad_ptr(mu_lam)) return LAM_EINVAL;
+    LAMCHK(set_step(ctx, t0));
+    Level& L = ctx->lv[0];
+    int np = 0;
+    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, ctx->W, 1, reinterpret_cast<const double2*>(mu_c),
+                           reinterpret_cast<const double2*>(mu_lam), L.d_v0, nullptr,
+                           reinterpret_cast<const double2*>(g), nullptr, reinterpret_cast<double2*>(rho),
+                           reinterpret_cast<double2*>(sigma), norm ? ctx->d_partial : nullptr, &np, ctx->st));
+    if (norm) {
+        HIPCHK(launch_reduce(ctx->d_partial, np, 1, ctx->d_red, ctx->st));
+        HIPCHK(hipMemcpyAsync(ctx->h_red, ctx->d_red, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        *norm = ctx->h_red[0];
+    }
+    return LAM_OK;
+}
+
+int lam_set_state(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c, const lam_c64* lam) {
+    if (!ctx || bad_ptr(psi0) || bad_ptr(c) || bad_ptr(lam)) return LAM_EINVAL;
+    LAMCHK(set_step(ctx, t0));
+    Level& L = ctx->lv[0];
+    const size_t P = L.g.P;
+    HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(psi0), L.d_bs, P, ctx->st));
+    HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(c), L.d_c, P * ctx->nt, ctx->st));
+    HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(lam), L.d_lam, P, ctx->st));
+    ctx->adjoint = 0;
+    ctx->have_state = 1;
+    return LAM_OK;
+}
+
+int lam_set_adjoint_state(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c, const lam_c64* mu_lam) {
+    if (!ctx || bad_ptr(g) || bad_ptr(mu_c) || bad_ptr(mu_lam)) return LAM_EINVAL;
+    LAMCHK(set_step(ctx, t0));
+    Level& L = ctx->lv[0];
+    const size_t P = L.g.P;
+    HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(g), ctx->d_g, P, ctx->st));
+    HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(mu_c), L.d_c, P * ctx->nt, ctx->st));
+    HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(mu_lam), L.d_lam, P, ctx->st));
+    ctx->adjoint = 1;
+    ctx->have_state = 1;
+    return LAM_OK;
+}
+
+int lam_get_state(lam_ctx* ctx, lam_c64* c, lam_c64* lam) {
+    if (!ctx || bad_ptr(c) || bad_ptr(lam)) return LAM_EINVAL;
+    if (!ctx->have_state) return LAM_ESTATE;
+    Level& L = ctx->lv[0];
+    const size_t P = L.g.P;
+    HIPCHK(launch_copy_c2(L.d_c, reinterpret_cast<double2*>(c), P * ctx->nt, ctx->st));
+    HIPCHK(launch_copy_c2(L.d_lam, reinterpret_cast<double2*>(lam), P, ctx->st));
+    return LAM_OK;
+}
+
+int lam_relax_sweep(lam_ctx* ctx, int level, int colour) {
+    if (!ctx || level < 0 || level >= ctx->L || (colour != 0 && colour != 1)) return LAM_EINVAL;
+    if (!ctx->have_state) return LAM_ESTATE;
+    if (level > 0) {
+        // a coarse level relaxes its own correction problem; it needs a right-hand side
+        // produced by a V-cycle, so only the finest level is addressable on its own
+        return LAM_EINVAL;
+    }
+    return sweep(ctx, level, colour);
+}
+
+int lam_vcycle(lam_ctx* ctx, double* norm) {
+    if (!ctx) return LAM_EINVAL;
+    if (!ctx->have_state) return LAM_ESTATE;
+    LAMCHK(vcycle(ctx, 0));
+    if (norm) LAMCHK(norm0(ctx, norm));
+    return LAM_OK;
+}
+
+int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_out, lam_stats* stats) {
+    if (!ctx || bad_ptr(psi_in) || bad_ptr(psi_out)) return LAM_EINVAL;
+    const auto t_a = std::chrono::steady_clock::now();
+    ctx->t_factor_ms = 0.0;
+    const int sw0 = ctx->sweeps_fine;
+    LAMCHK(set_step(ctx, t0));
+    Level& L = ctx->lv[0];
+    HIPCHK(launch_init_forward(ctx->nt, L.g.P, reinterpret_cast<const double2*>(psi_in), L.d_c, L.d_lam, L.d_bs,
+                               ctx->st));
+    ctx->adjoint = 0;
+    ctx->have_state = 1;
+    const int rc = solve_loop(ctx, stats);
+    if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
+    HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, reinterpret_cast<double2*>(psi_out), ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (stats) {
+        stats->sweeps_fine = ctx->sweeps_fine - sw0;
+        stats->t_factor_ms = ctx->t_factor_ms;
+        stats->t_solve_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
+    }
+    return rc;
+}
+
+int lam_adjoint_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, const lam_c64* g_out, lam_c64* g_in,
+                     double* dL_dv0, double* dL_dcoef, lam_stats* stats) {
+    if (!ctx || bad_ptr(psi_in) || bad_ptr(g_out) || bad_ptr(g_in) || bad_ptr(dL_dv0)) return LAM_EINVAL;
+    const auto t_a = std::chrono::steady_clock::now();
+    ctx->t_factor_ms = 0.0;
+    const int sw0 = ctx->sweeps_fine;
+    LAMCHK(set_step(ctx, t0));
+    Level& L = ctx->lv[0];
+    const int nt = ctx->nt;
+    const size_t P = L.g.P;
+    // 1. recompute the forward solution of this step from its checkpoint
+    HIPCHK(launch_init_forward(nt, (int)P, reinterpret_cast<const double2*>(psi_in), L.d_c, L.d_lam, L.d_bs,
+                               ctx->st));
+    ctx->adjoint = 0;
+    ctx->have_state = 1;
+    int rc = solve_loop(ctx, nullptr);
+    if (rc != LAM_OK) return rc;
+    HIPCHK(launch_copy_c2(L.d_c, ctx->d_cf, P * nt, ctx->st));
+    // 2. adjoint solve K^H mu = E^H g_out from mu = 0
+    HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(g_out), ctx->d_g, P, ctx->st));
+    HIPCHK(launch_init_zero(nt, (int)P, L.d_c, L.d_lam, ctx->st));
+    ctx->adjoint = 1;
+    rc = solve_loop(ctx, stats);
+    if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
+    // 3. gradients
+    int np = 0;
+    const bool want_coef = dL_dcoef && !ctx->coef.empty() &&
+                           (ctx->ham.pulse_kind == LAM_PULSE_FOURIER || ctx->ham.pulse_kind == LAM_PULSE_SIN2_FOURIER);
+    HIPCHK(launch_gradients(nt, L.g, ctx->U, ctx->d_cf, L.d_c, dL_dv0, want_coef ? ctx->d_Gpart : nullptr, &np,
+                            ctx->st));
+    HIPCHK(launch_copy_c2(L.d_lam, reinterpret_cast<double2*>(g_in), P, ctx->st));
+    if (want_coef) {
+        HIPCHK(launch_reduce_c2(ctx->d_Gpart, np, nt * nt, ctx->d_G, ctx->st));
+        HIPCHK(hipMemcpyAsync(ctx->h_G, ctx->d_G, sizeof(double2) * nt * nt, hipMemcpyDeviceToHost, ctx->st));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (want_coef) {
+        double Wq[kMaxNT * kMaxNT];
+        for (size_t q = 0; q < ctx->coef.size(); ++q) {
+            time_matrix(ctx, t0, (int)q, Wq);
+            double acc = 0.0;
+            for (int m = 0; m < nt; ++m)
+                for (int n = 0; n < nt; ++n) acc += Wq[m * nt + n] * ctx->h_G[m * nt + n].x;
+            dL_dcoef[q] += 2.0 * acc;
+        }
+    }
+    if (stats) {
+        stats->sweeps_fine = ctx->sweeps_fine - sw0;
+        stats->t_factor_ms = ctx->t_factor_ms;
+        stats->t_solve_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
+    }
+    return rc;
+}
+
+int lam_restrict(lam_ctx* ctx, int level, const lam_c64* rho_f, const lam_c64* sigma_f, lam_c64* rho_c,
+                 lam_c64* sigma_c) {
+    if (!ctx || level < 0 || level + 1 >= ctx->L) return LAM_EINVAL;
+    if (bad_ptr(rho_f) || bad_ptr(sigma_f) || bad_ptr(rho_c) || bad_ptr(sigma_c)) return LAM_EINVAL;
+    HIPCHK(launch_restrict(ctx->nt, ctx->lv[level].g, ctx->lv[level + 1].g, reinterpret_cast<const double2*>(rho_f),
+                           reinterpret_cast<const double2*>(sigma_f), reinterpret_cast<double2*>(rho_c),
+                           reinterpret_cast<double2*>(sigma_c), nullptr, nullptr, ctx->st));
+    return LAM_OK;
+}
+
+int lam_prolong_add(lam_ctx* ctx, int level, const lam_c64* c_c, const lam_c64* lam_c, lam_c64* c_f,
+                    lam_c64* lam_f) {
+    if (!ctx || level < 0 || level + 1 >= ctx->L) return LAM_EINVAL;
+    if (bad_ptr(c_c) || bad_ptr(lam_c) || bad_ptr(c_f) || bad_ptr(lam_f)) return LAM_EINVAL;
+    HIPCHK(launch_prolong(ctx->nt, ctx->lv[level].g, ctx->lv[level + 1].g, ctx->grid.interp,
+                          reinterpret_cast<const double2*>(c_c), reinterpret_cast<const double2*>(lam_c),
+                          reinterpret_cast<double2*>(c_f), reinterpret_cast<double2*>(lam_f), ctx->st));
+    return LAM_OK;
+}
+
+int lam_level_shape(const lam_ctx* ctx, int level, int* n) {
+    if (!ctx || !n || level < 0 || level >= ctx->L) return LAM_EINVAL;
+    for (int a = 0; a < 3; ++a) n[a] = a < ctx->grid.dim ? ctx->lv[level].g.n[a] : 1;
+    return LAM_OK;
+}
+
+int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, double* vals) {
+    if (!ctx || !vecs || !vals || level < 0 || level >= ctx->L) return LAM_EINVAL;
+    const Level& L = ctx->lv[level];
+    if (block < 0 || block >= L.nblocks) return LAM_EINVAL;
+    const size_t B = L.g.bpts;
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    HIPCHK(hipMemcpy(vecs, L.d_V + block * B * B, sizeof(double) * B * B, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(vals, L.d_e + block * B, sizeof(double) * B, hipMemcpyDeviceToHost));
+    return LAM_OK;
+}
+
+int lam_profile(lam_ctx* ctx, int enable) {
+    if (!ctx) return LAM_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    ctx->prof = enable != 0;
+    if (enable) ctx->nev = 0;
+    return LAM_OK;
+}
+
+int lam_profile_read(lam_ctx* ctx, int* launches, double* total_ms) {
+    if (!ctx || !launches || !total_ms) return LAM_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    double tot = 0.0;
+    for (int k = 0; k + 1 < ctx->nev; k += 2) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev[k], ctx->ev[k + 1]));
+        tot += ms;
+    }
+    *launches = ctx->nev / 2;
+    *total_ms = tot;
+    return LAM_OK;
+}
+
+const char* lam_strerror(int code) {
+    switch (code) {
+        case LAM_OK: return "ok";
+        case LAM_EINVAL: return "invalid argument";
+        case LAM_ENOMEM: return "device allocation failed";
+        case LAM_EHIP: return "HIP runtime error";
+        case LAM_ENOCONV: return "tolerance not reached within max_cycles";
+        case LAM_EDIVERGED: return "residual norm diverged";
+        case LAM_ESTATE: return "no state loaded";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

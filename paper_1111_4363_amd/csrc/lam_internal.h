@@ -1,0 +1,99 @@
+// Internal declarations shared by the kernels and the host side of liblam.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "lam.h"
+
+namespace lam {
+
+constexpr int kMaxNT = LAM_MAX_NT;
+constexpr int kMaxB = LAM_MAX_BLOCK;
+constexpr int kThreads = 256;
+constexpr int kLdsPad = kMaxB + 1;   // row stride of per-block matrices in LDS
+
+// Geometry of one level, passed by value to kernels.
+struct LevelGeom {
+    int dim;
+    int n[3];        // points per axis (unused axes = 1)
+    int P;           // total points
+    double h;
+    int periodic;
+    int fax;         // dipole axis
+    double kin;      // 1/(2 m h^2): T = -kin * (sum of neighbours - 2 d u)
+    int bdim[3];     // block points per axis (unused axes = 1)
+    int nblk[3];     // blocks per axis
+    int bpts;        // points per block
+};
+
+// Time operators of one step: diagonal of U and the field matrix W (symmetric).
+template <int NT>
+struct TimeOps {
+    double U[NT];
+    double W[NT * NT];
+};
+
+struct SweepArgs {
+    LevelGeom g;
+    const int* blocks;        // block ids of the colour being relaxed
+    double2* c;               // [P][NT]
+    double2* lam;             // [P]
+    const double* v0;         // [P]
+    const double2* bc;        // stationarity right-hand side [P][NT], may be null
+    const double2* bg;        // or: the same value on every row (j, n): bg[j]; may be null
+    const double2* bs;        // constraint right-hand side [P], may be null (= 0)
+    const void* V;            // [nblocks][bpts][bpts] eigenvectors (double or float)
+    const void* Minv;         // [nblocks][NT+1][NT+1][bpts] mode inverses (double2 or float2)
+    int adjoint;
+    int n_inner;
+};
+
+// ---- launchers (lam_kernels.hip) -------------------------------------------
+// All return hipSuccess or the launch error.
+
+hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const double* W, int adjoint,
+                           const double2* c, const double2* lam, const double* v0, const double2* bc,
+                           const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
+                           int* nparts, hipStream_t st);
+
+hipError_t launch_reduce(const double* partial, int nparts, int width, double* out, hipStream_t st);
+
+hipError_t launch_restrict(int nt, const LevelGeom& fine, const LevelGeom& coarse, const double2* rcf,
+                           const double2* rsf, double2* bcc, double2* bsc, double2* zero_c,
+                           double2* zero_l, hipStream_t st);
+
+hipError_t launch_prolong(int nt, const LevelGeom& fine, const LevelGeom& coarse, int interp,
+                          const double2* cc, const double2* lc, double2* cf, double2* lf,
+                          hipStream_t st);
+
+hipError_t launch_average_potential(const LevelGeom& fine, const LevelGeom& coarse, const double* vf,
+                                    double* vc, hipStream_t st);
+
+hipError_t launch_block_eig(const LevelGeom& g, const double* v0, double* V, double* e, float* Vf,
+                            hipStream_t st);
+
+hipError_t launch_mode_factor(int nt, int nblocks, int bpts, const double* U, const double* e,
+                              const double* shift, double2* Minv, float2* Minvf, hipStream_t st);
+
+hipError_t launch_sweep(int nt, int mixed, const SweepArgs& a, const double* U, const double* W,
+                        int nblocks_colour, hipStream_t st);
+
+hipError_t launch_init_forward(int nt, int P, const double2* psi, double2* c, double2* lam, double2* bs,
+                               hipStream_t st);
+
+hipError_t launch_init_zero(int nt, int P, double2* c, double2* lam, hipStream_t st);
+
+hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStream_t st);
+
+hipError_t launch_copy_c2(const double2* src, double2* dst, size_t n, hipStream_t st);
+
+hipError_t launch_gradients(int nt, const LevelGeom& g, const double* U, const double2* cfwd,
+                            const double2* mu, double* dv0, double2* Gpart, int* nparts,
+                            hipStream_t st);
+
+hipError_t launch_reduce_c2(const double2* partial, int nparts, int width, double2* out,
+                            hipStream_t st);
+
+}  // namespace lam

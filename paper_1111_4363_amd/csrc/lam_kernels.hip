@@ -1,0 +1,1025 @@
+// HIP kernels of liblam for gfx950 (CDNA4, wave64).
+//
+// Layout in HBM: per grid point, n_t consecutive complex FP64 coefficients
+// c[j][n] (interleaved re/im), one complex multiplier lam[j], one real V0[j].
+// Grid points are in C order over the axes.  Per subvolume ("block"): the
+// eigenvectors of its real symmetric spatial operator [point][mode] and, per
+// mode, the inverse of the (n_t+1) x (n_t+1) time system, stored
+// [block][row][col][mode] so that one wave reads 64 modes of one entry as a
+// contiguous 1 KB segment.
+
+#include "lam_internal.h"
+
+namespace lam {
+namespace {
+
+// ---------------------------------------------------------------------------
+// small complex helpers (T = float or double)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct cx {
+    T r, i;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
+    return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> rmul(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+
+__device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 sub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 scl2(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+
+// ---------------------------------------------------------------------------
+// grid indexing
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void point_coords(const LevelGeom& g, int j, int* i) {
+    i[1] = 0;
+    i[2] = 0;
+    if (g.dim == 1) {
+        i[0] = j;
+    } else if (g.dim == 2) {
+        i[0] = j / g.n[1];
+        i[1] = j - i[0] * g.n[1];
+    } else {
+        const int t = j / g.n[2];
+        i[2] = j - t * g.n[2];
+        i[0] = t / g.n[1];
+        i[1] = t - i[0] * g.n[1];
+    }
+}
+
+__device__ __forceinline__ int point_index(const LevelGeom& g, const int* i) {
+    if (g.dim == 1) return i[0];
+    if (g.dim == 2) return i[0] * g.n[1] + i[1];
+    return (i[0] * g.n[1] + i[1]) * g.n[2] + i[2];
+}
+
+// Neighbour of point i along axis ax in direction d: global index, or -1
+// outside a Dirichlet grid.  gi receives the (wrapped) coordinates.
+__device__ __forceinline__ int neighbour(const LevelGeom& g, const int* i, int ax, int d, int* gi) {
+    gi[0] = i[0];
+    gi[1] = i[1];
+    gi[2] = i[2];
+    gi[ax] += d;
+    if (gi[ax] < 0 || gi[ax] >= g.n[ax]) {
+        if (!g.periodic) return -1;
+        gi[ax] = (gi[ax] + g.n[ax]) % g.n[ax];
+    }
+    return point_index(g, gi);
+}
+
+__device__ __forceinline__ double zcoord(const LevelGeom& g, const int* i) {
+    return (i[g.fax] - 0.5 * (g.n[g.fax] - 1)) * g.h;
+}
+
+// Block bookkeeping: block id -> block coordinates; local index -> local coords.
+__device__ __forceinline__ void block_coords(const LevelGeom& g, int blk, int* bc) {
+    bc[0] = bc[1] = bc[2] = 0;
+    int t = blk;
+    for (int ax = g.dim - 1; ax >= 0; --ax) {
+        bc[ax] = t % g.nblk[ax];
+        t /= g.nblk[ax];
+    }
+}
+
+__device__ __forceinline__ void local_coords(const LevelGeom& g, int l, int* lc) {
+    lc[0] = lc[1] = lc[2] = 0;
+    int t = l;
+    for (int ax = g.dim - 1; ax >= 0; --ax) {
+        lc[ax] = t % g.bdim[ax];
+        t /= g.bdim[ax];
+    }
+}
+
+__device__ __forceinline__ int local_index(const LevelGeom& g, const int* lc) {
+    int l = 0;
+    for (int ax = 0; ax < g.dim; ++ax) l = l * g.bdim[ax] + lc[ax];
+    return l;
+}
+
+// Neighbour of local point lc of block bc: returns the local index when the
+// (wrapped) neighbour lies inside the block, else -1; *glob receives its
+// global index (-1 outside a Dirichlet grid).
+__device__ __forceinline__ int block_neighbour(const LevelGeom& g, const int* bc, const int* lc, int ax,
+                                               int d, int* glob) {
+    int i[3] = {0, 0, 0};
+    for (int a = 0; a < g.dim; ++a) i[a] = bc[a] * g.bdim[a] + lc[a];
+    int gi[3];
+    const int gn = neighbour(g, i, ax, d, gi);
+    *glob = gn;
+    if (gn < 0) return -1;
+    int ln[3] = {0, 0, 0};
+    for (int a = 0; a < g.dim; ++a) {
+        ln[a] = gi[a] - bc[a] * g.bdim[a];
+        if (ln[a] < 0 || ln[a] >= g.bdim[a]) return -1;
+    }
+    return local_index(g, ln);
+}
+
+// ---------------------------------------------------------------------------
+// reductions (deterministic: fixed thread -> element assignment, fixed tree)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += sh[k];
+    __syncthreads();
+    return tot;
+}
+
+// ---------------------------------------------------------------------------
+// K1: action residual of the step system (or its adjoint) + norm partials.
+// One thread per grid point, all n_t time components in registers.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> to, int adjoint,
+                                                       const double2* __restrict__ c,
+                                                       const double2* __restrict__ lam,
+                                                       const double* __restrict__ v0,
+                                                       const double2* __restrict__ bc,
+                                                       const double2* __restrict__ bg,
+                                                       const double2* __restrict__ bs,
+                                                       double2* __restrict__ rc, double2* __restrict__ rs,
+                                                       double* __restrict__ partial) {
+    __shared__ double red[kThreads / 64];
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    double acc = 0.0;
+    if (j < g.P) {
+        int i[3];
+        point_coords(g, j, i);
+        double2 cj[NT], lap[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            cj[n] = c[(size_t)j * NT + n];
+            lap[n] = scl2(-2.0 * g.dim, cj[n]);
+        }
+        for (int ax = 0; ax < g.dim; ++ax) {
+            for (int d = -1; d <= 1; d += 2) {
+                int gi[3];
+                const int nb = neighbour(g, i, ax, d, gi);
+                if (nb >= 0) {
+#pragma unroll
+                    for (int n = 0; n < NT; ++n) lap[n] = add2(lap[n], c[(size_t)nb * NT + n]);
+                }
+            }
+        }
+        const double vj = v0[j];
+        const double z = zcoord(g, i);
+        const double2 lj = lam[j];
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+            double2 tq = make_double2(0.0, 0.0);
+            if (!adjoint) {
+#pragma unroll
+                for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cj[n]);
+            } else {
+#pragma unroll
+                for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cj[n]);
+            }
+            // forward: i * 2 tq ; adjoint: -i * 2 tq
+            const double2 tim = adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x)
+                                        : make_double2(-2.0 * tq.y, 2.0 * tq.x);
+            const double2 hc = add2(scl2(-g.kin, lap[m]), scl2(vj, cj[m]));
+            double2 wc = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cj[n]));
+            const double sm = (m & 1) ? -1.0 : 1.0;
+            double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(z, wc));
+            row = add2(row, scl2(sm, lj));
+            const double2 rhs = bc ? bc[(size_t)j * NT + m] : (bg ? bg[j] : make_double2(0.0, 0.0));
+            const double2 rho = sub2(rhs, row);
+            if (rc) rc[(size_t)j * NT + m] = rho;
+            acc += to.U[m] * (rho.x * rho.x + rho.y * rho.y);
+        }
+        double2 sg = bs ? bs[j] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cj[n]) : sub2(sg, cj[n]);
+        if (rs) rs[j] = sg;
+        acc += sg.x * sg.x + sg.y * sg.y;
+    }
+    if (partial) {
+        const double tot = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partial, int nparts,
+                                                     double* __restrict__ out) {
+    __shared__ double red[kThreads / 64];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kThreads) acc += partial[k];
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) out[0] = tot;
+}
+
+// One workgroup per output element w: out[w] = sum_p partial[p * width + w].
+__global__ __launch_bounds__(kThreads) void k_reduce_c2(const double2* __restrict__ partial, int nparts,
+                                                        int width, double2* __restrict__ out) {
+    __shared__ double red[kThreads / 64];
+    const int w = blockIdx.x;
+    double ar = 0.0, ai = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kThreads) {
+        const double2 v = partial[(size_t)k * width + w];
+        ar += v.x;
+        ai += v.y;
+    }
+    const double tr = block_sum(ar, red);
+    const double ti = block_sum(ai, red);
+    if (threadIdx.x == 0) out[w] = make_double2(tr, ti);
+}
+
+// ---------------------------------------------------------------------------
+// K4: projection of a residual to the next level (average of the 2^d
+// children); also clears the coarse correction.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_restrict(LevelGeom f, LevelGeom cg,
+                                                       const double2* __restrict__ rcf,
+                                                       const double2* __restrict__ rsf,
+                                                       double2* __restrict__ bcc, double2* __restrict__ bsc,
+                                                       double2* __restrict__ zc, double2* __restrict__ zl) {
+    const int J = blockIdx.x * kThreads + threadIdx.x;
+    if (J >= cg.P) return;
+    int I[3];
+    point_coords(cg, J, I);
+    double2 acc[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = make_double2(0.0, 0.0);
+    double2 accs = make_double2(0.0, 0.0);
+    const int nch = 1 << f.dim;
+    for (int ch = 0; ch < nch; ++ch) {
+        int fi[3] = {0, 0, 0};
+        for (int a = 0; a < f.dim; ++a) fi[a] = 2 * I[a] + ((ch >> a) & 1);
+        const int fj = point_index(f, fi);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[n] = add2(acc[n], rcf[(size_t)fj * NT + n]);
+        accs = add2(accs, rsf[fj]);
+    }
+    const double sc = 1.0 / nch;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        bcc[(size_t)J * NT + n] = scl2(sc, acc[n]);
+        if (zc) zc[(size_t)J * NT + n] = make_double2(0.0, 0.0);
+    }
+    bsc[J] = scl2(sc, accs);
+    if (zl) zl[J] = make_double2(0.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// K5: interpolation of a coarse correction, added into the fine state.
+// interp 0: cell-centred tensor-linear (3/4 parent, 1/4 nearer neighbour per
+// axis; zero outside a Dirichlet grid); 1: piecewise constant.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg, int interp,
+                                                      const double2* __restrict__ cc,
+                                                      const double2* __restrict__ lc,
+                                                      double2* __restrict__ cf, double2* __restrict__ lf) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= f.P) return;
+    int i[3];
+    point_coords(f, j, i);
+    int par[3] = {0, 0, 0}, nb[3] = {0, 0, 0}, ok[3] = {1, 1, 1};
+    for (int a = 0; a < f.dim; ++a) {
+        par[a] = i[a] >> 1;
+        nb[a] = (i[a] & 1) ? par[a] + 1 : par[a] - 1;
+        if (nb[a] < 0 || nb[a] >= cg.n[a]) {
+            if (f.periodic)
+                nb[a] = (nb[a] + cg.n[a]) % cg.n[a];
+            else
+                ok[a] = 0;
+        }
+    }
+    double2 acc[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = make_double2(0.0, 0.0);
+    double2 accl = make_double2(0.0, 0.0);
+    const int ncomb = interp ? 1 : (1 << f.dim);
+    for (int cmb = 0; cmb < ncomb; ++cmb) {
+        double w = 1.0;
+        int J3[3] = {0, 0, 0};
+        bool valid = true;
+        for (int a = 0; a < f.dim; ++a) {
+            const int bit = (cmb >> a) & 1;
+            if (bit) {
+                valid = valid && ok[a];
+                J3[a] = nb[a];
+                w *= 0.25;
+            } else {
+                J3[a] = par[a];
+                w *= interp ? 1.0 : 0.75;
+            }
+        }
+        if (!valid) continue;
+        const int J = point_index(cg, J3);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[n] = add2(acc[n], scl2(w, cc[(size_t)J * NT + n]));
+        accl = add2(accl, scl2(w, lc[J]));
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) cf[(size_t)j * NT + n] = add2(cf[(size_t)j * NT + n], acc[n]);
+    lf[j] = add2(lf[j], accl);
+}
+
+__global__ __launch_bounds__(kThreads) void k_average_potential(LevelGeom f, LevelGeom cg,
+                                                                const double* __restrict__ vf,
+                                                                double* __restrict__ vc) {
+    const int J = blockIdx.x * kThreads + threadIdx.x;
+    if (J >= cg.P) return;
+    int I[3];
+    point_coords(cg, J, I);
+    const int nch = 1 << f.dim;
+    double acc = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+        int fi[3] = {0, 0, 0};
+        for (int a = 0; a < f.dim; ++a) fi[a] = 2 * I[a] + ((ch >> a) & 1);
+        acc += vf[point_index(f, fi)];
+    }
+    vc[J] = acc / nch;
+}
+
+// ---------------------------------------------------------------------------
+// K2a: spectral factor of every block's spatial operator A_U = T_U + diag(V0_U)
+// (T_U: the kinetic stencil restricted to the block, exterior fixed at zero).
+// Parallel cyclic Jacobi in LDS, one workgroup per block, round-robin pairing
+// so that nn/2 disjoint rotations run at once.  Output V[blk][point][mode],
+// e[blk][mode].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const double* __restrict__ v0,
+                                                        double* __restrict__ Vout, double* __restrict__ eout,
+                                                        float* __restrict__ Vfout) {
+    __shared__ double A[kMaxB * kLdsPad];
+    __shared__ double V[kMaxB * kLdsPad];
+    __shared__ double rot_c[kMaxB / 2], rot_s[kMaxB / 2];
+    __shared__ int rot_p[kMaxB / 2], rot_q[kMaxB / 2];
+    __shared__ double red[kThreads / 64];
+    __shared__ int stop;
+
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int b = g.bpts;
+    const int nn = b + (b & 1);
+    const int half = nn / 2;
+    int bc[3];
+    block_coords(g, blk, bc);
+
+    for (int t = tid; t < b * b; t += kThreads) {
+        const int j = t / b, k = t - j * b;
+        A[j * kLdsPad + k] = 0.0;
+        V[j * kLdsPad + k] = (j == k) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int l = tid; l < b; l += kThreads) {
+        int lc[3];
+        local_coords(g, l, lc);
+        int i[3] = {0, 0, 0};
+        for (int a = 0; a < g.dim; ++a) i[a] = bc[a] * g.bdim[a] + lc[a];
+        A[l * kLdsPad + l] += 2.0 * g.dim * g.kin + v0[point_index(g, i)];
+        for (int ax = 0; ax < g.dim; ++ax)
+            for (int d = -1; d <= 1; d += 2) {
+                int glob;
+                const int ln = block_neighbour(g, bc, lc, ax, d, &glob);
+                if (ln >= 0) A[l * kLdsPad + ln] += -g.kin;
+            }
+    }
+    __syncthreads();
+
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int t = tid; t < b * b; t += kThreads) {
+            const int j = t / b, k = t - j * b;
+            const double v = A[j * kLdsPad + k];
+            tot += v * v;
+            if (j != k) off += v * v;
+        }
+        off = block_sum(off, red);
+        tot = block_sum(tot, red);
+        if (tid == 0) stop = (off <= 1e-30 * tot) ? 1 : 0;
+        __syncthreads();
+        if (stop) break;
+        for (int r = 0; r < nn - 1; ++r) {
+            if (tid < half) {
+                int p, q;
+                if (tid == 0) {
+                    p = r;
+                    q = nn - 1;
+                } else {
+                    p = (r + tid) % (nn - 1);
+                    q = (r - tid + nn - 1) % (nn - 1);
+                }
+                if (p > q) {
+                    const int tmp = p;
+                    p = q;
+                    q = tmp;
+                }
+                double cth = 1.0, sth = 0.0;
+                if (q < b) {
+                    const double apq = A[p * kLdsPad + q];
+                    if (fabs(apq) > 1e-300) {
+                        const double tau = (A[q * kLdsPad + q] - A[p * kLdsPad + p]) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        cth = 1.0 / sqrt(1.0 + t * t);
+                        sth = t * cth;
+                    }
+                }
+                rot_p[tid] = p;
+                rot_q[tid] = q;
+                rot_c[tid] = cth;
+                rot_s[tid] = sth;
+            }
+            __syncthreads();
+            for (int t = tid; t < half * b; t += kThreads) {
+                const int pr = t / b, k = t - pr * b;
+                const int p = rot_p[pr], q = rot_q[pr];
+                if (q < b) {
+                    const double cth = rot_c[pr], sth = rot_s[pr];
+                    const double ap = A[p * kLdsPad + k], aq = A[q * kLdsPad + k];
+                    A[p * kLdsPad + k] = cth * ap - sth * aq;
+                    A[q * kLdsPad + k] = sth * ap + cth * aq;
+                }
+            }
+            __syncthreads();
+            for (int t = tid; t < half * b; t += kThreads) {
+                const int pr = t / b, k = t - pr * b;
+                const int p = rot_p[pr], q = rot_q[pr];
+                if (q < b) {
+                    const double cth = rot_c[pr], sth = rot_s[pr];
+                    const double ap = A[k * kLdsPad + p], aq = A[k * kLdsPad + q];
+                    A[k * kLdsPad + p] = cth * ap - sth * aq;
+                    A[k * kLdsPad + q] = sth * ap + cth * aq;
+                    const double vp = V[k * kLdsPad + p], vq = V[k * kLdsPad + q];
+                    V[k * kLdsPad + p] = cth * vp - sth * vq;
+                    V[k * kLdsPad + q] = sth * vp + cth * vq;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double* Vb = Vout + (size_t)blk * b * b;
+    for (int t = tid; t < b * b; t += kThreads) {
+        const int j = t / b, k = t - j * b;
+        const double v = V[j * kLdsPad + k];
+        Vb[t] = v;
+        if (Vfout) Vfout[(size_t)blk * b * b + t] = (float)v;
+    }
+    for (int k = tid; k < b; k += kThreads) eout[(size_t)blk * b + k] = A[k * kLdsPad + k];
+}
+
+// ---------------------------------------------------------------------------
+// K2b: per block and mode, invert the time system of eigenvalue e,
+//   M(e) = [[ iQ^T - e U, s ], [ s^T, 0 ]],  s_n = (-1)^n,
+// by in-place Gauss-Jordan with partial pivoting.  One thread per mode; the
+// matrix lives in LDS, interleaved across the 64 threads of the workgroup.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(64) void k_mode_factor(int b, TimeOps<NT> to, const double* __restrict__ e,
+                                                    const double* __restrict__ shift,
+                                                    double2* __restrict__ Minv, float2* __restrict__ Minvf) {
+    constexpr int NQ = NT + 1;
+    __shared__ double2 M[NQ * NQ * 64];
+    const int blk = blockIdx.x;
+    const int k = threadIdx.x;
+    if (k >= b) return;
+    const double ev = e[(size_t)blk * b + k] + (shift ? shift[blk] : 0.0);
+#define MAT(r, cc) M[((r) * NQ + (cc)) * 64 + k]
+    for (int m = 0; m < NQ; ++m)
+        for (int n = 0; n < NQ; ++n) {
+            double2 v = make_double2(0.0, 0.0);
+            if (m < NT && n < NT) {
+                if (n > m && ((n - m) & 1)) v.y = 2.0;  // i Q_nm
+                if (m == n) v.x = -ev * to.U[m];
+            } else if (m < NT && n == NT) {
+                v.x = (m & 1) ? -1.0 : 1.0;
+            } else if (m == NT && n < NT) {
+                v.x = (n & 1) ? -1.0 : 1.0;
+            }
+            MAT(m, n) = v;
+        }
+    int piv[NQ];
+    for (int col = 0; col < NQ; ++col) {
+        int p = col;
+        double best = -1.0;
+        for (int r = col; r < NQ; ++r) {
+            const double2 v = MAT(r, col);
+            const double a = v.x * v.x + v.y * v.y;
+            if (a > best) {
+                best = a;
+                p = r;
+            }
+        }
+        piv[col] = p;
+        if (p != col)
+            for (int n = 0; n < NQ; ++n) {
+                const double2 t = MAT(col, n);
+                MAT(col, n) = MAT(p, n);
+                MAT(p, n) = t;
+            }
+        const double2 d = MAT(col, col);
+        const double den = d.x * d.x + d.y * d.y;
+        const double2 inv = make_double2(d.x / den, -d.y / den);
+        MAT(col, col) = make_double2(1.0, 0.0);
+        for (int n = 0; n < NQ; ++n) {
+            const double2 v = MAT(col, n);
+            MAT(col, n) = make_double2(v.x * inv.x - v.y * inv.y, v.x * inv.y + v.y * inv.x);
+        }
+        for (int r = 0; r < NQ; ++r) {
+            if (r == col) continue;
+            const double2 f = MAT(r, col);
+            MAT(r, col) = make_double2(0.0, 0.0);
+            for (int n = 0; n < NQ; ++n) {
+                const double2 a = MAT(col, n);
+                const double2 v = MAT(r, n);
+                MAT(r, n) = make_double2(v.x - (f.x * a.x - f.y * a.y), v.y - (f.x * a.y + f.y * a.x));
+            }
+        }
+    }
+    for (int col = NQ - 1; col >= 0; --col) {
+        const int p = piv[col];
+        if (p != col)
+            for (int r = 0; r < NQ; ++r) {
+                const double2 t = MAT(r, col);
+                MAT(r, col) = MAT(r, p);
+                MAT(r, p) = t;
+            }
+    }
+    for (int p = 0; p < NQ; ++p)
+        for (int q = 0; q < NQ; ++q) {
+            const size_t o = (((size_t)blk * NQ + p) * NQ + q) * b + k;
+            const double2 v = MAT(p, q);
+            Minv[o] = v;
+            if (Minvf) Minvf[o] = make_float2((float)v.x, (float)v.y);
+        }
+#undef MAT
+}
+
+// ---------------------------------------------------------------------------
+// K3: relax every block of one colour.  One workgroup per block:
+//   1. stage the block's c, lambda, V0, eigenvectors in LDS;
+//   2. local residual r_U = (b - K x)_U, halo values read from HBM;
+//   3. delta = V (M(e_k)^{-1} (V^T r)) per mode k    [K_UU^{-1} r in factored form]
+//   4. (field steps) n_inner corrections r <- r - K_UU delta, repeat 3;
+//   5. write c_U += delta_c, lambda_U += delta_lambda.
+// BT is the precision of the factors and of step 3 (double, or float for the
+// mixed path); the state and the residual of step 2 are always FP64.
+// ---------------------------------------------------------------------------
+template <int NT, typename BT>
+__global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to) {
+    constexpr int NQ = NT + 1;
+    using C = cx<BT>;
+    __shared__ BT Vs[kMaxB * kLdsPad];
+    __shared__ double2 cs[kMaxB * NT];
+    __shared__ double2 ls[kMaxB];
+    __shared__ double v0s[kMaxB];
+    __shared__ double zs[kMaxB];
+    __shared__ int gidx[kMaxB];
+    __shared__ C rs[kMaxB * NQ];
+    __shared__ C rh[kMaxB * NQ];
+    __shared__ C di[kMaxB * NQ];
+
+    const LevelGeom& g = a.g;
+    const int tid = threadIdx.x;
+    const int blk = a.blocks[blockIdx.x];
+    const int b = g.bpts;
+    int bc[3];
+    block_coords(g, blk, bc);
+
+    for (int l = tid; l < b; l += kThreads) {
+        int lc[3];
+        local_coords(g, l, lc);
+        int i[3] = {0, 0, 0};
+        for (int ax = 0; ax < g.dim; ++ax) i[ax] = bc[ax] * g.bdim[ax] + lc[ax];
+        const int gj = point_index(g, i);
+        gidx[l] = gj;
+        v0s[l] = a.v0[gj];
+        ls[l] = a.lam[gj];
+        zs[l] = zcoord(g, i);
+    }
+    const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
+    for (int t = tid; t < b * b; t += kThreads) {
+        const int j = t / b, k = t - j * b;
+        Vs[j * kLdsPad + k] = Vg[t];
+    }
+    __syncthreads();
+    for (int t = tid; t < b * NT; t += kThreads) {
+        const int l = t / NT, n = t - l * NT;
+        cs[t] = a.c[(size_t)gidx[l] * NT + n];
+    }
+    __syncthreads();
+
+    // ---- 2. local residual (FP64) ----
+    for (int t = tid; t < b * NT; t += kThreads) {
+        const int l = t / NT, m = t - l * NT;
+        int lc[3];
+        local_coords(g, l, lc);
+        double2 lap = scl2(-2.0 * g.dim, cs[t]);
+        for (int ax = 0; ax < g.dim; ++ax)
+            for (int d = -1; d <= 1; d += 2) {
+                int glob;
+                const int ln = block_neighbour(g, bc, lc, ax, d, &glob);
+                if (ln >= 0)
+                    lap = add2(lap, cs[ln * NT + m]);
+                else if (glob >= 0)
+                    lap = add2(lap, a.c[(size_t)glob * NT + m]);
+            }
+        const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], cs[t]));
+        double2 tq = make_double2(0.0, 0.0);
+        if (!a.adjoint) {
+            for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cs[l * NT + n]);
+        } else {
+            for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cs[l * NT + n]);
+        }
+        const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
+        double2 wc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cs[l * NT + n]));
+        const double sm = (m & 1) ? -1.0 : 1.0;
+        double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(zs[l], wc));
+        row = add2(row, scl2(sm, ls[l]));
+        const double2 rhs =
+            a.bc ? a.bc[(size_t)gidx[l] * NT + m] : (a.bg ? a.bg[gidx[l]] : make_double2(0.0, 0.0));
+        const double2 rho = sub2(rhs, row);
+        rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
+    }
+    for (int l = tid; l < b; l += kThreads) {
+        double2 sg = a.bs ? a.bs[gidx[l]] : make_double2(0.0, 0.0);
+        for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cs[l * NT + n]) : sub2(sg, cs[l * NT + n]);
+        rs[l * NQ + NT] = C{(BT)sg.x, (BT)sg.y};
+    }
+    __syncthreads();
+
+    const C* Mi = static_cast<const C*>(a.Minv);
+    for (int pass = 0; pass <= a.n_inner; ++pass) {
+        // ---- 3a. rh[k][q] = sum_j V[j][k] rs[j][q] ----
+        {
+            const int k = tid & 63, qg = tid >> 6;
+            if (k < b) {
+                C acc[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) acc[r] = C{0, 0};
+                for (int j = 0; j < b; ++j) {
+                    const BT v = Vs[j * kLdsPad + k];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const int q = qg + 4 * r;
+                        if (q < NQ) acc[r] = acc[r] + rmul(v, rs[j * NQ + q]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int q = qg + 4 * r;
+                    if (q < NQ) rh[k * NQ + q] = acc[r];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 3b. per-mode time solve ----
+        {
+            const int k = tid & 63, pg = tid >> 6;
+            C out[3];
+            if (k < b) {
+                C rv[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) rv[q] = rh[k * NQ + q];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int p = pg + 4 * r;
+                    C acc = C{0, 0};
+                    if (p < NQ) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) {
+                            if (!a.adjoint) {
+                                const C mv = Mi[(((size_t)blk * NQ + p) * NQ + q) * b + k];
+                                acc = acc + cmul(mv, rv[q]);
+                            } else {
+                                const C mv = Mi[(((size_t)blk * NQ + q) * NQ + p) * b + k];
+                                acc = acc + cmulc(mv, rv[q]);
+                            }
+                        }
+                    }
+                    out[r] = acc;
+                }
+            }
+            __syncthreads();
+            if (k < b) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int p = pg + 4 * r;
+                    if (p < NQ) rh[k * NQ + p] = out[r];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 3c. di[j][q] = sum_k V[j][k] rh[k][q] ----
+        {
+            const int j = tid & 63, qg = tid >> 6;
+            if (j < b) {
+                C acc[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) acc[r] = C{0, 0};
+                for (int k = 0; k < b; ++k) {
+                    const BT v = Vs[j * kLdsPad + k];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const int q = qg + 4 * r;
+                        if (q < NQ) acc[r] = acc[r] + rmul(v, rh[k * NQ + q]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int q = qg + 4 * r;
+                    if (q < NQ) di[j * NQ + q] = acc[r];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- accumulate, and for inner passes update the local residual ----
+        for (int t = tid; t < b * NQ; t += kThreads) {
+            const int l = t / NQ, q = t - l * NQ;
+            const C dv = di[t];
+            if (q < NT)
+                cs[l * NT + q] = add2(cs[l * NT + q], make_double2((double)dv.r, (double)dv.i));
+            else
+                ls[l] = add2(ls[l], make_double2((double)dv.r, (double)dv.i));
+            if (pass < a.n_inner) {
+                C y;
+                if (q < NT) {
+                    const int m = q;
+                    int lc[3];
+                    local_coords(g, l, lc);
+                    C lap = rmul((BT)(-2.0 * g.dim), dv);
+                    for (int ax = 0; ax < g.dim; ++ax)
+                        for (int d = -1; d <= 1; d += 2) {
+                            int glob;
+                            const int ln = block_neighbour(g, bc, lc, ax, d, &glob);
+                            if (ln >= 0) lap = lap + di[ln * NQ + m];
+                        }
+                    const C hd = rmul((BT)(-g.kin), lap) + rmul((BT)v0s[l], dv);
+                    C tq = C{0, 0};
+                    if (!a.adjoint) {
+                        for (int n = m + 1; n < NT; n += 2) tq = tq + di[l * NQ + n];
+                    } else {
+                        for (int n = m - 1; n >= 0; n -= 2) tq = tq + di[l * NQ + n];
+                    }
+                    const C tim = a.adjoint ? C{(BT)2 * tq.i, (BT)(-2) * tq.r} : C{(BT)(-2) * tq.i, (BT)2 * tq.r};
+                    C wd = C{0, 0};
+                    for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)to.W[m * NT + n], di[l * NQ + n]);
+                    const BT sm = (m & 1) ? (BT)-1 : (BT)1;
+                    y = tim - rmul((BT)to.U[m], hd) - rmul((BT)zs[l], wd) + rmul(sm, di[l * NQ + NT]);
+                } else {
+                    y = C{0, 0};
+                    for (int n = 0; n < NT; ++n) y = (n & 1) ? y - di[l * NQ + n] : y + di[l * NQ + n];
+                }
+                rs[t] = rs[t] - y;
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int t = tid; t < b * NT; t += kThreads) {
+        const int l = t / NT, n = t - l * NT;
+        a.c[(size_t)gidx[l] * NT + n] = cs[t];
+    }
+    for (int l = tid; l < b; l += kThreads) a.lam[gidx[l]] = ls[l];
+}
+
+// ---------------------------------------------------------------------------
+// K11: step I/O and the adjoint right-hand side.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_init_forward(int P, const double2* __restrict__ psi,
+                                                           double2* __restrict__ c, double2* __restrict__ lam,
+                                                           double2* __restrict__ bs) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= P) return;
+    const double2 p = psi[j];
+    c[(size_t)j * NT] = p;  // s_0 = T_0(t0) = 1
+#pragma unroll
+    for (int n = 1; n < NT; ++n) c[(size_t)j * NT + n] = make_double2(0.0, 0.0);
+    lam[j] = make_double2(0.0, 0.0);
+    bs[j] = p;
+}
+
+// Zero state (the adjoint solve starts from mu = 0).
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_init_zero(int P, double2* __restrict__ c,
+                                                        double2* __restrict__ lam) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= P) return;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) c[(size_t)j * NT + n] = make_double2(0.0, 0.0);
+    lam[j] = make_double2(0.0, 0.0);
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_end_eval(int P, const double2* __restrict__ c,
+                                                       double2* __restrict__ psi) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= P) return;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc = add2(acc, c[(size_t)j * NT + n]);
+    psi[j] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy_c2(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                      size_t n) {
+    const size_t k = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k < n) dst[k] = src[k];
+}
+
+// ---------------------------------------------------------------------------
+// K10: gradients from the forward solution c and the adjoint solution mu.
+//   dv0[j] += 2 Re sum_m conj(mu_jm) U_mm c_jm
+//   Gpart[wg][m][n] = sum_{j in wg} z_j conj(mu_jm) c_jn
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_gradients(LevelGeom g, TimeOps<NT> to,
+                                                        const double2* __restrict__ cf,
+                                                        const double2* __restrict__ mu,
+                                                        double* __restrict__ dv0, double2* __restrict__ Gpart) {
+    __shared__ double red[kThreads / 64];
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    const bool on = j < g.P;
+    double2 cj[NT], mj[NT];
+    double z = 0.0;
+    if (on) {
+        int i[3];
+        point_coords(g, j, i);
+        z = zcoord(g, i);
+        double acc = 0.0;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            cj[n] = cf[(size_t)j * NT + n];
+            mj[n] = mu[(size_t)j * NT + n];
+            acc += to.U[n] * (mj[n].x * cj[n].x + mj[n].y * cj[n].y);
+        }
+        dv0[j] += 2.0 * acc;
+    } else {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            cj[n] = make_double2(0.0, 0.0);
+            mj[n] = make_double2(0.0, 0.0);
+        }
+    }
+    if (!Gpart) return;
+    for (int m = 0; m < NT; ++m)
+        for (int n = 0; n < NT; ++n) {
+            // z conj(mu_m) c_n
+            const double gr = z * (mj[m].x * cj[n].x + mj[m].y * cj[n].y);
+            const double gim = z * (mj[m].x * cj[n].y - mj[m].y * cj[n].x);
+            const double tr = block_sum(gr, red);
+            const double ti = block_sum(gim, red);
+            if (threadIdx.x == 0) Gpart[(size_t)blockIdx.x * NT * NT + m * NT + n] = make_double2(tr, ti);
+        }
+}
+
+template <int NT>
+TimeOps<NT> make_ops(const double* U, const double* W) {
+    TimeOps<NT> t;
+    for (int m = 0; m < NT; ++m) t.U[m] = U[m];
+    for (int k = 0; k < NT * NT; ++k) t.W[k] = W ? W[k] : 0.0;
+    return t;
+}
+
+inline int nblk_for(size_t n) { return (int)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+#define LAM_DISPATCH_NT(nt, CALL)    \
+    switch (nt) {                     \
+        case 1: { constexpr int NT = 1; CALL; } break; \
+        case 2: { constexpr int NT = 2; CALL; } break; \
+        case 3: { constexpr int NT = 3; CALL; } break; \
+        case 4: { constexpr int NT = 4; CALL; } break; \
+        case 5: { constexpr int NT = 5; CALL; } break; \
+        case 6: { constexpr int NT = 6; CALL; } break; \
+        case 7: { constexpr int NT = 7; CALL; } break; \
+        case 8: { constexpr int NT = 8; CALL; } break; \
+        default: return hipErrorInvalidValue;           \
+    }
+
+hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const double* W, int adjoint,
+                           const double2* c, const double2* lam, const double* v0, const double2* bc,
+                           const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
+                           int* nparts, hipStream_t st) {
+    const int nb = nblk_for(g.P);
+    if (nparts) *nparts = nb;
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_residual<NT>, dim3(nb), dim3(kThreads), 0, st, g,
+                                           make_ops<NT>(U, W), adjoint, c, lam, v0, bc, bg, bs, rc, rs,
+                                           partial));
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, int nparts, int, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, st, partial, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_c2(const double2* partial, int nparts, int width, double2* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_c2, dim3(width), dim3(kThreads), 0, st, partial, nparts, width, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(int nt, const LevelGeom& fine, const LevelGeom& coarse, const double2* rcf,
+                           const double2* rsf, double2* bcc, double2* bsc, double2* zero_c, double2* zero_l,
+                           hipStream_t st) {
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_restrict<NT>, dim3(nblk_for(coarse.P)), dim3(kThreads), 0, st,
+                                           fine, coarse, rcf, rsf, bcc, bsc, zero_c, zero_l));
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(int nt, const LevelGeom& fine, const LevelGeom& coarse, int interp, const double2* cc,
+                          const double2* lc, double2* cf, double2* lf, hipStream_t st) {
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_prolong<NT>, dim3(nblk_for(fine.P)), dim3(kThreads), 0, st, fine,
+                                           coarse, interp, cc, lc, cf, lf));
+    return hipGetLastError();
+}
+
+hipError_t launch_average_potential(const LevelGeom& fine, const LevelGeom& coarse, const double* vf, double* vc,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(k_average_potential, dim3(nblk_for(coarse.P)), dim3(kThreads), 0, st, fine, coarse, vf, vc);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_eig(const LevelGeom& g, const double* v0, double* V, double* e, float* Vf,
+                            hipStream_t st) {
+    const int nblocks = g.nblk[0] * g.nblk[1] * g.nblk[2];
+    hipLaunchKernelGGL(k_block_eig, dim3(nblocks), dim3(kThreads), 0, st, g, v0, V, e, Vf);
+    return hipGetLastError();
+}
+
+hipError_t launch_mode_factor(int nt, int nblocks, int bpts, const double* U, const double* e, const double* shift,
+                              double2* Minv, float2* Minvf, hipStream_t st) {
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_mode_factor<NT>, dim3(nblocks), dim3(64), 0, st, bpts,
+                                           make_ops<NT>(U, nullptr), e, shift, Minv, Minvf));
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(int nt, int mixed, const SweepArgs& a, const double* U, const double* W,
+                        int nblocks_colour, hipStream_t st) {
+    if (nblocks_colour <= 0) return hipSuccess;
+    if (mixed) {
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, float>), dim3(nblocks_colour), dim3(kThreads), 0,
+                                               st, a, make_ops<NT>(U, W)));
+    } else {
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, double>), dim3(nblocks_colour), dim3(kThreads), 0,
+                                               st, a, make_ops<NT>(U, W)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_forward(int nt, int P, const double2* psi, double2* c, double2* lam, double2* bs,
+                               hipStream_t st) {
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_init_forward<NT>, dim3(nblk_for(P)), dim3(kThreads), 0, st, P, psi,
+                                           c, lam, bs));
+    return hipGetLastError();
+}
+
+hipError_t launch_init_zero(int nt, int P, double2* c, double2* lam, hipStream_t st) {
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_init_zero<NT>, dim3(nblk_for(P)), dim3(kThreads), 0, st, P, c, lam));
+    return hipGetLastError();
+}
+
+hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStream_t st) {
+    LAM_DISPATCH_NT(nt,
+                    hipLaunchKernelGGL(k_end_eval<NT>, dim3(nblk_for(P)), dim3(kThreads), 0, st, P, c, psi));
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_c2(const double2* src, double2* dst, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_c2, dim3(nblk_for(n)), dim3(kThreads), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradients(int nt, const LevelGeom& g, const double* U, const double2* cfwd, const double2* mu,
+                            double* dv0, double2* Gpart, int* nparts, hipStream_t st) {
+    const int nb = nblk_for(g.P);
+    if (nparts) *nparts = nb;
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_gradients<NT>, dim3(nb), dim3(kThreads), 0, st, g,
+                                           make_ops<NT>(U, nullptr), cfwd, mu, dv0, Gpart));
+    return hipGetLastError();
+}
+
+}  // namespace lam

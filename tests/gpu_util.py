@@ -1,0 +1,104 @@
+"""Helpers shared by the GPU parity tests (not a test module).
+
+Inputs come from ``workloads`` / numpy seeds; expected values come from the
+oracle only.  Tolerances are derived from the arithmetic and stated where used.
+"""
+import sys
+
+import numpy as np
+
+from oracle import grid as G
+from oracle import timebasis as tb
+
+EPS = np.finfo(np.float64).eps
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def t_c(a):
+    torch = torch_mod()
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.complex128).ravel()), device="cuda")
+
+
+def t_r(a):
+    torch = torch_mod()
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel()), device="cuda")
+
+
+def n(t):
+    return t.detach().cpu().numpy()
+
+
+def field_fn(pulse):
+    if not pulse or pulse.get("kind", "none") == "none":
+        return None
+    kind = pulse["kind"]
+    T = pulse["t_total"]
+    parts = []
+    if kind in ("sin2", "sin2+fourier"):
+        parts.append(tb.pulse_sin2_cos(pulse["e0"], pulse["omega"], T))
+    if kind in ("fourier", "sin2+fourier"):
+        parts.append(tb.pulse_fourier_sine(pulse["coef"], T))
+    if len(parts) == 1:
+        return parts[0]
+    return lambda t: parts[0](t) + parts[1](t)
+
+
+class Case:
+    def __init__(self, shape, h=0.25, n_t=4, dt=0.05, block=None, levels=1, periodic=False, pulse=None,
+                 seed=0, potential="softcoulomb", mass=1.0, field_axis=-1, interp="linear"):
+        self.shape = tuple(shape)
+        self.dim = len(self.shape)
+        self.h, self.n_t, self.dt = h, n_t, dt
+        self.block = tuple(block) if block else (4,) * self.dim
+        self.levels, self.periodic, self.pulse = levels, periodic, pulse
+        self.mass, self.field_axis, self.interp = mass, field_axis, interp
+        self.grid = G.Grid(self.shape, h, periodic, mass, field_axis)
+        rng = np.random.default_rng(seed)
+        X = self.grid.coords()
+        r2 = sum(x * x for x in X).ravel()
+        if potential == "softcoulomb":
+            self.v0 = -1.0 / np.sqrt(r2 + 1.0)
+        elif potential == "harmonic":
+            self.v0 = 0.5 * r2
+        elif potential == "random":
+            self.v0 = rng.normal(size=self.grid.npts)
+        else:
+            self.v0 = np.zeros(self.grid.npts)
+        self.psi0 = np.exp(-r2 / 4.0) * np.exp(1j * rng.uniform(0, 2 * np.pi, self.grid.npts))
+        self.rng = rng
+        self.field = field_fn(pulse)
+
+    @property
+    def npts(self):
+        return self.grid.npts
+
+    def random_state(self, scale=1.0):
+        P, nt = self.npts, self.n_t
+        c = scale * (self.rng.normal(size=(P, nt)) + 1j * self.rng.normal(size=(P, nt)))
+        lam = scale * (self.rng.normal(size=P) + 1j * self.rng.normal(size=P))
+        return c, lam
+
+    def prop(self, **kw):
+        from paper_1111_4363_amd import lam
+        args = dict(levels=self.levels, periodic=self.periodic, mass=self.mass, field_axis=self.field_axis,
+                    pulse=self.pulse, interp=self.interp)
+        args.update(kw)
+        return lam.Propagator(self.shape, self.h, t_r(self.v0), self.n_t, self.dt, self.block, **args)
+
+    def __repr__(self):
+        return f"Case(shape={self.shape}, n_t={self.n_t}, block={self.block}, levels={self.levels}, " \
+               f"periodic={self.periodic}, pulse={None if not self.pulse else self.pulse['kind']})"
+
+
+def rounding_bound(K, x, b, factor=64):
+    """Elementwise bound on the rounding error of b - K x: factor * eps * (|K||x| + |b|)."""
+    return factor * EPS * (abs(K) @ np.abs(x) + np.abs(b))

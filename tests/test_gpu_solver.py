@@ -1,0 +1,178 @@
+"""GPU V-cycles, step solves and adjoint steps against the oracle.
+
+V-cycle: one cycle from a random state against the oracle's reference
+V-cycle with the same sweep counts, transfers and coarse operators; agreement
+to 1e-10 of the state (dozens of local solves, each good to ~1e-13).
+Step solve: coefficients against the oracle's direct solve, relative error
+<= 1e-10 (FP64 path) and <= 1e-8 (mixed path), the target accuracies.
+Adjoint step: the adjoint solution and the gradients against the oracle's
+direct K^H solve.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import Case, n, note, t_c, t_r
+from oracle import adjoint as A
+from oracle import kkt, relax
+
+pytestmark = pytest.mark.gpu
+
+PULSE_SIN2 = dict(kind="sin2", e0=0.05, omega=0.057, t_total=1.0)
+PULSE_FOURIER = dict(kind="fourier", t_total=0.4, coef=[0.03, -0.02, 0.05])
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(shape=(32, 32), n_t=4, block=(4, 4), levels=3, h=0.2),
+    dict(shape=(32, 16), n_t=6, block=(4, 4), levels=2, h=0.2, pulse=PULSE_SIN2, interp="constant"),
+    dict(shape=(64,), n_t=8, block=(8,), levels=3, h=0.3, potential="harmonic"),
+    dict(shape=(8, 8, 16), n_t=3, block=(2, 2, 2), levels=2, h=0.3),
+], ids=lambda c: f"{c['shape']}-L{c['levels']}")
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_vcycle_parity(cfg, adjoint):
+    case = Case(**cfg)
+    note(f"vcycle adjoint={adjoint} {case}")
+    t0 = 0.1
+    H = relax.build_hierarchy(case.grid, case.v0, case.n_t, case.dt, case.block, case.levels, t0=t0,
+                              field=case.field, interp=case.interp)
+    sysm = H[0].system
+    c, lam = case.random_state(0.1)
+    x = kkt.join(c, lam)
+    prop = case.prop(nu_pre=1, nu_post=1, nu_coarse=2, n_inner=(8 if case.field else -1))
+    if adjoint:
+        b = A.adjoint_rhs(sysm, case.psi0)
+        prop.set_adjoint_state(t0, t_c(case.psi0), t_c(c), t_c(lam))
+    else:
+        b = kkt.rhs(sysm, case.psi0)
+        prop.set_state(t0, t_c(case.psi0), t_c(c), t_c(lam))
+    x_ref = relax.reference_vcycle(H, 0, x, b, 1, 1, 2, adjoint=adjoint)
+    N = prop.vcycle()
+    cg, lg = prop.get_state()
+    x_gpu = np.concatenate([n(cg), n(lg)])
+    err = np.abs(x_gpu - x_ref).max()
+    assert err <= 1e-10 * np.abs(x_ref).max(), err
+    K = sysm.K.conj().T if adjoint else sysm.K
+    N_ref = kkt.residual_norm(sysm, b - K @ x_ref)
+    assert abs(N - N_ref) <= 1e-6 * N_ref + 1e-26
+    prop.close()
+
+
+SOLVE_CASES = [
+    # the 1D workload at its full size
+    dict(shape=(256,), h=40 / 256, n_t=8, block=(8,), levels=1, potential="harmonic", nu_coarse=2),
+    dict(shape=(256,), h=40 / 256, n_t=8, block=(8,), levels=5, potential="harmonic", nu_coarse=2),
+    # the 2D soft-Coulomb workload reduced to 64^2 (same h, dt, n_t, blocks)
+    dict(shape=(64, 64), h=0.2, n_t=8, block=(8, 8), levels=3, nu_coarse=2),
+    # the 3D laser workload reduced to 16^3
+    dict(shape=(16, 16, 16), h=0.3, n_t=6, block=(4, 4, 4), levels=2, pulse=PULSE_SIN2, nu_coarse=2),
+    # the 2D adjoint workload reduced to 32^2 with its Fourier pulse
+    dict(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=PULSE_FOURIER, nu_coarse=2),
+]
+
+
+@pytest.mark.parametrize("cfg", SOLVE_CASES, ids=lambda c: f"{c['shape']}-L{c['levels']}")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_step_parity(cfg, precision):
+    cfg = dict(cfg)
+    nu_coarse = cfg.pop("nu_coarse")
+    case = Case(**cfg)
+    note(f"solve {precision} {case}")
+    t0 = 0.15
+    sysm = kkt.StepSystem(case.grid, case.v0, case.n_t, case.dt, t0, case.field)
+    b = kkt.rhs(sysm, case.psi0)
+    x_ref = kkt.solve_direct(sysm.K, b)
+    prop = case.prop(precision=precision, tol=1e-10, max_cycles=40, nu_coarse=nu_coarse)
+    psi_out, st = prop.solve_step(t0, t_c(case.psi0))
+    cg, lg = prop.get_state()
+    c_ref, _ = kkt.split(x_ref, case.npts, case.n_t)
+    rel = np.abs(n(cg).reshape(-1, case.n_t) - c_ref).max() / np.abs(c_ref).max()
+    target = 1e-10 if precision == "fp64" else 1e-8
+    note(f"cycles={st['cycles']} resid ratio={st['resid'] / st['resid0']:.2e} coef rel err={rel:.2e}")
+    assert rel <= target
+    psi_ref = kkt.end_state(sysm, x_ref)
+    assert np.abs(n(psi_out) - psi_ref).max() <= target * np.abs(psi_ref).max()
+    prop.close()
+
+
+def test_multi_step_propagation_matches_direct_steps():
+    case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=PULSE_FOURIER)
+    note(f"propagate 8 steps {case}")
+    psis = kkt.propagate(case.grid, case.v0, case.psi0, case.n_t, case.dt, 8, case.field)
+    prop = case.prop(tol=1e-12, max_cycles=60)
+    psi, _ = prop.propagate(t_c(case.psi0), 8)
+    assert np.abs(n(psi) - psis[-1]).max() <= 1e-10 * np.abs(psis[-1]).max()
+    prop.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adjoint_step_parity(precision):
+    case = Case(shape=(16, 16), h=0.25, n_t=6, block=(4, 4), levels=2, pulse=PULSE_FOURIER)
+    note(f"adjoint step {precision} {case}")
+    t0 = 0.1
+    sysm = kkt.StepSystem(case.grid, case.v0, case.n_t, case.dt, t0, case.field)
+    x = kkt.solve_direct(sysm.K, kkt.rhs(sysm, case.psi0))
+    g_out = case.rng.normal(size=case.npts) + 1j * case.rng.normal(size=case.npts)
+    mu = A.adjoint_solve(sysm, A.adjoint_rhs(sysm, g_out))
+    from oracle import timebasis as tb
+    basis = [tb.fourier_basis_function(q, PULSE_FOURIER["t_total"]) for q in (1, 2, 3)]
+    g_in_ref, dv0_ref, da_ref = A.step_gradients(sysm, x, mu, basis)
+    prop = case.prop(precision=precision, tol=1e-12, max_cycles=60)
+    import torch
+    dv0 = torch.zeros(case.npts, dtype=torch.float64, device="cuda")
+    dcoef = [0.0, 0.0, 0.0]
+    g_in, st = prop.adjoint_step(t0, t_c(case.psi0), t_c(g_out), dv0, dcoef)
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    assert np.abs(n(g_in) - g_in_ref).max() <= tol * np.abs(g_in_ref).max()
+    assert np.abs(n(dv0) - dv0_ref).max() <= tol * np.abs(dv0_ref).max()
+    assert np.abs(np.array(dcoef) - da_ref).max() <= tol * np.abs(da_ref).max()
+    prop.close()
+
+
+def test_autograd_gradients_match_finite_differences():
+    """Loss = population of the grid ground state after K steps; gradients with
+    respect to the pulse amplitudes and sampled V0 points against central
+    differences of the GPU forward (eps = 1e-5), absolute 1e-6."""
+    import torch
+    from paper_1111_4363_amd import lam
+    import workloads as W
+    case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=None)
+    gs = W.ground_state(case.shape, case.h, case.v0)
+    n_steps, T = 6, 6 * case.dt
+    coef = np.array([0.3, -0.2, 0.25, 0.1])
+    pulse = dict(kind="fourier", t_total=T, coef=list(coef))
+    note(f"autograd vs FD {case}")
+    prop = case.prop(pulse=pulse, tol=1e-13, max_cycles=80)
+    g_t = t_c(gs)
+    w = case.h ** 2
+
+    def loss_of(psi):
+        ov = w * torch.sum(torch.conj(g_t) * psi)
+        return (ov * torch.conj(ov)).real
+
+    psi0 = t_c(gs).requires_grad_(False)
+    v0 = t_r(case.v0).requires_grad_(True)
+    cf = torch.tensor(coef, dtype=torch.float64, requires_grad=True)
+    psiK = lam.propagate_differentiable(prop, psi0, v0, cf, n_steps)
+    L = loss_of(psiK)
+    L.backward()
+
+    def fwd(vv, cc):
+        prop.set_potential(t_r(vv))
+        prop.set_pulse(list(cc))
+        psi, _ = prop.propagate(t_c(gs), n_steps)
+        return float(loss_of(psi))
+
+    eps = 1e-5
+    for q in range(len(coef)):
+        cp, cm = coef.copy(), coef.copy()
+        cp[q] += eps
+        cm[q] -= eps
+        fd = (fwd(case.v0, cp) - fwd(case.v0, cm)) / (2 * eps)
+        assert abs(fd - cf.grad[q].item()) < 1e-6, (q, fd, cf.grad[q].item())
+    gv = n(v0.grad)
+    for i in [0, 300, 528, 1000]:
+        vp, vm = case.v0.copy(), case.v0.copy()
+        vp[i] += eps
+        vm[i] -= eps
+        fd = (fwd(vp, coef) - fwd(vm, coef)) / (2 * eps)
+        assert abs(fd - gv[i]) < 1e-6, (i, fd, gv[i])
+    prop.close()
