@@ -68,6 +68,9 @@ extern "C" {
 #define LAM_PULSE_FOURIER       2  /* E = sum_q coef[q-1] sin(q pi t/T) on [0,T] */
 #define LAM_PULSE_SIN2_FOURIER  3  /* sum of the two */
 
+#define LAM_TF_SHARED 0
+#define LAM_TF_STORED 1
+
 #define LAM_FP64   0   /* every kernel in FP64 */
 #define LAM_MIXED  1   /* subvolume solves in FP32, residuals/transfers/state in FP64 */
 
@@ -110,8 +113,15 @@ typedef struct {
     int precision;    /* LAM_FP64 or LAM_MIXED */
     double tol;       /* stop when sqrt(N / N0) <= tol (N: residual norm, N0: at the start) */
     int max_cycles;   /* V-cycle limit per solve */
-    int n_inner;      /* inner corrections of each subvolume solve when E(t) != 0;
-                         -1 = automatic (3 when the step has a field, else 0) */
+    int n_inner;      /* most inner corrections of each subvolume solve when E(t) != 0
+                         (the factor freezes the field at its step mean and block centre;
+                         each block stops once its own residual fell by 1e-13 in FP64,
+                         1e-6 in FP32); -1 = automatic (16 with a field, 0 without) */
+    int time_factor;  /* how each mode's (n_t+1) time system is solved inside a sweep:
+                         LAM_TF_SHARED (0): one shared Schur factor per context, per-mode
+                         triangular solve (streams one eigenvalue per mode);
+                         LAM_TF_STORED (1): stored per-mode inverses ((n_t+1)^2 complex per
+                         mode, refactored when the step's mean field changes) */
 } lam_solver;
 
 typedef struct {

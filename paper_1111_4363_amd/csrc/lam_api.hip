@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -84,6 +85,160 @@ void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Shared factor of the per-mode time systems.  M(e) = M0 - e D with
+// M0 = [[iQ^T, s], [s^T, 0]] and D = diag(U, 0), so M(e) = M0 (I - e G),
+// G = M0^{-1} D.  With the complex Schur form G = Z T Z^H (Z unitary, T upper
+// triangular): M(e)^{-1} = Z (I - e T)^{-1} B, B = Z^H M0^{-1}.  G has a 2x2
+// Jordan block at 0, so an eigenvector basis would be singular; the Schur
+// form stays unitary.  n <= 9: plain shifted QR on the full matrix.
+// ---------------------------------------------------------------------------
+using cd = std::complex<double>;
+
+// In-place inverse of an n x n row-major complex matrix (Gauss-Jordan, partial pivoting).
+bool invert_small(int n, cd* A) {
+    std::vector<int> piv(n);
+    for (int col = 0; col < n; ++col) {
+        int p = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::abs(A[r * n + col]) > std::abs(A[p * n + col])) p = r;
+        piv[col] = p;
+        if (std::abs(A[p * n + col]) == 0.0) return false;
+        if (p != col)
+            for (int k = 0; k < n; ++k) std::swap(A[col * n + k], A[p * n + k]);
+        const cd inv = 1.0 / A[col * n + col];
+        A[col * n + col] = 1.0;
+        for (int k = 0; k < n; ++k) A[col * n + k] *= inv;
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const cd f = A[r * n + col];
+            A[r * n + col] = 0.0;
+            for (int k = 0; k < n; ++k) A[r * n + k] -= f * A[col * n + k];
+        }
+    }
+    for (int col = n - 1; col >= 0; --col)
+        if (piv[col] != col)
+            for (int r = 0; r < n; ++r) std::swap(A[r * n + col], A[r * n + piv[col]]);
+    return true;
+}
+
+// Householder QR of the leading m x m block of A (stride n): A = Q R.
+void householder_qr(int m, int n, const cd* A, cd* Q, cd* R) {
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            R[i * m + j] = A[i * n + j];
+            Q[i * m + j] = (i == j) ? 1.0 : 0.0;
+        }
+    std::vector<cd> v(m);
+    for (int k = 0; k + 1 < m; ++k) {
+        double nx = 0.0;
+        for (int i = k; i < m; ++i) nx += std::norm(R[i * m + k]);
+        nx = std::sqrt(nx);
+        if (nx == 0.0) continue;
+        const cd x0 = R[k * m + k];
+        const cd alpha = (std::abs(x0) > 0.0) ? -(x0 / std::abs(x0)) * nx : cd(-nx);
+        double nv = 0.0;
+        for (int i = k; i < m; ++i) {
+            v[i] = R[i * m + k] - (i == k ? alpha : cd(0.0));
+            nv += std::norm(v[i]);
+        }
+        nv = std::sqrt(nv);
+        if (nv == 0.0) continue;
+        for (int i = k; i < m; ++i) v[i] /= nv;
+        for (int j = 0; j < m; ++j) {  // R <- (I - 2 v v^H) R
+            cd dot = 0.0;
+            for (int i = k; i < m; ++i) dot += std::conj(v[i]) * R[i * m + j];
+            for (int i = k; i < m; ++i) R[i * m + j] -= 2.0 * v[i] * dot;
+        }
+        for (int i = 0; i < m; ++i) {  // Q <- Q (I - 2 v v^H)
+            cd dot = 0.0;
+            for (int j = k; j < m; ++j) dot += Q[i * m + j] * v[j];
+            for (int j = k; j < m; ++j) Q[i * m + j] -= 2.0 * dot * std::conj(v[j]);
+        }
+    }
+}
+
+// Complex Schur form of the n x n matrix A (row-major, overwritten by T); Z unitary.
+bool schur_small(int n, cd* A, cd* Z) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Z[i * n + j] = (i == j) ? 1.0 : 0.0;
+    double nrm = 0.0;
+    for (int k = 0; k < n * n; ++k) nrm += std::norm(A[k]);
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) return true;
+    std::vector<cd> Q(n * n), R(n * n), tmp(n * n);
+    for (int m = n; m > 1; --m) {
+        bool done = false;
+        for (int it = 0; it < 300 && !done; ++it) {
+            double off = 0.0;
+            for (int j = 0; j + 1 < m; ++j) off += std::norm(A[(m - 1) * n + j]);
+            if (std::sqrt(off) <= 1e-15 * nrm) {
+                for (int j = 0; j + 1 < m; ++j) A[(m - 1) * n + j] = 0.0;
+                done = true;
+                break;
+            }
+            const cd a = A[(m - 2) * n + m - 2], b = A[(m - 2) * n + m - 1];
+            const cd c = A[(m - 1) * n + m - 2], d = A[(m - 1) * n + m - 1];
+            const cd tr = 0.5 * (a + d);
+            const cd disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
+            cd mu = (std::abs(tr + disc - d) < std::abs(tr - disc - d)) ? tr + disc : tr - disc;
+            if (it % 11 == 10) mu += 0.75 * std::abs(c);
+            for (int i = 0; i < m; ++i) A[i * n + i] -= mu;
+            householder_qr(m, n, A, Q.data(), R.data());
+            for (int i = 0; i < m; ++i)  // A[:m,:m] = R Q + mu I
+                for (int j = 0; j < m; ++j) {
+                    cd acc = 0.0;
+                    for (int k = 0; k < m; ++k) acc += R[i * m + k] * Q[k * m + j];
+                    A[i * n + j] = acc + (i == j ? mu : cd(0.0));
+                }
+            for (int j = m; j < n; ++j) {  // A[:m, m:] = Q^H A[:m, m:]
+                for (int i = 0; i < m; ++i) {
+                    cd acc = 0.0;
+                    for (int k = 0; k < m; ++k) acc += std::conj(Q[k * m + i]) * A[k * n + j];
+                    tmp[i] = acc;
+                }
+                for (int i = 0; i < m; ++i) A[i * n + j] = tmp[i];
+            }
+            for (int i = 0; i < n; ++i) {  // Z[:, :m] = Z[:, :m] Q
+                for (int j = 0; j < m; ++j) {
+                    cd acc = 0.0;
+                    for (int k = 0; k < m; ++k) acc += Z[i * n + k] * Q[k * m + j];
+                    tmp[j] = acc;
+                }
+                for (int j = 0; j < m; ++j) Z[i * n + j] = tmp[j];
+            }
+        }
+        if (!done) return false;
+    }
+    return true;
+}
+
+// B, Z, T (each (nt+1)^2 complex, row-major) of the shared time factor.
+bool time_factor(int nt, const double* U, cd* B, cd* Z, cd* T) {
+    const int n = nt + 1;
+    std::vector<cd> M0(n * n, 0.0), Minv(n * n), G(n * n, 0.0);
+    for (int m = 0; m < nt; ++m) {
+        for (int k = 0; k < nt; ++k)
+            if (k > m && ((k - m) & 1)) M0[m * n + k] = cd(0.0, 2.0);  // i Q_km
+        const double s = (m & 1) ? -1.0 : 1.0;
+        M0[m * n + nt] = s;
+        M0[nt * n + m] = s;
+    }
+    Minv = M0;
+    if (!invert_small(n, Minv.data())) return false;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < nt; ++j) G[i * n + j] = Minv[i * n + j] * U[j];
+    for (int k = 0; k < n * n; ++k) T[k] = G[k];
+    if (!schur_small(n, T, Z)) return false;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            cd acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += std::conj(Z[k * n + i]) * Minv[k * n + j];
+            B[i * n + j] = acc;
+        }
+    return true;
+}
+
 void legendre_values(int nt, double y, double* P) {
     P[0] = 1.0;
     if (nt > 1) P[1] = y;
@@ -121,6 +276,8 @@ struct lam_ctx {
     double2* d_G = nullptr;
     double2* h_G = nullptr;       // pinned
     double2* d_cf = nullptr;      // forward coefficients kept for the gradients
+    double2* d_tf = nullptr;      // shared time factor B, Z, T (FP64)
+    float2* d_tff = nullptr;      // and its FP32 copy
     // profiling of finest-level sweeps
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -174,11 +331,12 @@ int refactor_modes(lam_ctx* c, Level& L) {
     if (L.factored_field == c->Ebar) return LAM_OK;
     std::vector<double> sh(L.nblocks);
     for (int b = 0; b < L.nblocks; ++b) sh[b] = c->Ebar * L.zc[b];
-    HIPCHK(hipMemcpyAsync(L.d_shift, sh.data(), sizeof(double) * L.nblocks, hipMemcpyHostToDevice, c->st));
-    HIPCHK(launch_mode_factor(c->nt, L.nblocks, L.g.bpts, c->U, L.d_e, L.d_shift, L.d_Minv,
-                              L.fp32 ? L.d_Minvf : nullptr, c->st));
-    // the shift array must stay valid until the kernel has read it
+    // make sure no queued sweep still reads the previous shifts, then upload
     HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(L.d_shift, sh.data(), sizeof(double) * L.nblocks, hipMemcpyHostToDevice));
+    if (c->solver.time_factor == LAM_TF_STORED)
+        HIPCHK(launch_mode_factor(c->nt, L.nblocks, L.g.bpts, c->U, L.d_e, L.d_shift, L.d_Minv,
+                                  L.fp32 ? L.d_Minvf : nullptr, c->st));
     L.factored_field = c->Ebar;
     return LAM_OK;
 }
@@ -194,7 +352,7 @@ int set_step(lam_ctx* c, double t0) {
     for (int k = 0; k < nt * nt; ++k) on |= (c->W[k] != 0.0);
     c->field_on = on;
     c->Ebar = c->W[0] / c->U[0];
-    c->n_inner = c->solver.n_inner >= 0 ? c->solver.n_inner : (on ? 3 : 0);
+    c->n_inner = c->solver.n_inner >= 0 ? c->solver.n_inner : (on ? 16 : 0);
     auto t_a = std::chrono::steady_clock::now();
     for (auto& L : c->lv) LAMCHK(refactor_modes(c, L));
     c->t_factor_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
@@ -225,7 +383,13 @@ int sweep(lam_ctx* c, int l, int colour) {
         a.bs = L.d_bs;
     }
     a.V = L.fp32 ? static_cast<const void*>(L.d_Vf) : static_cast<const void*>(L.d_V);
-    a.Minv = L.fp32 ? static_cast<const void*>(L.d_Minvf) : static_cast<const void*>(L.d_Minv);
+    if (c->solver.time_factor == LAM_TF_STORED)
+        a.Minv = L.fp32 ? static_cast<const void*>(L.d_Minvf) : static_cast<const void*>(L.d_Minv);
+    else
+        a.Minv = nullptr;
+    a.tf = L.fp32 ? static_cast<const void*>(c->d_tff) : static_cast<const void*>(c->d_tf);
+    a.e = L.d_e;
+    a.shift = L.d_shift;
     a.adjoint = c->adjoint;
     a.n_inner = c->n_inner;
     const bool rec = c->prof && l == 0;
@@ -301,7 +465,9 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
     N = N0;
     int cycles = 0;
     int rc = LAM_OK;
-    if (N0 > 0.0) {
+    if (!std::isfinite(N0)) {
+        rc = LAM_EDIVERGED;
+    } else if (N0 > 0.0) {
         rc = LAM_ENOCONV;
         for (cycles = 0; cycles < c->solver.max_cycles;) {
             LAMCHK(vcycle(c, 0));
@@ -342,6 +508,7 @@ int validate(const lam_grid* g, const lam_time* t, const lam_ham* h, const lam_s
     if (!h->v0) return LAM_EINVAL;
     if (s->precision != LAM_FP64 && s->precision != LAM_MIXED) return LAM_EINVAL;
     if (s->max_cycles < 0 || !(s->tol >= 0.0) || s->n_inner < -1) return LAM_EINVAL;
+    if (s->time_factor != LAM_TF_SHARED && s->time_factor != LAM_TF_STORED) return LAM_EINVAL;
     long bpts = 1;
     for (int a = 0; a < g->dim; ++a) {
         if (g->n[a] < 1 || g->block[a] < 1) return LAM_EINVAL;
@@ -403,6 +570,8 @@ void free_ctx(lam_ctx* c) {
     (void)hipFree(c->d_Gpart);
     (void)hipFree(c->d_G);
     (void)hipFree(c->d_cf);
+    (void)hipFree(c->d_tf);
+    (void)hipFree(c->d_tff);
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->h_G) (void)hipHostFree(c->h_G);
     for (auto e : c->ev) (void)hipEventDestroy(e);
@@ -466,11 +635,12 @@ int build(lam_ctx* c, const double* v0_dev) {
         if (l > 0) LAMCHK(dalloc(&L.d_bc, P * nt));
         LAMCHK(dalloc(&L.d_V, L.nblocks * B * B));
         LAMCHK(dalloc(&L.d_e, L.nblocks * B));
-        LAMCHK(dalloc(&L.d_Minv, L.nblocks * B * (nt + 1) * (nt + 1)));
+        const bool stored = c->solver.time_factor == LAM_TF_STORED;
+        if (stored) LAMCHK(dalloc(&L.d_Minv, L.nblocks * B * (nt + 1) * (nt + 1)));
         LAMCHK(dalloc(&L.d_shift, (size_t)L.nblocks));
         if (L.fp32) {
             LAMCHK(dalloc(&L.d_Vf, L.nblocks * B * B));
-            LAMCHK(dalloc(&L.d_Minvf, L.nblocks * B * (nt + 1) * (nt + 1)));
+            if (stored) LAMCHK(dalloc(&L.d_Minvf, L.nblocks * B * (nt + 1) * (nt + 1)));
         }
     }
     HIPCHK(hipMemcpyAsync(c->lv[0].d_v0, v0_dev, sizeof(double) * c->lv[0].g.P, hipMemcpyDeviceToDevice, c->st));
@@ -487,6 +657,23 @@ int build(lam_ctx* c, const double* v0_dev) {
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_red), sizeof(double)) != hipSuccess) return LAM_ENOMEM;
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
         return LAM_ENOMEM;
+    {
+        const int n = nt + 1;
+        std::vector<cd> B(n * n), Z(n * n), T(n * n);
+        if (!time_factor(nt, c->U, B.data(), Z.data(), T.data())) return LAM_EINVAL;
+        std::vector<double2> h(3 * n * n);
+        std::vector<float2> hf(3 * n * n);
+        const cd* parts[3] = {B.data(), Z.data(), T.data()};
+        for (int p = 0; p < 3; ++p)
+            for (int k = 0; k < n * n; ++k) {
+                h[p * n * n + k] = make_double2(parts[p][k].real(), parts[p][k].imag());
+                hf[p * n * n + k] = make_float2((float)parts[p][k].real(), (float)parts[p][k].imag());
+            }
+        LAMCHK(dalloc(&c->d_tf, h.size()));
+        LAMCHK(dalloc(&c->d_tff, hf.size()));
+        HIPCHK(hipMemcpy(c->d_tf, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->d_tff, hf.data(), sizeof(float2) * hf.size(), hipMemcpyHostToDevice));
+    }
     c->Ebar = 0.0;
     for (auto& L : c->lv) LAMCHK(factor_level(c, L));
     HIPCHK(hipStreamSynchronize(c->st));

@@ -45,7 +45,10 @@ struct SweepArgs {
     const double2* bg;        // or: the same value on every row (j, n): bg[j]; may be null
     const double2* bs;        // constraint right-hand side [P], may be null (= 0)
     const void* V;            // [nblocks][bpts][bpts] eigenvectors (double or float)
-    const void* Minv;         // [nblocks][NT+1][NT+1][bpts] mode inverses (double2 or float2)
+    const void* Minv;         // [nblocks][NT+1][NT+1][bpts] mode inverses (double2 or float2), or null:
+    const void* tf;           // shared time factor B, Z, T ((NT+1)^2 complex each, row-major)
+    const double* e;          // [nblocks][bpts] eigenvalues of the block operators
+    const double* shift;      // [nblocks] frozen-field eigenvalue shift
     int adjoint;
     int n_inner;
 };

@@ -35,95 +35,102 @@ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
 }
 template <typename T>
 __device__ __forceinline__ cx<T> rmul(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
+    const T den = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / den, (a.i * b.r - a.r * b.i) / den};
+}
 
 __device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 sub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 scl2(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 
 // ---------------------------------------------------------------------------
-// grid indexing
+// grid indexing.  Coordinates are three scalars; axes beyond the grid's rank
+// have extent 1 (n, bdim, nblk), so the three-axis C-order formulas hold for
+// 1D, 2D and 3D alike and no loop is bounded by the rank.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void point_coords(const LevelGeom& g, int j, int* i) {
-    i[1] = 0;
-    i[2] = 0;
-    if (g.dim == 1) {
-        i[0] = j;
-    } else if (g.dim == 2) {
-        i[0] = j / g.n[1];
-        i[1] = j - i[0] * g.n[1];
-    } else {
-        const int t = j / g.n[2];
-        i[2] = j - t * g.n[2];
-        i[0] = t / g.n[1];
-        i[1] = t - i[0] * g.n[1];
-    }
+struct I3 {
+    int x, y, z;
+};
+
+__device__ __forceinline__ int comp(const I3& v, int ax) { return ax == 0 ? v.x : (ax == 1 ? v.y : v.z); }
+
+__device__ __forceinline__ I3 with_comp(I3 v, int ax, int val) {
+    if (ax == 0) v.x = val;
+    else if (ax == 1) v.y = val;
+    else v.z = val;
+    return v;
 }
 
-__device__ __forceinline__ int point_index(const LevelGeom& g, const int* i) {
-    if (g.dim == 1) return i[0];
-    if (g.dim == 2) return i[0] * g.n[1] + i[1];
-    return (i[0] * g.n[1] + i[1]) * g.n[2] + i[2];
+__device__ __forceinline__ I3 point_coords(const LevelGeom& g, int j) {
+    I3 i;
+    i.z = j % g.n[2];
+    const int t = j / g.n[2];
+    i.y = t % g.n[1];
+    i.x = t / g.n[1];
+    return i;
+}
+
+__device__ __forceinline__ int point_index(const LevelGeom& g, const I3& i) {
+    return (i.x * g.n[1] + i.y) * g.n[2] + i.z;
 }
 
 // Neighbour of point i along axis ax in direction d: global index, or -1
-// outside a Dirichlet grid.  gi receives the (wrapped) coordinates.
-__device__ __forceinline__ int neighbour(const LevelGeom& g, const int* i, int ax, int d, int* gi) {
-    gi[0] = i[0];
-    gi[1] = i[1];
-    gi[2] = i[2];
-    gi[ax] += d;
-    if (gi[ax] < 0 || gi[ax] >= g.n[ax]) {
+// outside a Dirichlet grid.  *gi receives the (wrapped) coordinates.
+__device__ __forceinline__ int neighbour(const LevelGeom& g, const I3& i, int ax, int d, I3* gi) {
+    const int na = g.n[ax];
+    int v = comp(i, ax) + d;
+    if (v < 0 || v >= na) {
         if (!g.periodic) return -1;
-        gi[ax] = (gi[ax] + g.n[ax]) % g.n[ax];
+        v = (v + na) % na;
     }
-    return point_index(g, gi);
+    *gi = with_comp(i, ax, v);
+    return point_index(g, *gi);
 }
 
-__device__ __forceinline__ double zcoord(const LevelGeom& g, const int* i) {
-    return (i[g.fax] - 0.5 * (g.n[g.fax] - 1)) * g.h;
+__device__ __forceinline__ double zcoord(const LevelGeom& g, const I3& i) {
+    return (comp(i, g.fax) - 0.5 * (g.n[g.fax] - 1)) * g.h;
 }
 
 // Block bookkeeping: block id -> block coordinates; local index -> local coords.
-__device__ __forceinline__ void block_coords(const LevelGeom& g, int blk, int* bc) {
-    bc[0] = bc[1] = bc[2] = 0;
-    int t = blk;
-    for (int ax = g.dim - 1; ax >= 0; --ax) {
-        bc[ax] = t % g.nblk[ax];
-        t /= g.nblk[ax];
-    }
+__device__ __forceinline__ I3 block_coords(const LevelGeom& g, int blk) {
+    I3 b;
+    b.z = blk % g.nblk[2];
+    const int t = blk / g.nblk[2];
+    b.y = t % g.nblk[1];
+    b.x = t / g.nblk[1];
+    return b;
 }
 
-__device__ __forceinline__ void local_coords(const LevelGeom& g, int l, int* lc) {
-    lc[0] = lc[1] = lc[2] = 0;
-    int t = l;
-    for (int ax = g.dim - 1; ax >= 0; --ax) {
-        lc[ax] = t % g.bdim[ax];
-        t /= g.bdim[ax];
-    }
+__device__ __forceinline__ I3 local_coords(const LevelGeom& g, int l) {
+    I3 c;
+    c.z = l % g.bdim[2];
+    const int t = l / g.bdim[2];
+    c.y = t % g.bdim[1];
+    c.x = t / g.bdim[1];
+    return c;
 }
 
-__device__ __forceinline__ int local_index(const LevelGeom& g, const int* lc) {
-    int l = 0;
-    for (int ax = 0; ax < g.dim; ++ax) l = l * g.bdim[ax] + lc[ax];
-    return l;
+__device__ __forceinline__ int local_index(const LevelGeom& g, const I3& lc) {
+    return (lc.x * g.bdim[1] + lc.y) * g.bdim[2] + lc.z;
+}
+
+__device__ __forceinline__ I3 global_of_local(const LevelGeom& g, const I3& bc, const I3& lc) {
+    return I3{bc.x * g.bdim[0] + lc.x, bc.y * g.bdim[1] + lc.y, bc.z * g.bdim[2] + lc.z};
 }
 
 // Neighbour of local point lc of block bc: returns the local index when the
 // (wrapped) neighbour lies inside the block, else -1; *glob receives its
 // global index (-1 outside a Dirichlet grid).
-__device__ __forceinline__ int block_neighbour(const LevelGeom& g, const int* bc, const int* lc, int ax,
-                                               int d, int* glob) {
-    int i[3] = {0, 0, 0};
-    for (int a = 0; a < g.dim; ++a) i[a] = bc[a] * g.bdim[a] + lc[a];
-    int gi[3];
-    const int gn = neighbour(g, i, ax, d, gi);
+__device__ __forceinline__ int block_neighbour(const LevelGeom& g, const I3& bc, const I3& lc, int ax, int d,
+                                               int* glob) {
+    I3 gi;
+    const int gn = neighbour(g, global_of_local(g, bc, lc), ax, d, &gi);
     *glob = gn;
     if (gn < 0) return -1;
-    int ln[3] = {0, 0, 0};
-    for (int a = 0; a < g.dim; ++a) {
-        ln[a] = gi[a] - bc[a] * g.bdim[a];
-        if (ln[a] < 0 || ln[a] >= g.bdim[a]) return -1;
-    }
+    const I3 ln{gi.x - bc.x * g.bdim[0], gi.y - bc.y * g.bdim[1], gi.z - bc.z * g.bdim[2]};
+    if (ln.x < 0 || ln.x >= g.bdim[0] || ln.y < 0 || ln.y >= g.bdim[1] || ln.z < 0 || ln.z >= g.bdim[2]) return -1;
     return local_index(g, ln);
 }
 
@@ -166,23 +173,33 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
     const int j = blockIdx.x * kThreads + threadIdx.x;
     double acc = 0.0;
     if (j < g.P) {
-        int i[3];
-        point_coords(g, j, i);
+        const I3 i = point_coords(g, j);
         double2 cj[NT], lap[NT];
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
             cj[n] = c[(size_t)j * NT + n];
             lap[n] = scl2(-2.0 * g.dim, cj[n]);
         }
-        for (int ax = 0; ax < g.dim; ++ax) {
-            for (int d = -1; d <= 1; d += 2) {
-                int gi[3];
-                const int nb = neighbour(g, i, ax, d, gi);
-                if (nb >= 0) {
+        // all neighbour loads issued unconditionally (clamped index, 0/1 weight)
+        int nbi[6];
+        double nbw[6];
 #pragma unroll
-                    for (int n = 0; n < NT; ++n) lap[n] = add2(lap[n], c[(size_t)nb * NT + n]);
+        for (int dir = 0; dir < 6; ++dir) {
+            nbi[dir] = j;
+            nbw[dir] = 0.0;
+            if (dir < 2 * g.dim) {
+                I3 gi;
+                const int nb = neighbour(g, i, dir >> 1, (dir & 1) ? 1 : -1, &gi);
+                if (nb >= 0) {
+                    nbi[dir] = nb;
+                    nbw[dir] = 1.0;
                 }
             }
+        }
+#pragma unroll
+        for (int dir = 0; dir < 6; ++dir) {
+#pragma unroll
+            for (int n = 0; n < NT; ++n) lap[n] = add2(lap[n], scl2(nbw[dir], c[(size_t)nbi[dir] * NT + n]));
         }
         const double vj = v0[j];
         const double z = zcoord(g, i);
@@ -261,20 +278,23 @@ __global__ __launch_bounds__(kThreads) void k_restrict(LevelGeom f, LevelGeom cg
                                                        double2* __restrict__ zc, double2* __restrict__ zl) {
     const int J = blockIdx.x * kThreads + threadIdx.x;
     if (J >= cg.P) return;
-    int I[3];
-    point_coords(cg, J, I);
+    const I3 I = point_coords(cg, J);
     double2 acc[NT];
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[n] = make_double2(0.0, 0.0);
     double2 accs = make_double2(0.0, 0.0);
     const int nch = 1 << f.dim;
-    for (int ch = 0; ch < nch; ++ch) {
-        int fi[3] = {0, 0, 0};
-        for (int a = 0; a < f.dim; ++a) fi[a] = 2 * I[a] + ((ch >> a) & 1);
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+        const int chc = ch < nch ? ch : 0;
+        const double w = ch < nch ? 1.0 : 0.0;
+        // child offsets only along the grid's axes (unused axes have extent 1)
+        const I3 fi{2 * I.x + ((chc >> 0) & 1), f.dim > 1 ? 2 * I.y + ((chc >> 1) & 1) : 0,
+                    f.dim > 2 ? 2 * I.z + ((chc >> 2) & 1) : 0};
         const int fj = point_index(f, fi);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) acc[n] = add2(acc[n], rcf[(size_t)fj * NT + n]);
-        accs = add2(accs, rsf[fj]);
+        for (int n = 0; n < NT; ++n) acc[n] = add2(acc[n], scl2(w, rcf[(size_t)fj * NT + n]));
+        accs = add2(accs, scl2(w, rsf[fj]));
     }
     const double sc = 1.0 / nch;
 #pragma unroll
@@ -298,17 +318,26 @@ __global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg,
                                                       double2* __restrict__ cf, double2* __restrict__ lf) {
     const int j = blockIdx.x * kThreads + threadIdx.x;
     if (j >= f.P) return;
-    int i[3];
-    point_coords(f, j, i);
-    int par[3] = {0, 0, 0}, nb[3] = {0, 0, 0}, ok[3] = {1, 1, 1};
-    for (int a = 0; a < f.dim; ++a) {
-        par[a] = i[a] >> 1;
-        nb[a] = (i[a] & 1) ? par[a] + 1 : par[a] - 1;
-        if (nb[a] < 0 || nb[a] >= cg.n[a]) {
+    const I3 i = point_coords(f, j);
+    // per axis: parent, nearer coarse neighbour, and whether that neighbour exists
+    int par[3], nb[3], ok[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int ia = comp(i, a);
+        const int nc = cg.n[a];
+        par[a] = ia >> 1;
+        nb[a] = (ia & 1) ? par[a] + 1 : par[a] - 1;
+        ok[a] = 1;
+        if (nb[a] < 0 || nb[a] >= nc) {
             if (f.periodic)
-                nb[a] = (nb[a] + cg.n[a]) % cg.n[a];
+                nb[a] = (nb[a] + nc) % nc;
             else
                 ok[a] = 0;
+        }
+        if (a >= f.dim) {  // unused axis: extent 1, no neighbour
+            par[a] = 0;
+            nb[a] = 0;
+            ok[a] = 0;
         }
     }
     double2 acc[NT];
@@ -316,23 +345,24 @@ __global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg,
     for (int n = 0; n < NT; ++n) acc[n] = make_double2(0.0, 0.0);
     double2 accl = make_double2(0.0, 0.0);
     const int ncomb = interp ? 1 : (1 << f.dim);
-    for (int cmb = 0; cmb < ncomb; ++cmb) {
-        double w = 1.0;
-        int J3[3] = {0, 0, 0};
-        bool valid = true;
-        for (int a = 0; a < f.dim; ++a) {
+    // all parent loads issued unconditionally (clamped to the parent, weight 0 when unused)
+#pragma unroll
+    for (int cmb = 0; cmb < 8; ++cmb) {
+        double w = cmb < ncomb ? 1.0 : 0.0;
+        int J3[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
             const int bit = (cmb >> a) & 1;
+            J3[a] = par[a];
             if (bit) {
-                valid = valid && ok[a];
-                J3[a] = nb[a];
+                if (ok[a]) J3[a] = nb[a];
+                else w = 0.0;
                 w *= 0.25;
             } else {
-                J3[a] = par[a];
-                w *= interp ? 1.0 : 0.75;
+                w *= (interp || a >= f.dim) ? 1.0 : 0.75;
             }
         }
-        if (!valid) continue;
-        const int J = point_index(cg, J3);
+        const int J = point_index(cg, I3{J3[0], J3[1], J3[2]});
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[n] = add2(acc[n], scl2(w, cc[(size_t)J * NT + n]));
         accl = add2(accl, scl2(w, lc[J]));
@@ -347,13 +377,12 @@ __global__ __launch_bounds__(kThreads) void k_average_potential(LevelGeom f, Lev
                                                                 double* __restrict__ vc) {
     const int J = blockIdx.x * kThreads + threadIdx.x;
     if (J >= cg.P) return;
-    int I[3];
-    point_coords(cg, J, I);
+    const I3 I = point_coords(cg, J);
     const int nch = 1 << f.dim;
     double acc = 0.0;
     for (int ch = 0; ch < nch; ++ch) {
-        int fi[3] = {0, 0, 0};
-        for (int a = 0; a < f.dim; ++a) fi[a] = 2 * I[a] + ((ch >> a) & 1);
+        const I3 fi{2 * I.x + (ch & 1), f.dim > 1 ? 2 * I.y + ((ch >> 1) & 1) : 0,
+                    f.dim > 2 ? 2 * I.z + ((ch >> 2) & 1) : 0};
         acc += vf[point_index(f, fi)];
     }
     vc[J] = acc / nch;
@@ -381,8 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const doubl
     const int b = g.bpts;
     const int nn = b + (b & 1);
     const int half = nn / 2;
-    int bc[3];
-    block_coords(g, blk, bc);
+    const I3 bc = block_coords(g, blk);
 
     for (int t = tid; t < b * b; t += kThreads) {
         const int j = t / b, k = t - j * b;
@@ -391,11 +419,8 @@ __global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const doubl
     }
     __syncthreads();
     for (int l = tid; l < b; l += kThreads) {
-        int lc[3];
-        local_coords(g, l, lc);
-        int i[3] = {0, 0, 0};
-        for (int a = 0; a < g.dim; ++a) i[a] = bc[a] * g.bdim[a] + lc[a];
-        A[l * kLdsPad + l] += 2.0 * g.dim * g.kin + v0[point_index(g, i)];
+        const I3 lc = local_coords(g, l);
+        A[l * kLdsPad + l] += 2.0 * g.dim * g.kin + v0[point_index(g, global_of_local(g, bc, lc))];
         for (int ax = 0; ax < g.dim; ++ax)
             for (int d = -1; d <= 1; d += 2) {
                 int glob;
@@ -415,7 +440,9 @@ __global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const doubl
         }
         off = block_sum(off, red);
         tot = block_sum(tot, red);
-        if (tid == 0) stop = (off <= 1e-30 * tot) ? 1 : 0;
+        // off-diagonal Frobenius norm below 1e-14 of the total: at the level
+        // the rotations themselves leave, so further sweeps cannot lower it
+        if (tid == 0) stop = (off <= 1e-28 * tot) ? 1 : 0;
         __syncthreads();
         if (stop) break;
         for (int r = 0; r < nn - 1; ++r) {
@@ -575,10 +602,14 @@ __global__ __launch_bounds__(64) void k_mode_factor(int b, TimeOps<NT> to, const
 
 // ---------------------------------------------------------------------------
 // K3: relax every block of one colour.  One workgroup per block:
-//   1. stage the block's c, lambda, V0, eigenvectors in LDS;
-//   2. local residual r_U = (b - K x)_U, halo values read from HBM;
-//   3. delta = V (M(e_k)^{-1} (V^T r)) per mode k    [K_UU^{-1} r in factored form]
-//   4. (field steps) n_inner corrections r <- r - K_UU delta, repeat 3;
+//   1. issue every global load of the block at once (own coefficients, the
+//      halo neighbours outside the block, right-hand side, lambda, V0,
+//      eigenvectors, eigenvalues) with clamped addresses and 0/1 weights, so
+//      that a single memory latency covers the whole block;
+//   2. local residual r_U = (b - K x)_U from LDS and registers (FP64);
+//   3. delta = V (M(e_k)^{-1} (V^T r)) per mode k    [K_UU^{-1} r in factored form];
+//   4. (field steps) corrections r <- r - K_UU delta, repeat 3, until the
+//      block's residual fell by 1e-13 (FP64) / 1e-6 (FP32), at most n_inner;
 //   5. write c_U += delta_c, lambda_U += delta_lambda.
 // BT is the precision of the factors and of step 3 (double, or float for the
 // mixed path); the state and the residual of step 2 are always FP64.
@@ -586,6 +617,7 @@ __global__ __launch_bounds__(64) void k_mode_factor(int b, TimeOps<NT> to, const
 template <int NT, typename BT>
 __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to) {
     constexpr int NQ = NT + 1;
+    constexpr int IPT = (kMaxB * NT + kThreads - 1) / kThreads;  // residual items per thread
     using C = cx<BT>;
     __shared__ BT Vs[kMaxB * kLdsPad];
     __shared__ double2 cs[kMaxB * NT];
@@ -593,80 +625,138 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
     __shared__ double v0s[kMaxB];
     __shared__ double zs[kMaxB];
     __shared__ int gidx[kMaxB];
-    __shared__ C rs[kMaxB * NQ];
-    __shared__ C rh[kMaxB * NQ];
-    __shared__ C di[kMaxB * NQ];
+    __shared__ C rs[kMaxB * NQ];   // local residual
+    __shared__ C rh[kMaxB * NQ];   // V^T r, per-mode solutions, then the correction
+    __shared__ C tfs[3 * NQ * NQ];
+    __shared__ BT es[kMaxB];
+    __shared__ double red[kThreads / 64];
+    __shared__ double rnorm_sh;
 
     const LevelGeom& g = a.g;
     const int tid = threadIdx.x;
     const int blk = a.blocks[blockIdx.x];
     const int b = g.bpts;
-    int bc[3];
-    block_coords(g, blk, bc);
+    const int nd = 2 * g.dim;
+    // inner passes stop once the block's own residual fell below this fraction (in norm)
+    const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-12;
+    const I3 bc = block_coords(g, blk);
 
-    for (int l = tid; l < b; l += kThreads) {
-        int lc[3];
-        local_coords(g, l, lc);
-        int i[3] = {0, 0, 0};
-        for (int ax = 0; ax < g.dim; ++ax) i[ax] = bc[ax] * g.bdim[ax] + lc[ax];
+    // ---- 1. loads ----
+    double2 own[IPT], halo[IPT], rhsv[IPT];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int t = tid + it * kThreads;
+        own[it] = halo[it] = rhsv[it] = make_double2(0.0, 0.0);
+        if (t < b * NT) {
+            const int l = t / NT, m = t - l * NT;
+            const I3 lc = local_coords(g, l);
+            const int gj = point_index(g, global_of_local(g, bc, lc));
+            int hidx[6];
+            double hw[6];
+#pragma unroll
+            for (int dir = 0; dir < 6; ++dir) {
+                hidx[dir] = gj;
+                hw[dir] = 0.0;
+                if (dir < nd) {
+                    int glob;
+                    const int ln = block_neighbour(g, bc, lc, dir >> 1, (dir & 1) ? 1 : -1, &glob);
+                    if (ln < 0 && glob >= 0) {
+                        hidx[dir] = glob;
+                        hw[dir] = 1.0;
+                    }
+                }
+            }
+            own[it] = a.c[(size_t)gj * NT + m];
+            double2 hv[6];
+#pragma unroll
+            for (int dir = 0; dir < 6; ++dir) hv[dir] = a.c[(size_t)hidx[dir] * NT + m];
+            if (a.bc)
+                rhsv[it] = a.bc[(size_t)gj * NT + m];
+            else if (a.bg)
+                rhsv[it] = a.bg[gj];
+            double2 hs = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int dir = 0; dir < 6; ++dir) hs = add2(hs, scl2(hw[dir], hv[dir]));
+            halo[it] = hs;
+        }
+    }
+    double2 sgv = make_double2(0.0, 0.0);
+    if (tid < b) {
+        const I3 i = global_of_local(g, bc, local_coords(g, tid));
         const int gj = point_index(g, i);
-        gidx[l] = gj;
-        v0s[l] = a.v0[gj];
-        ls[l] = a.lam[gj];
-        zs[l] = zcoord(g, i);
+        gidx[tid] = gj;
+        v0s[tid] = a.v0[gj];
+        ls[tid] = a.lam[gj];
+        zs[tid] = zcoord(g, i);
+        if (a.bs) sgv = a.bs[gj];
     }
-    const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
-    for (int t = tid; t < b * b; t += kThreads) {
-        const int j = t / b, k = t - j * b;
-        Vs[j * kLdsPad + k] = Vg[t];
+    {
+        const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
+        for (int t = tid; t < b * b; t += kThreads) {
+            const int j = t / b, k = t - j * b;
+            Vs[j * kLdsPad + k] = Vg[t];
+        }
     }
-    __syncthreads();
-    for (int t = tid; t < b * NT; t += kThreads) {
-        const int l = t / NT, n = t - l * NT;
-        cs[t] = a.c[(size_t)gidx[l] * NT + n];
+    if (!a.Minv) {
+        const C* tfg = static_cast<const C*>(a.tf);
+        for (int t = tid; t < 3 * NQ * NQ; t += kThreads) tfs[t] = tfg[t];
+        const double sh = a.shift[blk];
+        for (int k = tid; k < b; k += kThreads) es[k] = (BT)(a.e[(size_t)blk * b + k] + sh);
+    }
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int t = tid + it * kThreads;
+        if (t < b * NT) cs[t] = own[it];
     }
     __syncthreads();
 
     // ---- 2. local residual (FP64) ----
-    for (int t = tid; t < b * NT; t += kThreads) {
-        const int l = t / NT, m = t - l * NT;
-        int lc[3];
-        local_coords(g, l, lc);
-        double2 lap = scl2(-2.0 * g.dim, cs[t]);
-        for (int ax = 0; ax < g.dim; ++ax)
-            for (int d = -1; d <= 1; d += 2) {
-                int glob;
-                const int ln = block_neighbour(g, bc, lc, ax, d, &glob);
-                if (ln >= 0)
-                    lap = add2(lap, cs[ln * NT + m]);
-                else if (glob >= 0)
-                    lap = add2(lap, a.c[(size_t)glob * NT + m]);
-            }
-        const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], cs[t]));
-        double2 tq = make_double2(0.0, 0.0);
-        if (!a.adjoint) {
-            for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cs[l * NT + n]);
-        } else {
-            for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cs[l * NT + n]);
-        }
-        const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
-        double2 wc = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cs[l * NT + n]));
-        const double sm = (m & 1) ? -1.0 : 1.0;
-        double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(zs[l], wc));
-        row = add2(row, scl2(sm, ls[l]));
-        const double2 rhs =
-            a.bc ? a.bc[(size_t)gidx[l] * NT + m] : (a.bg ? a.bg[gidx[l]] : make_double2(0.0, 0.0));
-        const double2 rho = sub2(rhs, row);
-        rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
+    for (int it = 0; it < IPT; ++it) {
+        const int t = tid + it * kThreads;
+        if (t < b * NT) {
+            const int l = t / NT, m = t - l * NT;
+            const I3 lc = local_coords(g, l);
+            double2 lap = add2(scl2(-2.0 * g.dim, own[it]), halo[it]);
+            for (int dir = 0; dir < nd; ++dir) {
+                int glob;
+                const int ln = block_neighbour(g, bc, lc, dir >> 1, (dir & 1) ? 1 : -1, &glob);
+                if (ln >= 0) lap = add2(lap, cs[ln * NT + m]);
+            }
+            const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], own[it]));
+            double2 tq = make_double2(0.0, 0.0);
+            if (!a.adjoint) {
+                for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cs[l * NT + n]);
+            } else {
+                for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cs[l * NT + n]);
+            }
+            const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
+            double2 wc = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cs[l * NT + n]));
+            const double sm = (m & 1) ? -1.0 : 1.0;
+            double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(zs[l], wc));
+            row = add2(row, scl2(sm, ls[l]));
+            const double2 rho = sub2(rhsv[it], row);
+            rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
+        }
     }
-    for (int l = tid; l < b; l += kThreads) {
-        double2 sg = a.bs ? a.bs[gidx[l]] : make_double2(0.0, 0.0);
-        for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cs[l * NT + n]) : sub2(sg, cs[l * NT + n]);
-        rs[l * NQ + NT] = C{(BT)sg.x, (BT)sg.y};
+    if (tid < b) {
+        double2 sg = sgv;
+        for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cs[tid * NT + n]) : sub2(sg, cs[tid * NT + n]);
+        rs[tid * NQ + NT] = C{(BT)sg.x, (BT)sg.y};
     }
     __syncthreads();
+    double r0n = 0.0;
+    if (a.n_inner > 0) {
+        double loc = 0.0;
+        for (int t = tid; t < b * NQ; t += kThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
+        const double tot = block_sum(loc, red);
+        if (tid == 0) rnorm_sh = tot;
+        __syncthreads();
+        r0n = rnorm_sh;
+        __syncthreads();
+    }
 
     const C* Mi = static_cast<const C*>(a.Minv);
     for (int pass = 0; pass <= a.n_inner; ++pass) {
@@ -694,7 +784,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
         }
         __syncthreads();
         // ---- 3b. per-mode time solve ----
-        {
+        if (a.Minv) {
+            // stored inverses M(e_k)^{-1}
             const int k = tid & 63, pg = tid >> 6;
             C out[3];
             if (k < b) {
@@ -728,13 +819,89 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
                     if (p < NQ) rh[k * NQ + p] = out[r];
                 }
             }
+        } else {
+            // shared factor: M(e)^{-1} = Z (I - e T)^{-1} B   (adjoint: B^H (I - e T)^{-H} Z^H)
+            const C* Bm = tfs;
+            const C* Zm = tfs + NQ * NQ;
+            const C* Tm = tfs + 2 * NQ * NQ;
+            const int k = tid & 63, pg = tid >> 6;
+            C out[3];
+            if (k < b) {
+                C rv[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) rv[q] = rh[k * NQ + q];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int p = pg + 4 * r;
+                    C acc = C{0, 0};
+                    if (p < NQ) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+                            acc = acc + (a.adjoint ? cmulc(Zm[q * NQ + p], rv[q]) : cmul(Bm[p * NQ + q], rv[q]));
+                    }
+                    out[r] = acc;
+                }
+            }
+            __syncthreads();
+            if (k < b) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int p = pg + 4 * r;
+                    if (p < NQ) rh[k * NQ + p] = out[r];
+                }
+            }
+            __syncthreads();
+            if (pg == 0 && k < b) {
+                const BT ev = es[k];
+                C* y = rh + k * NQ;
+                if (!a.adjoint) {
+                    for (int p = NQ - 1; p >= 0; --p) {
+                        C acc = y[p];
+                        for (int q = p + 1; q < NQ; ++q) acc = acc + rmul(ev, cmul(Tm[p * NQ + q], y[q]));
+                        const C tp = Tm[p * NQ + p];
+                        y[p] = cdiv(acc, C{(BT)1 - ev * tp.r, -ev * tp.i});
+                    }
+                } else {
+                    for (int p = 0; p < NQ; ++p) {
+                        C acc = y[p];
+                        for (int q = 0; q < p; ++q) acc = acc + rmul(ev, cmulc(Tm[q * NQ + p], y[q]));
+                        const C tp = Tm[p * NQ + p];
+                        y[p] = cdiv(acc, C{(BT)1 - ev * tp.r, ev * tp.i});
+                    }
+                }
+            }
+            __syncthreads();
+            if (k < b) {
+                C rv[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) rv[q] = rh[k * NQ + q];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int p = pg + 4 * r;
+                    C acc = C{0, 0};
+                    if (p < NQ) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+                            acc = acc + (a.adjoint ? cmulc(Bm[q * NQ + p], rv[q]) : cmul(Zm[p * NQ + q], rv[q]));
+                    }
+                    out[r] = acc;
+                }
+            }
+            __syncthreads();
+            if (k < b) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int p = pg + 4 * r;
+                    if (p < NQ) rh[k * NQ + p] = out[r];
+                }
+            }
         }
         __syncthreads();
-        // ---- 3c. di[j][q] = sum_k V[j][k] rh[k][q] ----
+        // ---- 3c. correction di[j][q] = sum_k V[j][k] rh[k][q], written back into rh ----
         {
             const int j = tid & 63, qg = tid >> 6;
+            C acc[3];
             if (j < b) {
-                C acc[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) acc[r] = C{0, 0};
                 for (int k = 0; k < b; ++k) {
@@ -745,14 +912,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
                         if (q < NQ) acc[r] = acc[r] + rmul(v, rh[k * NQ + q]);
                     }
                 }
+            }
+            __syncthreads();
+            if (j < b) {
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const int q = qg + 4 * r;
-                    if (q < NQ) di[j * NQ + q] = acc[r];
+                    if (q < NQ) rh[j * NQ + q] = acc[r];
                 }
             }
         }
         __syncthreads();
+        const C* di = rh;
         // ---- accumulate, and for inner passes update the local residual ----
         for (int t = tid; t < b * NQ; t += kThreads) {
             const int l = t / NQ, q = t - l * NQ;
@@ -765,15 +936,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
                 C y;
                 if (q < NT) {
                     const int m = q;
-                    int lc[3];
-                    local_coords(g, l, lc);
+                    const I3 lc = local_coords(g, l);
                     C lap = rmul((BT)(-2.0 * g.dim), dv);
-                    for (int ax = 0; ax < g.dim; ++ax)
-                        for (int d = -1; d <= 1; d += 2) {
-                            int glob;
-                            const int ln = block_neighbour(g, bc, lc, ax, d, &glob);
-                            if (ln >= 0) lap = lap + di[ln * NQ + m];
-                        }
+                    for (int dir = 0; dir < nd; ++dir) {
+                        int glob;
+                        const int ln = block_neighbour(g, bc, lc, dir >> 1, (dir & 1) ? 1 : -1, &glob);
+                        if (ln >= 0) lap = lap + di[ln * NQ + m];
+                    }
                     const C hd = rmul((BT)(-g.kin), lap) + rmul((BT)v0s[l], dv);
                     C tq = C{0, 0};
                     if (!a.adjoint) {
@@ -794,8 +963,20 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
             }
         }
         __syncthreads();
+        if (pass < a.n_inner) {
+            // stop the defect corrections once the local system is solved
+            double loc = 0.0;
+            for (int t = tid; t < b * NQ; t += kThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
+            const double tot = block_sum(loc, red);
+            if (tid == 0) rnorm_sh = tot;
+            __syncthreads();
+            const bool done = rnorm_sh <= inner_tol2 * r0n;
+            __syncthreads();
+            if (done) break;
+        }
     }
 
+    // ---- 5. write back ----
     for (int t = tid; t < b * NT; t += kThreads) {
         const int l = t / NT, n = t - l * NT;
         a.c[(size_t)gidx[l] * NT + n] = cs[t];
@@ -864,9 +1045,7 @@ __global__ __launch_bounds__(kThreads) void k_gradients(LevelGeom g, TimeOps<NT>
     double2 cj[NT], mj[NT];
     double z = 0.0;
     if (on) {
-        int i[3];
-        point_coords(g, j, i);
-        z = zcoord(g, i);
+        z = zcoord(g, point_coords(g, j));
         double acc = 0.0;
 #pragma unroll
         for (int n = 0; n < NT; ++n) {

@@ -27,6 +27,7 @@ LAM_MAX_BLOCK = 64
 PULSE = {"none": 0, "sin2": 1, "fourier": 2, "sin2+fourier": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 INTERP = {"linear": 0, "constant": 1}
+TIME_FACTOR = {"shared": 0, "stored": 1}
 
 
 class LamError(RuntimeError):
@@ -59,7 +60,7 @@ class LamHam(ctypes.Structure):
 
 class LamSolver(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_cycles", ctypes.c_int),
-                ("n_inner", ctypes.c_int)]
+                ("n_inner", ctypes.c_int), ("time_factor", ctypes.c_int)]
 
 
 class LamStats(ctypes.Structure):
@@ -169,7 +170,7 @@ class Propagator:
 
     def __init__(self, shape, h, v0, n_t, dt, block, levels=1, nu_pre=1, nu_post=1, nu_coarse=2,
                  interp="linear", periodic=False, mass=1.0, field_axis=-1, pulse=None,
-                 precision="fp64", tol=1e-10, max_cycles=50, n_inner=-1, stream=None):
+                 precision="fp64", tol=1e-10, max_cycles=50, n_inner=-1, time_factor="shared", stream=None):
         lib = load_library()
         shape = tuple(int(s) for s in shape)
         block = tuple(int(b) for b in block)
@@ -200,7 +201,7 @@ class Propagator:
         ham.pulse_kind, ham.e0, ham.omega, ham.t_total = kind, e0, omega, t_total
         ham.n_coef = len(coef)
         ham.coef = self._coef
-        s = LamSolver(PRECISION[precision], float(tol), int(max_cycles), int(n_inner))
+        s = LamSolver(PRECISION[precision], float(tol), int(max_cycles), int(n_inner), TIME_FACTOR[time_factor])
         self.levels = int(levels)
         self.precision = precision
         h_ctx = ctypes.c_void_p()

@@ -52,7 +52,7 @@ int main(void) {
   printf("lam_grid %zu\nlam_time %zu\nlam_ham %zu\nlam_solver %zu\nlam_stats %zu\n",
          sizeof(lam_grid), sizeof(lam_time), sizeof(lam_ham), sizeof(lam_solver), sizeof(lam_stats));
   P(lam_grid, h) P(lam_grid, block) P(lam_grid, interp) P(lam_ham, v0) P(lam_ham, coef)
-  P(lam_ham, t_total) P(lam_solver, n_inner) P(lam_stats, t_solve_ms)
+  P(lam_ham, t_total) P(lam_solver, n_inner) P(lam_solver, time_factor) P(lam_stats, t_solve_ms)
   return 0;
 }
 ''')
@@ -72,6 +72,7 @@ int main(void) {
     assert int(out["lam_ham.coef"]) == lam.LamHam.coef.offset
     assert int(out["lam_ham.t_total"]) == lam.LamHam.t_total.offset
     assert int(out["lam_solver.n_inner"]) == lam.LamSolver.n_inner.offset
+    assert int(out["lam_solver.time_factor"]) == lam.LamSolver.time_factor.offset
     assert int(out["lam_stats.t_solve_ms"]) == lam.LamStats.t_solve_ms.offset
 
 

@@ -1,0 +1,176 @@
+"""Parity at the workloads' full sizes, in the launch configuration bench.py uses.
+
+The oracle cannot assemble these systems, so it checks sampled outputs it can
+compute one by one from the definition: residual rows of sampled points
+(kkt.residual_at_points) and the exact local solves of sampled subvolumes
+(kkt.block_system), plus the converged residual of a full step estimated on
+a sample of points.  Inputs are seeded; the oracle reads back only the rows
+it needs.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import EPS, field_fn, n, note
+from oracle import grid as G
+from oracle import kkt
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+
+NAMES = ["1d_harmonic", "2d_softcoulomb", "3d_laser", "2d_adjoint", "3d_large"]
+
+
+class Rows:
+    """Host view of a few rows of a device array of shape (P, width)."""
+
+    def __init__(self, t, width, idx):
+        import torch
+        idx = np.unique(np.asarray(idx, dtype=np.int64))
+        sel = torch.as_tensor(idx, device=t.device)
+        rows = t.view(-1, width).index_select(0, sel).cpu().numpy()
+        self.map = {int(j): rows[k] if width > 1 else rows[k, 0] for k, j in enumerate(idx)}
+
+    def __getitem__(self, j):
+        return self.map[int(j)]
+
+
+def neighbourhood(grid, pts):
+    out = set()
+    for j in pts:
+        idx = np.unravel_index(int(j), grid.n)
+        out.add(int(j))
+        for a in range(grid.dim):
+            for d in (-1, 1):
+                nb = list(idx)
+                nb[a] += d
+                if 0 <= nb[a] < grid.n[a]:
+                    out.add(int(np.ravel_multi_index(tuple(nb), grid.n)))
+    return sorted(out)
+
+
+def setup(name, precision="fp64"):
+    import torch
+    from paper_1111_4363_amd import lam
+    cfg = W.config(name)
+    v0 = W.potential(cfg)
+    psi0 = W.initial_state(cfg, v0)
+    coef = W.pulse_coefficients(cfg)
+    p = cfg["pulse"]
+    pulse = None
+    if p:
+        pulse = dict(kind=p["kind"], e0=p.get("e0", 0.0), omega=p.get("omega", 0.0), t_total=cfg["t_total"],
+                     coef=list(coef))
+    dev = torch.device("cuda:0")
+    prop = lam.Propagator(cfg["shape"], cfg["h"], torch.as_tensor(v0, device=dev), cfg["n_t"], cfg["dt"],
+                          (cfg["block"],) * cfg["dim"], levels=cfg["levels"], pulse=pulse, precision=precision,
+                          tol=1e-10, max_cycles=60)
+    grid = G.Grid(cfg["shape"], cfg["h"])
+    return cfg, v0, psi0, pulse, prop, grid, dev
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_fullsize_residual_sampled(name):
+    import torch
+    cfg, v0, psi0, pulse, prop, grid, dev = setup(name)
+    note(f"full-size residual {name} {cfg['shape']}")
+    nt, P = cfg["n_t"], grid.npts
+    c, lam_ = W.random_state_device(P, nt, 11, dev)
+    psi_t = torch.as_tensor(psi0, device=dev)
+    t0 = 0.35 * cfg["t_total"]
+    rho, sig, N = prop.residual_action(t0, psi_t, c, lam_)
+    pts = np.random.default_rng(5).choice(P, size=min(P, 400), replace=False)
+    nbh = neighbourhood(grid, pts)
+    cr, lr = Rows(c, nt, nbh), Rows(lam_, 1, nbh)
+    r_ref, s_ref = kkt.residual_at_points(grid, v0, nt, cfg["dt"], t0, field_fn(pulse), cr, lr, psi0, pts)
+    rg, sg = Rows(rho, nt, pts), Rows(sig, 1, pts)
+    r_gpu = np.array([rg[j] for j in pts])
+    s_gpu = np.array([sg[j] for j in pts])
+    # magnitudes: |c| ~ 1, so 1024 eps times the row's absolute term sum (< 4 * (d/(m h^2) + 2 N_t))
+    scale = 4.0 * (grid.dim / grid.h ** 2 + 2 * nt + np.abs(v0).max())
+    assert np.abs(r_gpu - r_ref).max() <= 1024 * EPS * scale
+    assert np.abs(s_gpu - s_ref).max() <= 1024 * EPS * (2 * nt + 2)
+    prop.close()
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_fullsize_sweep_sampled_blocks(name):
+    import torch
+    cfg, v0, psi0, pulse, prop, grid, dev = setup(name)
+    note(f"full-size sweep {name} {cfg['shape']}")
+    nt, P = cfg["n_t"], grid.npts
+    c, lam_ = W.random_state_device(P, nt, 12, dev, scale=0.1)
+    psi_t = torch.as_tensor(psi0, device=dev)
+    t0 = 0.35 * cfg["t_total"]
+    prop.set_state(t0, psi_t, c, lam_)
+    block = (cfg["block"],) * cfg["dim"]
+    nblk = [s // b for s, b in zip(cfg["shape"], block)]
+    rng = np.random.default_rng(6)
+    # sample blocks: corners of the grid plus random ones
+    picks = set([0, int(np.prod(nblk)) - 1])
+    while len(picks) < 10:
+        picks.add(int(rng.integers(np.prod(nblk))))
+    idx_all = np.arange(P).reshape(cfg["shape"])
+    samples = []
+    for bid in sorted(picks):
+        bc = np.unravel_index(bid, nblk)
+        sl = tuple(slice(k * b, (k + 1) * b) for k, b in zip(bc, block))
+        samples.append((int(sum(bc)) % 2, idx_all[sl].ravel()))
+    allpts = np.concatenate([p for _, p in samples])
+    nbh = neighbourhood(grid, allpts)
+    c_old, l_old = Rows(c, nt, nbh), Rows(lam_, 1, nbh)
+    prop.relax_sweep(0)
+    c_new_t, l_new_t = prop.get_state()
+    c_new, l_new = Rows(c_new_t, nt, allpts), Rows(l_new_t, 1, allpts)
+    field = field_fn(pulse)
+    for colour, pts in samples:
+        x_old = np.concatenate([np.array([c_old[j] for j in pts]).ravel(), np.array([l_old[j] for j in pts])])
+        x_new = np.concatenate([np.array([c_new[j] for j in pts]).ravel(), np.array([l_new[j] for j in pts])])
+        if colour == 1:
+            assert np.array_equal(x_new, x_old)
+            continue
+        r, s = kkt.residual_at_points(grid, v0, nt, cfg["dt"], t0, field, c_old, l_old, psi0, pts)
+        Kbb = kkt.block_system(grid, v0, nt, cfg["dt"], t0, field, pts)
+        delta = np.linalg.solve(Kbb, np.concatenate([r.ravel(), s]))
+        err = np.abs((x_new - x_old) - delta).max()
+        assert err <= 1e-11 * np.abs(delta).max() + 64 * EPS * np.abs(x_old).max(), (name, err)
+    prop.close()
+
+
+@pytest.mark.parametrize("name,precision", [("2d_softcoulomb", "fp64"), ("2d_softcoulomb", "mixed"),
+                                            ("3d_laser", "mixed"), ("3d_large", "mixed"),
+                                            ("1d_harmonic", "fp64")])
+def test_fullsize_step_converges(name, precision):
+    """One step in the bench configuration: the library's FP64 residual reaches
+    sqrt(N/N0) <= 1e-10, and the oracle's residual on 1000 sampled points of the
+    converged state, relative to its residual at the initial guess on the same
+    points, is below 1e-8 (the sample cannot exceed the global ratio by more
+    than sqrt(P / sample) ~ 500 for the largest grid)."""
+    import torch
+    cfg, v0, psi0, pulse, prop, grid, dev = setup(name, precision)
+    note(f"full-size step {name} {precision} {cfg['shape']}")
+    nt, P = cfg["n_t"], grid.npts
+    t0 = 0.5 * cfg["t_total"]
+    psi_out, st = prop.solve_step(t0, torch.as_tensor(psi0, device=dev))
+    note(f"cycles={st['cycles']} ratio={st['resid'] / st['resid0']:.2e} ms={st['t_solve_ms']:.1f}")
+    assert st["resid"] <= 1e-10 * st["resid0"]
+    c_t, l_t = prop.get_state()
+    pts = np.random.default_rng(7).choice(P, size=min(P, 1000), replace=False)
+    nbh = neighbourhood(grid, pts)
+    cr, lr = Rows(c_t, nt, nbh), Rows(l_t, 1, nbh)
+    field = field_fn(pulse)
+    r, s = kkt.residual_at_points(grid, v0, nt, cfg["dt"], t0, field, cr, lr, psi0, pts)
+    # residual of the initial guess on the same points: c_j0 = psi0_j, other coefficients and lambda zero
+    class Init:
+        def __getitem__(self, j):
+            v = np.zeros(nt, complex)
+            v[0] = psi0[int(j)]
+            return v
+    class Zero:
+        def __getitem__(self, j):
+            return 0.0
+    r0, s0 = kkt.residual_at_points(grid, v0, nt, cfg["dt"], t0, field, Init(), Zero(), psi0, pts)
+    U = np.array([cfg["dt"] / (2 * m + 1) for m in range(nt)])
+    N = np.sum(U * np.abs(r) ** 2) + np.sum(np.abs(s) ** 2)
+    N0 = np.sum(U * np.abs(r0) ** 2) + np.sum(np.abs(s0) ** 2)
+    assert N0 > 0 and np.sqrt(N / N0) <= 1e-8
+    prop.close()

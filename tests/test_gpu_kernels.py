@@ -1,7 +1,8 @@
 """GPU parity of the individual kernels against the oracle (through the C ABI).
 
-Residual: elementwise within 64 eps (|K||x| + |b|), the rounding bound of a
-row sum of at most (2d + 2 n_t + 2) terms with FP64 products.
+Residual: elementwise within 1024 eps (|K||x| + |b|): the rounding of a row sum
+of at most (2d + 2 n_t + 2) FP64 products on the HIP side plus the rounding the
+oracle's quadrature-evaluated Q carries (gpu_util.rounding_bound).
 Block factor: V orthogonal and V diag(e) V^T = T_U + diag(V0_U) within
 1e-13 of ||A||_F (Jacobi converged to an off-diagonal Frobenius ratio 1e-15).
 Transfers: averages and interpolation weights are exact binary fractions, so
@@ -83,7 +84,7 @@ def test_block_factor_parity(cfg):
 
 
 @pytest.mark.parametrize("cfg", [dict(shape=(16, 24), block=(4, 4), levels=2),
-                                 dict(shape=(8, 4, 12), block=(2, 2, 2), levels=3),
+                                 dict(shape=(8, 8, 16), block=(2, 2, 2), levels=3),
                                  dict(shape=(32,), block=(4,), levels=2, periodic=True),
                                  dict(shape=(16, 8), block=(2, 2), levels=2, periodic=True)],
                          ids=lambda c: f"{c['shape']}-L{c['levels']}-p{c.get('periodic', False)}")
@@ -128,7 +129,8 @@ SWEEP_CASES = [
 @pytest.mark.parametrize("cfg", SWEEP_CASES, ids=lambda c: f"{c['shape']}-{c['block']}-nt{c['n_t']}")
 @pytest.mark.parametrize("adjoint", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_sweep_parity(cfg, adjoint, precision):
+@pytest.mark.parametrize("time_factor", ["shared", "stored"])
+def test_sweep_parity(cfg, adjoint, precision, time_factor):
     """One colour, then the other, against the oracle's plain-loop local solves.
 
     FP64: the subvolume solve goes through an orthogonal eigenbasis and a
@@ -137,7 +139,7 @@ def test_sweep_parity(cfg, adjoint, precision):
     1e-11 of its size.  Mixed: the same in FP32, 1e-4 of its size.
     """
     case = Case(**cfg)
-    note(f"sweep adjoint={adjoint} {precision} {case}")
+    note(f"sweep adjoint={adjoint} {precision} {time_factor} {case}")
     t0 = 0.2
     sysm = kkt.StepSystem(case.grid, case.v0, case.n_t, case.dt, t0, case.field)
     K = sysm.K.conj().T.tocsr() if adjoint else sysm.K
@@ -148,7 +150,7 @@ def test_sweep_parity(cfg, adjoint, precision):
     else:
         b = kkt.rhs(sysm, case.psi0)
     x = kkt.join(c, lam)
-    prop = case.prop(precision=precision, n_inner=(6 if case.field is not None else -1))
+    prop = case.prop(precision=precision, n_inner=(6 if case.field is not None else -1), time_factor=time_factor)
     if adjoint:
         prop.set_adjoint_state(t0, t_c(case.psi0), t_c(c), t_c(lam))
     else:

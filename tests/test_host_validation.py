@@ -1,0 +1,61 @@
+"""Host-side argument validation of lam_create (no device call is made before
+validation, so these run without a GPU)."""
+import ctypes
+
+import pytest
+
+from paper_1111_4363_amd import lam
+
+
+def _create(**over):
+    lib = lam.load_library()
+    g = lam.LamGrid()
+    g.dim = over.get("dim", 2)
+    n = over.get("n", (16, 16, 1))
+    blk = over.get("block", (4, 4, 1))
+    for a in range(3):
+        g.n[a] = n[a]
+        g.block[a] = blk[a]
+    g.h = over.get("h", 0.2)
+    g.periodic = over.get("periodic", 0)
+    g.levels = over.get("levels", 2)
+    g.nu_pre, g.nu_post, g.nu_coarse = 1, 1, 2
+    g.interp = over.get("interp", 0)
+    t = lam.LamTime(over.get("n_t", 4), over.get("dt", 0.05))
+    dummy = ctypes.c_double(0.0)
+    h = lam.LamHam()
+    h.mass = over.get("mass", 1.0)
+    h.v0 = over.get("v0", ctypes.cast(ctypes.pointer(dummy), ctypes.c_void_p))
+    h.field_axis = over.get("field_axis", 1)
+    h.pulse_kind = over.get("pulse_kind", 0)
+    h.t_total = over.get("t_total", 1.0)
+    h.n_coef = over.get("n_coef", 0)
+    s = lam.LamSolver(over.get("precision", 0), over.get("tol", 1e-10), over.get("max_cycles", 10),
+                      over.get("n_inner", -1), over.get("time_factor", 0))
+    out = ctypes.c_void_p()
+    return lib.lam_create(ctypes.byref(g), ctypes.byref(t), ctypes.byref(h), ctypes.byref(s), None,
+                          ctypes.byref(out))
+
+
+@pytest.mark.parametrize("over", [
+    dict(dim=0), dict(dim=4), dict(n=(0, 16, 1)), dict(n=(16, 0, 1)),
+    dict(block=(3, 4, 1)),                      # block does not divide n
+    dict(levels=4, block=(4, 4, 1)),            # 16 -> 2 at level 3: block 4 no longer divides
+    dict(levels=0), dict(n_t=0), dict(n_t=9), dict(h=0.0), dict(h=-1.0), dict(dt=0.0), dict(mass=0.0),
+    dict(block=(16, 8, 1)),                     # 128 points > LAM_MAX_BLOCK
+    dict(n=(20, 16, 1), block=(4, 4, 1), periodic=1, levels=1),   # 5 blocks: odd count on a periodic axis
+    dict(n=(18, 16, 1), block=(3, 4, 1), levels=3),              # 18 -> 9 -> odd axis cannot coarsen again
+    dict(field_axis=2), dict(pulse_kind=7), dict(pulse_kind=1, t_total=0.0), dict(n_coef=3),
+    dict(precision=2), dict(tol=-1.0), dict(n_inner=-2), dict(interp=3), dict(v0=None), dict(time_factor=2),
+])
+def test_invalid_arguments_are_rejected(over):
+    assert _create(**over) == lam.LAM_EINVAL
+
+
+def test_null_output_pointer():
+    lib = lam.load_library()
+    assert lib.lam_create(None, None, None, None, None, None) == lam.LAM_EINVAL
+
+
+def test_destroy_accepts_null():
+    assert lam.load_library().lam_destroy(None) == lam.LAM_OK

@@ -110,3 +110,22 @@ def test_coarse_operator_is_rediscretisation():
     gc = H[1].grid
     assert gc.n == (4, 4) and abs(gc.h - 0.4) < 1e-15
     np.testing.assert_allclose(H[1].v0, G.restriction(g) @ v0, atol=1e-15)
+
+
+def test_coarsest_level_sweeps_reduce_residual_by_a_thousand():
+    """Reading of the coarsest solve: nu_coarse = 2 colour sweeps on the 2D workload's
+    coarsest level (512^2 coarsened four times: 32^2, h = 3.2, kappa = dt/(2h^2) ~ 0.0024)
+    reduce a random right-hand side's residual norm by at least 1e3, the reduction the
+    direct coarse solve would be replaced by."""
+    g = G.Grid((32, 32), 3.2)
+    r2 = sum(c ** 2 for c in g.coords()).ravel()
+    v0 = -1.0 / np.sqrt(r2 + 1.0)
+    sysm = kkt.StepSystem(g, v0, 8, 0.05)
+    rng = np.random.default_rng(2)
+    b = rng.normal(size=sysm.size) + 1j * rng.normal(size=sysm.size)
+    x = np.zeros_like(b)
+    bl = G.blocks(g, (8, 8))
+    N0 = kkt.residual_norm(sysm, b - sysm.K @ x)
+    for _ in range(2):
+        x = relax.reference_sweep(sysm.K, b, x, bl, g.npts, 8)
+    assert kkt.residual_norm(sysm, b - sysm.K @ x) <= 1e-6 * N0

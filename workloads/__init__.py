@@ -139,3 +139,17 @@ def random_complex(n, seed, scale=1.0):
 
 def random_real(n, seed, scale=1.0):
     return scale * np.random.default_rng(seed).normal(size=n)
+
+
+def random_state_device(npts, n_t, seed, device, scale=1.0):
+    """Seeded random (c, lambda) generated on the device (torch Philox stream).
+
+    For full-size workloads where a host copy would be large; tests read back
+    only the entries they sample.
+    """
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    c = torch.randn(npts * n_t, dtype=torch.complex128, device=device, generator=gen) * scale
+    lam = torch.randn(npts, dtype=torch.complex128, device=device, generator=gen) * scale
+    return c, lam
