@@ -276,7 +276,7 @@ struct lam_ctx {
     double2* d_G = nullptr;
     double2* h_G = nullptr;       // pinned
     double2* d_cf = nullptr;      // forward coefficients kept for the gradients
-    double2* d_tf = nullptr;      // shared time factor B, Z, T (FP64)
+    double2* d_tf = nullptr;      // shared time factor (T, B, Z: complex (n_t+1)^2 each), FP64
     float2* d_tff = nullptr;      // and its FP32 copy
     // profiling of finest-level sweeps
     bool prof = false;
@@ -392,6 +392,7 @@ int sweep(lam_ctx* c, int l, int colour) {
     a.shift = L.d_shift;
     a.adjoint = c->adjoint;
     a.n_inner = c->n_inner;
+    a.field_on = c->field_on ? 1 : 0;
     const bool rec = c->prof && l == 0;
     if (rec) {
         while ((int)c->ev.size() < c->nev + 2) {
@@ -518,6 +519,7 @@ int validate(const lam_grid* g, const lam_time* t, const lam_ham* h, const lam_s
             if (n % g->block[a]) return LAM_EINVAL;
             const long nb = n / g->block[a];
             if (g->periodic && nb > 1 && (nb & 1)) return LAM_EINVAL;
+            if (g->periodic && n < 2) return LAM_EINVAL;
             if (l + 1 < g->levels) {
                 if (n & 1) return LAM_EINVAL;
                 n /= 2;
@@ -658,21 +660,22 @@ int build(lam_ctx* c, const double* v0_dev) {
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
         return LAM_ENOMEM;
     {
+        // shared time factor: T, B, Z (complex n x n, row-major), as interleaved reals
         const int n = nt + 1;
         std::vector<cd> B(n * n), Z(n * n), T(n * n);
         if (!time_factor(nt, c->U, B.data(), Z.data(), T.data())) return LAM_EINVAL;
-        std::vector<double2> h(3 * n * n);
-        std::vector<float2> hf(3 * n * n);
-        const cd* parts[3] = {B.data(), Z.data(), T.data()};
-        for (int p = 0; p < 3; ++p)
-            for (int k = 0; k < n * n; ++k) {
-                h[p * n * n + k] = make_double2(parts[p][k].real(), parts[p][k].imag());
-                hf[p * n * n + k] = make_float2((float)parts[p][k].real(), (float)parts[p][k].imag());
+        std::vector<double> h;
+        h.reserve(6 * n * n);
+        for (const auto* M : {&T, &B, &Z})
+            for (const cd& v : *M) {
+                h.push_back(v.real());
+                h.push_back(v.imag());
             }
-        LAMCHK(dalloc(&c->d_tf, h.size()));
-        LAMCHK(dalloc(&c->d_tff, hf.size()));
-        HIPCHK(hipMemcpy(c->d_tf, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(c->d_tff, hf.data(), sizeof(float2) * hf.size(), hipMemcpyHostToDevice));
+        std::vector<float> hf(h.begin(), h.end());
+        LAMCHK(dalloc(&c->d_tf, h.size() / 2));
+        LAMCHK(dalloc(&c->d_tff, hf.size() / 2));
+        HIPCHK(hipMemcpy(c->d_tf, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->d_tff, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice));
     }
     c->Ebar = 0.0;
     for (auto& L : c->lv) LAMCHK(factor_level(c, L));

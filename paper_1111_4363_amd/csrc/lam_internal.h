@@ -12,6 +12,7 @@ namespace lam {
 constexpr int kMaxNT = LAM_MAX_NT;
 constexpr int kMaxB = LAM_MAX_BLOCK;
 constexpr int kThreads = 256;
+constexpr int kSweepThreads = 512;   // the colour sweep: 8 waves per block
 constexpr int kLdsPad = kMaxB + 1;   // row stride of per-block matrices in LDS
 
 // Geometry of one level, passed by value to kernels.
@@ -46,11 +47,12 @@ struct SweepArgs {
     const double2* bs;        // constraint right-hand side [P], may be null (= 0)
     const void* V;            // [nblocks][bpts][bpts] eigenvectors (double or float)
     const void* Minv;         // [nblocks][NT+1][NT+1][bpts] mode inverses (double2 or float2), or null:
-    const void* tf;           // shared time factor B, Z, T ((NT+1)^2 complex each, row-major)
+    const void* tf;           // shared time factor: T, B, Z ((NT+1)^2 complex each, row-major)
     const double* e;          // [nblocks][bpts] eigenvalues of the block operators
     const double* shift;      // [nblocks] frozen-field eigenvalue shift
     int adjoint;
     int n_inner;
+    int field_on;             // W (the field's time matrix) is nonzero this step
 };
 
 // ---- launchers (lam_kernels.hip) -------------------------------------------

@@ -41,6 +41,80 @@ __device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
     return {(a.r * b.r + a.i * b.i) / den, (a.i * b.r - a.r * b.i) / den};
 }
 
+// ---------------------------------------------------------------------------
+// 16x16x4 matrix-core tiles (one wave).  Operand layout (checked on gfx950):
+// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k; the 16x16 result has
+// column j = lane % 16 and, per result slot r, row
+//   FP64: i = lane/16 + 4r          FP32: i = 4(lane/16) + r.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef v4d acc_t;
+    static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+    typedef v4f acc_t;
+    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// One 16 x 16 output tile per wave of out[m][c] = sum_p Op(m, p) in[p][c]
+// (m, p < b, c < ncol <= 32), with Op(m, p) = Vs[p][m] (TRANS: into the block
+// eigenbasis) or Vs[m][p] (back to points).  Wave w owns rows 16 (w % 4) ..
+// and columns 16 (w / 4) ..; every operand load is unconditional (clamped
+// address times a 0/1 factor) so successive K steps stay in flight.
+template <typename T, bool TRANS>
+__device__ __forceinline__ typename Mfma<T>::acc_t tile_gemm(const T* __restrict__ Vs, const T* __restrict__ in,
+                                                             int b, int ncol, int lane, int wave) {
+    typename Mfma<T>::acc_t acc;
+    for (int r = 0; r < 4; ++r) acc[r] = (T)0;
+    const int mt = wave & 3, nt = wave >> 2;
+    if (16 * mt >= b || 16 * nt >= ncol) return acc;
+    const int i = lane & 15, kq = lane >> 4;
+    const int m = 16 * mt + i, col = 16 * nt + i;
+    const T fm = m < b ? (T)1 : (T)0, fc = col < ncol ? (T)1 : (T)0;
+    const int mc = m < b ? m : b - 1, cc = col < ncol ? col : ncol - 1;
+    // K in groups of 16 (four MFMA steps): the group's loads are issued together
+    for (int kb = 0; kb < kMaxB; kb += 16) {
+        if (kb >= b) break;
+        T av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = kb + 4 * u + kq;
+            const T fp = p < b ? (T)1 : (T)0;
+            const int pc = p < b ? p : b - 1;
+            av[u] = (TRANS ? Vs[pc * kLdsPad + mc] : Vs[mc * kLdsPad + pc]) * (fm * fp);
+            bv[u] = in[pc * ncol + cc] * fc;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = Mfma<T>::step(av[u], bv[u], acc);
+    }
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_store(T* __restrict__ out, int b, int ncol, int lane, int wave,
+                                           const typename Mfma<T>::acc_t& acc) {
+    const int mt = wave & 3, nt = wave >> 2;
+    if (16 * mt >= b || 16 * nt >= ncol) return;
+    for (int r = 0; r < 4; ++r) {
+        const int m = 16 * mt + Mfma<T>::row(lane, r);
+        const int col = 16 * nt + (lane & 15);
+        if (m < b && col < ncol) out[m * ncol + col] = acc[r];
+    }
+}
+
 __device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 sub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 scl2(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
@@ -601,23 +675,148 @@ __global__ __launch_bounds__(64) void k_mode_factor(int b, TimeOps<NT> to, const
 }
 
 // ---------------------------------------------------------------------------
-// K3: relax every block of one colour.  One workgroup per block:
-//   1. issue every global load of the block at once (own coefficients, the
-//      halo neighbours outside the block, right-hand side, lambda, V0,
-//      eigenvectors, eigenvalues) with clamped addresses and 0/1 weights, so
-//      that a single memory latency covers the whole block;
+// K3: relax every block of one colour.  One workgroup (4 waves) per block:
+//   1. issue every global load of the block (own coefficients, halo
+//      neighbours outside the block, right-hand side, lambda, V0,
+//      eigenvectors, eigenvalues, the shared time factor) before consuming
+//      any of them, so one memory latency covers the block;
 //   2. local residual r_U = (b - K x)_U from LDS and registers (FP64);
-//   3. delta = V (M(e_k)^{-1} (V^T r)) per mode k    [K_UU^{-1} r in factored form];
+//   3. delta = V (M(e_k)^{-1} (V^T r)) per mode k   [K_UU^{-1} r in factored form]
+//      (a) V^T r and (c) V d on the matrix cores, (b) the per-mode time solve;
 //   4. (field steps) corrections r <- r - K_UU delta, repeat 3, until the
 //      block's residual fell by 1e-13 (FP64) / 1e-6 (FP32), at most n_inner;
 //   5. write c_U += delta_c, lambda_U += delta_lambda.
 // BT is the precision of the factors and of step 3 (double, or float for the
 // mixed path); the state and the residual of step 2 are always FP64.
 // ---------------------------------------------------------------------------
-template <int NT, typename BT>
-__global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to) {
+
+// In-block neighbour of local point lc along axis ax, direction d, or -1.  A
+// block that spans a periodic axis is its own neighbour across the wrap.
+__device__ __forceinline__ int local_nb(const LevelGeom& g, const I3& lc, int ax, int d) {
+    const int bd = g.bdim[ax];
+    int la = comp(lc, ax) + d;
+    if (la < 0 || la >= bd) {
+        if (!(g.periodic && g.nblk[ax] == 1)) return -1;
+        la = (la + bd) % bd;
+    }
+    return local_index(g, with_comp(lc, ax, la));
+}
+
+// Global halo neighbour (outside the block) of global point gi, or -1.
+__device__ __forceinline__ int halo_nb(const LevelGeom& g, const I3& gi, const I3& lc, int ax, int d) {
+    const int la = comp(lc, ax) + d;
+    if (la >= 0 && la < g.bdim[ax]) return -1;            // inside the block
+    if (g.periodic && g.nblk[ax] == 1) return -1;         // wraps onto this block
+    const int na = g.n[ax];
+    int ga = comp(gi, ax) + d;
+    if (ga < 0 || ga >= na) {
+        if (!g.periodic) return -1;
+        ga = (ga + na) % na;
+    }
+    return point_index(g, with_comp(gi, ax, ga));
+}
+
+// Broadcast within groups of eight lanes: every lane receives the value of
+// lane R of its group (ds_swizzle, bit mode: and-mask 0x18, or-mask R).
+template <int R>
+__device__ __forceinline__ float bcast8(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x18 | (R << 5)));
+}
+template <int R>
+__device__ __forceinline__ double bcast8(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(u & 0xffffffffLL), 0x18 | (R << 5));
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(u >> 32), 0x18 | (R << 5));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Per-mode time solve with the shared factor, for all modes of a block at once.
+// y_k = Z (I - e_k T)^{-1} B r_k (adjoint: B^H (I - e_k T)^{-H} Z^H r_k), with T
+// upper triangular; r_k = rh[k][.] is replaced by y_k.  Eight lanes per mode
+// (512 threads: 64 modes): lane r owns rows r and r + 8.  The lanes first form
+// x = B r_k (Z^H r_k) for their rows, then substitute through (I - e T) one
+// unknown at a time, broadcasting each solved unknown inside the 8-lane group
+// and folding it straight into the final product with Z (B^H).  The group is
+// one wave's slice, so no barrier is needed: rh[k] is read and written only by
+// the lanes of mode k, reads first.
+template <int NQ, typename T, bool adjoint>
+__device__ __forceinline__ void mode_solve(const cx<T>* __restrict__ tfc, const T* __restrict__ es,
+                                           cx<T>* __restrict__ rh, int b, int tid) {
+    using C = cx<T>;
+    constexpr int NS = (NQ + 7) / 8;
+    const C* Tm = tfc;
+    const C* Bm = tfc + NQ * NQ;
+    const C* Zm = Bm + NQ * NQ;
+    const int k = tid >> 3, r = tid & 7;
+    const int kc = k < b ? k : b - 1;
+    const T ev = es[kc];
+    C rk[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) rk[q] = rh[kc * NQ + q];
+    C acc[NS], out[NS], inv[NS];
+    int pc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int p = r + 8 * s;
+        pc[s] = p < NQ ? p : NQ - 1;
+        C x = C{(T)0, (T)0};
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (!adjoint) x = x + cmul(Bm[pc[s] * NQ + q], rk[q]);
+            else x = x + cmulc(Zm[q * NQ + pc[s]], rk[q]);
+        }
+        acc[s] = x;
+        const C tpp = Tm[pc[s] * NQ + pc[s]];
+        inv[s] = cdiv(C{(T)1, (T)0}, C{(T)1 - ev * tpp.r, (adjoint ? ev : -ev) * tpp.i});
+        out[s] = C{(T)0, (T)0};
+    }
+#pragma unroll
+    for (int jj = 0; jj < NQ; ++jj) {
+        // forward: back substitution (j = NQ-1 .. 0); adjoint: forward substitution
+        const int j = adjoint ? jj : NQ - 1 - jj;
+        C y = (j < 8) ? cmul(acc[0], inv[0]) : cmul(acc[NS - 1], inv[NS - 1]);
+        switch (j & 7) {
+            case 0: y = C{bcast8<0>(y.r), bcast8<0>(y.i)}; break;
+            case 1: y = C{bcast8<1>(y.r), bcast8<1>(y.i)}; break;
+            case 2: y = C{bcast8<2>(y.r), bcast8<2>(y.i)}; break;
+            case 3: y = C{bcast8<3>(y.r), bcast8<3>(y.i)}; break;
+            case 4: y = C{bcast8<4>(y.r), bcast8<4>(y.i)}; break;
+            case 5: y = C{bcast8<5>(y.r), bcast8<5>(y.i)}; break;
+            case 6: y = C{bcast8<6>(y.r), bcast8<6>(y.i)}; break;
+            default: y = C{bcast8<7>(y.r), bcast8<7>(y.i)}; break;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int p = r + 8 * s;
+            // couple the unknowns still to be solved: rows above j (forward) / below j (adjoint)
+            const bool open = adjoint ? (p > j && p < NQ) : (p < j);
+            const T f = open ? ev : (T)0;
+            const C tc = adjoint ? C{Tm[j * NQ + pc[s]].r, -Tm[j * NQ + pc[s]].i} : Tm[pc[s] * NQ + j];
+            acc[s] = acc[s] + rmul(f, cmul(tc, y));
+            const C e3 = adjoint ? C{Bm[j * NQ + pc[s]].r, -Bm[j * NQ + pc[s]].i} : Zm[pc[s] * NQ + j];
+            out[s] = out[s] + cmul(e3, y);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int p = r + 8 * s;
+        if (k < b && p < NQ) rh[k * NQ + p] = out[s];
+    }
+}
+
+// Waves per SIMD the sweep is compiled for: the FP32 shared-factor variant fits
+// 128 registers, so two workgroups share a compute unit; the others take 256.
+template <typename BT, bool STORED>
+constexpr int sweep_waves_per_simd() { return (sizeof(BT) == 4 && !STORED) ? 4 : 2; }
+
+template <int NT, typename BT, bool STORED>
+__global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())) void k_sweep(SweepArgs a, TimeOps<NT> to) {
     constexpr int NQ = NT + 1;
-    constexpr int IPT = (kMaxB * NT + kThreads - 1) / kThreads;  // residual items per thread
+    constexpr int N2 = 2 * NQ;                               // reals per point / mode
+    constexpr int IPT = (kMaxB * NT + kSweepThreads - 1) / kSweepThreads;  // residual items per thread
+    constexpr int VPT = kMaxB * kMaxB / kSweepThreads;       // eigenvector entries per thread
+    constexpr int TFR = 6 * NQ * NQ;                         // reals of T, B, Z (complex NQ x NQ each)
+    constexpr int TPT = (TFR + kSweepThreads - 1) / kSweepThreads;
     using C = cx<BT>;
     __shared__ BT Vs[kMaxB * kLdsPad];
     __shared__ double2 cs[kMaxB * NT];
@@ -627,100 +826,133 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
     __shared__ int gidx[kMaxB];
     __shared__ C rs[kMaxB * NQ];   // local residual
     __shared__ C rh[kMaxB * NQ];   // V^T r, per-mode solutions, then the correction
-    __shared__ C tfs[3 * NQ * NQ];
+    __shared__ BT tfs[TFR];        // shared time factor: T, B, Z (complex NQ x NQ, row-major)
     __shared__ BT es[kMaxB];
-    __shared__ double red[kThreads / 64];
+    __shared__ double red[kSweepThreads / 64];
     __shared__ double rnorm_sh;
 
     const LevelGeom& g = a.g;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int blk = a.blocks[blockIdx.x];
     const int b = g.bpts;
     const int nd = 2 * g.dim;
+    constexpr bool shared_tf = !STORED;
     // inner passes stop once the block's own residual fell below this fraction (in norm)
     const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-12;
     const I3 bc = block_coords(g, blk);
 
-    // ---- 1. loads ----
-    double2 own[IPT], halo[IPT], rhsv[IPT];
+    // ---- 1a. addresses (no loads yet) ----
+    int gjv[IPT], mv[IPT], hidx[IPT][6], hmask[IPT];
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
-        const int t = tid + it * kThreads;
-        own[it] = halo[it] = rhsv[it] = make_double2(0.0, 0.0);
-        if (t < b * NT) {
-            const int l = t / NT, m = t - l * NT;
-            const I3 lc = local_coords(g, l);
-            const int gj = point_index(g, global_of_local(g, bc, lc));
-            int hidx[6];
-            double hw[6];
+        const int t0 = tid + it * kSweepThreads;
+        const int t = t0 < b * NT ? t0 : 0;
+        const int l = t / NT;
+        mv[it] = t - l * NT;
+        const I3 lc = local_coords(g, l);
+        const I3 gi = global_of_local(g, bc, lc);
+        gjv[it] = point_index(g, gi);
+        hmask[it] = 0;
 #pragma unroll
-            for (int dir = 0; dir < 6; ++dir) {
-                hidx[dir] = gj;
-                hw[dir] = 0.0;
-                if (dir < nd) {
-                    int glob;
-                    const int ln = block_neighbour(g, bc, lc, dir >> 1, (dir & 1) ? 1 : -1, &glob);
-                    if (ln < 0 && glob >= 0) {
-                        hidx[dir] = glob;
-                        hw[dir] = 1.0;
-                    }
+        for (int dir = 0; dir < 6; ++dir) {
+            hidx[it][dir] = gjv[it];
+            if (dir < nd) {
+                const int h = halo_nb(g, gi, lc, dir >> 1, (dir & 1) ? 1 : -1);
+                if (h >= 0) {
+                    hidx[it][dir] = h;
+                    hmask[it] |= 1 << dir;
                 }
             }
-            own[it] = a.c[(size_t)gj * NT + m];
-            double2 hv[6];
-#pragma unroll
-            for (int dir = 0; dir < 6; ++dir) hv[dir] = a.c[(size_t)hidx[dir] * NT + m];
-            if (a.bc)
-                rhsv[it] = a.bc[(size_t)gj * NT + m];
-            else if (a.bg)
-                rhsv[it] = a.bg[gj];
-            double2 hs = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int dir = 0; dir < 6; ++dir) hs = add2(hs, scl2(hw[dir], hv[dir]));
-            halo[it] = hs;
         }
     }
-    double2 sgv = make_double2(0.0, 0.0);
-    if (tid < b) {
-        const I3 i = global_of_local(g, bc, local_coords(g, tid));
-        const int gj = point_index(g, i);
-        gidx[tid] = gj;
-        v0s[tid] = a.v0[gj];
-        ls[tid] = a.lam[gj];
-        zs[tid] = zcoord(g, i);
-        if (a.bs) sgv = a.bs[gj];
-    }
-    {
-        const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
-        for (int t = tid; t < b * b; t += kThreads) {
-            const int j = t / b, k = t - j * b;
-            Vs[j * kLdsPad + k] = Vg[t];
-        }
-    }
-    if (!a.Minv) {
-        const C* tfg = static_cast<const C*>(a.tf);
-        for (int t = tid; t < 3 * NQ * NQ; t += kThreads) tfs[t] = tfg[t];
-        const double sh = a.shift[blk];
-        for (int k = tid; k < b; k += kThreads) es[k] = (BT)(a.e[(size_t)blk * b + k] + sh);
-    }
+    const int tp = tid < b ? tid : 0;
+    const I3 gip = global_of_local(g, bc, local_coords(g, tp));
+    const int gjp = point_index(g, gip);
+
+    // ---- 1b. loads, all in flight together ----
+    double2 own[IPT], rhsv[IPT], hv[IPT][6];
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
-        const int t = tid + it * kThreads;
+        own[it] = a.c[(size_t)gjv[it] * NT + mv[it]];
+#pragma unroll
+        for (int dir = 0; dir < 6; ++dir) hv[it][dir] = a.c[(size_t)hidx[it][dir] * NT + mv[it]];
+        rhsv[it] = a.bc ? a.bc[(size_t)gjv[it] * NT + mv[it]]
+                        : (a.bg ? a.bg[gjv[it]] : make_double2(0.0, 0.0));
+    }
+    const double v0p = a.v0[gjp];
+    const double2 lp = a.lam[gjp];
+    const double2 sgv = a.bs ? a.bs[gjp] : make_double2(0.0, 0.0);
+    BT vr[VPT];
+    {
+        const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
+        const int bb = b * b;
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) {
+            const int t = tid + r * kSweepThreads;
+            vr[r] = Vg[t < bb ? t : bb - 1];
+        }
+    }
+    BT tr[TPT];
+    BT ep = (BT)0;
+    if constexpr (shared_tf) {
+        const BT* tfg = static_cast<const BT*>(a.tf);
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) {
+            const int t = tid + r * kSweepThreads;
+            tr[r] = tfg[t < TFR ? t : TFR - 1];
+        }
+        ep = (BT)(a.e[(size_t)blk * b + tp] + a.shift[blk]);
+    }
+
+    // ---- 1c. consume into LDS ----
+    double2 halo[IPT];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        double2 hs = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int dir = 0; dir < 6; ++dir) hs = add2(hs, scl2((hmask[it] >> dir) & 1 ? 1.0 : 0.0, hv[it][dir]));
+        halo[it] = hs;
+        const int t = tid + it * kSweepThreads;
         if (t < b * NT) cs[t] = own[it];
+    }
+    if (tid < b) {
+        gidx[tid] = gjp;
+        v0s[tid] = v0p;
+        ls[tid] = lp;
+        zs[tid] = zcoord(g, gip);
+        es[tid] = ep;
+    }
+    {
+        const int bb = b * b;
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) {
+            const int t = tid + r * kSweepThreads;
+            if (t < bb) {
+                const int j = t / b, k = t - j * b;
+                Vs[j * kLdsPad + k] = vr[r];
+            }
+        }
+    }
+    if constexpr (shared_tf) {
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) {
+            const int t = tid + r * kSweepThreads;
+            if (t < TFR) tfs[t] = tr[r];
+        }
     }
     __syncthreads();
 
     // ---- 2. local residual (FP64) ----
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
-        const int t = tid + it * kThreads;
+        const int t = tid + it * kSweepThreads;
         if (t < b * NT) {
             const int l = t / NT, m = t - l * NT;
             const I3 lc = local_coords(g, l);
             double2 lap = add2(scl2(-2.0 * g.dim, own[it]), halo[it]);
             for (int dir = 0; dir < nd; ++dir) {
-                int glob;
-                const int ln = block_neighbour(g, bc, lc, dir >> 1, (dir & 1) ? 1 : -1, &glob);
+                const int ln = local_nb(g, lc, dir >> 1, (dir & 1) ? 1 : -1);
                 if (ln >= 0) lap = add2(lap, cs[ln * NT + m]);
             }
             const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], own[it]));
@@ -732,8 +964,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
             }
             const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
             double2 wc = make_double2(0.0, 0.0);
+            if (a.field_on) {
 #pragma unroll
-            for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cs[l * NT + n]));
+                for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cs[l * NT + n]));
+            }
             const double sm = (m & 1) ? -1.0 : 1.0;
             double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(zs[l], wc));
             row = add2(row, scl2(sm, ls[l]));
@@ -750,7 +984,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
     double r0n = 0.0;
     if (a.n_inner > 0) {
         double loc = 0.0;
-        for (int t = tid; t < b * NQ; t += kThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
+        for (int t = tid; t < b * NQ; t += kSweepThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
         const double tot = block_sum(loc, red);
         if (tid == 0) rnorm_sh = tot;
         __syncthreads();
@@ -760,35 +994,19 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
 
     const C* Mi = static_cast<const C*>(a.Minv);
     for (int pass = 0; pass <= a.n_inner; ++pass) {
-        // ---- 3a. rh[k][q] = sum_j V[j][k] rs[j][q] ----
+        // ---- 3a. rh[k][.] = sum_j V[j][k] rs[j][.]  (matrix cores) ----
         {
-            const int k = tid & 63, qg = tid >> 6;
-            if (k < b) {
-                C acc[3];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) acc[r] = C{0, 0};
-                for (int j = 0; j < b; ++j) {
-                    const BT v = Vs[j * kLdsPad + k];
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) {
-                        const int q = qg + 4 * r;
-                        if (q < NQ) acc[r] = acc[r] + rmul(v, rs[j * NQ + q]);
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int q = qg + 4 * r;
-                    if (q < NQ) rh[k * NQ + q] = acc[r];
-                }
-            }
+            const auto acc = tile_gemm<BT, true>(Vs, reinterpret_cast<const BT*>(rs), b, N2, lane, wave);
+            tile_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
         }
         __syncthreads();
         // ---- 3b. per-mode time solve ----
-        if (a.Minv) {
-            // stored inverses M(e_k)^{-1}
+        if constexpr (STORED) {
+            // stored inverses M(e_k)^{-1}; waves 0..3, thread (k, pg) computes rows pg, pg+4, pg+8
             const int k = tid & 63, pg = tid >> 6;
+            const bool act = pg < 4;
             C out[3];
-            if (k < b) {
+            if (act && k < b) {
                 C rv[NQ];
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) rv[q] = rh[k * NQ + q];
@@ -812,7 +1030,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
                 }
             }
             __syncthreads();
-            if (k < b) {
+            if (act && k < b) {
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const int p = pg + 4 * r;
@@ -821,111 +1039,20 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
             }
         } else {
             // shared factor: M(e)^{-1} = Z (I - e T)^{-1} B   (adjoint: B^H (I - e T)^{-H} Z^H)
-            const C* Bm = tfs;
-            const C* Zm = tfs + NQ * NQ;
-            const C* Tm = tfs + 2 * NQ * NQ;
-            const int k = tid & 63, pg = tid >> 6;
-            C out[3];
-            if (k < b) {
-                C rv[NQ];
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) rv[q] = rh[k * NQ + q];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int p = pg + 4 * r;
-                    C acc = C{0, 0};
-                    if (p < NQ) {
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q)
-                            acc = acc + (a.adjoint ? cmulc(Zm[q * NQ + p], rv[q]) : cmul(Bm[p * NQ + q], rv[q]));
-                    }
-                    out[r] = acc;
-                }
-            }
-            __syncthreads();
-            if (k < b) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int p = pg + 4 * r;
-                    if (p < NQ) rh[k * NQ + p] = out[r];
-                }
-            }
-            __syncthreads();
-            if (pg == 0 && k < b) {
-                const BT ev = es[k];
-                C* y = rh + k * NQ;
-                if (!a.adjoint) {
-                    for (int p = NQ - 1; p >= 0; --p) {
-                        C acc = y[p];
-                        for (int q = p + 1; q < NQ; ++q) acc = acc + rmul(ev, cmul(Tm[p * NQ + q], y[q]));
-                        const C tp = Tm[p * NQ + p];
-                        y[p] = cdiv(acc, C{(BT)1 - ev * tp.r, -ev * tp.i});
-                    }
-                } else {
-                    for (int p = 0; p < NQ; ++p) {
-                        C acc = y[p];
-                        for (int q = 0; q < p; ++q) acc = acc + rmul(ev, cmulc(Tm[q * NQ + p], y[q]));
-                        const C tp = Tm[p * NQ + p];
-                        y[p] = cdiv(acc, C{(BT)1 - ev * tp.r, ev * tp.i});
-                    }
-                }
-            }
-            __syncthreads();
-            if (k < b) {
-                C rv[NQ];
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) rv[q] = rh[k * NQ + q];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int p = pg + 4 * r;
-                    C acc = C{0, 0};
-                    if (p < NQ) {
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q)
-                            acc = acc + (a.adjoint ? cmulc(Bm[q * NQ + p], rv[q]) : cmul(Zm[p * NQ + q], rv[q]));
-                    }
-                    out[r] = acc;
-                }
-            }
-            __syncthreads();
-            if (k < b) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int p = pg + 4 * r;
-                    if (p < NQ) rh[k * NQ + p] = out[r];
-                }
-            }
+            if (a.adjoint) mode_solve<NQ, BT, true>(reinterpret_cast<const C*>(tfs), es, rh, b, tid);
+            else mode_solve<NQ, BT, false>(reinterpret_cast<const C*>(tfs), es, rh, b, tid);
         }
         __syncthreads();
-        // ---- 3c. correction di[j][q] = sum_k V[j][k] rh[k][q], written back into rh ----
+        // ---- 3c. correction di[j][.] = sum_k V[j][k] rh[k][.], written back into rh ----
         {
-            const int j = tid & 63, qg = tid >> 6;
-            C acc[3];
-            if (j < b) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) acc[r] = C{0, 0};
-                for (int k = 0; k < b; ++k) {
-                    const BT v = Vs[j * kLdsPad + k];
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) {
-                        const int q = qg + 4 * r;
-                        if (q < NQ) acc[r] = acc[r] + rmul(v, rh[k * NQ + q]);
-                    }
-                }
-            }
+            const auto acc = tile_gemm<BT, false>(Vs, reinterpret_cast<const BT*>(rh), b, N2, lane, wave);
             __syncthreads();
-            if (j < b) {
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int q = qg + 4 * r;
-                    if (q < NQ) rh[j * NQ + q] = acc[r];
-                }
-            }
+            tile_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
         }
         __syncthreads();
         const C* di = rh;
         // ---- accumulate, and for inner passes update the local residual ----
-        for (int t = tid; t < b * NQ; t += kThreads) {
+        for (int t = tid; t < b * NQ; t += kSweepThreads) {
             const int l = t / NQ, q = t - l * NQ;
             const C dv = di[t];
             if (q < NT)
@@ -939,8 +1066,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
                     const I3 lc = local_coords(g, l);
                     C lap = rmul((BT)(-2.0 * g.dim), dv);
                     for (int dir = 0; dir < nd; ++dir) {
-                        int glob;
-                        const int ln = block_neighbour(g, bc, lc, dir >> 1, (dir & 1) ? 1 : -1, &glob);
+                        const int ln = local_nb(g, lc, dir >> 1, (dir & 1) ? 1 : -1);
                         if (ln >= 0) lap = lap + di[ln * NQ + m];
                     }
                     const C hd = rmul((BT)(-g.kin), lap) + rmul((BT)v0s[l], dv);
@@ -952,7 +1078,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
                     }
                     const C tim = a.adjoint ? C{(BT)2 * tq.i, (BT)(-2) * tq.r} : C{(BT)(-2) * tq.i, (BT)2 * tq.r};
                     C wd = C{0, 0};
-                    for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)to.W[m * NT + n], di[l * NQ + n]);
+                    if (a.field_on)
+                        for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)to.W[m * NT + n], di[l * NQ + n]);
                     const BT sm = (m & 1) ? (BT)-1 : (BT)1;
                     y = tim - rmul((BT)to.U[m], hd) - rmul((BT)zs[l], wd) + rmul(sm, di[l * NQ + NT]);
                 } else {
@@ -966,7 +1093,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
         if (pass < a.n_inner) {
             // stop the defect corrections once the local system is solved
             double loc = 0.0;
-            for (int t = tid; t < b * NQ; t += kThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
+            for (int t = tid; t < b * NQ; t += kSweepThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
             const double tot = block_sum(loc, red);
             if (tid == 0) rnorm_sh = tot;
             __syncthreads();
@@ -977,11 +1104,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SweepArgs a, TimeOps<NT> to)
     }
 
     // ---- 5. write back ----
-    for (int t = tid; t < b * NT; t += kThreads) {
+    for (int t = tid; t < b * NT; t += kSweepThreads) {
         const int l = t / NT, n = t - l * NT;
         a.c[(size_t)gidx[l] * NT + n] = cs[t];
     }
-    for (int l = tid; l < b; l += kThreads) a.lam[gidx[l]] = ls[l];
+    for (int l = tid; l < b; l += kSweepThreads) a.lam[gidx[l]] = ls[l];
 }
 
 // ---------------------------------------------------------------------------
@@ -1158,12 +1285,15 @@ hipError_t launch_mode_factor(int nt, int nblocks, int bpts, const double* U, co
 hipError_t launch_sweep(int nt, int mixed, const SweepArgs& a, const double* U, const double* W,
                         int nblocks_colour, hipStream_t st) {
     if (nblocks_colour <= 0) return hipSuccess;
-    if (mixed) {
-        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, float>), dim3(nblocks_colour), dim3(kThreads), 0,
-                                               st, a, make_ops<NT>(U, W)));
+    const dim3 grid(nblocks_colour), threads(kSweepThreads);
+    if (mixed && a.Minv) {
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, float, true>), grid, threads, 0, st, a, make_ops<NT>(U, W)));
+    } else if (mixed) {
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, float, false>), grid, threads, 0, st, a, make_ops<NT>(U, W)));
+    } else if (a.Minv) {
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, double, true>), grid, threads, 0, st, a, make_ops<NT>(U, W)));
     } else {
-        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, double>), dim3(nblocks_colour), dim3(kThreads), 0,
-                                               st, a, make_ops<NT>(U, W)));
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, double, false>), grid, threads, 0, st, a, make_ops<NT>(U, W)));
     }
     return hipGetLastError();
 }
