@@ -31,13 +31,14 @@ COUNTERS = os.path.join(ROOT, "profiles", "sweep_counters.json")
 
 
 def sweep_launch_bytes(shape, block, n_t, colour, precision):
-    """Algorithmic HBM bytes of one finest-level colour launch.
+    """Algorithmic HBM bytes of one finest-level colour launch (forward step).
 
-    Per block of b points: eigenvectors b^2 reals, per-mode time inverses
-    (N_t+1)^2 b complex, block id 4 B; per own point: read c (N_t complex),
-    lambda, psi0 (complex), V0 (real), write c and lambda; per distinct halo
-    point of the launch: read N_t complex.  Real = 8 B (FP64) or 4 B (mixed),
-    complex = 2 reals for the factors; the state is always FP64.
+    Per block of b points: its eigenvectors, b^2 reals (8 B FP64, 4 B mixed),
+    its b eigenvalues (FP64) and frozen-field shift (8 B), its id (4 B).  Per
+    own point: read c (N_t complex FP64), lambda, the constraint right-hand
+    side (complex) and V0 (real); write c and lambda.  Per distinct halo point
+    of the launch: read c (N_t complex).  The shared time factor (3 (N_t+1)^2
+    complex, under 4 KB) is read once per launch and not counted.
     """
     import numpy as np
     nblk = [s // b for s, b in zip(shape, block)]
@@ -45,7 +46,7 @@ def sweep_launch_bytes(shape, block, n_t, colour, precision):
     rb = 8 if precision == "fp64" else 4
     coords = np.indices(nblk).reshape(len(nblk), -1).T
     ncol = int(np.sum(coords.sum(axis=1) % 2 == colour))
-    per_block = b * b * rb + (n_t + 1) ** 2 * b * 2 * rb + 4
+    per_block = b * b * rb + b * 8 + 8 + 4
     per_point = (n_t * 16 + 16 + 16 + 8) + (n_t * 16 + 16)
     # distinct halo points: points outside a colour block, face-adjacent to one
     owner_colour = np.zeros(shape, dtype=np.int8)

@@ -716,20 +716,6 @@ __device__ __forceinline__ int halo_nb(const LevelGeom& g, const I3& gi, const I
     return point_index(g, with_comp(gi, ax, ga));
 }
 
-// Broadcast within groups of eight lanes: every lane receives the value of
-// lane R of its group (ds_swizzle, bit mode: and-mask 0x18, or-mask R).
-template <int R>
-__device__ __forceinline__ float bcast8(float v) {
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x18 | (R << 5)));
-}
-template <int R>
-__device__ __forceinline__ double bcast8(double v) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_swizzle((int)(u & 0xffffffffLL), 0x18 | (R << 5));
-    const int hi = __builtin_amdgcn_ds_swizzle((int)(u >> 32), 0x18 | (R << 5));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Per-mode time solve with the shared factor, for all modes of a block at once.
 // y_k = Z (I - e_k T)^{-1} B r_k (adjoint: B^H (I - e_k T)^{-H} Z^H r_k), with T
 // upper triangular; r_k = rh[k][.] is replaced by y_k.  Eight lanes per mode
@@ -738,7 +724,8 @@ __device__ __forceinline__ double bcast8(double v) {
 // unknown at a time, broadcasting each solved unknown inside the 8-lane group
 // and folding it straight into the final product with Z (B^H).  The group is
 // one wave's slice, so no barrier is needed: rh[k] is read and written only by
-// the lanes of mode k, reads first.
+// the lanes of mode k, reads first.  The loops stay rolled: unrolled, the
+// compiler hoists every step's operand loads and the register count doubles.
 template <int NQ, typename T, bool adjoint>
 __device__ __forceinline__ void mode_solve(const cx<T>* __restrict__ tfc, const T* __restrict__ es,
                                            cx<T>* __restrict__ rh, int b, int tid) {
@@ -749,42 +736,39 @@ __device__ __forceinline__ void mode_solve(const cx<T>* __restrict__ tfc, const 
     const C* Zm = Bm + NQ * NQ;
     const int k = tid >> 3, r = tid & 7;
     const int kc = k < b ? k : b - 1;
+    const int lane = tid & 63, gbase = lane & ~7;
     const T ev = es[kc];
-    C rk[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) rk[q] = rh[kc * NQ + q];
     C acc[NS], out[NS], inv[NS];
     int pc[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int p = r + 8 * s;
         pc[s] = p < NQ ? p : NQ - 1;
-        C x = C{(T)0, (T)0};
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if (!adjoint) x = x + cmul(Bm[pc[s] * NQ + q], rk[q]);
-            else x = x + cmulc(Zm[q * NQ + pc[s]], rk[q]);
-        }
-        acc[s] = x;
+        acc[s] = C{(T)0, (T)0};
+        out[s] = C{(T)0, (T)0};
         const C tpp = Tm[pc[s] * NQ + pc[s]];
         inv[s] = cdiv(C{(T)1, (T)0}, C{(T)1 - ev * tpp.r, (adjoint ? ev : -ev) * tpp.i});
-        out[s] = C{(T)0, (T)0};
     }
+#pragma unroll 3
+    for (int q = 0; q < NQ; ++q) {
+        const C rq = rh[kc * NQ + q];
 #pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (!adjoint) acc[s] = acc[s] + cmul(Bm[pc[s] * NQ + q], rq);
+            else acc[s] = acc[s] + cmulc(Zm[q * NQ + pc[s]], rq);
+        }
+    }
+#pragma unroll 1
     for (int jj = 0; jj < NQ; ++jj) {
         // forward: back substitution (j = NQ-1 .. 0); adjoint: forward substitution
         const int j = adjoint ? jj : NQ - 1 - jj;
-        C y = (j < 8) ? cmul(acc[0], inv[0]) : cmul(acc[NS - 1], inv[NS - 1]);
-        switch (j & 7) {
-            case 0: y = C{bcast8<0>(y.r), bcast8<0>(y.i)}; break;
-            case 1: y = C{bcast8<1>(y.r), bcast8<1>(y.i)}; break;
-            case 2: y = C{bcast8<2>(y.r), bcast8<2>(y.i)}; break;
-            case 3: y = C{bcast8<3>(y.r), bcast8<3>(y.i)}; break;
-            case 4: y = C{bcast8<4>(y.r), bcast8<4>(y.i)}; break;
-            case 5: y = C{bcast8<5>(y.r), bcast8<5>(y.i)}; break;
-            case 6: y = C{bcast8<6>(y.r), bcast8<6>(y.i)}; break;
-            default: y = C{bcast8<7>(y.r), bcast8<7>(y.i)}; break;
-        }
+        const bool hi = j >= 8;
+        const C own = hi ? acc[NS - 1] : acc[0];
+        const C iv = hi ? inv[NS - 1] : inv[0];
+        C y = cmul(own, iv);
+        const int src = gbase | (j & 7);
+        y.r = __shfl(y.r, src, 64);
+        y.i = __shfl(y.i, src, 64);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int p = r + 8 * s;
@@ -804,10 +788,11 @@ __device__ __forceinline__ void mode_solve(const cx<T>* __restrict__ tfc, const 
     }
 }
 
-// Waves per SIMD the sweep is compiled for: the FP32 shared-factor variant fits
-// 128 registers, so two workgroups share a compute unit; the others take 256.
+// Waves per SIMD the sweep is compiled for: the shared-factor variants fit 128
+// registers, so two workgroups share a compute unit (LDS: under 80 KB each);
+// the stored-inverse variants take 256.
 template <typename BT, bool STORED>
-constexpr int sweep_waves_per_simd() { return (sizeof(BT) == 4 && !STORED) ? 4 : 2; }
+constexpr int sweep_waves_per_simd() { return STORED ? 2 : 4; }
 
 template <int NT, typename BT, bool STORED>
 __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())) void k_sweep(SweepArgs a, TimeOps<NT> to) {
