@@ -423,7 +423,7 @@ int level_residual(lam_ctx* c, int l) {
     const double2* bc = l == 0 ? nullptr : L.d_bc;
     const double2* bg = (l == 0 && c->adjoint) ? c->d_g : nullptr;
     const double2* bs = (l == 0 && c->adjoint) ? nullptr : L.d_bs;
-    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, L.d_c, L.d_lam, L.d_v0, bc, bg, bs, L.d_rc,
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, bc, bg, bs, L.d_rc,
                            L.d_rs, nullptr, nullptr, c->st));
     return LAM_OK;
 }
@@ -434,7 +434,7 @@ int norm0(lam_ctx* c, double* out) {
     const double2* bg = c->adjoint ? c->d_g : nullptr;
     const double2* bs = c->adjoint ? nullptr : L.d_bs;
     int np = 0;
-    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, L.d_c, L.d_lam, L.d_v0, nullptr, bg, bs, nullptr,
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, nullptr, bg, bs, nullptr,
                            nullptr, c->d_partial, &np, c->st));
     HIPCHK(launch_reduce(c->d_partial, np, 1, c->d_red, c->st));
     HIPCHK(hipMemcpyAsync(c->h_red, c->d_red, sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -743,7 +743,7 @@ int lam_residual_action(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_
     LAMCHK(set_step(ctx, t0));
     Level& L = ctx->lv[0];
     int np = 0;
-    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, ctx->W, 0, reinterpret_cast<const double2*>(c),
+    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, ctx->W, 0, ctx->field_on, reinterpret_cast<const double2*>(c),
                            reinterpret_cast<const double2*>(lam), L.d_v0, nullptr, nullptr,
                            reinterpret_cast<const double2*>(psi0), reinterpret_cast<double2*>(rho),
                            reinterpret_cast<double2*>(sigma), norm ? ctx->d_partial : nullptr, &np, ctx->st));
@@ -762,7 +762,7 @@ int lam_residual_adjoint(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c6
     LAMCHK(set_step(ctx, t0));
     Level& L = ctx->lv[0];
     int np = 0;
-    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, ctx->W, 1, reinterpret_cast<const double2*>(mu_c),
+    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, ctx->W, 1, ctx->field_on, reinterpret_cast<const double2*>(mu_c),
                            reinterpret_cast<const double2*>(mu_lam), L.d_v0, nullptr,
                            reinterpret_cast<const double2*>(g), nullptr, reinterpret_cast<double2*>(rho),
                            reinterpret_cast<double2*>(sigma), norm ? ctx->d_partial : nullptr, &np, ctx->st));

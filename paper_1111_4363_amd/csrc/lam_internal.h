@@ -59,7 +59,7 @@ struct SweepArgs {
 // All return hipSuccess or the launch error.
 
 hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const double* W, int adjoint,
-                           const double2* c, const double2* lam, const double* v0, const double2* bc,
+                           int field_on, const double2* c, const double2* lam, const double* v0, const double2* bc,
                            const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
                            int* nparts, hipStream_t st);
 

@@ -231,10 +231,13 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ---------------------------------------------------------------------------
 // K1: action residual of the step system (or its adjoint) + norm partials.
-// One thread per grid point, all n_t time components in registers.
+// One thread per (point, time component): a workgroup covers kThreads points
+// in rounds of kThreads / NT points, so that every load and store of c and of
+// the residual is contiguous across the wave.  A round stages its points'
+// coefficients in LDS for the couplings between time components.
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> to, int adjoint,
+__global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> to, int adjoint, int field_on,
                                                        const double2* __restrict__ c,
                                                        const double2* __restrict__ lam,
                                                        const double* __restrict__ v0,
@@ -243,71 +246,76 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
                                                        const double2* __restrict__ bs,
                                                        double2* __restrict__ rc, double2* __restrict__ rs,
                                                        double* __restrict__ partial) {
+    constexpr int PW = kThreads / NT;  // points per round
+    __shared__ double2 cs[PW * NT];
     __shared__ double red[kThreads / 64];
-    const int j = blockIdx.x * kThreads + threadIdx.x;
+    const int t = threadIdx.x;
+    const int lp = t / NT, m = t - lp * NT;
+    const size_t first = (size_t)blockIdx.x * kThreads;
     double acc = 0.0;
-    if (j < g.P) {
+    for (int base = 0; base < kThreads; base += PW) {
+        const size_t jw = first + base + lp;
+        const bool act = lp < PW && base + lp < kThreads && jw < (size_t)g.P;
+        const int j = act ? (int)jw : 0;
         const I3 i = point_coords(g, j);
-        double2 cj[NT], lap[NT];
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            cj[n] = c[(size_t)j * NT + n];
-            lap[n] = scl2(-2.0 * g.dim, cj[n]);
-        }
-        // all neighbour loads issued unconditionally (clamped index, 0/1 weight)
-        int nbi[6];
+        const double2 own = c[(size_t)j * NT + m];
+        // neighbour loads issued unconditionally (clamped index, 0/1 weight)
+        double2 nbv[6];
         double nbw[6];
 #pragma unroll
         for (int dir = 0; dir < 6; ++dir) {
-            nbi[dir] = j;
+            int nb = j;
             nbw[dir] = 0.0;
             if (dir < 2 * g.dim) {
                 I3 gi;
-                const int nb = neighbour(g, i, dir >> 1, (dir & 1) ? 1 : -1, &gi);
-                if (nb >= 0) {
-                    nbi[dir] = nb;
+                const int q = neighbour(g, i, dir >> 1, (dir & 1) ? 1 : -1, &gi);
+                if (q >= 0) {
+                    nb = q;
                     nbw[dir] = 1.0;
                 }
             }
-        }
-#pragma unroll
-        for (int dir = 0; dir < 6; ++dir) {
-#pragma unroll
-            for (int n = 0; n < NT; ++n) lap[n] = add2(lap[n], scl2(nbw[dir], c[(size_t)nbi[dir] * NT + n]));
+            nbv[dir] = c[(size_t)nb * NT + m];
         }
         const double vj = v0[j];
-        const double z = zcoord(g, i);
         const double2 lj = lam[j];
+        const double2 rhs = bc ? bc[(size_t)j * NT + m] : (bg ? bg[j] : make_double2(0.0, 0.0));
+        const double2 sgb = (bs && m == 0) ? bs[j] : make_double2(0.0, 0.0);
+        if (lp < PW) cs[t] = own;
+        __syncthreads();
+        double2 lap = scl2(-2.0 * g.dim, own);
 #pragma unroll
-        for (int m = 0; m < NT; ++m) {
-            double2 tq = make_double2(0.0, 0.0);
-            if (!adjoint) {
-#pragma unroll
-                for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cj[n]);
-            } else {
-#pragma unroll
-                for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cj[n]);
-            }
-            // forward: i * 2 tq ; adjoint: -i * 2 tq
-            const double2 tim = adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x)
-                                        : make_double2(-2.0 * tq.y, 2.0 * tq.x);
-            const double2 hc = add2(scl2(-g.kin, lap[m]), scl2(vj, cj[m]));
+        for (int dir = 0; dir < 6; ++dir) lap = add2(lap, scl2(nbw[dir], nbv[dir]));
+        const double2* cj = cs + (lp < PW ? lp : 0) * NT;
+        double2 tq = make_double2(0.0, 0.0);
+        if (!adjoint) {
+            for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cj[n]);
+        } else {
+            for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cj[n]);
+        }
+        // forward: i * 2 tq ; adjoint: -i * 2 tq
+        const double2 tim = adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
+        const double2 hc = add2(scl2(-g.kin, lap), scl2(vj, own));
+        double2 row = sub2(tim, scl2(to.U[m], hc));
+        if (field_on) {
             double2 wc = make_double2(0.0, 0.0);
 #pragma unroll
             for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cj[n]));
-            const double sm = (m & 1) ? -1.0 : 1.0;
-            double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(z, wc));
-            row = add2(row, scl2(sm, lj));
-            const double2 rhs = bc ? bc[(size_t)j * NT + m] : (bg ? bg[j] : make_double2(0.0, 0.0));
-            const double2 rho = sub2(rhs, row);
+            row = sub2(row, scl2(zcoord(g, i), wc));
+        }
+        row = add2(row, scl2((m & 1) ? -1.0 : 1.0, lj));
+        const double2 rho = sub2(rhs, row);
+        if (act) {
             if (rc) rc[(size_t)j * NT + m] = rho;
             acc += to.U[m] * (rho.x * rho.x + rho.y * rho.y);
-        }
-        double2 sg = bs ? bs[j] : make_double2(0.0, 0.0);
+            if (m == 0) {
+                double2 sg = sgb;
 #pragma unroll
-        for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cj[n]) : sub2(sg, cj[n]);
-        if (rs) rs[j] = sg;
-        acc += sg.x * sg.x + sg.y * sg.y;
+                for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cj[n]) : sub2(sg, cj[n]);
+                if (rs) rs[j] = sg;
+                acc += sg.x * sg.x + sg.y * sg.y;
+            }
+        }
+        __syncthreads();
     }
     if (partial) {
         const double tot = block_sum(acc, red);
@@ -350,14 +358,17 @@ __global__ __launch_bounds__(kThreads) void k_restrict(LevelGeom f, LevelGeom cg
                                                        const double2* __restrict__ rsf,
                                                        double2* __restrict__ bcc, double2* __restrict__ bsc,
                                                        double2* __restrict__ zc, double2* __restrict__ zl) {
-    const int J = blockIdx.x * kThreads + threadIdx.x;
-    if (J >= cg.P) return;
+    // one thread per (coarse point, component): components 0..NT-1 of c, then lambda
+    constexpr int NQ = NT + 1;
+    const size_t t = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= (size_t)cg.P * NQ) return;
+    const int J = (int)(t / NQ), n = (int)(t - (size_t)J * NQ);
+    const bool isc = n < NT;
+    const double2* src = isc ? rcf + n : rsf;
+    const int stride = isc ? NT : 1;
     const I3 I = point_coords(cg, J);
-    double2 acc[NT];
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[n] = make_double2(0.0, 0.0);
-    double2 accs = make_double2(0.0, 0.0);
     const int nch = 1 << f.dim;
+    double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch) {
         const int chc = ch < nch ? ch : 0;
@@ -365,19 +376,16 @@ __global__ __launch_bounds__(kThreads) void k_restrict(LevelGeom f, LevelGeom cg
         // child offsets only along the grid's axes (unused axes have extent 1)
         const I3 fi{2 * I.x + ((chc >> 0) & 1), f.dim > 1 ? 2 * I.y + ((chc >> 1) & 1) : 0,
                     f.dim > 2 ? 2 * I.z + ((chc >> 2) & 1) : 0};
-        const int fj = point_index(f, fi);
-#pragma unroll
-        for (int n = 0; n < NT; ++n) acc[n] = add2(acc[n], scl2(w, rcf[(size_t)fj * NT + n]));
-        accs = add2(accs, scl2(w, rsf[fj]));
+        acc = add2(acc, scl2(w, src[(size_t)point_index(f, fi) * stride]));
     }
-    const double sc = 1.0 / nch;
-#pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        bcc[(size_t)J * NT + n] = scl2(sc, acc[n]);
+    acc = scl2(1.0 / nch, acc);
+    if (isc) {
+        bcc[(size_t)J * NT + n] = acc;
         if (zc) zc[(size_t)J * NT + n] = make_double2(0.0, 0.0);
+    } else {
+        bsc[J] = acc;
+        if (zl) zl[J] = make_double2(0.0, 0.0);
     }
-    bsc[J] = scl2(sc, accs);
-    if (zl) zl[J] = make_double2(0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,8 +398,15 @@ __global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg,
                                                       const double2* __restrict__ cc,
                                                       const double2* __restrict__ lc,
                                                       double2* __restrict__ cf, double2* __restrict__ lf) {
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    if (j >= f.P) return;
+    // one thread per (fine point, component): components 0..NT-1 of c, then lambda
+    constexpr int NQ = NT + 1;
+    const size_t t = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= (size_t)f.P * NQ) return;
+    const int j = (int)(t / NQ), n = (int)(t - (size_t)j * NQ);
+    const bool isc = n < NT;
+    const double2* src = isc ? cc + n : lc;
+    double2* dst = isc ? cf + (size_t)j * NT + n : lf + j;
+    const int stride = isc ? NT : 1;
     const I3 i = point_coords(f, j);
     // per axis: parent, nearer coarse neighbour, and whether that neighbour exists
     int par[3], nb[3], ok[3];
@@ -414,10 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg,
             ok[a] = 0;
         }
     }
-    double2 acc[NT];
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[n] = make_double2(0.0, 0.0);
-    double2 accl = make_double2(0.0, 0.0);
+    double2 acc = make_double2(0.0, 0.0);
     const int ncomb = interp ? 1 : (1 << f.dim);
     // all parent loads issued unconditionally (clamped to the parent, weight 0 when unused)
 #pragma unroll
@@ -437,13 +449,9 @@ __global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg,
             }
         }
         const int J = point_index(cg, I3{J3[0], J3[1], J3[2]});
-#pragma unroll
-        for (int n = 0; n < NT; ++n) acc[n] = add2(acc[n], scl2(w, cc[(size_t)J * NT + n]));
-        accl = add2(accl, scl2(w, lc[J]));
+        acc = add2(acc, scl2(w, src[(size_t)J * stride]));
     }
-#pragma unroll
-    for (int n = 0; n < NT; ++n) cf[(size_t)j * NT + n] = add2(cf[(size_t)j * NT + n], acc[n]);
-    lf[j] = add2(lf[j], accl);
+    *dst = add2(*dst, acc);
 }
 
 __global__ __launch_bounds__(kThreads) void k_average_potential(LevelGeom f, LevelGeom cg,
@@ -1211,14 +1219,14 @@ inline int nblk_for(size_t n) { return (int)((n + kThreads - 1) / kThreads); }
     }
 
 hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const double* W, int adjoint,
-                           const double2* c, const double2* lam, const double* v0, const double2* bc,
+                           int field_on, const double2* c, const double2* lam, const double* v0, const double2* bc,
                            const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
                            int* nparts, hipStream_t st) {
     const int nb = nblk_for(g.P);
     if (nparts) *nparts = nb;
     LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_residual<NT>, dim3(nb), dim3(kThreads), 0, st, g,
-                                           make_ops<NT>(U, W), adjoint, c, lam, v0, bc, bg, bs, rc, rs,
-                                           partial));
+                                           make_ops<NT>(U, W), adjoint, field_on, c, lam, v0, bc, bg, bs, rc,
+                                           rs, partial));
     return hipGetLastError();
 }
 
@@ -1235,14 +1243,16 @@ hipError_t launch_reduce_c2(const double2* partial, int nparts, int width, doubl
 hipError_t launch_restrict(int nt, const LevelGeom& fine, const LevelGeom& coarse, const double2* rcf,
                            const double2* rsf, double2* bcc, double2* bsc, double2* zero_c, double2* zero_l,
                            hipStream_t st) {
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_restrict<NT>, dim3(nblk_for(coarse.P)), dim3(kThreads), 0, st,
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_restrict<NT>, dim3(nblk_for((size_t)coarse.P * (nt + 1))),
+                                           dim3(kThreads), 0, st,
                                            fine, coarse, rcf, rsf, bcc, bsc, zero_c, zero_l));
     return hipGetLastError();
 }
 
 hipError_t launch_prolong(int nt, const LevelGeom& fine, const LevelGeom& coarse, int interp, const double2* cc,
                           const double2* lc, double2* cf, double2* lf, hipStream_t st) {
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_prolong<NT>, dim3(nblk_for(fine.P)), dim3(kThreads), 0, st, fine,
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_prolong<NT>, dim3(nblk_for((size_t)fine.P * (nt + 1))),
+                                           dim3(kThreads), 0, st, fine,
                                            coarse, interp, cc, lc, cf, lf));
     return hipGetLastError();
 }
