@@ -650,7 +650,7 @@ int build(lam_ctx* c, const double* v0_dev) {
         HIPCHK(launch_average_potential(c->lv[l - 1].g, c->lv[l].g, c->lv[l - 1].d_v0, c->lv[l].d_v0, c->st));
     const int P0 = c->lv[0].g.P;
     c->max_parts = (P0 + kThreads - 1) / kThreads;
-    LAMCHK(dalloc(&c->d_partial, (size_t)c->max_parts));
+    LAMCHK(dalloc(&c->d_partial, (size_t)residual_blocks(nt, P0)));
     LAMCHK(dalloc(&c->d_red, 1));
     LAMCHK(dalloc(&c->d_g, (size_t)P0));
     LAMCHK(dalloc(&c->d_cf, (size_t)P0 * nt));

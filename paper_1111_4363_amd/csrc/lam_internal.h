@@ -55,6 +55,12 @@ struct SweepArgs {
     int field_on;             // W (the field's time matrix) is nonzero this step
 };
 
+// Workgroups (and norm partials) of a residual launch over P points.
+inline int residual_blocks(int nt, int P) {
+    const int pw = kThreads / nt;
+    return (P + pw - 1) / pw;
+}
+
 // ---- launchers (lam_kernels.hip) -------------------------------------------
 // All return hipSuccess or the launch error.
 

@@ -231,10 +231,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ---------------------------------------------------------------------------
 // K1: action residual of the step system (or its adjoint) + norm partials.
-// One thread per (point, time component): a workgroup covers kThreads points
-// in rounds of kThreads / NT points, so that every load and store of c and of
-// the residual is contiguous across the wave.  A round stages its points'
-// coefficients in LDS for the couplings between time components.
+// One thread per (point, time component), kThreads / NT points per workgroup,
+// so that every load and store of c and of the residual is contiguous across
+// the wave; the workgroup stages its points' coefficients in LDS for the
+// couplings between time components.
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> to, int adjoint, int field_on,
@@ -251,11 +251,10 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
     __shared__ double red[kThreads / 64];
     const int t = threadIdx.x;
     const int lp = t / NT, m = t - lp * NT;
-    const size_t first = (size_t)blockIdx.x * kThreads;
     double acc = 0.0;
-    for (int base = 0; base < kThreads; base += PW) {
-        const size_t jw = first + base + lp;
-        const bool act = lp < PW && base + lp < kThreads && jw < (size_t)g.P;
+    {
+        const size_t jw = (size_t)blockIdx.x * PW + lp;
+        const bool act = lp < PW && jw < (size_t)g.P;
         const int j = act ? (int)jw : 0;
         const I3 i = point_coords(g, j);
         const double2 own = c[(size_t)j * NT + m];
@@ -315,7 +314,6 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
                 acc += sg.x * sg.x + sg.y * sg.y;
             }
         }
-        __syncthreads();
     }
     if (partial) {
         const double tot = block_sum(acc, red);
@@ -1222,7 +1220,7 @@ hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const do
                            int field_on, const double2* c, const double2* lam, const double* v0, const double2* bc,
                            const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
                            int* nparts, hipStream_t st) {
-    const int nb = nblk_for(g.P);
+    const int nb = residual_blocks(nt, g.P);
     if (nparts) *nparts = nb;
     LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_residual<NT>, dim3(nb), dim3(kThreads), 0, st, g,
                                            make_ops<NT>(U, W), adjoint, field_on, c, lam, v0, bc, bg, bs, rc,
