@@ -603,6 +603,12 @@ int build(lam_ctx* c, const double* v0_dev) {
         g.fax = c->ham.field_axis;
         g.kin = 1.0 / (2.0 * c->ham.mass * g.h * g.h);
         g.bpts = g.bdim[0] * g.bdim[1] * g.bdim[2];
+        g.rbp = 1.0f / (float)g.bpts;
+        for (int a = 0; a < 3; ++a) {
+            g.rn[a] = 1.0 / g.n[a];
+            g.rnb[a] = 1.0 / g.nblk[a];
+            g.rbd[a] = 1.0f / (float)g.bdim[a];
+        }
         L.nblocks = g.nblk[0] * g.nblk[1] * g.nblk[2];
         L.fp32 = c->solver.precision == LAM_MIXED && (l < gr.levels - 1 || gr.levels == 1);
         // colour lists and block centres along the field axis

@@ -27,6 +27,10 @@ struct LevelGeom {
     int bdim[3];     // block points per axis (unused axes = 1)
     int nblk[3];     // blocks per axis
     int bpts;        // points per block
+    double rn[3];    // 1 / n[a], for division-free index arithmetic
+    double rnb[3];   // 1 / nblk[a]
+    float rbd[3];    // 1 / bdim[a]
+    float rbp;       // 1 / bpts
 };
 
 // Time operators of one step: diagonal of U and the field matrix W (symmetric).

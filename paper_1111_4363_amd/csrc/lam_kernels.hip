@@ -137,12 +137,20 @@ __device__ __forceinline__ I3 with_comp(I3 v, int ax, int val) {
     return v;
 }
 
+// Quotients without integer division: floor(j / n) as (j + 1/2) times the
+// rounded reciprocal 1/n, truncated.  (j + 1/2)/n lies at least 1/(2n) from an
+// integer and the two roundings move it by at most (j + 1/2)/n * 2 eps, so the
+// quotient is exact when (j + 1/2) * 2 eps < 1/2: for 0 <= j < 2^31 in FP64
+// (qdiv) and for 0 <= j < 2^21 in FP32 (qdiv_small), for any n >= 1.
+__device__ __forceinline__ int qdiv(int j, double rn) { return (int)(((double)j + 0.5) * rn); }
+__device__ __forceinline__ int qdiv_small(int j, float rn) { return (int)(((float)j + 0.5f) * rn); }
+
 __device__ __forceinline__ I3 point_coords(const LevelGeom& g, int j) {
     I3 i;
-    i.z = j % g.n[2];
-    const int t = j / g.n[2];
-    i.y = t % g.n[1];
-    i.x = t / g.n[1];
+    const int t = qdiv(j, g.rn[2]);
+    i.z = j - t * g.n[2];
+    i.x = qdiv(t, g.rn[1]);
+    i.y = t - i.x * g.n[1];
     return i;
 }
 
@@ -157,7 +165,7 @@ __device__ __forceinline__ int neighbour(const LevelGeom& g, const I3& i, int ax
     int v = comp(i, ax) + d;
     if (v < 0 || v >= na) {
         if (!g.periodic) return -1;
-        v = (v + na) % na;
+        v += v < 0 ? na : -na;
     }
     *gi = with_comp(i, ax, v);
     return point_index(g, *gi);
@@ -170,19 +178,19 @@ __device__ __forceinline__ double zcoord(const LevelGeom& g, const I3& i) {
 // Block bookkeeping: block id -> block coordinates; local index -> local coords.
 __device__ __forceinline__ I3 block_coords(const LevelGeom& g, int blk) {
     I3 b;
-    b.z = blk % g.nblk[2];
-    const int t = blk / g.nblk[2];
-    b.y = t % g.nblk[1];
-    b.x = t / g.nblk[1];
+    const int t = qdiv(blk, g.rnb[2]);
+    b.z = blk - t * g.nblk[2];
+    b.x = qdiv(t, g.rnb[1]);
+    b.y = t - b.x * g.nblk[1];
     return b;
 }
 
 __device__ __forceinline__ I3 local_coords(const LevelGeom& g, int l) {
     I3 c;
-    c.z = l % g.bdim[2];
-    const int t = l / g.bdim[2];
-    c.y = t % g.bdim[1];
-    c.x = t / g.bdim[1];
+    const int t = qdiv_small(l, g.rbd[2]);
+    c.z = l - t * g.bdim[2];
+    c.x = qdiv_small(t, g.rbd[1]);
+    c.y = t - c.x * g.bdim[1];
     return c;
 }
 
@@ -417,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg,
         ok[a] = 1;
         if (nb[a] < 0 || nb[a] >= nc) {
             if (f.periodic)
-                nb[a] = (nb[a] + nc) % nc;
+                nb[a] += nb[a] < 0 ? nc : -nc;
             else
                 ok[a] = 0;
         }
@@ -703,7 +711,7 @@ __device__ __forceinline__ int local_nb(const LevelGeom& g, const I3& lc, int ax
     int la = comp(lc, ax) + d;
     if (la < 0 || la >= bd) {
         if (!(g.periodic && g.nblk[ax] == 1)) return -1;
-        la = (la + bd) % bd;
+        la += la < 0 ? bd : -bd;
     }
     return local_index(g, with_comp(lc, ax, la));
 }
@@ -717,7 +725,7 @@ __device__ __forceinline__ int halo_nb(const LevelGeom& g, const I3& gi, const I
     int ga = comp(gi, ax) + d;
     if (ga < 0 || ga >= na) {
         if (!g.periodic) return -1;
-        ga = (ga + na) % na;
+        ga += ga < 0 ? na : -na;
     }
     return point_index(g, with_comp(gi, ax, ga));
 }
@@ -833,28 +841,27 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-12;
     const I3 bc = block_coords(g, blk);
 
-    // ---- 1a. addresses (no loads yet) ----
-    int gjv[IPT], mv[IPT], hidx[IPT][6], hmask[IPT];
+    // ---- 1a. addresses (no loads yet); thread = residual item (point l, component m) ----
+    static_assert(kMaxB * kMaxNT <= kSweepThreads, "one residual item per thread");
+    const bool item = tid < b * NT;
+    const int t_it = item ? tid : 0;
+    const int l_it = t_it / NT, m_it = t_it - (t_it / NT) * NT;
+    const I3 lc_it = local_coords(g, l_it);
+    const I3 gi_it = global_of_local(g, bc, lc_it);
+    const int gj_it = point_index(g, gi_it);
+    // halo neighbours (outside the block; clamped to the point itself when absent)
+    // and in-block neighbours (local index, or -1)
+    int hidx[6], lnb[6], hmask = 0;
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-        const int t0 = tid + it * kSweepThreads;
-        const int t = t0 < b * NT ? t0 : 0;
-        const int l = t / NT;
-        mv[it] = t - l * NT;
-        const I3 lc = local_coords(g, l);
-        const I3 gi = global_of_local(g, bc, lc);
-        gjv[it] = point_index(g, gi);
-        hmask[it] = 0;
-#pragma unroll
-        for (int dir = 0; dir < 6; ++dir) {
-            hidx[it][dir] = gjv[it];
-            if (dir < nd) {
-                const int h = halo_nb(g, gi, lc, dir >> 1, (dir & 1) ? 1 : -1);
-                if (h >= 0) {
-                    hidx[it][dir] = h;
-                    hmask[it] |= 1 << dir;
-                }
-            }
+    for (int dir = 0; dir < 6; ++dir) {
+        hidx[dir] = gj_it;
+        lnb[dir] = -1;
+        if (dir < nd) {
+            const int ax = dir >> 1, d = (dir & 1) ? 1 : -1;
+            const int h = halo_nb(g, gi_it, lc_it, ax, d);
+            hidx[dir] = h >= 0 ? h : gj_it;
+            hmask |= (h >= 0 ? 1 : 0) << dir;
+            lnb[dir] = local_nb(g, lc_it, ax, d);
         }
     }
     const int tp = tid < b ? tid : 0;
@@ -862,15 +869,11 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const int gjp = point_index(g, gip);
 
     // ---- 1b. loads, all in flight together ----
-    double2 own[IPT], rhsv[IPT], hv[IPT][6];
+    const double2 own = a.c[(size_t)gj_it * NT + m_it];
+    double2 hv[6];
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-        own[it] = a.c[(size_t)gjv[it] * NT + mv[it]];
-#pragma unroll
-        for (int dir = 0; dir < 6; ++dir) hv[it][dir] = a.c[(size_t)hidx[it][dir] * NT + mv[it]];
-        rhsv[it] = a.bc ? a.bc[(size_t)gjv[it] * NT + mv[it]]
-                        : (a.bg ? a.bg[gjv[it]] : make_double2(0.0, 0.0));
-    }
+    for (int dir = 0; dir < 6; ++dir) hv[dir] = a.c[(size_t)hidx[dir] * NT + m_it];
+    const double2 rhsv = a.bc ? a.bc[(size_t)gj_it * NT + m_it] : (a.bg ? a.bg[gj_it] : make_double2(0.0, 0.0));
     const double v0p = a.v0[gjp];
     const double2 lp = a.lam[gjp];
     const double2 sgv = a.bs ? a.bs[gjp] : make_double2(0.0, 0.0);
@@ -897,16 +900,10 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     }
 
     // ---- 1c. consume into LDS ----
-    double2 halo[IPT];
+    double2 halo = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-        double2 hs = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int dir = 0; dir < 6; ++dir) hs = add2(hs, scl2((hmask[it] >> dir) & 1 ? 1.0 : 0.0, hv[it][dir]));
-        halo[it] = hs;
-        const int t = tid + it * kSweepThreads;
-        if (t < b * NT) cs[t] = own[it];
-    }
+    for (int dir = 0; dir < 6; ++dir) halo = add2(halo, scl2((hmask >> dir) & 1 ? 1.0 : 0.0, hv[dir]));
+    if (item) cs[tid] = own;
     if (tid < b) {
         gidx[tid] = gjp;
         v0s[tid] = v0p;
@@ -920,7 +917,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         for (int r = 0; r < VPT; ++r) {
             const int t = tid + r * kSweepThreads;
             if (t < bb) {
-                const int j = t / b, k = t - j * b;
+                const int j = qdiv_small(t, g.rbp), k = t - j * b;
                 Vs[j * kLdsPad + k] = vr[r];
             }
         }
@@ -935,39 +932,36 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __syncthreads();
 
     // ---- 2. local residual (FP64) ----
+    if (item) {
+        const int l = l_it, m = m_it;
+        double2 lap = add2(scl2(-2.0 * g.dim, own), halo);
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-        const int t = tid + it * kSweepThreads;
-        if (t < b * NT) {
-            const int l = t / NT, m = t - l * NT;
-            const I3 lc = local_coords(g, l);
-            double2 lap = add2(scl2(-2.0 * g.dim, own[it]), halo[it]);
-            for (int dir = 0; dir < nd; ++dir) {
-                const int ln = local_nb(g, lc, dir >> 1, (dir & 1) ? 1 : -1);
-                if (ln >= 0) lap = add2(lap, cs[ln * NT + m]);
-            }
-            const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], own[it]));
-            double2 tq = make_double2(0.0, 0.0);
-            if (!a.adjoint) {
-                for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cs[l * NT + n]);
-            } else {
-                for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cs[l * NT + n]);
-            }
-            const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
-            double2 wc = make_double2(0.0, 0.0);
-            if (a.field_on) {
-#pragma unroll
-                for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cs[l * NT + n]));
-            }
-            const double sm = (m & 1) ? -1.0 : 1.0;
-            double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(zs[l], wc));
-            row = add2(row, scl2(sm, ls[l]));
-            const double2 rho = sub2(rhsv[it], row);
-            rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
+        for (int dir = 0; dir < 6; ++dir) {
+            const int ln = lnb[dir];
+            lap = add2(lap, scl2(ln >= 0 ? 1.0 : 0.0, cs[(ln >= 0 ? ln : l) * NT + m]));
         }
+        const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], own));
+        // time coupling: i (Q^T c)_m, with Q_nm = 2 for n > m, n - m odd (adjoint: the transpose)
+        double2 tq = make_double2(0.0, 0.0);
+        double2 wc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const double2 cn = cs[l * NT + n];
+            const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
+            tq = add2(tq, scl2(cpl ? 1.0 : 0.0, cn));
+            if (a.field_on) wc = add2(wc, scl2(to.W[m * NT + n], cn));
+        }
+        const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
+        const double sm = (m & 1) ? -1.0 : 1.0;
+        double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(zs[l], wc));
+        row = add2(row, scl2(sm, ls[l]));
+        const double2 rho = sub2(rhsv, row);
+        rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
     }
     if (tid < b) {
+        // constraint rows
         double2 sg = sgv;
+#pragma unroll
         for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cs[tid * NT + n]) : sub2(sg, cs[tid * NT + n]);
         rs[tid * NQ + NT] = C{(BT)sg.x, (BT)sg.y};
     }
