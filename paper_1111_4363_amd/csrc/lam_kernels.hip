@@ -74,17 +74,35 @@ struct Mfma<float> {
 // eigenbasis) or Vs[m][p] (back to points).  Wave w owns rows 16 (w % 4) ..
 // and columns 16 (w / 4) ..; every operand load is unconditional (clamped
 // address times a 0/1 factor) so successive K steps stay in flight.
-template <typename T, bool TRANS>
+template <typename T, bool TRANS, int NCOL>
 __device__ __forceinline__ typename Mfma<T>::acc_t tile_gemm(const T* __restrict__ Vs, const T* __restrict__ in,
-                                                             int b, int ncol, int lane, int wave) {
+                                                             int b, int lane, int wave) {
     typename Mfma<T>::acc_t acc;
     for (int r = 0; r < 4; ++r) acc[r] = (T)0;
     const int mt = wave & 3, nt = wave >> 2;
-    if (16 * mt >= b || 16 * nt >= ncol) return acc;
+    if (16 * mt >= b || 16 * nt >= NCOL) return acc;
     const int i = lane & 15, kq = lane >> 4;
     const int m = 16 * mt + i, col = 16 * nt + i;
-    const T fm = m < b ? (T)1 : (T)0, fc = col < ncol ? (T)1 : (T)0;
-    const int mc = m < b ? m : b - 1, cc = col < ncol ? col : ncol - 1;
+    // columns past NCOL only feed result columns that are never stored: read column NCOL-1
+    const int cc = col < NCOL ? col : NCOL - 1;
+    if (b == kMaxB) {
+        // full block: every operand in range; two halves of eight MFMA steps,
+        // each half's loads issued together with offsets folded into the LDS instructions
+#pragma unroll 1
+        for (int kh = 0; kh < kMaxB; kh += kMaxB / 2) {
+            const T* va = TRANS ? Vs + kh * kLdsPad + m : Vs + m * kLdsPad + kh;
+            const T* vb = in + kh * NCOL + cc;
+#pragma unroll
+            for (int kk = 0; kk < kMaxB / 8; ++kk) {
+                const int p = 4 * kk + kq;
+                const T av = TRANS ? va[p * kLdsPad] : va[p];
+                acc = Mfma<T>::step(av, vb[p * NCOL], acc);
+            }
+        }
+        return acc;
+    }
+    const T fm = m < b ? (T)1 : (T)0;
+    const int mc = m < b ? m : b - 1;
     // K in groups of 16 (four MFMA steps): the group's loads are issued together
     for (int kb = 0; kb < kMaxB; kb += 16) {
         if (kb >= b) break;
@@ -95,7 +113,7 @@ __device__ __forceinline__ typename Mfma<T>::acc_t tile_gemm(const T* __restrict
             const T fp = p < b ? (T)1 : (T)0;
             const int pc = p < b ? p : b - 1;
             av[u] = (TRANS ? Vs[pc * kLdsPad + mc] : Vs[mc * kLdsPad + pc]) * (fm * fp);
-            bv[u] = in[pc * ncol + cc] * fc;
+            bv[u] = in[pc * NCOL + cc];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = Mfma<T>::step(av[u], bv[u], acc);
@@ -772,10 +790,37 @@ __device__ __forceinline__ void mode_solve(const cx<T>* __restrict__ tfc, const 
             else acc[s] = acc[s] + cmulc(Zm[q * NQ + pc[s]], rq);
         }
     }
+    // coupling and output coefficients of step j for row slot s
+    auto coef_t = [&](int j, int s) -> C {
+        return adjoint ? C{Tm[j * NQ + pc[s]].r, -Tm[j * NQ + pc[s]].i} : Tm[pc[s] * NQ + j];
+    };
+    auto coef_o = [&](int j, int s) -> C {
+        return adjoint ? C{Bm[j * NQ + pc[s]].r, -Bm[j * NQ + pc[s]].i} : Zm[pc[s] * NQ + j];
+    };
+    C tcn[NS], e3n[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        tcn[s] = coef_t(adjoint ? 0 : NQ - 1, s);
+        e3n[s] = coef_o(adjoint ? 0 : NQ - 1, s);
+    }
 #pragma unroll 1
     for (int jj = 0; jj < NQ; ++jj) {
         // forward: back substitution (j = NQ-1 .. 0); adjoint: forward substitution
         const int j = adjoint ? jj : NQ - 1 - jj;
+        C tc[NS], e3[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            tc[s] = tcn[s];
+            e3[s] = e3n[s];
+        }
+        if (jj + 1 < NQ) {  // the next step's coefficients, loaded a step ahead
+            const int jn = adjoint ? j + 1 : j - 1;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                tcn[s] = coef_t(jn, s);
+                e3n[s] = coef_o(jn, s);
+            }
+        }
         const bool hi = j >= 8;
         const C own = hi ? acc[NS - 1] : acc[0];
         const C iv = hi ? inv[NS - 1] : inv[0];
@@ -789,10 +834,8 @@ __device__ __forceinline__ void mode_solve(const cx<T>* __restrict__ tfc, const 
             // couple the unknowns still to be solved: rows above j (forward) / below j (adjoint)
             const bool open = adjoint ? (p > j && p < NQ) : (p < j);
             const T f = open ? ev : (T)0;
-            const C tc = adjoint ? C{Tm[j * NQ + pc[s]].r, -Tm[j * NQ + pc[s]].i} : Tm[pc[s] * NQ + j];
-            acc[s] = acc[s] + rmul(f, cmul(tc, y));
-            const C e3 = adjoint ? C{Bm[j * NQ + pc[s]].r, -Bm[j * NQ + pc[s]].i} : Zm[pc[s] * NQ + j];
-            out[s] = out[s] + cmul(e3, y);
+            acc[s] = acc[s] + cmul(C{f * tc[s].r, f * tc[s].i}, y);
+            out[s] = out[s] + cmul(e3[s], y);
         }
     }
 #pragma unroll
@@ -981,7 +1024,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     for (int pass = 0; pass <= a.n_inner; ++pass) {
         // ---- 3a. rh[k][.] = sum_j V[j][k] rs[j][.]  (matrix cores) ----
         {
-            const auto acc = tile_gemm<BT, true>(Vs, reinterpret_cast<const BT*>(rs), b, N2, lane, wave);
+            const auto acc = tile_gemm<BT, true, N2>(Vs, reinterpret_cast<const BT*>(rs), b, lane, wave);
             tile_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
         }
         __syncthreads();
@@ -1030,7 +1073,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         __syncthreads();
         // ---- 3c. correction di[j][.] = sum_k V[j][k] rh[k][.], written back into rh ----
         {
-            const auto acc = tile_gemm<BT, false>(Vs, reinterpret_cast<const BT*>(rh), b, N2, lane, wave);
+            const auto acc = tile_gemm<BT, false, N2>(Vs, reinterpret_cast<const BT*>(rh), b, lane, wave);
             __syncthreads();
             tile_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
         }
