@@ -219,7 +219,7 @@ def main():
     achieved = bytes_per_launch / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9 if r["sweep_kernel_ms_avg"] else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": counters_for_current_kernel(), "kernel": f"k_sweep<8,{'double' if main_prec == 'fp64' else 'float'}>",
+                "traffic": counters_for_current_kernel(), "kernel": f"k_sweep<8, {'double' if main_prec == 'fp64' else 'float'}, false> (finest level)",
                 "bytes_per_launch": bytes_per_launch}
 
     cpu = None
