@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -213,10 +214,19 @@ bool schur_small(int n, cd* A, cd* Z) {
     return true;
 }
 
-// B, Z, T (each (nt+1)^2 complex, row-major) of the shared time factor.
-bool time_factor(int nt, const double* U, cd* B, cd* Z, cd* T) {
+// Shared time factor in the eigenbasis of G = M0^{-1} diag(U, 0):
+//   M(e) = M0 (I - e G),   G = S J S^{-1},   M(e)^{-1} = S (I - e J)^{-1} S^{-1} M0^{-1},
+// with J = diag(lam) except J[0][1] = 1.  G has a two-long Jordan chain at 0
+// whose vectors are known exactly: v1 = e_nt (the multiplier unit vector spans
+// the null space of diag(U, 0)) and v2 = (U^{-1} s, 0), since G v2 = M0^{-1}(s, 0)
+// = v1, the last column of M0 being (s, 0).  The other nt - 1 eigenvalues
+// are nonzero and distinct; their eigenvectors come from the complex Schur
+// form G = Z T Z^H by back substitution in T.  Outputs (row-major, n = nt + 1):
+// E3 = S, E1 = S^{-1} M0^{-1} (n x n complex each) and lam (n complex; the
+// Jordan pair's entries are 0).  Returns false if G S = S J fails to 1e-12.
+bool time_factor(int nt, const double* U, cd* E1, cd* E3, cd* lam) {
     const int n = nt + 1;
-    std::vector<cd> M0(n * n, 0.0), Minv(n * n), G(n * n, 0.0);
+    std::vector<cd> M0(n * n, 0.0), Minv(n * n), G(n * n, 0.0), T(n * n), Z(n * n);
     for (int m = 0; m < nt; ++m) {
         for (int k = 0; k < nt; ++k)
             if (k > m && ((k - m) & 1)) M0[m * n + k] = cd(0.0, 2.0);  // i Q_km
@@ -228,13 +238,61 @@ bool time_factor(int nt, const double* U, cd* B, cd* Z, cd* T) {
     if (!invert_small(n, Minv.data())) return false;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < nt; ++j) G[i * n + j] = Minv[i * n + j] * U[j];
-    for (int k = 0; k < n * n; ++k) T[k] = G[k];
-    if (!schur_small(n, T, Z)) return false;
+    T = G;
+    if (!schur_small(n, T.data(), Z.data())) return false;
+    // the Jordan pair: the two diagonal entries of T of smallest modulus
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return std::abs(T[x * n + x]) < std::abs(T[y * n + y]); });
+    std::vector<cd> S(n * n, 0.0), w(n);
+    double s2 = 0.0;
+    for (int m = 0; m < nt; ++m) s2 += 1.0 / (U[m] * U[m]);
+    const double sc = 1.0 / std::sqrt(s2);  // |v2| = |U^{-1} s|
+    S[nt * n + 0] = sc;                      // v1
+    for (int m = 0; m < nt; ++m) S[m * n + 1] = sc * ((m & 1) ? -1.0 : 1.0) / U[m];  // v2
+    lam[0] = lam[1] = 0.0;
+    for (int c = 2; c < n; ++c) {
+        const int k = idx[c];
+        const cd lk = T[k * n + k];
+        for (int i = 0; i < n; ++i) w[i] = 0.0;
+        w[k] = 1.0;
+        for (int i = k - 1; i >= 0; --i) {
+            cd acc = 0.0;
+            for (int m = i + 1; m <= k; ++m) acc += T[i * n + m] * w[m];
+            const cd den = T[i * n + i] - lk;
+            if (std::abs(den) < 1e-12 * std::abs(lk)) return false;
+            w[i] = -acc / den;
+        }
+        double nv = 0.0;
+        std::vector<cd> v(n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            for (int m = 0; m <= k; ++m) v[i] += Z[i * n + m] * w[m];
+            nv += std::norm(v[i]);
+        }
+        nv = std::sqrt(nv);
+        for (int i = 0; i < n; ++i) S[i * n + c] = v[i] / nv;
+        lam[c] = lk;
+    }
+    // check G S = S J
+    double gn = 0.0, err = 0.0;
+    for (int k = 0; k < n * n; ++k) gn = std::max(gn, std::abs(G[k]));
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
+            cd gs = 0.0;
+            for (int k = 0; k < n; ++k) gs += G[i * n + k] * S[k * n + j];
+            cd sj = S[i * n + j] * lam[j];
+            if (j == 1) sj += S[i * n + 0];
+            err = std::max(err, std::abs(gs - sj));
+        }
+    if (!(err <= 1e-12 * std::max(gn, 1.0))) return false;
+    std::vector<cd> Sinv = S;
+    if (!invert_small(n, Sinv.data())) return false;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            E3[i * n + j] = S[i * n + j];
             cd acc = 0.0;
-            for (int k = 0; k < n; ++k) acc += std::conj(Z[k * n + i]) * Minv[k * n + j];
-            B[i * n + j] = acc;
+            for (int k = 0; k < n; ++k) acc += Sinv[i * n + k] * Minv[k * n + j];
+            E1[i * n + j] = acc;
         }
     return true;
 }
@@ -276,7 +334,7 @@ struct lam_ctx {
     double2* d_G = nullptr;
     double2* h_G = nullptr;       // pinned
     double2* d_cf = nullptr;      // forward coefficients kept for the gradients
-    double2* d_tf = nullptr;      // shared time factor (T, B, Z: complex (n_t+1)^2 each), FP64
+    double2* d_tf = nullptr;      // shared time factor (real forms of E1, E3, E3^H, E1^H; eigenvalues), FP64
     float2* d_tff = nullptr;      // and its FP32 copy
     // profiling of finest-level sweeps
     bool prof = false;
@@ -666,17 +724,34 @@ int build(lam_ctx* c, const double* v0_dev) {
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
         return LAM_ENOMEM;
     {
-        // shared time factor: T, B, Z (complex n x n, row-major), as interleaved reals
-        const int n = nt + 1;
-        std::vector<cd> B(n * n), Z(n * n), T(n * n);
-        if (!time_factor(nt, c->U, B.data(), Z.data(), T.data())) return LAM_EINVAL;
+        // shared time factor, as reals: the real forms (2n x 2n, acting on interleaved
+        // re/im) of E1, E3 (forward) and E3^H, E1^H (adjoint), then lam (n complex)
+        const int n = nt + 1, n2 = 2 * n;
+        std::vector<cd> E1(n * n), E3(n * n), lam(n);
+        if (!time_factor(nt, c->U, E1.data(), E3.data(), lam.data())) return LAM_EINVAL;
         std::vector<double> h;
-        h.reserve(6 * n * n);
-        for (const auto* M : {&T, &B, &Z})
-            for (const cd& v : *M) {
-                h.push_back(v.real());
-                h.push_back(v.imag());
-            }
+        h.reserve(4 * n2 * n2 + 2 * n);
+        auto expand = [&](const std::vector<cd>& M, bool herm) {
+            for (int r = 0; r < n2; ++r)
+                for (int q = 0; q < n2; ++q) {
+                    const int p = r >> 1, a = r & 1, qq = q >> 1, cc = q & 1;
+                    const cd m = herm ? std::conj(M[qq * n + p]) : M[p * n + qq];
+                    double v;
+                    if (a == 0 && cc == 0) v = m.real();
+                    else if (a == 0 && cc == 1) v = -m.imag();
+                    else if (a == 1 && cc == 0) v = m.imag();
+                    else v = m.real();
+                    h.push_back(v);
+                }
+        };
+        expand(E1, false);
+        expand(E3, false);
+        expand(E3, true);
+        expand(E1, true);
+        for (const cd& v : lam) {
+            h.push_back(v.real());
+            h.push_back(v.imag());
+        }
         std::vector<float> hf(h.begin(), h.end());
         LAMCHK(dalloc(&c->d_tf, h.size() / 2));
         LAMCHK(dalloc(&c->d_tff, hf.size() / 2));

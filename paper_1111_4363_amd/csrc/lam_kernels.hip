@@ -748,100 +748,45 @@ __device__ __forceinline__ int halo_nb(const LevelGeom& g, const I3& gi, const I
     return point_index(g, with_comp(gi, ax, ga));
 }
 
-// Per-mode time solve with the shared factor, for all modes of a block at once.
-// y_k = Z (I - e_k T)^{-1} B r_k (adjoint: B^H (I - e_k T)^{-H} Z^H r_k), with T
-// upper triangular; r_k = rh[k][.] is replaced by y_k.  Eight lanes per mode
-// (512 threads: 64 modes): lane r owns rows r and r + 8.  The lanes first form
-// x = B r_k (Z^H r_k) for their rows, then substitute through (I - e T) one
-// unknown at a time, broadcasting each solved unknown inside the 8-lane group
-// and folding it straight into the final product with Z (B^H).  The group is
-// one wave's slice, so no barrier is needed: rh[k] is read and written only by
-// the lanes of mode k, reads first.  The loops stay rolled: unrolled, the
-// compiler hoists every step's operand loads and the register count doubles.
-template <int NQ, typename T, bool adjoint>
-__device__ __forceinline__ void mode_solve(const cx<T>* __restrict__ tfc, const T* __restrict__ es,
-                                           cx<T>* __restrict__ rh, int b, int tid) {
-    using C = cx<T>;
-    constexpr int NS = (NQ + 7) / 8;
-    const C* Tm = tfc;
-    const C* Bm = tfc + NQ * NQ;
-    const C* Zm = Bm + NQ * NQ;
-    const int k = tid >> 3, r = tid & 7;
-    const int kc = k < b ? k : b - 1;
-    const int lane = tid & 63, gbase = lane & ~7;
-    const T ev = es[kc];
-    C acc[NS], out[NS], inv[NS];
-    int pc[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int p = r + 8 * s;
-        pc[s] = p < NQ ? p : NQ - 1;
-        acc[s] = C{(T)0, (T)0};
-        out[s] = C{(T)0, (T)0};
-        const C tpp = Tm[pc[s] * NQ + pc[s]];
-        inv[s] = cdiv(C{(T)1, (T)0}, C{(T)1 - ev * tpp.r, (adjoint ? ev : -ev) * tpp.i});
+// Per-mode mixing on the matrix cores: Y[mode][.] = E X[mode][.] for every mode of
+// the block, with E a real n2 x n2 matrix (the real form of a complex NQ x NQ
+// matrix acting on interleaved (re, im) values) and X, Y rows of length n2.
+// Wave w owns modes 16 (w % 4) .. and result rows 16 (w / 4) ..; operand loads
+// are unconditional (clamped index times a 0/1 factor).
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::acc_t mode_mix(const T* __restrict__ E, const T* __restrict__ X,
+                                                            int b, int n2, int lane, int wave) {
+    typename Mfma<T>::acc_t acc;
+    for (int r = 0; r < 4; ++r) acc[r] = (T)0;
+    const int nt = wave & 3, mt = wave >> 2;
+    if (16 * nt >= b || 16 * mt >= n2) return acc;
+    const int i = lane & 15, kq = lane >> 4;
+    const int mode = 16 * nt + i, row = 16 * mt + i;
+    const T fmode = mode < b ? (T)1 : (T)0;
+    const int modec = mode < b ? mode : b - 1, rowc = row < n2 ? row : n2 - 1;
+    const int ksteps = (n2 + 3) >> 2;
+#pragma unroll 5
+    for (int kk = 0; kk < ksteps; ++kk) {
+        const int k = 4 * kk + kq;
+        const T fk = k < n2 ? (T)1 : (T)0;
+        const int kc = k < n2 ? k : n2 - 1;
+        const T bv = X[modec * n2 + kc] * (fmode * fk);
+        const T av = E[rowc * n2 + kc];
+        acc = Mfma<T>::step(av, bv, acc);
     }
-#pragma unroll 3
-    for (int q = 0; q < NQ; ++q) {
-        const C rq = rh[kc * NQ + q];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (!adjoint) acc[s] = acc[s] + cmul(Bm[pc[s] * NQ + q], rq);
-            else acc[s] = acc[s] + cmulc(Zm[q * NQ + pc[s]], rq);
-        }
-    }
-    // coupling and output coefficients of step j for row slot s
-    auto coef_t = [&](int j, int s) -> C {
-        return adjoint ? C{Tm[j * NQ + pc[s]].r, -Tm[j * NQ + pc[s]].i} : Tm[pc[s] * NQ + j];
-    };
-    auto coef_o = [&](int j, int s) -> C {
-        return adjoint ? C{Bm[j * NQ + pc[s]].r, -Bm[j * NQ + pc[s]].i} : Zm[pc[s] * NQ + j];
-    };
-    C tcn[NS], e3n[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        tcn[s] = coef_t(adjoint ? 0 : NQ - 1, s);
-        e3n[s] = coef_o(adjoint ? 0 : NQ - 1, s);
-    }
-#pragma unroll 1
-    for (int jj = 0; jj < NQ; ++jj) {
-        // forward: back substitution (j = NQ-1 .. 0); adjoint: forward substitution
-        const int j = adjoint ? jj : NQ - 1 - jj;
-        C tc[NS], e3[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            tc[s] = tcn[s];
-            e3[s] = e3n[s];
-        }
-        if (jj + 1 < NQ) {  // the next step's coefficients, loaded a step ahead
-            const int jn = adjoint ? j + 1 : j - 1;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                tcn[s] = coef_t(jn, s);
-                e3n[s] = coef_o(jn, s);
-            }
-        }
-        const bool hi = j >= 8;
-        const C own = hi ? acc[NS - 1] : acc[0];
-        const C iv = hi ? inv[NS - 1] : inv[0];
-        C y = cmul(own, iv);
-        const int src = gbase | (j & 7);
-        y.r = __shfl(y.r, src, 64);
-        y.i = __shfl(y.i, src, 64);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int p = r + 8 * s;
-            // couple the unknowns still to be solved: rows above j (forward) / below j (adjoint)
-            const bool open = adjoint ? (p > j && p < NQ) : (p < j);
-            const T f = open ? ev : (T)0;
-            acc[s] = acc[s] + cmul(C{f * tc[s].r, f * tc[s].i}, y);
-            out[s] = out[s] + cmul(e3[s], y);
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int p = r + 8 * s;
-        if (k < b && p < NQ) rh[k * NQ + p] = out[s];
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ void mode_mix_store(T* __restrict__ Y, int b, int n2, int lane, int wave,
+                                               const typename Mfma<T>::acc_t& acc) {
+    const int nt = wave & 3, mt = wave >> 2;
+    if (16 * nt >= b || 16 * mt >= n2) return;
+    const int mode = 16 * nt + (lane & 15);
+    if (mode >= b) return;
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * mt + Mfma<T>::row(lane, r);
+        if (row < n2) Y[mode * n2 + row] = acc[r];
     }
 }
 
@@ -857,7 +802,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     constexpr int N2 = 2 * NQ;                               // reals per point / mode
     constexpr int IPT = (kMaxB * NT + kSweepThreads - 1) / kSweepThreads;  // residual items per thread
     constexpr int VPT = kMaxB * kMaxB / kSweepThreads;       // eigenvector entries per thread
-    constexpr int TFR = 6 * NQ * NQ;                         // reals of T, B, Z (complex NQ x NQ each)
+    constexpr int TFR = 8 * NQ * NQ + 2 * NQ;                // reals of the two mixing matrices and lam
     constexpr int TPT = (TFR + kSweepThreads - 1) / kSweepThreads;
     using C = cx<BT>;
     __shared__ BT Vs[kMaxB * kLdsPad];
@@ -868,7 +813,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __shared__ int gidx[kMaxB];
     __shared__ C rs[kMaxB * NQ];   // local residual
     __shared__ C rh[kMaxB * NQ];   // V^T r, per-mode solutions, then the correction
-    __shared__ BT tfs[TFR];        // shared time factor: T, B, Z (complex NQ x NQ, row-major)
+    __shared__ BT tfs[TFR];        // shared time factor: E1, E3 (adjoint: E3^H, E1^H) real forms, lam
     __shared__ BT es[kMaxB];
     __shared__ double red[kSweepThreads / 64];
     __shared__ double rnorm_sh;
@@ -934,10 +879,13 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     BT ep = (BT)0;
     if constexpr (shared_tf) {
         const BT* tfg = static_cast<const BT*>(a.tf);
+        // the mixing pair of this direction (the adjoint pair follows the forward one), then lam
+        const int off_mix = a.adjoint ? 8 * NQ * NQ : 0;
 #pragma unroll
         for (int r = 0; r < TPT; ++r) {
             const int t = tid + r * kSweepThreads;
-            tr[r] = tfg[t < TFR ? t : TFR - 1];
+            const int tt = t < TFR ? t : TFR - 1;
+            tr[r] = tfg[tt < 8 * NQ * NQ ? off_mix + tt : 8 * NQ * NQ + tt];
         }
         ep = (BT)(a.e[(size_t)blk * b + tp] + a.shift[blk]);
     }
@@ -1066,9 +1014,39 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                 }
             }
         } else {
-            // shared factor: M(e)^{-1} = Z (I - e T)^{-1} B   (adjoint: B^H (I - e T)^{-H} Z^H)
-            if (a.adjoint) mode_solve<NQ, BT, true>(reinterpret_cast<const C*>(tfs), es, rh, b, tid);
-            else mode_solve<NQ, BT, false>(reinterpret_cast<const C*>(tfs), es, rh, b, tid);
+            // shared factor: M(e)^{-1} = E3 (I - e J)^{-1} E1   (adjoint: E1^H (I - e J)^{-H} E3^H),
+            // J = diag(lam) + (the Jordan pair's coupling, 1 at row 0, column 1)
+            const BT* E1 = tfs;                      // adjoint: E3^H
+            const BT* E3 = tfs + 4 * NQ * NQ;        // adjoint: E1^H
+            const C* lamv = reinterpret_cast<const C*>(tfs + 8 * NQ * NQ);
+            {
+                const auto acc = mode_mix<BT>(E1, reinterpret_cast<const BT*>(rh), b, N2, lane, wave);
+                __syncthreads();
+                mode_mix_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
+            }
+            __syncthreads();
+            // (I - e J)^{-1}: 1 / (1 - e lam_p) per entry, and the Jordan pair's coupling
+            // (forward: x0 += e x1; adjoint: x1 += e x0; both read an entry left unchanged)
+            for (int t = tid; t < b * NQ; t += kSweepThreads) {
+                const int k = t / NQ, p = t - (t / NQ) * NQ;
+                const BT ev = es[k];
+                const C x = rh[t];
+                if (p >= 2) {
+                    const C lp = lamv[p];
+                    const BT dr = (BT)1 - ev * lp.r, di = (a.adjoint ? ev : -ev) * lp.i;
+                    const BT sc = (BT)1 / (dr * dr + di * di);
+                    rh[t] = C{(x.r * dr + x.i * di) * sc, (x.i * dr - x.r * di) * sc};
+                } else if (p == (a.adjoint ? 1 : 0)) {
+                    const C o = rh[t + (a.adjoint ? -1 : 1)];
+                    rh[t] = C{x.r + ev * o.r, x.i + ev * o.i};
+                }
+            }
+            __syncthreads();
+            {
+                const auto acc = mode_mix<BT>(E3, reinterpret_cast<const BT*>(rh), b, N2, lane, wave);
+                __syncthreads();
+                mode_mix_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
+            }
         }
         __syncthreads();
         // ---- 3c. correction di[j][.] = sum_k V[j][k] rh[k][.], written back into rh ----
