@@ -428,6 +428,8 @@ int sweep(lam_ctx* c, int l, int colour) {
     SweepArgs a{};
     a.g = L.g;
     a.blocks = L.d_blocks[colour];
+    a.colour = colour;
+    a.arith_blocks = (L.g.nblk[L.g.dim - 1] % 2 == 0) ? 1 : 0;
     a.c = L.d_c;
     a.lam = L.d_lam;
     a.v0 = L.d_v0;

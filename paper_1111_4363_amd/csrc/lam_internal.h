@@ -43,6 +43,9 @@ struct TimeOps {
 struct SweepArgs {
     LevelGeom g;
     const int* blocks;        // block ids of the colour being relaxed
+    int colour;               // that colour (parity of the sum of block coordinates)
+    int arith_blocks;         // 1: the block grid's last axis has an even count, and the
+                              //    colour's blocks are enumerated arithmetically (no table)
     double2* c;               // [P][NT]
     double2* lam;             // [P]
     const double* v0;         // [P]

@@ -821,13 +821,33 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const LevelGeom& g = a.g;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int blk = a.blocks[blockIdx.x];
+    // block of this workgroup: the colour's blocks in C order
+    int blk;
+    I3 bc;
+    if (a.arith_blocks) {
+        // each line along the last block axis holds nblk/2 blocks of each colour,
+        // at 2i + (colour + sum of the line's other coordinates) mod 2
+        const int la = g.dim - 1;
+        const int half = g.nblk[la] >> 1;
+        const int line = (int)blockIdx.x / half, i = (int)blockIdx.x - line * half;
+        int lead0 = 0, lead1 = 0;
+        if (g.dim == 2) lead0 = line;
+        if (g.dim == 3) {
+            lead0 = line / g.nblk[1];
+            lead1 = line - lead0 * g.nblk[1];
+        }
+        const int last = 2 * i + ((a.colour + lead0 + lead1) & 1);
+        bc = I3{g.dim == 1 ? last : lead0, g.dim == 2 ? last : (g.dim == 3 ? lead1 : 0), g.dim == 3 ? last : 0};
+        blk = (bc.x * g.nblk[1] + bc.y) * g.nblk[2] + bc.z;
+    } else {
+        blk = a.blocks[blockIdx.x];
+        bc = block_coords(g, blk);
+    }
     const int b = g.bpts;
     const int nd = 2 * g.dim;
     constexpr bool shared_tf = !STORED;
     // inner passes stop once the block's own residual fell below this fraction (in norm)
     const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-12;
-    const I3 bc = block_coords(g, blk);
 
     // ---- 1a. addresses (no loads yet); thread = residual item (point l, component m) ----
     static_assert(kMaxB * kMaxNT <= kSweepThreads, "one residual item per thread");
@@ -1057,10 +1077,19 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         }
         __syncthreads();
         const C* di = rh;
-        // ---- accumulate, and for inner passes update the local residual ----
+        // ---- accumulate, and for inner passes update the local residual; the
+        //      last possible pass writes the updated state straight to HBM ----
+        const bool last = pass == a.n_inner;
         for (int t = tid; t < b * NQ; t += kSweepThreads) {
             const int l = t / NQ, q = t - l * NQ;
             const C dv = di[t];
+            if (last) {
+                if (q < NT)
+                    a.c[(size_t)gidx[l] * NT + q] = add2(cs[l * NT + q], make_double2((double)dv.r, (double)dv.i));
+                else
+                    a.lam[gidx[l]] = add2(ls[l], make_double2((double)dv.r, (double)dv.i));
+                continue;
+            }
             if (q < NT)
                 cs[l * NT + q] = add2(cs[l * NT + q], make_double2((double)dv.r, (double)dv.i));
             else
@@ -1095,6 +1124,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                 rs[t] = rs[t] - y;
             }
         }
+        if (last) break;
         __syncthreads();
         if (pass < a.n_inner) {
             // stop the defect corrections once the local system is solved
@@ -1105,16 +1135,17 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             __syncthreads();
             const bool done = rnorm_sh <= inner_tol2 * r0n;
             __syncthreads();
-            if (done) break;
+            if (done) {
+                // ---- 5. write back (after an early stop of the passes) ----
+                for (int t = tid; t < b * NT; t += kSweepThreads) {
+                    const int l = t / NT, n = t - l * NT;
+                    a.c[(size_t)gidx[l] * NT + n] = cs[t];
+                }
+                for (int l = tid; l < b; l += kSweepThreads) a.lam[gidx[l]] = ls[l];
+                break;
+            }
         }
     }
-
-    // ---- 5. write back ----
-    for (int t = tid; t < b * NT; t += kSweepThreads) {
-        const int l = t / NT, n = t - l * NT;
-        a.c[(size_t)gidx[l] * NT + n] = cs[t];
-    }
-    for (int l = tid; l < b; l += kSweepThreads) a.lam[gidx[l]] = ls[l];
 }
 
 // ---------------------------------------------------------------------------
