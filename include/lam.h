@@ -202,6 +202,18 @@ int lam_vcycle(lam_ctx* ctx, double* norm);
 int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_out,
                    lam_stats* stats);
 
+/* Propagate n_steps consecutive steps, step k starting at t0 + k dt, each
+ * solved as by lam_solve_step: psi_in (device, P) -> psi_out (device, P); the
+ * buffers may coincide.  The steps run back to back on the context stream
+ * with no host round trip between them.  stats (may be NULL): cycles and
+ * sweeps_fine summed over the steps, resid0/resid of the step with the
+ * largest resid/resid0, t_factor_ms and t_solve_ms summed.  Stops at the first
+ * step that does not return LAM_OK and returns its code (psi_out then holds
+ * that step's result for LAM_ENOCONV); n_steps = 0 copies nothing and
+ * returns LAM_OK. */
+int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, lam_c64* psi_out,
+                  lam_stats* stats);
+
 /* Backward pass of one step for a real loss L.  psi_in: the step's initial
  * wavefunction (device checkpoint; the forward solve is recomputed from it).
  * g_out = dL/dpsi_out^* (device, P).  Solves K^H mu = E^H g_out with the same

@@ -329,7 +329,13 @@ struct lam_ctx {
     double* d_partial = nullptr;
     int max_parts = 0;
     double* d_red = nullptr;
-    double* h_red = nullptr;      // pinned
+    double* h_red = nullptr;      // pinned, mapped: the norm reduction writes it directly
+    double* h_red_dev = nullptr;  // its device-side address
+    hipEvent_t ev_norm = nullptr; // completion of the latest norm reduction
+    double* h_norms = nullptr;    // pinned, mapped: N after each queued V-cycle of a solve (slot 0: N0)
+    double* h_norms_dev = nullptr;
+    int predict[2] = {0, 0};      // V-cycles the last forward / adjoint solve needed (0: none yet)
+    std::vector<double> gl_x, gl_w;  // Gauss-Legendre nodes of the field quadrature
     double2* d_Gpart = nullptr;
     double2* d_G = nullptr;
     double2* h_G = nullptr;       // pinned
@@ -365,8 +371,8 @@ double field_value(const lam_ctx* c, double t) {
 void time_matrix(const lam_ctx* c, double t0, int q, double* W) {
     const int nt = c->nt;
     const double dt = c->time.dt;
-    std::vector<double> x, w;
-    gauss_legendre(48, x, w);
+    const std::vector<double>& x = c->gl_x;
+    const std::vector<double>& w = c->gl_w;
     for (int k = 0; k < nt * nt; ++k) W[k] = 0.0;
     double P[kMaxNT];
     for (size_t k = 0; k < x.size(); ++k) {
@@ -488,6 +494,20 @@ int level_residual(lam_ctx* c, int l) {
     return LAM_OK;
 }
 
+// Wait for the work queued on the context stream (e.g. a norm reduction that
+// writes host memory): an event polled in a loop, so the host resumes as soon
+// as the work is done (a blocking stream synchronisation can add tens of
+// microseconds of wake-up latency to every V-cycle).
+int wait_stream(lam_ctx* c) {
+    HIPCHK(hipEventRecord(c->ev_norm, c->st));
+    for (;;) {
+        const hipError_t e = hipEventQuery(c->ev_norm);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) return LAM_EHIP;
+    }
+    return LAM_OK;
+}
+
 // N of the finest level for the context state (synchronises).
 int norm0(lam_ctx* c, double* out) {
     Level& L = c->lv[0];
@@ -496,9 +516,8 @@ int norm0(lam_ctx* c, double* out) {
     int np = 0;
     HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, nullptr, bg, bs, nullptr,
                            nullptr, c->d_partial, &np, c->st));
-    HIPCHK(launch_reduce(c->d_partial, np, 1, c->d_red, c->st));
-    HIPCHK(hipMemcpyAsync(c->h_red, c->d_red, sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(launch_reduce(c->d_partial, np, 1, c->h_red_dev, c->st));
+    LAMCHK(wait_stream(c));
     *out = c->h_red[0];
     return LAM_OK;
 }
@@ -520,32 +539,74 @@ int vcycle(lam_ctx* c, int l) {
 }
 
 // V-cycles on the context state until sqrt(N/N0) <= tol.
+// Queue N of the finest level for the context state into h_norms[slot] (no wait).
+int queue_norm(lam_ctx* c, int slot) {
+    Level& L = c->lv[0];
+    const double2* bg = c->adjoint ? c->d_g : nullptr;
+    const double2* bs = c->adjoint ? nullptr : L.d_bs;
+    int np = 0;
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, nullptr, bg,
+                           bs, nullptr, nullptr, c->d_partial, &np, c->st));
+    HIPCHK(launch_reduce(c->d_partial, np, 1, c->h_norms_dev + slot, c->st));
+    return LAM_OK;
+}
+
+// V-cycles until sqrt(N/N0) <= tol.  The cycles are queued in batches: as many
+// as the previous solve of the same kind needed (none before the first wait of
+// a context's first solve), each followed by its norm (written to host
+// memory), then one wait; after that one cycle per wait.  A
+// host round trip per cycle would leave the GPU idle while the next cycle is
+// launched.  When a batch overshoots, the extra cycles only refine the state;
+// `cycles` reports the cycles run.
 int solve_loop(lam_ctx* c, lam_stats* stats) {
+    const int maxc = c->solver.max_cycles;
+    int& predict = c->predict[c->adjoint ? 1 : 0];
+    LAMCHK(queue_norm(c, 0));
+    int queued = 0, conv = -1;
+    int rc = LAM_ENOCONV;
+    int batch = std::min(predict, maxc);  // 0 on a context's first solve: look at N0 first
     double N0 = 0.0, N = 0.0;
-    LAMCHK(norm0(c, &N0));
-    N = N0;
-    int cycles = 0;
-    int rc = LAM_OK;
-    if (!std::isfinite(N0)) {
-        rc = LAM_EDIVERGED;
-    } else if (N0 > 0.0) {
-        rc = LAM_ENOCONV;
-        for (cycles = 0; cycles < c->solver.max_cycles;) {
+    for (;;) {
+        const int nb = std::min(batch, maxc - queued);
+        for (int i = 0; i < nb; ++i) {
             LAMCHK(vcycle(c, 0));
-            ++cycles;
-            LAMCHK(norm0(c, &N));
-            if (!std::isfinite(N) || N > 1e12 * N0) {
-                rc = LAM_EDIVERGED;
-                break;
-            }
-            if (std::sqrt(N / N0) <= c->solver.tol) {
-                rc = LAM_OK;
-                break;
-            }
+            ++queued;
+            LAMCHK(queue_norm(c, queued));
         }
+        LAMCHK(wait_stream(c));
+        N0 = c->h_norms[0];
+        N = c->h_norms[queued];
+        if (!std::isfinite(N0)) {
+            rc = LAM_EDIVERGED;
+            break;
+        }
+        if (N0 == 0.0) {
+            rc = LAM_OK;
+            break;
+        }
+        bool div = false;
+        for (int k = queued - nb + 1; k <= queued; ++k) {
+            const double Nk = c->h_norms[k];
+            if (!std::isfinite(Nk) || Nk > 1e12 * N0) {
+                div = true;
+                break;
+            }
+            if (conv < 0 && std::sqrt(Nk / N0) <= c->solver.tol) conv = k;
+        }
+        if (div) {
+            rc = LAM_EDIVERGED;
+            break;
+        }
+        if (conv >= 0) {
+            rc = LAM_OK;
+            break;
+        }
+        if (queued >= maxc) break;
+        batch = 1;
     }
+    if (conv > 0) predict = conv;
     if (stats) {
-        stats->cycles = cycles;
+        stats->cycles = queued;
         stats->resid0 = std::sqrt(N0);
         stats->resid = std::sqrt(N);
     }
@@ -635,6 +696,8 @@ void free_ctx(lam_ctx* c) {
     (void)hipFree(c->d_tf);
     (void)hipFree(c->d_tff);
     if (c->h_red) (void)hipHostFree(c->h_red);
+    if (c->ev_norm) (void)hipEventDestroy(c->ev_norm);
+    if (c->h_norms) (void)hipHostFree(c->h_norms);
     if (c->h_G) (void)hipHostFree(c->h_G);
     for (auto e : c->ev) (void)hipEventDestroy(e);
     delete c;
@@ -722,7 +785,15 @@ int build(lam_ctx* c, const double* v0_dev) {
     LAMCHK(dalloc(&c->d_cf, (size_t)P0 * nt));
     LAMCHK(dalloc(&c->d_Gpart, (size_t)c->max_parts * nt * nt));
     LAMCHK(dalloc(&c->d_G, (size_t)nt * nt));
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_red), sizeof(double)) != hipSuccess) return LAM_ENOMEM;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_red), sizeof(double), hipHostMallocMapped) != hipSuccess)
+        return LAM_ENOMEM;
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_red_dev), c->h_red, 0));
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(double) * (c->solver.max_cycles + 2),
+                      hipHostMallocMapped) != hipSuccess)
+        return LAM_ENOMEM;
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_norms_dev), c->h_norms, 0));
+    gauss_legendre(48, c->gl_x, c->gl_w);
+    HIPCHK(hipEventCreateWithFlags(&c->ev_norm, hipEventDisableTiming));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
         return LAM_ENOMEM;
     {
@@ -831,9 +902,8 @@ int lam_residual_action(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_
                            reinterpret_cast<const double2*>(psi0), reinterpret_cast<double2*>(rho),
                            reinterpret_cast<double2*>(sigma), norm ? ctx->d_partial : nullptr, &np, ctx->st));
     if (norm) {
-        HIPCHK(launch_reduce(ctx->d_partial, np, 1, ctx->d_red, ctx->st));
-        HIPCHK(hipMemcpyAsync(ctx->h_red, ctx->d_red, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
-        HIPCHK(hipStreamSynchronize(ctx->st));
+        HIPCHK(launch_reduce(ctx->d_partial, np, 1, ctx->h_red_dev, ctx->st));
+        LAMCHK(wait_stream(ctx));
         *norm = ctx->h_red[0];
     }
     return LAM_OK;
@@ -850,9 +920,8 @@ int lam_residual_adjoint(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c6
                            reinterpret_cast<const double2*>(g), nullptr, reinterpret_cast<double2*>(rho),
                            reinterpret_cast<double2*>(sigma), norm ? ctx->d_partial : nullptr, &np, ctx->st));
     if (norm) {
-        HIPCHK(launch_reduce(ctx->d_partial, np, 1, ctx->d_red, ctx->st));
-        HIPCHK(hipMemcpyAsync(ctx->h_red, ctx->d_red, sizeof(double), hipMemcpyDeviceToHost, ctx->st));
-        HIPCHK(hipStreamSynchronize(ctx->st));
+        HIPCHK(launch_reduce(ctx->d_partial, np, 1, ctx->h_red_dev, ctx->st));
+        LAMCHK(wait_stream(ctx));
         *norm = ctx->h_red[0];
     }
     return LAM_OK;
@@ -927,12 +996,53 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
     const int rc = solve_loop(ctx, stats);
     if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
     HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, reinterpret_cast<double2*>(psi_out), ctx->st));
-    HIPCHK(hipStreamSynchronize(ctx->st));
+    LAMCHK(wait_stream(ctx));
     if (stats) {
         stats->sweeps_fine = ctx->sweeps_fine - sw0;
         stats->t_factor_ms = ctx->t_factor_ms;
         stats->t_solve_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
+    }
+    return rc;
+}
+
+int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, lam_c64* psi_out,
+                  lam_stats* stats) {
+    if (!ctx || bad_ptr(psi_in) || bad_ptr(psi_out) || n_steps < 0) return LAM_EINVAL;
+    const auto t_a = std::chrono::steady_clock::now();
+    ctx->t_factor_ms = 0.0;
+    const int sw0 = ctx->sweeps_fine;
+    Level& L = ctx->lv[0];
+    lam_stats tot{};
+    double worst = -1.0;
+    int rc = LAM_OK;
+    const lam_c64* src = psi_in;
+    for (int k = 0; k < n_steps; ++k) {
+        LAMCHK(set_step(ctx, t0 + k * ctx->time.dt));
+        HIPCHK(launch_init_forward(ctx->nt, L.g.P, reinterpret_cast<const double2*>(src), L.d_c, L.d_lam, L.d_bs,
+                                   ctx->st));
+        ctx->adjoint = 0;
+        ctx->have_state = 1;
+        lam_stats st{};
+        rc = solve_loop(ctx, &st);
+        if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
+        HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, reinterpret_cast<double2*>(psi_out), ctx->st));
+        src = psi_out;
+        tot.cycles += st.cycles;
+        const double ratio = st.resid0 > 0.0 ? st.resid / st.resid0 : 0.0;
+        if (ratio > worst) {
+            worst = ratio;
+            tot.resid0 = st.resid0;
+            tot.resid = st.resid;
+        }
+        if (rc != LAM_OK) break;
+    }
+    LAMCHK(wait_stream(ctx));
+    if (stats) {
+        tot.sweeps_fine = ctx->sweeps_fine - sw0;
+        tot.t_factor_ms = ctx->t_factor_ms;
+        tot.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
+        *stats = tot;
     }
     return rc;
 }

@@ -858,19 +858,29 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const I3 gi_it = global_of_local(g, bc, lc_it);
     const int gj_it = point_index(g, gi_it);
     // halo neighbours (outside the block; clamped to the point itself when absent)
-    // and in-block neighbours (local index, or -1)
+    // and in-block neighbours (local index, or -1), with selects only
     int hidx[6], lnb[6], hmask = 0;
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) {
-        hidx[dir] = gj_it;
-        lnb[dir] = -1;
-        if (dir < nd) {
-            const int ax = dir >> 1, d = (dir & 1) ? 1 : -1;
-            const int h = halo_nb(g, gi_it, lc_it, ax, d);
-            hidx[dir] = h >= 0 ? h : gj_it;
-            hmask |= (h >= 0 ? 1 : 0) << dir;
-            lnb[dir] = local_nb(g, lc_it, ax, d);
-        }
+        const int ax = dir >> 1;
+        const bool up = dir & 1;
+        const int la = comp(lc_it, ax), ga = comp(gi_it, ax);
+        const int bd = g.bdim[ax], na = g.n[ax];
+        const int lstr = ax == 0 ? g.bdim[1] * g.bdim[2] : (ax == 1 ? g.bdim[2] : 1);
+        const int gstr = ax == 0 ? g.n[1] * g.n[2] : (ax == 1 ? g.n[2] : 1);
+        const bool used = dir < nd;
+        const bool inside = up ? la + 1 < bd : la > 0;           // neighbour inside the block
+        const bool self_wrap = g.periodic && g.nblk[ax] == 1;    // the block spans a periodic axis
+        const bool edge = up ? ga + 1 >= na : ga == 0;           // neighbour outside the grid
+        const int lstep = up ? lstr : -lstr, gstep = up ? gstr : -gstr;
+        // in-block: plain step, or the wrap of a block that spans a periodic axis
+        const int lw = inside ? l_it + lstep : l_it - (up ? 1 : -1) * (bd - 1) * lstr;
+        lnb[dir] = used && (inside || self_wrap) ? lw : -1;
+        // halo: plain step, or the wrap of a periodic grid; none on a Dirichlet edge
+        const bool halo = used && !inside && !self_wrap && (!edge || g.periodic);
+        const int hw = edge ? gj_it - (up ? 1 : -1) * (na - 1) * gstr : gj_it + gstep;
+        hidx[dir] = halo ? hw : gj_it;
+        hmask |= (halo ? 1 : 0) << dir;
     }
     const int tp = tid < b ? tid : 0;
     const I3 gip = global_of_local(g, bc, local_coords(g, tp));

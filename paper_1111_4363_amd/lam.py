@@ -91,6 +91,7 @@ SIGNATURES = {
     "lam_relax_sweep": (_I, [_P, _I, _I]),
     "lam_vcycle": (_I, [_P, _PD]),
     "lam_solve_step": (_I, [_P, _D, _P, _P, ctypes.POINTER(LamStats)]),
+    "lam_propagate": (_I, [_P, _D, _I, _P, _P, ctypes.POINTER(LamStats)]),
     "lam_adjoint_step": (_I, [_P, _D, _P, _P, _P, _P, _PD, ctypes.POINTER(LamStats)]),
     "lam_restrict": (_I, [_P, _I, _P, _P, _P, _P]),
     "lam_prolong_add": (_I, [_P, _I, _P, _P, _P, _P]),
@@ -365,15 +366,28 @@ class Propagator:
 
     # -- conveniences ------------------------------------------------------
     def propagate(self, psi0, n_steps, t_start=0.0, keep=False):
+        """n_steps steps from t_start.  keep=False: one lam_propagate call (no
+        host round trip between steps); returns (psi, [summed stats]).
+        keep=True: step by step, returns ([psi_0, ..., psi_K], [stats per step])."""
         psi = psi0.contiguous()
-        out = [psi] if keep else None
+        if not keep:
+            if n_steps == 0:
+                return psi.clone(), [LamStats().as_dict()]
+            P = self.npts
+            out = self._new(P)
+            st = LamStats()
+            _check(self._lib.lam_propagate(self._ctx, float(t_start), int(n_steps),
+                                           _ptr(psi, torch.complex128, P, "psi0"),
+                                           _ptr(out, torch.complex128, P, "psi_out"), ctypes.byref(st)),
+                   "lam_propagate")
+            return out, [st.as_dict()]
+        out = [psi]
         stats = []
         for k in range(n_steps):
             psi, st = self.solve_step(t_start + k * self.dt, psi)
             stats.append(st)
-            if keep:
-                out.append(psi)
-        return (out if keep else psi), stats
+            out.append(psi)
+        return out, stats
 
 
 class LeastActionPropagate(torch.autograd.Function):

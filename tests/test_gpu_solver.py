@@ -177,3 +177,34 @@ def test_autograd_gradients_match_finite_differences():
         fd = (fwd(vp, coef) - fwd(vm, coef)) / (2 * eps)
         assert abs(fd - gv[i]) < 1e-6, (i, fd, gv[i])
     prop.close()
+
+
+def test_native_propagate_matches_stepwise_and_edge_cases():
+    """lam_propagate (steps back to back, batched convergence checks) against
+    step-by-step lam_solve_step and against the oracle's direct steps; the
+    in-place form (psi_in == psi_out) and n_steps = 0."""
+    import torch
+    case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=PULSE_FOURIER)
+    note(f"native propagate {case}")
+    psis = kkt.propagate(case.grid, case.v0, case.psi0, case.n_t, case.dt, 5, case.field)
+    prop = case.prop(tol=1e-12, max_cycles=60)
+    psi_native, st = prop.propagate(t_c(case.psi0), 5)
+    seq, _ = prop.propagate(t_c(case.psi0), 5, keep=True)
+    ref = np.abs(psis[-1]).max()
+    assert np.abs(n(psi_native) - psis[-1]).max() <= 1e-10 * ref
+    assert np.abs(n(psi_native) - n(seq[-1])).max() <= 1e-10 * ref
+    assert st[0]["cycles"] >= 5 and st[0]["resid"] <= 1e-12 * st[0]["resid0"] * 1.0001
+    # in place
+    from paper_1111_4363_amd import lam
+    buf = t_c(case.psi0).clone()
+    code = prop._lib.lam_propagate(prop._ctx, 0.0, 5, lam._ptr(buf, torch.complex128, case.npts),
+                                   lam._ptr(buf, torch.complex128, case.npts), None)
+    assert code == lam.LAM_OK
+    assert np.abs(n(buf) - psis[-1]).max() <= 1e-10 * ref
+    # zero steps: nothing written
+    keep = t_c(case.psi0).clone()
+    out = torch.full_like(keep, 7.0)
+    assert prop._lib.lam_propagate(prop._ctx, 0.0, 0, lam._ptr(keep, torch.complex128, case.npts),
+                                   lam._ptr(out, torch.complex128, case.npts), None) == lam.LAM_OK
+    assert torch.all(out == 7.0)
+    prop.close()
