@@ -436,6 +436,7 @@ int sweep(lam_ctx* c, int l, int colour) {
     a.blocks = L.d_blocks[colour];
     a.colour = colour;
     a.arith_blocks = (L.g.nblk[L.g.dim - 1] % 2 == 0) ? 1 : 0;
+    a.half_last = std::max(1, L.g.nblk[L.g.dim - 1] / 2);
     a.c = L.d_c;
     a.lam = L.d_lam;
     a.v0 = L.d_v0;

@@ -41,11 +41,14 @@ struct TimeOps {
 };
 
 struct SweepArgs {
-    LevelGeom g;
-    const int* blocks;        // block ids of the colour being relaxed
-    int colour;               // that colour (parity of the sum of block coordinates)
+    // first: what a workgroup needs to find its block (read together at entry)
+    int colour;               // the colour relaxed (parity of the sum of block coordinates)
     int arith_blocks;         // 1: the block grid's last axis has an even count, and the
                               //    colour's blocks are enumerated arithmetically (no table)
+    int half_last;            // half the block count of the last axis (arithmetic enumeration)
+    int pad_;
+    LevelGeom g;
+    const int* blocks;        // block ids of the colour being relaxed
     double2* c;               // [P][NT]
     double2* lam;             // [P]
     const double* v0;         // [P]

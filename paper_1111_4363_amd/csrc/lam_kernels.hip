@@ -777,6 +777,65 @@ __device__ __forceinline__ typename Mfma<T>::acc_t mode_mix(const T* __restrict_
     return acc;
 }
 
+// 1/d for normal, finite d: the hardware reciprocal estimate refined by
+// Newton-Raphson steps r <- r (2 - d r), each of which squares the relative
+// error (two steps in FP64, one in FP32 reach the last bit), without the
+// special-case handling of a full IEEE division.
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = r * (2.0 - d * r);
+    return r * (2.0 - d * r);
+}
+__device__ __forceinline__ float recip(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    return r * (2.0f - d * r);
+}
+
+// mode_mix whose input is first multiplied by (I - e_k J)^{-1} (adjoint: its
+// conjugate transpose), with J = diag(lam) + the Jordan pair's coupling (1 at
+// row 0, column 1; lam_0 = lam_1 = 0): entry p of mode k's vector becomes
+// x_p / (1 - e_k lam_p) (adjoint: conj(lam_p)), plus e_k x_1 for p = 0
+// (adjoint: e_k x_0 for p = 1).  Done on the operand loads, so the scaled
+// vector is never stored.  X holds NQ complex entries per mode.
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::acc_t mode_mix_scaled(const T* __restrict__ E, const cx<T>* __restrict__ X,
+                                                                   const T* __restrict__ es,
+                                                                   const cx<T>* __restrict__ lamv, bool adjoint,
+                                                                   int b, int nq, int lane, int wave) {
+    typename Mfma<T>::acc_t acc;
+    for (int r = 0; r < 4; ++r) acc[r] = (T)0;
+    const int n2 = 2 * nq;
+    const int nt = wave & 3, mt = wave >> 2;
+    if (16 * nt >= b || 16 * mt >= n2) return acc;
+    const int i = lane & 15, kq = lane >> 4;
+    const int mode = 16 * nt + i, row = 16 * mt + i;
+    const T fmode = mode < b ? (T)1 : (T)0;
+    const int modec = mode < b ? mode : b - 1, rowc = row < n2 ? row : n2 - 1;
+    const T ev = es[modec];
+    const int pj = adjoint ? 1 : 0, po = adjoint ? 0 : 1;   // the coupled entry and its partner
+    const cx<T> xo = X[modec * nq + po];
+    const int ksteps = (n2 + 3) >> 2;
+#pragma unroll 5
+    for (int kk = 0; kk < ksteps; ++kk) {
+        const int k = 4 * kk + kq;
+        const T fk = k < n2 ? (T)1 : (T)0;
+        const int kc = k < n2 ? k : n2 - 1;
+        const int p = kc >> 1;
+        const cx<T> x = X[modec * nq + p];
+        const cx<T> lp = lamv[p];
+        const T dr = (T)1 - ev * lp.r, di = (adjoint ? ev : -ev) * lp.i;   // 1 - e lam (adjoint: conj)
+        const T sc = recip(dr * dr + di * di);
+        T yr = (x.r * dr + x.i * di) * sc, yi = (x.i * dr - x.r * di) * sc;
+        const T fj = p == pj ? ev : (T)0;
+        yr += fj * xo.r;
+        yi += fj * xo.i;
+        const T bv = ((kc & 1) ? yi : yr) * (fmode * fk);
+        const T av = E[rowc * n2 + kc];
+        acc = Mfma<T>::step(av, bv, acc);
+    }
+    return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ void mode_mix_store(T* __restrict__ Y, int b, int n2, int lane, int wave,
                                                const typename Mfma<T>::acc_t& acc) {
@@ -812,7 +871,8 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __shared__ double zs[kMaxB];
     __shared__ int gidx[kMaxB];
     __shared__ C rs[kMaxB * NQ];   // local residual
-    __shared__ C rh[kMaxB * NQ];   // V^T r, per-mode solutions, then the correction
+    __shared__ C rh[kMaxB * NQ];   // V^T r, then the per-mode solutions
+    __shared__ C xb[kMaxB * NQ];   // E1 V^T r (shared factor), then the correction V y
     __shared__ BT tfs[TFR];        // shared time factor: E1, E3 (adjoint: E3^H, E1^H) real forms, lam
     __shared__ BT es[kMaxB];
     __shared__ double red[kSweepThreads / 64];
@@ -821,26 +881,21 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const LevelGeom& g = a.g;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    // block of this workgroup: the colour's blocks in C order
-    int blk;
-    I3 bc;
-    if (a.arith_blocks) {
-        // each line along the last block axis holds nblk/2 blocks of each colour,
-        // at 2i + (colour + sum of the line's other coordinates) mod 2
-        const int la = g.dim - 1;
-        const int half = g.nblk[la] >> 1;
-        const int line = (int)blockIdx.x / half, i = (int)blockIdx.x - line * half;
-        int lead0 = 0, lead1 = 0;
-        if (g.dim == 2) lead0 = line;
-        if (g.dim == 3) {
-            lead0 = line / g.nblk[1];
-            lead1 = line - lead0 * g.nblk[1];
-        }
-        const int last = 2 * i + ((a.colour + lead0 + lead1) & 1);
-        bc = I3{g.dim == 1 ? last : lead0, g.dim == 2 ? last : (g.dim == 3 ? lead1 : 0), g.dim == 3 ? last : 0};
-        blk = (bc.x * g.nblk[1] + bc.y) * g.nblk[2] + bc.z;
-    } else {
-        blk = a.blocks[blockIdx.x];
+    // block of this workgroup: the colour's blocks in C order.  Everything the
+    // arithmetic enumeration needs is read up front (no load depends on another).
+    const int dim = g.dim, colour = a.colour, half = a.half_last, nb1 = g.nblk[1], nb2 = g.nblk[2];
+    // each line along the last block axis holds nblk/2 blocks of each colour, at
+    // 2i + (colour + sum of the line's other coordinates) mod 2 (computed before the
+    // branch so that its inputs are loaded with the first batch)
+    const int idx = (int)blockIdx.x;
+    const int line = idx / half, i = idx - line * half;
+    const int lead0 = dim == 3 ? line / nb1 : line;
+    const int lead1 = dim == 3 ? line - lead0 * nb1 : 0;
+    const int last = 2 * i + ((colour + lead0 + lead1) & 1);
+    I3 bc{dim == 1 ? last : lead0, dim == 2 ? last : (dim == 3 ? lead1 : 0), dim == 3 ? last : 0};
+    int blk = (bc.x * nb1 + bc.y) * nb2 + bc.z;
+    if (!a.arith_blocks) {
+        blk = a.blocks[idx];
         bc = block_coords(g, blk);
     }
     const int b = g.bpts;
@@ -1051,42 +1106,22 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             const C* lamv = reinterpret_cast<const C*>(tfs + 8 * NQ * NQ);
             {
                 const auto acc = mode_mix<BT>(E1, reinterpret_cast<const BT*>(rh), b, N2, lane, wave);
-                __syncthreads();
-                mode_mix_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
-            }
-            __syncthreads();
-            // (I - e J)^{-1}: 1 / (1 - e lam_p) per entry, and the Jordan pair's coupling
-            // (forward: x0 += e x1; adjoint: x1 += e x0; both read an entry left unchanged)
-            for (int t = tid; t < b * NQ; t += kSweepThreads) {
-                const int k = t / NQ, p = t - (t / NQ) * NQ;
-                const BT ev = es[k];
-                const C x = rh[t];
-                if (p >= 2) {
-                    const C lp = lamv[p];
-                    const BT dr = (BT)1 - ev * lp.r, di = (a.adjoint ? ev : -ev) * lp.i;
-                    const BT sc = (BT)1 / (dr * dr + di * di);
-                    rh[t] = C{(x.r * dr + x.i * di) * sc, (x.i * dr - x.r * di) * sc};
-                } else if (p == (a.adjoint ? 1 : 0)) {
-                    const C o = rh[t + (a.adjoint ? -1 : 1)];
-                    rh[t] = C{x.r + ev * o.r, x.i + ev * o.i};
-                }
+                mode_mix_store<BT>(reinterpret_cast<BT*>(xb), b, N2, lane, wave, acc);
             }
             __syncthreads();
             {
-                const auto acc = mode_mix<BT>(E3, reinterpret_cast<const BT*>(rh), b, N2, lane, wave);
-                __syncthreads();
+                const auto acc = mode_mix_scaled<BT>(E3, xb, es, lamv, a.adjoint, b, NQ, lane, wave);
                 mode_mix_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
             }
         }
         __syncthreads();
-        // ---- 3c. correction di[j][.] = sum_k V[j][k] rh[k][.], written back into rh ----
+        // ---- 3c. correction di[j][.] = sum_k V[j][k] rh[k][.], into xb ----
         {
             const auto acc = tile_gemm<BT, false, N2>(Vs, reinterpret_cast<const BT*>(rh), b, lane, wave);
-            __syncthreads();
-            tile_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
+            tile_store<BT>(reinterpret_cast<BT*>(xb), b, N2, lane, wave, acc);
         }
         __syncthreads();
-        const C* di = rh;
+        const C* di = xb;
         // ---- accumulate, and for inner passes update the local residual; the
         //      last possible pass writes the updated state straight to HBM ----
         const bool last = pass == a.n_inner;
