@@ -119,9 +119,15 @@ def cpu_baseline(budget_s=20.0):
 
 def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
     shape = cfg["shape"]
+    torch.cuda.synchronize()
+    t_f = time.perf_counter()
+    # context creation = hierarchy + factorisation of every block of every level (once per run for a
+    # static potential)
     prop = lam.Propagator(shape, cfg["h"], v0_t, cfg["n_t"], cfg["dt"], (cfg["block"],) * cfg["dim"],
                           levels=cfg["levels"], nu_pre=1, nu_post=1, nu_coarse=2, precision=precision,
                           tol=args.tol, max_cycles=60)
+    torch.cuda.synchronize()
+    factor_ms = (time.perf_counter() - t_f) * 1e3
     psi = psi0_t.clone()
     t = 0.0
     if args.warmup:
@@ -157,6 +163,7 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
         "sweep_kernel_ms_avg": sweep_ms / launches if launches else None,
         "sweep_kernel_munk_sweeps_per_s": kernel_rate,
         "norm_after": norm,
+        "factor_ms": factor_ms,
     }
 
 

@@ -497,18 +497,21 @@ __global__ __launch_bounds__(kThreads) void k_average_potential(LevelGeom f, Lev
 // ---------------------------------------------------------------------------
 // K2a: spectral factor of every block's spatial operator A_U = T_U + diag(V0_U)
 // (T_U: the kinetic stencil restricted to the block, exterior fixed at zero).
-// Parallel cyclic Jacobi in LDS, one workgroup per block, round-robin pairing
-// so that nn/2 disjoint rotations run at once.  Output V[blk][point][mode],
-// e[blk][mode].
+// Parallel cyclic Jacobi in LDS, one 512-thread workgroup per block, with the
+// round-robin pairing: each round rotates nn/2 disjoint index pairs (p_i, q_i)
+// at once, A <- G A G^T and V <- V G^T with G the direct sum of the 2 x 2
+// rotations.  The two-sided update is done in one pass over 2 x 2 blocks
+// (rows {p_i, q_i}, columns {p_j, q_j}), so a round has two barriers.
+// Output V[blk][point][mode], e[blk][mode].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const double* __restrict__ v0,
-                                                        double* __restrict__ Vout, double* __restrict__ eout,
-                                                        float* __restrict__ Vfout) {
+__global__ __launch_bounds__(kSweepThreads) void k_block_eig(LevelGeom g, const double* __restrict__ v0,
+                                                             double* __restrict__ Vout, double* __restrict__ eout,
+                                                             float* __restrict__ Vfout) {
     __shared__ double A[kMaxB * kLdsPad];
     __shared__ double V[kMaxB * kLdsPad];
-    __shared__ double rot_c[kMaxB / 2], rot_s[kMaxB / 2];
-    __shared__ int rot_p[kMaxB / 2], rot_q[kMaxB / 2];
-    __shared__ double red[kThreads / 64];
+    __shared__ double rot_c[kMaxB / 2 + 1], rot_s[kMaxB / 2 + 1];
+    __shared__ int rot_p[kMaxB / 2 + 1], rot_q[kMaxB / 2 + 1];
+    __shared__ double red[kSweepThreads / 64];
     __shared__ int stop;
 
     const int tid = threadIdx.x;
@@ -516,15 +519,16 @@ __global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const doubl
     const int b = g.bpts;
     const int nn = b + (b & 1);
     const int half = nn / 2;
+    const float rhalf = 1.0f / (float)half;
     const I3 bc = block_coords(g, blk);
 
-    for (int t = tid; t < b * b; t += kThreads) {
-        const int j = t / b, k = t - j * b;
+    for (int t = tid; t < b * b; t += kSweepThreads) {
+        const int j = qdiv_small(t, g.rbp), k = t - j * b;
         A[j * kLdsPad + k] = 0.0;
         V[j * kLdsPad + k] = (j == k) ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int l = tid; l < b; l += kThreads) {
+    for (int l = tid; l < b; l += kSweepThreads) {
         const I3 lc = local_coords(g, l);
         A[l * kLdsPad + l] += 2.0 * g.dim * g.kin + v0[point_index(g, global_of_local(g, bc, lc))];
         for (int ax = 0; ax < g.dim; ++ax)
@@ -538,8 +542,8 @@ __global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const doubl
 
     for (int sweep = 0; sweep < 40; ++sweep) {
         double off = 0.0, tot = 0.0;
-        for (int t = tid; t < b * b; t += kThreads) {
-            const int j = t / b, k = t - j * b;
+        for (int t = tid; t < b * b; t += kSweepThreads) {
+            const int j = qdiv_small(t, g.rbp), k = t - j * b;
             const double v = A[j * kLdsPad + k];
             tot += v * v;
             if (j != k) off += v * v;
@@ -553,13 +557,11 @@ __global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const doubl
         if (stop) break;
         for (int r = 0; r < nn - 1; ++r) {
             if (tid < half) {
-                int p, q;
-                if (tid == 0) {
-                    p = r;
-                    q = nn - 1;
-                } else {
-                    p = (r + tid) % (nn - 1);
-                    q = (r - tid + nn - 1) % (nn - 1);
+                // round r of the round-robin: pair 0 = (r, nn-1), pair i = (r+i, r-i) mod nn-1
+                int p = tid == 0 ? r : r + tid, q = tid == 0 ? nn - 1 : r - tid;
+                if (tid != 0) {
+                    p -= p >= nn - 1 ? nn - 1 : 0;
+                    q += q < 0 ? nn - 1 : 0;
                 }
                 if (p > q) {
                     const int tmp = p;
@@ -577,46 +579,51 @@ __global__ __launch_bounds__(kThreads) void k_block_eig(LevelGeom g, const doubl
                     }
                 }
                 rot_p[tid] = p;
-                rot_q[tid] = q;
+                rot_q[tid] = q < b ? q : p;   // a dummy pair (odd b) rotates nothing
                 rot_c[tid] = cth;
-                rot_s[tid] = sth;
+                rot_s[tid] = q < b ? sth : 0.0;
             }
             __syncthreads();
-            for (int t = tid; t < half * b; t += kThreads) {
-                const int pr = t / b, k = t - pr * b;
-                const int p = rot_p[pr], q = rot_q[pr];
-                if (q < b) {
-                    const double cth = rot_c[pr], sth = rot_s[pr];
-                    const double ap = A[p * kLdsPad + k], aq = A[q * kLdsPad + k];
-                    A[p * kLdsPad + k] = cth * ap - sth * aq;
-                    A[q * kLdsPad + k] = sth * ap + cth * aq;
-                }
+            // A <- G A G^T on 2 x 2 blocks: rows (p_i, q_i), columns (p_j, q_j)
+            for (int t = tid; t < half * half; t += kSweepThreads) {
+                const int i = qdiv_small(t, rhalf), j = t - i * half;
+                const int pi = rot_p[i], qi = rot_q[i], pj = rot_p[j], qj = rot_q[j];
+                if (qi == pi && qj == pj) continue;  // both dummies: nothing to rotate
+                const double ci = rot_c[i], si = rot_s[i], cj = rot_c[j], sj = rot_s[j];
+                const double a00 = A[pi * kLdsPad + pj], a01 = A[pi * kLdsPad + qj];
+                const double a10 = A[qi * kLdsPad + pj], a11 = A[qi * kLdsPad + qj];
+                // rows: (p, q) <- (c p - s q, s p + c q)
+                const double r00 = ci * a00 - si * a10, r01 = ci * a01 - si * a11;
+                const double r10 = si * a00 + ci * a10, r11 = si * a01 + ci * a11;
+                // columns: (p, q) <- (c p - s q, s p + c q)
+                const double n00 = cj * r00 - sj * r01, n01 = sj * r00 + cj * r01;
+                const double n10 = cj * r10 - sj * r11, n11 = sj * r10 + cj * r11;
+                A[pi * kLdsPad + pj] = n00;
+                if (qj != pj) A[pi * kLdsPad + qj] = n01;
+                if (qi != pi) A[qi * kLdsPad + pj] = n10;
+                if (qi != pi && qj != pj) A[qi * kLdsPad + qj] = n11;
             }
-            __syncthreads();
-            for (int t = tid; t < half * b; t += kThreads) {
-                const int pr = t / b, k = t - pr * b;
-                const int p = rot_p[pr], q = rot_q[pr];
-                if (q < b) {
-                    const double cth = rot_c[pr], sth = rot_s[pr];
-                    const double ap = A[k * kLdsPad + p], aq = A[k * kLdsPad + q];
-                    A[k * kLdsPad + p] = cth * ap - sth * aq;
-                    A[k * kLdsPad + q] = sth * ap + cth * aq;
-                    const double vp = V[k * kLdsPad + p], vq = V[k * kLdsPad + q];
-                    V[k * kLdsPad + p] = cth * vp - sth * vq;
-                    V[k * kLdsPad + q] = sth * vp + cth * vq;
-                }
+            // V <- V G^T: columns (p_j, q_j) of every row
+            for (int t = tid; t < b * half; t += kSweepThreads) {
+                const int k = qdiv_small(t, rhalf), j = t - k * half;
+                const int pj = rot_p[j], qj = rot_q[j];
+                if (qj == pj) continue;
+                const double cj = rot_c[j], sj = rot_s[j];
+                const double vp = V[k * kLdsPad + pj], vq = V[k * kLdsPad + qj];
+                V[k * kLdsPad + pj] = cj * vp - sj * vq;
+                V[k * kLdsPad + qj] = sj * vp + cj * vq;
             }
             __syncthreads();
         }
     }
     double* Vb = Vout + (size_t)blk * b * b;
-    for (int t = tid; t < b * b; t += kThreads) {
-        const int j = t / b, k = t - j * b;
+    for (int t = tid; t < b * b; t += kSweepThreads) {
+        const int j = qdiv_small(t, g.rbp), k = t - j * b;
         const double v = V[j * kLdsPad + k];
         Vb[t] = v;
         if (Vfout) Vfout[(size_t)blk * b * b + t] = (float)v;
     }
-    for (int k = tid; k < b; k += kThreads) eout[(size_t)blk * b + k] = A[k * kLdsPad + k];
+    for (int k = tid; k < b; k += kSweepThreads) eout[(size_t)blk * b + k] = A[k * kLdsPad + k];
 }
 
 // ---------------------------------------------------------------------------
@@ -1355,7 +1362,7 @@ hipError_t launch_average_potential(const LevelGeom& fine, const LevelGeom& coar
 hipError_t launch_block_eig(const LevelGeom& g, const double* v0, double* V, double* e, float* Vf,
                             hipStream_t st) {
     const int nblocks = g.nblk[0] * g.nblk[1] * g.nblk[2];
-    hipLaunchKernelGGL(k_block_eig, dim3(nblocks), dim3(kThreads), 0, st, g, v0, V, e, Vf);
+    hipLaunchKernelGGL(k_block_eig, dim3(nblocks), dim3(kSweepThreads), 0, st, g, v0, V, e, Vf);
     return hipGetLastError();
 }
 
