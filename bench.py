@@ -134,7 +134,9 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
         psi, _ = prop.propagate(psi, args.warmup, t_start=t)
         t += args.warmup * cfg["dt"]
     torch.cuda.synchronize()
-    prop.profile(1)
+    # HIP events around every 8th finest-level sweep launch of the timed steps (a sample: each
+    # event record costs stream time, so recording all 16 launches of a step would slow it ~5%)
+    prop.profile(8)
     torch.cuda.synchronize()
     # the timed steps run back to back inside one lam_propagate call
     t_a = time.perf_counter()
@@ -149,7 +151,7 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
     for s in shape:
         P *= s
     value = P * cfg["n_t"] * sweeps / elapsed / 1e6
-    kernel_rate = P * cfg["n_t"] * (launches / 2) / (sweep_ms / 1e3) / 1e6 if sweep_ms > 0 else None
+    kernel_rate = P * cfg["n_t"] * 0.5 / (sweep_ms / launches / 1e3) / 1e6 if sweep_ms > 0 else None
     norm = float(torch.sum(torch.abs(psi) ** 2).item()) * cfg["h"] ** cfg["dim"]
     prop.close()
     return {

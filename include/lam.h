@@ -247,9 +247,12 @@ int lam_level_shape(const lam_ctx* ctx, int level, int* n);
 int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, double* vals);
 
 /* Timing of finest-level sweep launches with HIP events on the context
- * stream.  enable = 1 starts recording (clearing previous records),
- * 0 stops.  lam_profile_read returns the launch count and summed kernel time
- * (ms) recorded since the last enable; it synchronises the stream. */
+ * stream.  enable = k > 0 starts recording (clearing previous records) the
+ * 1st, (k+1)-th, (2k+1)-th ... finest-level sweep launch: a sample, since each
+ * event record costs a few microseconds of stream time; 0 stops; negative is
+ * LAM_EINVAL.  lam_profile_read returns the number of recorded launches and
+ * their summed kernel time (ms) since the last enable; it synchronises the
+ * stream. */
 int lam_profile(lam_ctx* ctx, int enable);
 int lam_profile_read(lam_ctx* ctx, int* launches, double* total_ms);
 

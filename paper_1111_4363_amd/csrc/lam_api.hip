@@ -343,7 +343,8 @@ struct lam_ctx {
     double2* d_tf = nullptr;      // shared time factor (real forms of E1, E3, E3^H, E1^H; eigenvalues), FP64
     float2* d_tff = nullptr;      // and its FP32 copy
     // profiling of finest-level sweeps
-    bool prof = false;
+    int prof = 0;                 // record every prof-th finest-level sweep launch (0: off)
+    long prof_count = 0;
     std::vector<hipEvent_t> ev;
     int nev = 0;
     int sweeps_fine = 0;
@@ -460,7 +461,7 @@ int sweep(lam_ctx* c, int l, int colour) {
     a.adjoint = c->adjoint;
     a.n_inner = c->n_inner;
     a.field_on = c->field_on ? 1 : 0;
-    const bool rec = c->prof && l == 0;
+    const bool rec = c->prof > 0 && l == 0 && (c->prof_count++ % c->prof) == 0;
     if (rec) {
         while ((int)c->ev.size() < c->nev + 2) {
             hipEvent_t e;
@@ -1143,7 +1144,9 @@ int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, dou
 int lam_profile(lam_ctx* ctx, int enable) {
     if (!ctx) return LAM_EINVAL;
     HIPCHK(hipStreamSynchronize(ctx->st));
-    ctx->prof = enable != 0;
+    if (enable < 0) return LAM_EINVAL;
+    ctx->prof = enable;
+    ctx->prof_count = 0;
     if (enable) ctx->nev = 0;
     return LAM_OK;
 }

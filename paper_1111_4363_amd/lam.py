@@ -356,7 +356,7 @@ class Propagator:
         return np.array(vecs[:]).reshape(b, b), np.array(vals[:])
 
     def profile(self, enable):
-        _check(self._lib.lam_profile(self._ctx, int(bool(enable))), "lam_profile")
+        _check(self._lib.lam_profile(self._ctx, int(enable)), "lam_profile")
 
     def profile_read(self):
         n = ctypes.c_int()

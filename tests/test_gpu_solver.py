@@ -208,3 +208,19 @@ def test_native_propagate_matches_stepwise_and_edge_cases():
                                    lam._ptr(out, torch.complex128, case.npts), None) == lam.LAM_OK
     assert torch.all(out == 7.0)
     prop.close()
+
+
+def test_sweep_profiling_samples_every_kth_launch():
+    """lam_profile(k) records the 1st, (k+1)-th, ... finest-level sweep launch."""
+    case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2)
+    note(f"profile sampling {case}")
+    prop = case.prop(tol=1e-10, max_cycles=40)
+    for k in (1, 3):
+        prop.profile(k)
+        _, st = prop.solve_step(0.0, t_c(case.psi0))
+        launches, ms = prop.profile_read()
+        prop.profile(0)
+        total = 2 * st["sweeps_fine"]          # two colour launches per full sweep
+        assert launches == (total + k - 1) // k, (k, launches, total)
+        assert ms > 0.0
+    prop.close()
