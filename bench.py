@@ -117,6 +117,16 @@ def cpu_baseline(budget_s=20.0):
                       f"8x8 subvolumes on a 64x64 window (64 of its 4096 blocks), {dt:.1f} s"}
 
 
+def pulse_of(cfg):
+    """The workload's pulse as Propagator arguments (None without a field)."""
+    import workloads as W
+    p = cfg["pulse"]
+    if not p:
+        return None
+    return dict(kind=p["kind"], e0=p.get("e0", 0.0), omega=p.get("omega", 0.0), t_total=cfg["t_total"],
+                coef=list(W.pulse_coefficients(cfg)))
+
+
 def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
     shape = cfg["shape"]
     torch.cuda.synchronize()
@@ -125,7 +135,7 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
     # static potential)
     prop = lam.Propagator(shape, cfg["h"], v0_t, cfg["n_t"], cfg["dt"], (cfg["block"],) * cfg["dim"],
                           levels=cfg["levels"], nu_pre=1, nu_post=1, nu_coarse=2, precision=precision,
-                          tol=args.tol, max_cycles=60)
+                          tol=args.tol, max_cycles=60, pulse=pulse_of(cfg))
     torch.cuda.synchronize()
     factor_ms = (time.perf_counter() - t_f) * 1e3
     psi = psi0_t.clone()
@@ -169,13 +179,29 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
     }
 
 
+def workload_string(cfg, tol):
+    shape = "x".join(str(n) for n in cfg["shape"])
+    pot = {"softcoulomb": "V=-1/sqrt(r^2+1)", "harmonic": "V=x^2/2"}[cfg["potential"]]
+    p = cfg["pulse"]
+    field = ""
+    if p:
+        field = {"sin2": f", E0={p['e0']} sin^2 pulse w={p['omega']}",
+                 "fourier": f", {p['n_coef']}-amplitude Fourier pulse",
+                 "sin2+fourier": f", E0={p['e0']} sin^2 pulse + {p['n_coef']} Fourier amplitudes"}[p["kind"]]
+    blocks = "x".join([str(cfg["block"])] * cfg["dim"])
+    return (f"{cfg['name']} {shape} h={cfg['h']:g} {pot}{field}, N_t={cfg['n_t']}, dt={cfg['dt']}, "
+            f"{blocks} subvolumes, {cfg['levels']}-level V(1,1), tol {tol:g}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--levels", type=int, default=5)
+    ap.add_argument("--workload", default="2d_softcoulomb",
+                    help="2d_softcoulomb (the headline, default), 1d_harmonic, 3d_laser, 2d_adjoint, 3d_large")
+    ap.add_argument("--n", type=int, default=None, help="points per axis (default: the workload's)")
+    ap.add_argument("--levels", type=int, default=None, help="multigrid levels (default: the workload's)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
@@ -206,7 +232,7 @@ def main():
     import workloads as W
 
     lam.load_library()
-    cfg = W.config("2d_softcoulomb", n=args.n, levels=args.levels)
+    cfg = W.config(args.workload, n=args.n, levels=args.levels)
     v0 = W.potential(cfg)
     psi0 = W.initial_state(cfg, v0)
     dev = torch.device("cuda:0")
@@ -220,17 +246,32 @@ def main():
     main_prec = "fp64" if "fp64" in res else "mixed"
     r = res[main_prec]
 
-    nb0, _ = sweep_launch_bytes(cfg["shape"], (cfg["block"],) * 2, cfg["n_t"], 0, main_prec)
-    nb1, _ = sweep_launch_bytes(cfg["shape"], (cfg["block"],) * 2, cfg["n_t"], 1, main_prec)
+    blocks = (cfg["block"],) * cfg["dim"]
+    nb0, ncol0 = sweep_launch_bytes(cfg["shape"], blocks, cfg["n_t"], 0, main_prec)
+    nb1, ncol1 = sweep_launch_bytes(cfg["shape"], blocks, cfg["n_t"], 1, main_prec)
     bytes_per_launch = 0.5 * (nb0 + nb1)
     achieved = bytes_per_launch / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9 if r["sweep_kernel_ms_avg"] else None
+    traffic = counters_for_current_kernel() if (args.workload == "2d_softcoulomb" and args.n is None) else None
+    # matrix-core work issued per launch: per block, the two block transforms and the two per-mode
+    # mixes, each over 16x16 output tiles (points or modes x the 2 (N_t+1) reals) with 16x16x4 steps
+    b = int(np.prod(blocks))
+    n2 = 2 * (cfg["n_t"] + 1)
+    tiles = min(4, -(-b // 16)) * min(2, -(-n2 // 16))
+    mfma_per_block = 2 * tiles * 4 * (-(-b // 16)) + 2 * tiles * ((n2 + 3) // 4)
+    mfma_flops = 0.5 * (ncol0 + ncol1) * mfma_per_block * 2 * 16 * 16 * 4
+    mfma_peak = 78.6 if main_prec == "fp64" else 157.3
+    mfma_tf = mfma_flops / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e12 if r["sweep_kernel_ms_avg"] else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": counters_for_current_kernel(), "kernel": f"k_sweep<8, {'double' if main_prec == 'fp64' else 'float'}, false> (finest level)",
-                "bytes_per_launch": bytes_per_launch}
+                "traffic": traffic,
+                "kernel": f"k_sweep<{cfg['n_t']}, {'double' if main_prec == 'fp64' else 'float'}, false> (finest level)",
+                "bytes_per_launch": bytes_per_launch,
+                "mfma": {"achieved": mfma_tf, "peak": mfma_peak, "unit": "TFLOP/s",
+                         "frac": (mfma_tf / mfma_peak) if mfma_tf else None,
+                         "note": "matrix-core FLOPs issued (16x16 tiles, padding included)"}}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "2d_softcoulomb":
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline()
 
@@ -247,9 +288,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"2d_softcoulomb {args.n}x{args.n} h=0.2 V=-1/sqrt(r^2+1), N_t=8, dt=0.05, "
-                               f"8x8 subvolumes, {args.levels}-level V(1,1), tol {args.tol:g}",
-                   "grid": list(cfg["shape"]), "n_t": cfg["n_t"], "levels": args.levels,
+        "config": {"workload": workload_string(cfg, args.tol),
+                   "grid": list(cfg["shape"]), "n_t": cfg["n_t"], "levels": cfg["levels"],
                    "unknowns_per_step": int(np.prod(cfg["shape"])) * (cfg["n_t"] + 1)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -909,7 +909,10 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const int nd = 2 * g.dim;
     constexpr bool shared_tf = !STORED;
     // inner passes stop once the block's own residual fell below this fraction (in norm)
-    const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-12;
+    // (FP64: 1e-13; FP32: 1e-5, about what FP32 corrections can resolve), or once a pass
+    // gains less than a factor 4 (the corrections have reached their rounding floor)
+    const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-10;
+    double rprev = 0.0;
 
     // ---- 1a. addresses (no loads yet); thread = residual item (point l, component m) ----
     static_assert(kMaxB * kMaxNT <= kSweepThreads, "one residual item per thread");
@@ -1185,7 +1188,9 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             const double tot = block_sum(loc, red);
             if (tid == 0) rnorm_sh = tot;
             __syncthreads();
-            const bool done = rnorm_sh <= inner_tol2 * r0n;
+            const double rn = rnorm_sh;
+            const bool done = rn <= inner_tol2 * r0n || rn > 0.0625 * (pass > 0 ? rprev : r0n);
+            rprev = rn;
             __syncthreads();
             if (done) {
                 // ---- 5. write back (after an early stop of the passes) ----
