@@ -3,10 +3,12 @@
 // Layout in HBM: per grid point, n_t consecutive complex FP64 coefficients
 // c[j][n] (interleaved re/im), one complex multiplier lam[j], one real V0[j].
 // Grid points are in C order over the axes.  Per subvolume ("block"): the
-// eigenvectors of its real symmetric spatial operator [point][mode] and, per
-// mode, the inverse of the (n_t+1) x (n_t+1) time system, stored
-// [block][row][col][mode] so that one wave reads 64 modes of one entry as a
-// contiguous 1 KB segment.
+// eigenvectors of its real symmetric spatial operator [point][mode] (FP64, and
+// an FP32 copy for the mixed path), its eigenvalues and a frozen-field shift.
+// One time factor shared by all blocks (the eigenbasis form of the (n_t+1) x
+// (n_t+1) time system).  Optionally, per mode, the inverse of that system,
+// stored [block][row][col][mode] so that one wave reads 64 modes of one entry
+// as a contiguous segment.
 
 #include "lam_internal.h"
 
@@ -35,11 +37,6 @@ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
 }
 template <typename T>
 __device__ __forceinline__ cx<T> rmul(T s, cx<T> a) { return {s * a.r, s * a.i}; }
-template <typename T>
-__device__ __forceinline__ cx<T> cdiv(cx<T> a, cx<T> b) {
-    const T den = b.r * b.r + b.i * b.i;
-    return {(a.r * b.r + a.i * b.i) / den, (a.i * b.r - a.r * b.i) / den};
-}
 
 // ---------------------------------------------------------------------------
 // 16x16x4 matrix-core tiles (one wave).  Operand layout (checked on gfx950):
@@ -741,20 +738,6 @@ __device__ __forceinline__ int local_nb(const LevelGeom& g, const I3& lc, int ax
     return local_index(g, with_comp(lc, ax, la));
 }
 
-// Global halo neighbour (outside the block) of global point gi, or -1.
-__device__ __forceinline__ int halo_nb(const LevelGeom& g, const I3& gi, const I3& lc, int ax, int d) {
-    const int la = comp(lc, ax) + d;
-    if (la >= 0 && la < g.bdim[ax]) return -1;            // inside the block
-    if (g.periodic && g.nblk[ax] == 1) return -1;         // wraps onto this block
-    const int na = g.n[ax];
-    int ga = comp(gi, ax) + d;
-    if (ga < 0 || ga >= na) {
-        if (!g.periodic) return -1;
-        ga += ga < 0 ? na : -na;
-    }
-    return point_index(g, with_comp(gi, ax, ga));
-}
-
 // Per-mode mixing on the matrix cores: Y[mode][.] = E X[mode][.] for every mode of
 // the block, with E a real n2 x n2 matrix (the real form of a complex NQ x NQ
 // matrix acting on interleaved (re, im) values) and X, Y rows of length n2.
@@ -866,7 +849,6 @@ template <int NT, typename BT, bool STORED>
 __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())) void k_sweep(SweepArgs a, TimeOps<NT> to) {
     constexpr int NQ = NT + 1;
     constexpr int N2 = 2 * NQ;                               // reals per point / mode
-    constexpr int IPT = (kMaxB * NT + kSweepThreads - 1) / kSweepThreads;  // residual items per thread
     constexpr int VPT = kMaxB * kMaxB / kSweepThreads;       // eigenvector entries per thread
     constexpr int TFR = 8 * NQ * NQ + 2 * NQ;                // reals of the two mixing matrices and lam
     constexpr int TPT = (TFR + kSweepThreads - 1) / kSweepThreads;
