@@ -726,16 +726,17 @@ __global__ __launch_bounds__(64) void k_mode_factor(int b, TimeOps<NT> to, const
 // mixed path); the state and the residual of step 2 are always FP64.
 // ---------------------------------------------------------------------------
 
-// In-block neighbour of local point lc along axis ax, direction d, or -1.  A
-// block that spans a periodic axis is its own neighbour across the wrap.
-__device__ __forceinline__ int local_nb(const LevelGeom& g, const I3& lc, int ax, int d) {
-    const int bd = g.bdim[ax];
-    int la = comp(lc, ax) + d;
-    if (la < 0 || la >= bd) {
-        if (!(g.periodic && g.nblk[ax] == 1)) return -1;
-        la += la < 0 ? bd : -bd;
-    }
-    return local_index(g, with_comp(lc, ax, la));
+// In-block neighbour of local point l in direction dir (axis dir/2, upwards if
+// dir is odd) from its 2-bit code: 0 none, 1 the plain step, 2 the wrap of a
+// block that spans a periodic axis; -1 when there is none.
+__device__ __forceinline__ int code_nb(const LevelGeom& g, int lcode, int l, int dir) {
+    const int ax = dir >> 1;
+    const bool up = dir & 1;
+    const int lstr = ax == 0 ? g.bdim[1] * g.bdim[2] : (ax == 1 ? g.bdim[2] : 1);
+    const int code = (lcode >> (2 * dir)) & 3;
+    const int step = up ? lstr : -lstr;
+    const int wrap = (up ? -1 : 1) * (g.bdim[ax] - 1) * lstr;
+    return code == 0 ? -1 : l + (code == 1 ? step : wrap);
 }
 
 // Per-mode mixing on the matrix cores: Y[mode][.] = E X[mode][.] for every mode of
@@ -906,7 +907,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const int gj_it = point_index(g, gi_it);
     // halo neighbours (outside the block; clamped to the point itself when absent)
     // and in-block neighbours (local index, or -1), with selects only
-    int hidx[6], lnb[6], hmask = 0;
+    int hidx[6], hmask = 0, lcode = 0;
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) {
         const int ax = dir >> 1;
@@ -920,9 +921,9 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         const bool self_wrap = g.periodic && g.nblk[ax] == 1;    // the block spans a periodic axis
         const bool edge = up ? ga + 1 >= na : ga == 0;           // neighbour outside the grid
         const int lstep = up ? lstr : -lstr, gstep = up ? gstr : -gstr;
-        // in-block: plain step, or the wrap of a block that spans a periodic axis
-        const int lw = inside ? l_it + lstep : l_it - (up ? 1 : -1) * (bd - 1) * lstr;
-        lnb[dir] = used && (inside || self_wrap) ? lw : -1;
+        // in-block: plain step (code 1), or the wrap of a block that spans a periodic axis (code 2)
+        (void)lstep;
+        lcode |= (!used ? 0 : (inside ? 1 : (self_wrap ? 2 : 0))) << (2 * dir);
         // halo: plain step, or the wrap of a periodic grid; none on a Dirichlet edge
         const bool halo = used && !inside && !self_wrap && (!edge || g.periodic);
         const int hw = edge ? gj_it - (up ? 1 : -1) * (na - 1) * gstr : gj_it + gstep;
@@ -1005,7 +1006,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         double2 lap = add2(scl2(-2.0 * g.dim, own), halo);
 #pragma unroll
         for (int dir = 0; dir < 6; ++dir) {
-            const int ln = lnb[dir];
+            const int ln = code_nb(g, lcode, l, dir);
             lap = add2(lap, scl2(ln >= 0 ? 1.0 : 0.0, cs[(ln >= 0 ? ln : l) * NT + m]));
         }
         const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], own));
@@ -1115,50 +1116,52 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         __syncthreads();
         const C* di = xb;
         // ---- accumulate, and for inner passes update the local residual; the
-        //      last possible pass writes the updated state straight to HBM ----
+        //      last possible pass writes the updated state straight to HBM.
+        //      Same item per thread as the residual: (point l, component m) ----
         const bool last = pass == a.n_inner;
-        for (int t = tid; t < b * NQ; t += kSweepThreads) {
-            const int l = t / NQ, q = t - l * NQ;
-            const C dv = di[t];
+        if (item) {
+            const int l = l_it, m = m_it;
+            const C dv = di[l * NQ + m];
+            const double2 cnew = add2(cs[l * NT + m], make_double2((double)dv.r, (double)dv.i));
             if (last) {
-                if (q < NT)
-                    a.c[(size_t)gidx[l] * NT + q] = add2(cs[l * NT + q], make_double2((double)dv.r, (double)dv.i));
-                else
-                    a.lam[gidx[l]] = add2(ls[l], make_double2((double)dv.r, (double)dv.i));
-                continue;
-            }
-            if (q < NT)
-                cs[l * NT + q] = add2(cs[l * NT + q], make_double2((double)dv.r, (double)dv.i));
-            else
-                ls[l] = add2(ls[l], make_double2((double)dv.r, (double)dv.i));
-            if (pass < a.n_inner) {
-                C y;
-                if (q < NT) {
-                    const int m = q;
-                    const I3 lc = local_coords(g, l);
-                    C lap = rmul((BT)(-2.0 * g.dim), dv);
-                    for (int dir = 0; dir < nd; ++dir) {
-                        const int ln = local_nb(g, lc, dir >> 1, (dir & 1) ? 1 : -1);
-                        if (ln >= 0) lap = lap + di[ln * NQ + m];
-                    }
-                    const C hd = rmul((BT)(-g.kin), lap) + rmul((BT)v0s[l], dv);
-                    C tq = C{0, 0};
-                    if (!a.adjoint) {
-                        for (int n = m + 1; n < NT; n += 2) tq = tq + di[l * NQ + n];
-                    } else {
-                        for (int n = m - 1; n >= 0; n -= 2) tq = tq + di[l * NQ + n];
-                    }
-                    const C tim = a.adjoint ? C{(BT)2 * tq.i, (BT)(-2) * tq.r} : C{(BT)(-2) * tq.i, (BT)2 * tq.r};
-                    C wd = C{0, 0};
-                    if (a.field_on)
-                        for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)to.W[m * NT + n], di[l * NQ + n]);
-                    const BT sm = (m & 1) ? (BT)-1 : (BT)1;
-                    y = tim - rmul((BT)to.U[m], hd) - rmul((BT)zs[l], wd) + rmul(sm, di[l * NQ + NT]);
-                } else {
-                    y = C{0, 0};
-                    for (int n = 0; n < NT; ++n) y = (n & 1) ? y - di[l * NQ + n] : y + di[l * NQ + n];
+                a.c[(size_t)gj_it * NT + m] = cnew;
+            } else {
+                cs[l * NT + m] = cnew;
+                // y = (K_UU delta) on row (l, m); rolled loops keep the pass loop within 128 VGPRs
+                C lap = rmul((BT)(-2.0 * g.dim), dv);
+#pragma unroll 1
+                for (int dir = 0; dir < 6; ++dir) {
+                    const int ln = code_nb(g, lcode, l, dir);
+                    lap = lap + rmul(ln >= 0 ? (BT)1 : (BT)0, di[(ln >= 0 ? ln : l) * NQ + m]);
                 }
-                rs[t] = rs[t] - y;
+                const C hd = rmul((BT)(-g.kin), lap) + rmul((BT)v0s[l], dv);
+                C tq = C{0, 0}, wd = C{0, 0};
+#pragma unroll 1
+                for (int n = 0; n < NT; ++n) {
+                    const C dn = di[l * NQ + n];
+                    const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
+                    tq = tq + rmul(cpl ? (BT)1 : (BT)0, dn);
+                    if (a.field_on) wd = wd + rmul((BT)to.W[m * NT + n], dn);
+                }
+                const C tim = a.adjoint ? C{(BT)2 * tq.i, (BT)(-2) * tq.r} : C{(BT)(-2) * tq.i, (BT)2 * tq.r};
+                const BT sm = (m & 1) ? (BT)-1 : (BT)1;
+                const C y = tim - rmul((BT)to.U[m], hd) - rmul((BT)zs[l], wd) + rmul(sm, di[l * NQ + NT]);
+                rs[l * NQ + m] = rs[l * NQ + m] - y;
+            }
+        }
+        if (tid < b) {
+            // multiplier rows of point tid
+            const int l = tid;
+            const C dv = di[l * NQ + NT];
+            const double2 lnew = add2(ls[l], make_double2((double)dv.r, (double)dv.i));
+            if (last) {
+                a.lam[gjp] = lnew;
+            } else {
+                ls[l] = lnew;
+                C y = C{0, 0};
+#pragma unroll
+                for (int n = 0; n < NT; ++n) y = (n & 1) ? y - di[l * NQ + n] : y + di[l * NQ + n];
+                rs[l * NQ + NT] = rs[l * NQ + NT] - y;
             }
         }
         if (last) break;
