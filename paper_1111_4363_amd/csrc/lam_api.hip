@@ -555,8 +555,8 @@ int queue_norm(lam_ctx* c, int slot) {
 
 // V-cycles until sqrt(N/N0) <= tol.  The cycles are queued in batches: as many
 // as the previous solve of the same kind needed (none before the first wait of
-// a context's first solve), each followed by its norm (written to host
-// memory), then one wait; after that one cycle per wait.  A
+// a context's first solve), the last two followed by their norms (written to
+// host memory), then one wait; after that one cycle per wait.  A
 // host round trip per cycle would leave the GPU idle while the next cycle is
 // launched.  When a batch overshoots, the extra cycles only refine the state;
 // `cycles` reports the cycles run.
@@ -570,10 +570,12 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
     double N0 = 0.0, N = 0.0;
     for (;;) {
         const int nb = std::min(batch, maxc - queued);
+        // norms after the last two cycles of the batch only: the last decides,
+        // the one before tells whether the next solve can use one cycle less
         for (int i = 0; i < nb; ++i) {
             LAMCHK(vcycle(c, 0));
             ++queued;
-            LAMCHK(queue_norm(c, queued));
+            if (i >= nb - 2) LAMCHK(queue_norm(c, queued));
         }
         LAMCHK(wait_stream(c));
         N0 = c->h_norms[0];
@@ -587,7 +589,7 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
             break;
         }
         bool div = false;
-        for (int k = queued - nb + 1; k <= queued; ++k) {
+        for (int k = std::max(queued - nb + 1, queued - 1); k <= queued; ++k) {
             const double Nk = c->h_norms[k];
             if (!std::isfinite(Nk) || Nk > 1e12 * N0) {
                 div = true;

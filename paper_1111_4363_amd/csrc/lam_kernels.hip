@@ -344,12 +344,20 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_reduce(const double* __restrict__ partial, int nparts,
-                                                     double* __restrict__ out) {
-    __shared__ double red[kThreads / 64];
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += kThreads) acc += partial[k];
-    const double tot = block_sum(acc, red);
+// Sum of the partials in a fixed order (one 1024-thread workgroup, four
+// independent accumulators per thread so the loads stay in flight).
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const double* __restrict__ partial, int nparts,
+                                                           double* __restrict__ out) {
+    __shared__ double red[kReduceThreads / 64];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = threadIdx.x;
+    for (; k + 3 * kReduceThreads < nparts; k += 4 * kReduceThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += partial[k + u * kReduceThreads];
+    }
+    for (; k < nparts; k += kReduceThreads) acc[0] += partial[k];
+    const double tot = block_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), red);
     if (threadIdx.x == 0) out[0] = tot;
 }
 
@@ -1317,7 +1325,7 @@ hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const do
 }
 
 hipError_t launch_reduce(const double* partial, int nparts, int, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, st, partial, nparts, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kReduceThreads), 0, st, partial, nparts, out);
     return hipGetLastError();
 }
 
