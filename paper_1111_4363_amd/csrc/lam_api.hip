@@ -40,8 +40,6 @@ struct Level {
     double2* d_lam = nullptr;
     double2* d_bc = nullptr;    // right-hand side (coarse levels)
     double2* d_bs = nullptr;
-    double2* d_rc = nullptr;    // residual scratch
-    double2* d_rs = nullptr;
     double* d_V = nullptr;      // block eigenvectors (FP64)
     double* d_e = nullptr;      // block eigenvalues
     float* d_Vf = nullptr;      // FP32 copy (mixed path)
@@ -485,17 +483,6 @@ int full_sweep(lam_ctx* c, int l) {
     return LAM_OK;
 }
 
-// Residual of level l into its scratch (rc, rs).
-int level_residual(lam_ctx* c, int l) {
-    Level& L = c->lv[l];
-    const double2* bc = l == 0 ? nullptr : L.d_bc;
-    const double2* bg = (l == 0 && c->adjoint) ? c->d_g : nullptr;
-    const double2* bs = (l == 0 && c->adjoint) ? nullptr : L.d_bs;
-    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, bc, bg, bs, L.d_rc,
-                           L.d_rs, nullptr, nullptr, c->st));
-    return LAM_OK;
-}
-
 // Wait for the work queued on the context stream (e.g. a norm reduction that
 // writes host memory): an event polled in a loop, so the host resumes as soon
 // as the work is done (a blocking stream synchronisation can add tens of
@@ -530,10 +517,15 @@ int vcycle(lam_ctx* c, int l) {
         return LAM_OK;
     }
     for (int s = 0; s < c->grid.nu_pre; ++s) LAMCHK(full_sweep(c, l));
-    LAMCHK(level_residual(c, l));
     Level& F = c->lv[l];
     Level& C = c->lv[l + 1];
-    HIPCHK(launch_restrict(c->nt, F.g, C.g, F.d_rc, F.d_rs, C.d_bc, C.d_bs, C.d_c, C.d_lam, c->st));
+    // residual of level l restricted into the right-hand side of level l + 1,
+    // whose correction starts from zero
+    const double2* bc = l == 0 ? nullptr : F.d_bc;
+    const double2* bg = (l == 0 && c->adjoint) ? c->d_g : nullptr;
+    const double2* bs = (l == 0 && c->adjoint) ? nullptr : F.d_bs;
+    HIPCHK(launch_residual_restrict(c->nt, F.g, C.g, c->U, c->W, c->adjoint, c->field_on, F.d_c, F.d_lam, F.d_v0, bc,
+                                    bg, bs, C.d_bc, C.d_bs, C.d_c, C.d_lam, c->st));
     LAMCHK(vcycle(c, l + 1));
     HIPCHK(launch_prolong(c->nt, F.g, C.g, c->grid.interp, C.d_c, C.d_lam, F.d_c, F.d_lam, c->st));
     for (int s = 0; s < c->grid.nu_post; ++s) LAMCHK(full_sweep(c, l));
@@ -682,8 +674,6 @@ void free_ctx(lam_ctx* c) {
         (void)hipFree(L.d_lam);
         (void)hipFree(L.d_bc);
         (void)hipFree(L.d_bs);
-        (void)hipFree(L.d_rc);
-        (void)hipFree(L.d_rs);
         (void)hipFree(L.d_V);
         (void)hipFree(L.d_e);
         (void)hipFree(L.d_Vf);
@@ -764,8 +754,6 @@ int build(lam_ctx* c, const double* v0_dev) {
         LAMCHK(dalloc(&L.d_v0, P));
         LAMCHK(dalloc(&L.d_c, P * nt));
         LAMCHK(dalloc(&L.d_lam, P));
-        LAMCHK(dalloc(&L.d_rc, P * nt));
-        LAMCHK(dalloc(&L.d_rs, P));
         LAMCHK(dalloc(&L.d_bs, P));
         if (l > 0) LAMCHK(dalloc(&L.d_bc, P * nt));
         LAMCHK(dalloc(&L.d_V, L.nblocks * B * B));

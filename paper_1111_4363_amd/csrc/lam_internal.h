@@ -81,6 +81,11 @@ hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const do
 
 hipError_t launch_reduce(const double* partial, int nparts, int width, double* out, hipStream_t st);
 
+hipError_t launch_residual_restrict(int nt, const LevelGeom& fine, const LevelGeom& coarse, const double* U,
+                                    const double* W, int adjoint, int field_on, const double2* c,
+                                    const double2* lam, const double* v0, const double2* bc, const double2* bg,
+                                    const double2* bs, double2* bcc, double2* bsc, double2* zero_c,
+                                    double2* zero_l, hipStream_t st);
 hipError_t launch_restrict(int nt, const LevelGeom& fine, const LevelGeom& coarse, const double2* rcf,
                            const double2* rsf, double2* bcc, double2* bsc, double2* zero_c,
                            double2* zero_l, hipStream_t st);

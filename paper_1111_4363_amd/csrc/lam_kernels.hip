@@ -259,6 +259,72 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // the wave; the workgroup stages its points' coefficients in LDS for the
 // couplings between time components.
 // ---------------------------------------------------------------------------
+// Residual of item (point j, component m) of a group of points staged
+// together: every thread of the workgroup calls it (it holds a barrier).
+// cs holds the group's coefficients, slot = the thread's (point, m) position;
+// cj points at the item's point in cs.  Returns rho_jm; for m == 0 also the
+// constraint residual sigma_j (in *sg).
+template <int NT>
+__device__ __forceinline__ double2 residual_item(const LevelGeom& g, const TimeOps<NT>& to, int adjoint, int field_on,
+                                                 const double2* __restrict__ c, const double2* __restrict__ lam,
+                                                 const double* __restrict__ v0, const double2* __restrict__ bc,
+                                                 const double2* __restrict__ bg, const double2* __restrict__ bs,
+                                                 int j, int m, bool slot, double2* cs, int cslot, const double2* cj,
+                                                 double2* sg) {
+    const I3 i = point_coords(g, j);
+    const double2 own = c[(size_t)j * NT + m];
+    // neighbour loads issued unconditionally (clamped index, 0/1 weight)
+    double2 nbv[6];
+    double nbw[6];
+#pragma unroll
+    for (int dir = 0; dir < 6; ++dir) {
+        int nb = j;
+        nbw[dir] = 0.0;
+        if (dir < 2 * g.dim) {
+            I3 gi;
+            const int q = neighbour(g, i, dir >> 1, (dir & 1) ? 1 : -1, &gi);
+            if (q >= 0) {
+                nb = q;
+                nbw[dir] = 1.0;
+            }
+        }
+        nbv[dir] = c[(size_t)nb * NT + m];
+    }
+    const double vj = v0[j];
+    const double2 lj = lam[j];
+    const double2 rhs = bc ? bc[(size_t)j * NT + m] : (bg ? bg[j] : make_double2(0.0, 0.0));
+    const double2 sgb = (bs && m == 0) ? bs[j] : make_double2(0.0, 0.0);
+    if (slot) cs[cslot] = own;
+    __syncthreads();
+    double2 lap = scl2(-2.0 * g.dim, own);
+#pragma unroll
+    for (int dir = 0; dir < 6; ++dir) lap = add2(lap, scl2(nbw[dir], nbv[dir]));
+    double2 tq = make_double2(0.0, 0.0);
+    if (!adjoint) {
+        for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cj[n]);
+    } else {
+        for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cj[n]);
+    }
+    // forward: i * 2 tq ; adjoint: -i * 2 tq
+    const double2 tim = adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
+    const double2 hc = add2(scl2(-g.kin, lap), scl2(vj, own));
+    double2 row = sub2(tim, scl2(to.U[m], hc));
+    if (field_on) {
+        double2 wc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cj[n]));
+        row = sub2(row, scl2(zcoord(g, i), wc));
+    }
+    row = add2(row, scl2((m & 1) ? -1.0 : 1.0, lj));
+    if (m == 0) {
+        double2 s = sgb;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) s = (n & 1) ? add2(s, cj[n]) : sub2(s, cj[n]);
+        *sg = s;
+    }
+    return sub2(rhs, row);
+}
+
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> to, int adjoint, int field_on,
                                                        const double2* __restrict__ c,
@@ -269,78 +335,106 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
                                                        const double2* __restrict__ bs,
                                                        double2* __restrict__ rc, double2* __restrict__ rs,
                                                        double* __restrict__ partial) {
-    constexpr int PW = kThreads / NT;  // points per round
+    constexpr int PW = kThreads / NT;  // points per workgroup
     __shared__ double2 cs[PW * NT];
     __shared__ double red[kThreads / 64];
     const int t = threadIdx.x;
     const int lp = t / NT, m = t - lp * NT;
     double acc = 0.0;
-    {
-        const size_t jw = (size_t)blockIdx.x * PW + lp;
-        const bool act = lp < PW && jw < (size_t)g.P;
-        const int j = act ? (int)jw : 0;
-        const I3 i = point_coords(g, j);
-        const double2 own = c[(size_t)j * NT + m];
-        // neighbour loads issued unconditionally (clamped index, 0/1 weight)
-        double2 nbv[6];
-        double nbw[6];
-#pragma unroll
-        for (int dir = 0; dir < 6; ++dir) {
-            int nb = j;
-            nbw[dir] = 0.0;
-            if (dir < 2 * g.dim) {
-                I3 gi;
-                const int q = neighbour(g, i, dir >> 1, (dir & 1) ? 1 : -1, &gi);
-                if (q >= 0) {
-                    nb = q;
-                    nbw[dir] = 1.0;
-                }
-            }
-            nbv[dir] = c[(size_t)nb * NT + m];
-        }
-        const double vj = v0[j];
-        const double2 lj = lam[j];
-        const double2 rhs = bc ? bc[(size_t)j * NT + m] : (bg ? bg[j] : make_double2(0.0, 0.0));
-        const double2 sgb = (bs && m == 0) ? bs[j] : make_double2(0.0, 0.0);
-        if (lp < PW) cs[t] = own;
-        __syncthreads();
-        double2 lap = scl2(-2.0 * g.dim, own);
-#pragma unroll
-        for (int dir = 0; dir < 6; ++dir) lap = add2(lap, scl2(nbw[dir], nbv[dir]));
-        const double2* cj = cs + (lp < PW ? lp : 0) * NT;
-        double2 tq = make_double2(0.0, 0.0);
-        if (!adjoint) {
-            for (int n = m + 1; n < NT; n += 2) tq = add2(tq, cj[n]);
-        } else {
-            for (int n = m - 1; n >= 0; n -= 2) tq = add2(tq, cj[n]);
-        }
-        // forward: i * 2 tq ; adjoint: -i * 2 tq
-        const double2 tim = adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
-        const double2 hc = add2(scl2(-g.kin, lap), scl2(vj, own));
-        double2 row = sub2(tim, scl2(to.U[m], hc));
-        if (field_on) {
-            double2 wc = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cj[n]));
-            row = sub2(row, scl2(zcoord(g, i), wc));
-        }
-        row = add2(row, scl2((m & 1) ? -1.0 : 1.0, lj));
-        const double2 rho = sub2(rhs, row);
-        if (act) {
-            if (rc) rc[(size_t)j * NT + m] = rho;
-            acc += to.U[m] * (rho.x * rho.x + rho.y * rho.y);
-            if (m == 0) {
-                double2 sg = sgb;
-#pragma unroll
-                for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cj[n]) : sub2(sg, cj[n]);
-                if (rs) rs[j] = sg;
-                acc += sg.x * sg.x + sg.y * sg.y;
-            }
+    const size_t jw = (size_t)blockIdx.x * PW + lp;
+    const bool act = lp < PW && jw < (size_t)g.P;
+    const int j = act ? (int)jw : 0;
+    double2 sg = make_double2(0.0, 0.0);
+    const double2 rho = residual_item<NT>(g, to, adjoint, field_on, c, lam, v0, bc, bg, bs, j, m, lp < PW, cs, t,
+                                          cs + (lp < PW ? lp : 0) * NT, &sg);
+    if (act) {
+        if (rc) rc[(size_t)j * NT + m] = rho;
+        acc += to.U[m] * (rho.x * rho.x + rho.y * rho.y);
+        if (m == 0) {
+            if (rs) rs[j] = sg;
+            acc += sg.x * sg.x + sg.y * sg.y;
         }
     }
     if (partial) {
         const double tot = block_sum(acc, red);
         if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+    }
+}
+
+// K1+K4 fused: the residual of a level projected straight to the next coarser
+// level (average of the 2^d children), without storing the fine residual;
+// also clears the coarse correction.  A workgroup takes a tile of 32 fine
+// points: 2 along every axis but the last, 32 / 2^(d-1) along the last, which
+// holds whole child groups of 32 / 2^d coarse points.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_residual_restrict(LevelGeom f, LevelGeom cg, TimeOps<NT> to,
+                                                                int adjoint, int field_on,
+                                                                const double2* __restrict__ c,
+                                                                const double2* __restrict__ lam,
+                                                                const double* __restrict__ v0,
+                                                                const double2* __restrict__ bc,
+                                                                const double2* __restrict__ bg,
+                                                                const double2* __restrict__ bs,
+                                                                double2* __restrict__ bcc, double2* __restrict__ bsc,
+                                                                double2* __restrict__ zc, double2* __restrict__ zl) {
+    constexpr int PT = 32;
+    constexpr int NQ = NT + 1;
+    static_assert(PT * kMaxNT <= kThreads, "one item per thread");
+    __shared__ double2 cs[PT * NT];
+    __shared__ double2 rb[PT * NQ];
+    const int t = threadIdx.x;
+    const int lp = t / NT, m = t - lp * NT;
+    const int dim = f.dim;
+    const int sl = 6 - dim;                       // log2 of the tile extent along the last axis
+    // tile extents (unused axes 1) and tile counts
+    const int e0 = dim == 1 ? (1 << sl) : 2, e1 = dim == 1 ? 1 : (dim == 2 ? (1 << sl) : 2);
+    const int e2 = dim == 3 ? (1 << sl) : 1;
+    const int t1 = (f.n[1] + e1 - 1) / e1, t2 = (f.n[2] + e2 - 1) / e2;
+    const int bz = (int)blockIdx.x % t2, byx = (int)blockIdx.x / t2;
+    const int by = byx % t1, bx = byx / t1;
+    // this thread's fine point
+    const int lz = lp % e2, ly = (lp / e2) % e1, lx = lp / (e1 * e2);
+    const I3 fi{bx * e0 + lx, by * e1 + ly, bz * e2 + lz};
+    const bool inside = lp < PT && fi.x < f.n[0] && fi.y < f.n[1] && fi.z < f.n[2];
+    const int j = inside ? point_index(f, fi) : 0;
+    double2 sg = make_double2(0.0, 0.0);
+    const double2 rho = residual_item<NT>(f, to, adjoint, field_on, c, lam, v0, bc, bg, bs, j, m, lp < PT, cs, t,
+                                          cs + (lp < PT ? lp : 0) * NT, &sg);
+    if (lp < PT) {
+        rb[lp * NQ + m] = rho;
+        if (m == 0) rb[lp * NQ + NT] = sg;
+    }
+    __syncthreads();
+    // coarse points of the tile: extents e/2 (1 on unused axes)
+    const int c0 = dim == 1 ? e0 >> 1 : 1, c1 = dim == 2 ? e1 >> 1 : 1, c2 = dim == 3 ? e2 >> 1 : 1;
+    const int ncp = c0 * c1 * c2;
+    if (t < ncp * NQ) {
+        const int cp = t / NQ, n = t - cp * NQ;
+        const int cz = cp % c2, cy = (cp / c2) % c1, cx = cp / (c1 * c2);
+        const I3 ci{(bx * e0 >> 1) + cx, (by * e1 >> 1) + cy, (bz * e2 >> 1) + cz};
+        // with unused axes of extent 1 the formulas above give coordinate 0 there
+        const I3 cc{dim >= 1 ? ci.x : 0, dim >= 2 ? ci.y : 0, dim >= 3 ? ci.z : 0};
+        if (cc.x < cg.n[0] && cc.y < cg.n[1] && cc.z < cg.n[2]) {
+            const int nch = 1 << dim;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int ch = 0; ch < nch; ++ch) {
+                // child (2 cx + s0, 2 cy + s1, 2 cz + s2) in tile-local coordinates, along used axes
+                const int s0 = ch & 1, s1 = (ch >> 1) & 1, s2 = (ch >> 2) & 1;
+                const int fx = dim >= 1 ? (dim == 1 ? 2 * cx + s0 : s0) : 0;
+                const int fy = dim >= 2 ? (dim == 2 ? 2 * cy + s1 : s1) : 0;
+                const int fz = dim == 3 ? 2 * cz + s2 : 0;
+                acc = add2(acc, rb[((fx * e1 + fy) * e2 + fz) * NQ + n]);
+            }
+            acc = scl2(1.0 / nch, acc);
+            const int J = point_index(cg, cc);
+            if (n < NT) {
+                bcc[(size_t)J * NT + n] = acc;
+                zc[(size_t)J * NT + n] = make_double2(0.0, 0.0);
+            } else {
+                bsc[J] = acc;
+                zl[J] = make_double2(0.0, 0.0);
+            }
+        }
     }
 }
 
@@ -1331,6 +1425,21 @@ hipError_t launch_reduce(const double* partial, int nparts, int, double* out, hi
 
 hipError_t launch_reduce_c2(const double2* partial, int nparts, int width, double2* out, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_c2, dim3(width), dim3(kThreads), 0, st, partial, nparts, width, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_restrict(int nt, const LevelGeom& fine, const LevelGeom& coarse, const double* U,
+                                    const double* W, int adjoint, int field_on, const double2* c,
+                                    const double2* lam, const double* v0, const double2* bc, const double2* bg,
+                                    const double2* bs, double2* bcc, double2* bsc, double2* zero_c,
+                                    double2* zero_l, hipStream_t st) {
+    const int sl = 6 - fine.dim;
+    const int e0 = fine.dim == 1 ? (1 << sl) : 2, e1 = fine.dim == 1 ? 1 : (fine.dim == 2 ? (1 << sl) : 2);
+    const int e2 = fine.dim == 3 ? (1 << sl) : 1;
+    const int nb = ((fine.n[0] + e0 - 1) / e0) * ((fine.n[1] + e1 - 1) / e1) * ((fine.n[2] + e2 - 1) / e2);
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_residual_restrict<NT>, dim3(nb), dim3(kThreads), 0, st, fine, coarse,
+                                           make_ops<NT>(U, W), adjoint, field_on, c, lam, v0, bc, bg, bs, bcc, bsc,
+                                           zero_c, zero_l));
     return hipGetLastError();
 }
 
