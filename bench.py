@@ -252,12 +252,13 @@ def main():
     bytes_per_launch = 0.5 * (nb0 + nb1)
     achieved = bytes_per_launch / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9 if r["sweep_kernel_ms_avg"] else None
     traffic = counters_for_current_kernel() if (args.workload == "2d_softcoulomb" and args.n is None) else None
-    # matrix-core work issued per launch: per block, the two block transforms and the two per-mode
-    # mixes, each over 16x16 output tiles (points or modes x the 2 (N_t+1) reals) with 16x16x4 steps
+    # matrix-core work issued per launch: per block, the two block transforms (points x modes
+    # by the 2 N_t reals of the reduced block system) and the two per-mode mixes (modes x
+    # 2 N_t by 2 N_t x 2 N_t), each over 16x16 output tiles with 16x16x4 steps
     b = int(np.prod(blocks))
-    n2 = 2 * (cfg["n_t"] + 1)
-    tiles = min(4, -(-b // 16)) * min(2, -(-n2 // 16))
-    mfma_per_block = 2 * tiles * 4 * (-(-b // 16)) + 2 * tiles * ((n2 + 3) // 4)
+    nc = 2 * cfg["n_t"]
+    tiles = -(-b // 16) * -(-nc // 16)
+    mfma_per_block = 2 * tiles * 4 * (-(-b // 16)) + 2 * tiles * ((nc + 3) // 4)
     mfma_flops = 0.5 * (ncol0 + ncol1) * mfma_per_block * 2 * 16 * 16 * 4
     mfma_peak = 78.6 if main_prec == "fp64" else 157.3
     mfma_tf = mfma_flops / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e12 if r["sweep_kernel_ms_avg"] else None

@@ -212,45 +212,51 @@ bool schur_small(int n, cd* A, cd* Z) {
     return true;
 }
 
-// Shared time factor in the eigenbasis of G = M0^{-1} diag(U, 0):
-//   M(e) = M0 (I - e G),   G = S J S^{-1},   M(e)^{-1} = S (I - e J)^{-1} S^{-1} M0^{-1},
-// with J = diag(lam) except J[0][1] = 1.  G has a two-long Jordan chain at 0
-// whose vectors are known exactly: v1 = e_nt (the multiplier unit vector spans
-// the null space of diag(U, 0)) and v2 = (U^{-1} s, 0), since G v2 = M0^{-1}(s, 0)
-// = v1, the last column of M0 being (s, 0).  The other nt - 1 eigenvalues
-// are nonzero and distinct; their eigenvectors come from the complex Schur
-// form G = Z T Z^H by back substitution in T.  Outputs (row-major, n = nt + 1):
-// E3 = S, E1 = S^{-1} M0^{-1} (n x n complex each) and lam (n complex; the
-// Jordan pair's entries are 0).  Returns false if G S = S J fails to 1e-12.
-bool time_factor(int nt, const double* U, cd* E1, cd* E3, cd* lam) {
-    const int n = nt + 1;
-    std::vector<cd> M0(n * n, 0.0), Minv(n * n), G(n * n, 0.0), T(n * n), Z(n * n);
-    for (int m = 0; m < nt; ++m) {
-        for (int k = 0; k < nt; ++k)
-            if (k > m && ((k - m) & 1)) M0[m * n + k] = cd(0.0, 2.0);  // i Q_km
-        const double s = (m & 1) ? -1.0 : 1.0;
-        M0[m * n + nt] = s;
-        M0[nt * n + m] = s;
+// Shared time factor of the block systems with c_0 eliminated.  Per point the
+// constraint sum_n s_n dc_n = sigma (s_n = (-1)^n) fixes dc_0 = sigma -
+// sum_{j>=1} s_j dc_j, so the unknowns of a block mode are x = (dlam, dc_1 ..
+// dc_{nt-1}) and its nt rows read M_r(e) x = rho - sigma K(e) e_0 with
+// K(e) = M0c - e U (M0c: the time coupling, i 2 on (m, k), k > m, k - m odd;
+// adjoint: its conjugate transpose) and
+//   M_r(e)[:, 0] = s,   M_r(e)[:, j] = K(e)[:, j] - s_j K(e)[:, 0]   (j >= 1).
+// Split M_r(e) = M_r0 - e D_r (D_r[:, 0] = 0, D_r[:, j] = U_j e_j - s_j U_0 e_0)
+// and diagonalise G = M_r0^{-1} D_r = S diag(lam) S^{-1}: its eigenvalues are
+// simple (0 is one of them, with eigenvector e_0), so
+//   M_r(e)^{-1} = S (I - e diag(lam))^{-1} S^{-1} M_r0^{-1}.
+// Eigenvectors from the complex Schur form G = Z T Z^H by back substitution.
+// Outputs (row-major, nt x nt complex): E3 = S, E1 = S^{-1} M_r0^{-1}, and lam.
+// Returns false if G S = S diag(lam) fails to 1e-12.
+bool time_factor(int nt, const double* U, bool adjoint, cd* E1, cd* E3, cd* lam) {
+    const int n = nt;
+    std::vector<cd> M0c(n * n, 0.0), Mr0(n * n, 0.0), Dr(n * n, 0.0), Minv(n * n), G(n * n, 0.0), T(n * n),
+        Z(n * n);
+    for (int m = 0; m < n; ++m)
+        for (int k = 0; k < n; ++k)
+            if (k > m && ((k - m) & 1)) {
+                if (!adjoint) M0c[m * n + k] = cd(0.0, 2.0);
+                else M0c[k * n + m] = cd(0.0, -2.0);
+            }
+    auto sgn = [](int j) { return (j & 1) ? -1.0 : 1.0; };
+    for (int m = 0; m < n; ++m) {
+        Mr0[m * n + 0] = sgn(m);
+        for (int j = 1; j < n; ++j) Mr0[m * n + j] = M0c[m * n + j] - sgn(j) * M0c[m * n + 0];
     }
-    Minv = M0;
+    for (int j = 1; j < n; ++j) {
+        Dr[j * n + j] += U[j];
+        Dr[0 * n + j] -= sgn(j) * U[0];
+    }
+    Minv = Mr0;
     if (!invert_small(n, Minv.data())) return false;
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < nt; ++j) G[i * n + j] = Minv[i * n + j] * U[j];
+        for (int j = 0; j < n; ++j) {
+            cd acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += Minv[i * n + k] * Dr[k * n + j];
+            G[i * n + j] = acc;
+        }
     T = G;
     if (!schur_small(n, T.data(), Z.data())) return false;
-    // the Jordan pair: the two diagonal entries of T of smallest modulus
-    std::vector<int> idx(n);
-    for (int i = 0; i < n; ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return std::abs(T[x * n + x]) < std::abs(T[y * n + y]); });
     std::vector<cd> S(n * n, 0.0), w(n);
-    double s2 = 0.0;
-    for (int m = 0; m < nt; ++m) s2 += 1.0 / (U[m] * U[m]);
-    const double sc = 1.0 / std::sqrt(s2);  // |v2| = |U^{-1} s|
-    S[nt * n + 0] = sc;                      // v1
-    for (int m = 0; m < nt; ++m) S[m * n + 1] = sc * ((m & 1) ? -1.0 : 1.0) / U[m];  // v2
-    lam[0] = lam[1] = 0.0;
-    for (int c = 2; c < n; ++c) {
-        const int k = idx[c];
+    for (int k = 0; k < n; ++k) {
         const cd lk = T[k * n + k];
         for (int i = 0; i < n; ++i) w[i] = 0.0;
         w[k] = 1.0;
@@ -258,7 +264,7 @@ bool time_factor(int nt, const double* U, cd* E1, cd* E3, cd* lam) {
             cd acc = 0.0;
             for (int m = i + 1; m <= k; ++m) acc += T[i * n + m] * w[m];
             const cd den = T[i * n + i] - lk;
-            if (std::abs(den) < 1e-12 * std::abs(lk)) return false;
+            if (std::abs(den) < 1e-12 * std::max(std::abs(lk), std::abs(T[i * n + i]))) return false;
             w[i] = -acc / den;
         }
         double nv = 0.0;
@@ -268,19 +274,17 @@ bool time_factor(int nt, const double* U, cd* E1, cd* E3, cd* lam) {
             nv += std::norm(v[i]);
         }
         nv = std::sqrt(nv);
-        for (int i = 0; i < n; ++i) S[i * n + c] = v[i] / nv;
-        lam[c] = lk;
+        for (int i = 0; i < n; ++i) S[i * n + k] = v[i] / nv;
+        lam[k] = lk;
     }
-    // check G S = S J
+    // check G S = S diag(lam)
     double gn = 0.0, err = 0.0;
     for (int k = 0; k < n * n; ++k) gn = std::max(gn, std::abs(G[k]));
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             cd gs = 0.0;
             for (int k = 0; k < n; ++k) gs += G[i * n + k] * S[k * n + j];
-            cd sj = S[i * n + j] * lam[j];
-            if (j == 1) sj += S[i * n + 0];
-            err = std::max(err, std::abs(gs - sj));
+            err = std::max(err, std::abs(gs - S[i * n + j] * lam[j]));
         }
     if (!(err <= 1e-12 * std::max(gn, 1.0))) return false;
     std::vector<cd> Sinv = S;
@@ -790,17 +794,16 @@ int build(lam_ctx* c, const double* v0_dev) {
         return LAM_ENOMEM;
     {
         // shared time factor, as reals: the real forms (2n x 2n, acting on interleaved
-        // re/im) of E1, E3 (forward) and E3^H, E1^H (adjoint), then lam (n complex)
-        const int n = nt + 1, n2 = 2 * n;
-        std::vector<cd> E1(n * n), E3(n * n), lam(n);
-        if (!time_factor(nt, c->U, E1.data(), E3.data(), lam.data())) return LAM_EINVAL;
+        // re/im) of E1, E3 of the forward direction, then of the adjoint direction,
+        // then lam (n complex) of each direction; n = nt
+        const int n = nt, n2 = 2 * n;
         std::vector<double> h;
-        h.reserve(4 * n2 * n2 + 2 * n);
-        auto expand = [&](const std::vector<cd>& M, bool herm) {
+        h.reserve(4 * n2 * n2 + 4 * n);
+        auto expand = [&](const std::vector<cd>& M) {
             for (int r = 0; r < n2; ++r)
                 for (int q = 0; q < n2; ++q) {
                     const int p = r >> 1, a = r & 1, qq = q >> 1, cc = q & 1;
-                    const cd m = herm ? std::conj(M[qq * n + p]) : M[p * n + qq];
+                    const cd m = M[p * n + qq];
                     double v;
                     if (a == 0 && cc == 0) v = m.real();
                     else if (a == 0 && cc == 1) v = -m.imag();
@@ -809,14 +812,18 @@ int build(lam_ctx* c, const double* v0_dev) {
                     h.push_back(v);
                 }
         };
-        expand(E1, false);
-        expand(E3, false);
-        expand(E3, true);
-        expand(E1, true);
-        for (const cd& v : lam) {
-            h.push_back(v.real());
-            h.push_back(v.imag());
-        }
+        std::vector<cd> E1(n * n), E3(n * n), lam_f(n), lam_a(n);
+        if (!time_factor(nt, c->U, false, E1.data(), E3.data(), lam_f.data())) return LAM_EINVAL;
+        expand(E1);
+        expand(E3);
+        if (!time_factor(nt, c->U, true, E1.data(), E3.data(), lam_a.data())) return LAM_EINVAL;
+        expand(E1);
+        expand(E3);
+        for (const auto* lv : {&lam_f, &lam_a})
+            for (const cd& v : *lv) {
+                h.push_back(v.real());
+                h.push_back(v.imag());
+            }
         std::vector<float> hf(h.begin(), h.end());
         LAMCHK(dalloc(&c->d_tf, h.size() / 2));
         LAMCHK(dalloc(&c->d_tff, hf.size() / 2));

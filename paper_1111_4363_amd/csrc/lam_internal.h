@@ -57,7 +57,8 @@ struct SweepArgs {
     const double2* bs;        // constraint right-hand side [P], may be null (= 0)
     const void* V;            // [nblocks][bpts][bpts] eigenvectors (double or float)
     const void* Minv;         // [nblocks][NT+1][NT+1][bpts] mode inverses (double2 or float2), or null:
-    const void* tf;           // shared time factor: real forms of E1, E3, E3^H, E1^H, then lam
+    const void* tf;           // shared time factor: real forms of E1, E3 (forward), E1, E3 (adjoint),
+                              // then lam of each direction
     const double* e;          // [nblocks][bpts] eigenvalues of the block operators
     const double* shift;      // [nblocks] frozen-field eigenvalue shift
     int adjoint;

@@ -5,8 +5,9 @@
 // Grid points are in C order over the axes.  Per subvolume ("block"): the
 // eigenvectors of its real symmetric spatial operator [point][mode] (FP64, and
 // an FP32 copy for the mixed path), its eigenvalues and a frozen-field shift.
-// One time factor shared by all blocks (the eigenbasis form of the (n_t+1) x
-// (n_t+1) time system).  Optionally, per mode, the inverse of that system,
+// One time factor shared by all blocks (the eigenbasis form of the n_t x n_t
+// time system left once each point's continuity row has eliminated dc_0).
+// Optionally, per mode, the inverse of the full (n_t+1) x (n_t+1) system,
 // stored [block][row][col][mode] so that one wave reads 64 modes of one entry
 // as a contiguous segment.
 
@@ -67,11 +68,11 @@ struct Mfma<float> {
 };
 
 // One 16 x 16 output tile per wave of out[m][c] = sum_p Op(m, p) in[p][c]
-// (m, p < b, c < ncol <= 32), with Op(m, p) = Vs[p][m] (TRANS: into the block
-// eigenbasis) or Vs[m][p] (back to points).  Wave w owns rows 16 (w % 4) ..
+// (m, p < b, c < ncol <= 32; rows of in LD apart), with Op(m, p) = Vs[p][m]
+// (TRANS: into the block eigenbasis) or Vs[m][p] (back to points).  Wave w owns rows 16 (w % 4) ..
 // and columns 16 (w / 4) ..; every operand load is unconditional (clamped
 // address times a 0/1 factor) so successive K steps stay in flight.
-template <typename T, bool TRANS, int NCOL>
+template <typename T, bool TRANS, int NCOL, int LD>
 __device__ __forceinline__ typename Mfma<T>::acc_t tile_gemm(const T* __restrict__ Vs, const T* __restrict__ in,
                                                              int b, int lane, int wave) {
     typename Mfma<T>::acc_t acc;
@@ -88,12 +89,12 @@ __device__ __forceinline__ typename Mfma<T>::acc_t tile_gemm(const T* __restrict
 #pragma unroll 1
         for (int kh = 0; kh < kMaxB; kh += kMaxB / 2) {
             const T* va = TRANS ? Vs + kh * kLdsPad + m : Vs + m * kLdsPad + kh;
-            const T* vb = in + kh * NCOL + cc;
+            const T* vb = in + kh * LD + cc;
 #pragma unroll
             for (int kk = 0; kk < kMaxB / 8; ++kk) {
                 const int p = 4 * kk + kq;
                 const T av = TRANS ? va[p * kLdsPad] : va[p];
-                acc = Mfma<T>::step(av, vb[p * NCOL], acc);
+                acc = Mfma<T>::step(av, vb[p * LD], acc);
             }
         }
         return acc;
@@ -110,7 +111,7 @@ __device__ __forceinline__ typename Mfma<T>::acc_t tile_gemm(const T* __restrict
             const T fp = p < b ? (T)1 : (T)0;
             const int pc = p < b ? p : b - 1;
             av[u] = (TRANS ? Vs[pc * kLdsPad + mc] : Vs[mc * kLdsPad + pc]) * (fm * fp);
-            bv[u] = in[pc * NCOL + cc];
+            bv[u] = in[pc * LD + cc];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = Mfma<T>::step(av[u], bv[u], acc);
@@ -119,14 +120,14 @@ __device__ __forceinline__ typename Mfma<T>::acc_t tile_gemm(const T* __restrict
 }
 
 template <typename T>
-__device__ __forceinline__ void tile_store(T* __restrict__ out, int b, int ncol, int lane, int wave,
+__device__ __forceinline__ void tile_store(T* __restrict__ out, int b, int ncol, int ld, int lane, int wave,
                                            const typename Mfma<T>::acc_t& acc) {
     const int mt = wave & 3, nt = wave >> 2;
     if (16 * mt >= b || 16 * nt >= ncol) return;
     for (int r = 0; r < 4; ++r) {
         const int m = 16 * mt + Mfma<T>::row(lane, r);
         const int col = 16 * nt + (lane & 15);
-        if (m < b && col < ncol) out[m * ncol + col] = acc[r];
+        if (m < b && col < ncol) out[m * ld + col] = acc[r];
     }
 }
 
@@ -292,8 +293,10 @@ __device__ __forceinline__ double2 residual_item(const LevelGeom& g, const TimeO
     }
     const double vj = v0[j];
     const double2 lj = lam[j];
-    const double2 rhs = bc ? bc[(size_t)j * NT + m] : (bg ? bg[j] : make_double2(0.0, 0.0));
-    const double2 sgb = (bs && m == 0) ? bs[j] : make_double2(0.0, 0.0);
+    // optional right-hand sides loaded without branches (see k_sweep)
+    const double2* rbp = bc ? bc + (size_t)j * NT + m : (bg ? bg + j : c + (size_t)j * NT + m);
+    const double2 rhs = scl2((bc || bg) ? 1.0 : 0.0, *rbp);
+    const double2 sgb = scl2((bs && m == 0) ? 1.0 : 0.0, (bs ? bs : lam)[j]);
     if (slot) cs[cslot] = own;
     __syncthreads();
     double2 lap = scl2(-2.0 * g.dim, own);
@@ -842,13 +845,13 @@ __device__ __forceinline__ int code_nb(const LevelGeom& g, int lcode, int l, int
 }
 
 // Per-mode mixing on the matrix cores: Y[mode][.] = E X[mode][.] for every mode of
-// the block, with E a real n2 x n2 matrix (the real form of a complex NQ x NQ
-// matrix acting on interleaved (re, im) values) and X, Y rows of length n2.
+// the block, with E a real n2 x n2 matrix (the real form of a complex n2/2 x n2/2
+// matrix acting on interleaved (re, im) values) and X, Y rows of n2 values, ld apart.
 // Wave w owns modes 16 (w % 4) .. and result rows 16 (w / 4) ..; operand loads
 // are unconditional (clamped index times a 0/1 factor).
 template <typename T>
 __device__ __forceinline__ typename Mfma<T>::acc_t mode_mix(const T* __restrict__ E, const T* __restrict__ X,
-                                                            int b, int n2, int lane, int wave) {
+                                                            int b, int n2, int ld, int lane, int wave) {
     typename Mfma<T>::acc_t acc;
     for (int r = 0; r < 4; ++r) acc[r] = (T)0;
     const int nt = wave & 3, mt = wave >> 2;
@@ -863,7 +866,7 @@ __device__ __forceinline__ typename Mfma<T>::acc_t mode_mix(const T* __restrict_
         const int k = 4 * kk + kq;
         const T fk = k < n2 ? (T)1 : (T)0;
         const int kc = k < n2 ? k : n2 - 1;
-        const T bv = X[modec * n2 + kc] * (fmode * fk);
+        const T bv = X[modec * ld + kc] * (fmode * fk);
         const T av = E[rowc * n2 + kc];
         acc = Mfma<T>::step(av, bv, acc);
     }
@@ -884,17 +887,15 @@ __device__ __forceinline__ float recip(float d) {
     return r * (2.0f - d * r);
 }
 
-// mode_mix whose input is first multiplied by (I - e_k J)^{-1} (adjoint: its
-// conjugate transpose), with J = diag(lam) + the Jordan pair's coupling (1 at
-// row 0, column 1; lam_0 = lam_1 = 0): entry p of mode k's vector becomes
-// x_p / (1 - e_k lam_p) (adjoint: conj(lam_p)), plus e_k x_1 for p = 0
-// (adjoint: e_k x_0 for p = 1).  Done on the operand loads, so the scaled
-// vector is never stored.  X holds NQ complex entries per mode.
+// mode_mix whose input is first multiplied by (I - e_k diag(lam))^{-1}: entry p
+// of mode k's vector becomes x_p / (1 - e_k lam_p).  Done on the operand
+// loads, so the scaled vector is never stored.  X holds nq complex entries per
+// mode, rows ldc apart.
 template <typename T>
 __device__ __forceinline__ typename Mfma<T>::acc_t mode_mix_scaled(const T* __restrict__ E, const cx<T>* __restrict__ X,
                                                                    const T* __restrict__ es,
-                                                                   const cx<T>* __restrict__ lamv, bool adjoint,
-                                                                   int b, int nq, int lane, int wave) {
+                                                                   const cx<T>* __restrict__ lamv, int b, int nq,
+                                                                   int ldc, int lane, int wave) {
     typename Mfma<T>::acc_t acc;
     for (int r = 0; r < 4; ++r) acc[r] = (T)0;
     const int n2 = 2 * nq;
@@ -905,23 +906,18 @@ __device__ __forceinline__ typename Mfma<T>::acc_t mode_mix_scaled(const T* __re
     const T fmode = mode < b ? (T)1 : (T)0;
     const int modec = mode < b ? mode : b - 1, rowc = row < n2 ? row : n2 - 1;
     const T ev = es[modec];
-    const int pj = adjoint ? 1 : 0, po = adjoint ? 0 : 1;   // the coupled entry and its partner
-    const cx<T> xo = X[modec * nq + po];
     const int ksteps = (n2 + 3) >> 2;
-#pragma unroll 5
+#pragma unroll 4
     for (int kk = 0; kk < ksteps; ++kk) {
         const int k = 4 * kk + kq;
         const T fk = k < n2 ? (T)1 : (T)0;
         const int kc = k < n2 ? k : n2 - 1;
         const int p = kc >> 1;
-        const cx<T> x = X[modec * nq + p];
+        const cx<T> x = X[modec * ldc + p];
         const cx<T> lp = lamv[p];
-        const T dr = (T)1 - ev * lp.r, di = (adjoint ? ev : -ev) * lp.i;   // 1 - e lam (adjoint: conj)
+        const T dr = (T)1 - ev * lp.r, di = -ev * lp.i;   // 1 - e lam
         const T sc = recip(dr * dr + di * di);
-        T yr = (x.r * dr + x.i * di) * sc, yi = (x.i * dr - x.r * di) * sc;
-        const T fj = p == pj ? ev : (T)0;
-        yr += fj * xo.r;
-        yi += fj * xo.i;
+        const T yr = (x.r * dr + x.i * di) * sc, yi = (x.i * dr - x.r * di) * sc;
         const T bv = ((kc & 1) ? yi : yr) * (fmode * fk);
         const T av = E[rowc * n2 + kc];
         acc = Mfma<T>::step(av, bv, acc);
@@ -930,7 +926,7 @@ __device__ __forceinline__ typename Mfma<T>::acc_t mode_mix_scaled(const T* __re
 }
 
 template <typename T>
-__device__ __forceinline__ void mode_mix_store(T* __restrict__ Y, int b, int n2, int lane, int wave,
+__device__ __forceinline__ void mode_mix_store(T* __restrict__ Y, int b, int n2, int ld, int lane, int wave,
                                                const typename Mfma<T>::acc_t& acc) {
     const int nt = wave & 3, mt = wave >> 2;
     if (16 * nt >= b || 16 * mt >= n2) return;
@@ -938,8 +934,32 @@ __device__ __forceinline__ void mode_mix_store(T* __restrict__ Y, int b, int n2,
     if (mode >= b) return;
     for (int r = 0; r < 4; ++r) {
         const int row = 16 * mt + Mfma<T>::row(lane, r);
-        if (row < n2) Y[mode * n2 + row] = acc[r];
+        if (row < n2) Y[mode * ld + row] = acc[r];
     }
+}
+
+// Sum over aligned groups of G consecutive lanes (G = 1, 2, 4 or 8), returned
+// in every lane of the group: DPP moves within a quad (lanes ^ 1, ^ 2), then
+// between the two quads of a group of eight (row_half_mirror).  Every lane of
+// the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1, 2, 4 or 8 lanes");
+    if constexpr (G >= 2) v += dpp_move<0xB1>(v);    // quad_perm (1, 0, 3, 2)
+    if constexpr (G >= 4) v += dpp_move<0x4E>(v);    // quad_perm (2, 3, 0, 1)
+    if constexpr (G >= 8) v += dpp_move<0x141>(v);   // row_half_mirror
+    return v;
 }
 
 // Waves per SIMD the sweep is compiled for: the shared-factor variants fit 128
@@ -953,7 +973,11 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     constexpr int NQ = NT + 1;
     constexpr int N2 = 2 * NQ;                               // reals per point / mode
     constexpr int VPT = kMaxB * kMaxB / kSweepThreads;       // eigenvector entries per thread
-    constexpr int TFR = 8 * NQ * NQ + 2 * NQ;                // reals of the two mixing matrices and lam
+    // shared factor: the block systems with dc_0 eliminated have NT unknowns per
+    // mode (dlam, dc_1 .. dc_{NT-1}), so the eigenbasis transforms take NC = 2 NT
+    // real columns; the stored inverses act on all NQ components
+    constexpr int NC = STORED ? N2 : 2 * NT;
+    constexpr int TFR = 8 * NT * NT + 2 * NT;                // reals of the two mixing matrices and lam
     constexpr int TPT = (TFR + kSweepThreads - 1) / kSweepThreads;
     using C = cx<BT>;
     __shared__ BT Vs[kMaxB * kLdsPad];
@@ -965,11 +989,23 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __shared__ C rs[kMaxB * NQ];   // local residual
     __shared__ C rh[kMaxB * NQ];   // V^T r, then the per-mode solutions
     __shared__ C xb[kMaxB * NQ];   // E1 V^T r (shared factor), then the correction V y
-    __shared__ BT tfs[TFR];        // shared time factor: E1, E3 (adjoint: E3^H, E1^H) real forms, lam
+    __shared__ BT tfs[TFR];        // shared time factor of this direction: E1, E3 real forms, lam
     __shared__ BT es[kMaxB];
+    __shared__ double2 sgs[kMaxB];  // constraint residual per point (shared factor, NT a power of two)
     __shared__ double red[kSweepThreads / 64];
     __shared__ double rnorm_sh;
 
+    {
+        // touch every 64-byte line of the sweep arguments at once, so that the later
+        // reads of single arguments hit the scalar cache instead of waiting one by one
+        // (the time operators that follow them are needed later, and only in part)
+        const auto* kp = (const __attribute__((address_space(4))) int*)__builtin_amdgcn_kernarg_segment_ptr();
+        constexpr int kEnd = (int)sizeof(SweepArgs);
+        int t = kp[kEnd / 4 - 1];
+#pragma unroll
+        for (int off = 0; off < kEnd; off += 64) t ^= kp[off / 4];
+        asm volatile("" ::"s"(t));
+    }
     const LevelGeom& g = a.g;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -1041,10 +1077,13 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     double2 hv[6];
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) hv[dir] = a.c[(size_t)hidx[dir] * NT + m_it];
-    const double2 rhsv = a.bc ? a.bc[(size_t)gj_it * NT + m_it] : (a.bg ? a.bg[gj_it] : make_double2(0.0, 0.0));
+    // optional right-hand sides: always one load (from the state where a side is
+    // absent) times 0 or 1, so that no branch makes the loads in flight drain first
+    const double2* rbp = a.bc ? a.bc + (size_t)gj_it * NT + m_it : (a.bg ? a.bg + gj_it : a.c + (size_t)gj_it * NT + m_it);
+    const double2 rhsv = scl2((a.bc || a.bg) ? 1.0 : 0.0, *rbp);
     const double v0p = a.v0[gjp];
     const double2 lp = a.lam[gjp];
-    const double2 sgv = a.bs ? a.bs[gjp] : make_double2(0.0, 0.0);
+    const double2 sgv = scl2((a.bs && m_it == 0) ? 1.0 : 0.0, (a.bs ? a.bs : a.lam)[gj_it]);
     BT vr[VPT];
     {
         const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
@@ -1059,18 +1098,28 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     BT ep = (BT)0;
     if constexpr (shared_tf) {
         const BT* tfg = static_cast<const BT*>(a.tf);
-        // the mixing pair of this direction (the adjoint pair follows the forward one), then lam
-        const int off_mix = a.adjoint ? 8 * NQ * NQ : 0;
+        // the mixing pair of this direction (the adjoint pair follows the forward one),
+        // then its lam (after both pairs, forward first)
+        const int off_mix = a.adjoint ? 8 * NT * NT : 0;
+        const int off_lam = 16 * NT * NT + (a.adjoint ? 2 * NT : 0) - 8 * NT * NT;
 #pragma unroll
         for (int r = 0; r < TPT; ++r) {
             const int t = tid + r * kSweepThreads;
             const int tt = t < TFR ? t : TFR - 1;
-            tr[r] = tfg[tt < 8 * NQ * NQ ? off_mix + tt : 8 * NQ * NQ + tt];
+            tr[r] = tfg[tt < 8 * NT * NT ? off_mix + tt : off_lam + tt];
         }
         ep = (BT)(a.e[(size_t)blk * b + tp] + a.shift[blk]);
     }
 
     // ---- 1c. consume into LDS ----
+    // a point's NT items are NT consecutive lanes when NT is a power of two: its
+    // constraint residual sigma = bs - sum_n s_n c_n is then a group sum
+    constexpr bool lane_groups = NT == 1 || NT == 2 || NT == 4 || NT == 8;
+    if constexpr (shared_tf && lane_groups) {
+        const double sm = (m_it & 1) ? -1.0 : 1.0;
+        const double sr = group_sum<NT>(sm * own.x), si = group_sum<NT>(sm * own.y);
+        if (item && m_it == 0) sgs[l_it] = make_double2(sgv.x - sr, sgv.y - si);
+    }
     double2 halo = make_double2(0.0, 0.0);
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) halo = add2(halo, scl2((hmask >> dir) & 1 ? 1.0 : 0.0, hv[dir]));
@@ -1102,7 +1151,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     }
     __syncthreads();
 
-    // ---- 2. local residual (FP64) ----
+    // ---- 2. local residual (FP64); the item (l, 0) also takes the constraint row of point l ----
     if (item) {
         const int l = l_it, m = m_it;
         double2 lap = add2(scl2(-2.0 * g.dim, own), halo);
@@ -1115,12 +1164,14 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         // time coupling: i (Q^T c)_m, with Q_nm = 2 for n > m, n - m odd (adjoint: the transpose)
         double2 tq = make_double2(0.0, 0.0);
         double2 wc = make_double2(0.0, 0.0);
+        double2 sgl = sgv;
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
             const double2 cn = cs[l * NT + n];
             const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
             tq = add2(tq, scl2(cpl ? 1.0 : 0.0, cn));
             if (a.field_on) wc = add2(wc, scl2(to.W[m * NT + n], cn));
+            sgl = (n & 1) ? add2(sgl, cn) : sub2(sgl, cn);
         }
         const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
         const double sm = (m & 1) ? -1.0 : 1.0;
@@ -1128,15 +1179,56 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         row = add2(row, scl2(sm, ls[l]));
         const double2 rho = sub2(rhsv, row);
         rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
-    }
-    if (tid < b) {
-        // constraint rows
-        double2 sg = sgv;
+        if (m == 0) {
+            if constexpr (shared_tf && lane_groups) sgl = sgs[l];   // the same rounding as the reduced system
+            rs[l * NQ + NT] = C{(BT)sgl.x, (BT)sgl.y};
+        }
+        if constexpr (shared_tf && lane_groups) {
+            // reduced right-hand side (see below), sigma of the in-block neighbours from sgs
+            double2 r = rho;
+            const double2 sg = sgs[l];
+            if (m == 0) {
+                double2 lin = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) sg = (n & 1) ? add2(sg, cs[tid * NT + n]) : sub2(sg, cs[tid * NT + n]);
-        rs[tid * NQ + NT] = C{(BT)sg.x, (BT)sg.y};
+                for (int dir = 0; dir < 6; ++dir) {
+                    const int ln = code_nb(g, lcode, l, dir);
+                    lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, sgs[ln >= 0 ? ln : l]));
+                }
+                const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l] + a.shift[blk], sg));
+                r = add2(r, scl2(to.U[0], asg));
+            }
+            if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
+            xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
+        }
     }
     __syncthreads();
+    // right-hand side of the reduced system (dc_0 eliminated): rho - sigma K(e) e_0,
+    // i.e. + U_0 (A sigma) on component 0 (A: the block operator with the frozen-field
+    // shift, whose eigenvalues are e) and, adjoint, + 2 i sigma on odd components
+    const double shift = shared_tf ? a.shift[blk] : 0.0;
+    auto reduced_rhs = [&]() {
+        const int l = l_it, m = m_it;
+        const C rv = rs[l * NQ + m], sv = rs[l * NQ + NT];
+        double2 r = make_double2((double)rv.r, (double)rv.i);
+        const double2 sg = make_double2((double)sv.r, (double)sv.i);
+        if (m == 0) {
+            double2 lin = make_double2(0.0, 0.0);
+#pragma unroll 1
+            for (int dir = 0; dir < 6; ++dir) {
+                const int ln = code_nb(g, lcode, l, dir);
+                const C sv = rs[(ln >= 0 ? ln : l) * NQ + NT];
+                lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, make_double2((double)sv.r, (double)sv.i)));
+            }
+            const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l] + shift, sg));
+            r = add2(r, scl2(to.U[0], asg));
+        }
+        if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
+        xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
+    };
+    if constexpr (shared_tf && !lane_groups) {
+        if (item) reduced_rhs();
+        __syncthreads();
+    }
     double r0n = 0.0;
     if (a.n_inner > 0) {
         double loc = 0.0;
@@ -1150,10 +1242,12 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
 
     const C* Mi = static_cast<const C*>(a.Minv);
     for (int pass = 0; pass <= a.n_inner; ++pass) {
-        // ---- 3a. rh[k][.] = sum_j V[j][k] rs[j][.]  (matrix cores) ----
+        // ---- 3a. rh[k][.] = sum_j V[j][k] in[j][.]  (matrix cores; in = the local
+        //      residual, or the reduced right-hand side of the shared factor) ----
         {
-            const auto acc = tile_gemm<BT, true, N2>(Vs, reinterpret_cast<const BT*>(rs), b, lane, wave);
-            tile_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
+            const BT* in = STORED ? reinterpret_cast<const BT*>(rs) : reinterpret_cast<const BT*>(xb);
+            const auto acc = tile_gemm<BT, true, NC, N2>(Vs, in, b, lane, wave);
+            tile_store<BT>(reinterpret_cast<BT*>(rh), b, NC, N2, lane, wave, acc);
         }
         __syncthreads();
         // ---- 3b. per-mode time solve ----
@@ -1194,81 +1288,117 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                 }
             }
         } else {
-            // shared factor: M(e)^{-1} = E3 (I - e J)^{-1} E1   (adjoint: E1^H (I - e J)^{-H} E3^H),
-            // J = diag(lam) + (the Jordan pair's coupling, 1 at row 0, column 1)
-            const BT* E1 = tfs;                      // adjoint: E3^H
-            const BT* E3 = tfs + 4 * NQ * NQ;        // adjoint: E1^H
-            const C* lamv = reinterpret_cast<const C*>(tfs + 8 * NQ * NQ);
+            // shared factor: M_r(e)^{-1} = E3 (I - e diag(lam))^{-1} E1
+            const BT* E1 = tfs;
+            const BT* E3 = tfs + 4 * NT * NT;
+            const C* lamv = reinterpret_cast<const C*>(tfs + 8 * NT * NT);
             {
-                const auto acc = mode_mix<BT>(E1, reinterpret_cast<const BT*>(rh), b, N2, lane, wave);
-                mode_mix_store<BT>(reinterpret_cast<BT*>(xb), b, N2, lane, wave, acc);
+                const auto acc = mode_mix<BT>(E1, reinterpret_cast<const BT*>(rh), b, NC, N2, lane, wave);
+                mode_mix_store<BT>(reinterpret_cast<BT*>(xb), b, NC, N2, lane, wave, acc);
             }
             __syncthreads();
             {
-                const auto acc = mode_mix_scaled<BT>(E3, xb, es, lamv, a.adjoint, b, NQ, lane, wave);
-                mode_mix_store<BT>(reinterpret_cast<BT*>(rh), b, N2, lane, wave, acc);
+                const auto acc = mode_mix_scaled<BT>(E3, xb, es, lamv, b, NT, NQ, lane, wave);
+                mode_mix_store<BT>(reinterpret_cast<BT*>(rh), b, NC, N2, lane, wave, acc);
             }
         }
         __syncthreads();
-        // ---- 3c. correction di[j][.] = sum_k V[j][k] rh[k][.], into xb ----
+        // ---- 3c. back to points: xb[j][.] = sum_k V[j][k] rh[k][.] ----
         {
-            const auto acc = tile_gemm<BT, false, N2>(Vs, reinterpret_cast<const BT*>(rh), b, lane, wave);
-            tile_store<BT>(reinterpret_cast<BT*>(xb), b, N2, lane, wave, acc);
+            const auto acc = tile_gemm<BT, false, NC, N2>(Vs, reinterpret_cast<const BT*>(rh), b, lane, wave);
+            tile_store<BT>(reinterpret_cast<BT*>(xb), b, NC, N2, lane, wave, acc);
         }
         __syncthreads();
-        const C* di = xb;
-        // ---- accumulate, and for inner passes update the local residual; the
-        //      last possible pass writes the updated state straight to HBM.
-        //      Same item per thread as the residual: (point l, component m) ----
+        // ---- 4. corrections of this thread's item (point l, component m) and, for
+        //      m = 0, of the multiplier of point l.  Shared factor: xb[l] holds
+        //      (dlam, dc_1 .. dc_{NT-1}) and dc_0 = sigma - sum_{j>=1} s_j dc_j ----
         const bool last = pass == a.n_inner;
+        C dv = C{0, 0}, dl = C{0, 0};
+        if constexpr (STORED) {
+            if (item) {
+                dv = xb[l_it * NQ + m_it];
+                dl = xb[l_it * NQ + NT];
+            }
+        } else if constexpr (lane_groups) {
+            // every lane reads its own entry; dc_0 from a group sum (all lanes active)
+            const C x = xb[l_it * NQ + m_it];
+            const BT sm = m_it == 0 ? (BT)0 : ((m_it & 1) ? (BT)-1 : (BT)1);
+            const BT sr = group_sum<NT>(sm * x.r), si = group_sum<NT>(sm * x.i);
+            if (m_it > 0) {
+                dv = x;
+            } else {
+                const C sg = rs[l_it * NQ + NT];
+                dv = C{sg.r - sr, sg.i - si};
+                dl = x;
+            }
+        } else if (item) {
+            const int l = l_it, m = m_it;
+            if (m > 0) {
+                dv = xb[l * NQ + m];
+            } else {
+                dv = rs[l * NQ + NT];
+#pragma unroll 1
+                for (int j = 1; j < NT; ++j) {
+                    const C x = xb[l * NQ + j];
+                    dv = (j & 1) ? dv + x : dv - x;
+                }
+                dl = xb[l * NQ];
+            }
+        }
+        if (last) {
+            // the last possible pass writes the updated state straight to HBM
+            if (item) {
+                const int l = l_it, m = m_it;
+                a.c[(size_t)gj_it * NT + m] = add2(cs[l * NT + m], make_double2((double)dv.r, (double)dv.i));
+                if (m == 0) a.lam[gj_it] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
+            }
+            break;
+        }
+        // inner pass: keep the state in LDS and update the local residual by K_bb delta
+        C* di = STORED ? xb : rh;
         if (item) {
             const int l = l_it, m = m_it;
-            const C dv = di[l * NQ + m];
-            const double2 cnew = add2(cs[l * NT + m], make_double2((double)dv.r, (double)dv.i));
-            if (last) {
-                a.c[(size_t)gj_it * NT + m] = cnew;
-            } else {
-                cs[l * NT + m] = cnew;
-                // y = (K_UU delta) on row (l, m); rolled loops keep the pass loop within 128 VGPRs
-                C lap = rmul((BT)(-2.0 * g.dim), dv);
-#pragma unroll 1
-                for (int dir = 0; dir < 6; ++dir) {
-                    const int ln = code_nb(g, lcode, l, dir);
-                    lap = lap + rmul(ln >= 0 ? (BT)1 : (BT)0, di[(ln >= 0 ? ln : l) * NQ + m]);
-                }
-                const C hd = rmul((BT)(-g.kin), lap) + rmul((BT)v0s[l], dv);
-                C tq = C{0, 0}, wd = C{0, 0};
-#pragma unroll 1
-                for (int n = 0; n < NT; ++n) {
-                    const C dn = di[l * NQ + n];
-                    const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
-                    tq = tq + rmul(cpl ? (BT)1 : (BT)0, dn);
-                    if (a.field_on) wd = wd + rmul((BT)to.W[m * NT + n], dn);
-                }
-                const C tim = a.adjoint ? C{(BT)2 * tq.i, (BT)(-2) * tq.r} : C{(BT)(-2) * tq.i, (BT)2 * tq.r};
-                const BT sm = (m & 1) ? (BT)-1 : (BT)1;
-                const C y = tim - rmul((BT)to.U[m], hd) - rmul((BT)zs[l], wd) + rmul(sm, di[l * NQ + NT]);
-                rs[l * NQ + m] = rs[l * NQ + m] - y;
+            cs[l * NT + m] = add2(cs[l * NT + m], make_double2((double)dv.r, (double)dv.i));
+            if (m == 0) ls[l] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
+            if constexpr (!STORED) {
+                di[l * NQ + m] = dv;
+                if (m == 0) di[l * NQ + NT] = dl;
             }
         }
-        if (tid < b) {
-            // multiplier rows of point tid
-            const int l = tid;
-            const C dv = di[l * NQ + NT];
-            const double2 lnew = add2(ls[l], make_double2((double)dv.r, (double)dv.i));
-            if (last) {
-                a.lam[gjp] = lnew;
-            } else {
-                ls[l] = lnew;
-                C y = C{0, 0};
-#pragma unroll
-                for (int n = 0; n < NT; ++n) y = (n & 1) ? y - di[l * NQ + n] : y + di[l * NQ + n];
-                rs[l * NQ + NT] = rs[l * NQ + NT] - y;
+        if constexpr (!STORED) __syncthreads();
+        if (item) {
+            const int l = l_it, m = m_it;
+            // y = (K_bb delta) on row (l, m); rolled loops keep the pass loop within 128 VGPRs
+            const C dvm = di[l * NQ + m];
+            C lap = rmul((BT)(-2.0 * g.dim), dvm);
+#pragma unroll 1
+            for (int dir = 0; dir < 6; ++dir) {
+                const int ln = code_nb(g, lcode, l, dir);
+                lap = lap + rmul(ln >= 0 ? (BT)1 : (BT)0, di[(ln >= 0 ? ln : l) * NQ + m]);
             }
+            const C hd = rmul((BT)(-g.kin), lap) + rmul((BT)v0s[l], dvm);
+            C tq = C{0, 0}, wd = C{0, 0}, sy = C{0, 0};
+#pragma unroll 1
+            for (int n = 0; n < NT; ++n) {
+                const C dn = di[l * NQ + n];
+                const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
+                tq = tq + rmul(cpl ? (BT)1 : (BT)0, dn);
+                if (a.field_on) wd = wd + rmul((BT)to.W[m * NT + n], dn);
+                sy = (n & 1) ? sy - dn : sy + dn;
+            }
+            const C tim = a.adjoint ? C{(BT)2 * tq.i, (BT)(-2) * tq.r} : C{(BT)(-2) * tq.i, (BT)2 * tq.r};
+            const BT sm = (m & 1) ? (BT)-1 : (BT)1;
+            const C y = tim - rmul((BT)to.U[m], hd) - rmul((BT)zs[l], wd) + rmul(sm, di[l * NQ + NT]);
+            rs[l * NQ + m] = rs[l * NQ + m] - y;
+            // multiplier row of point l
+            if (m == 0) rs[l * NQ + NT] = rs[l * NQ + NT] - sy;
         }
-        if (last) break;
         __syncthreads();
-        if (pass < a.n_inner) {
+        if constexpr (!STORED) {
+            // the next pass's reduced right-hand side
+            if (item) reduced_rhs();
+        }
+        {
             // stop the defect corrections once the local system is solved
             double loc = 0.0;
             for (int t = tid; t < b * NQ; t += kSweepThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
