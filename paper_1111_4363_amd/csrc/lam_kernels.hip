@@ -938,6 +938,90 @@ __device__ __forceinline__ void mode_mix_store(T* __restrict__ Y, int b, int n2,
     }
 }
 
+// The per-mode half of the shared-factor block solve, chained in the registers
+// of one wave (no LDS round trip, no workgroup barrier): wave w (< 4) owns
+// modes 16w .. 16w+15 and all nc <= 16 real columns of the reduced system.
+//   X^T = R^T V            (comps x modes; A = R^T from LDS, B = V from LDS)
+//   Y   = E1 X^T           (A = E1; B = X^T straight from the result registers)
+//   S   = (I - e diag(lam))^{-1} Y   (per mode e, per component lam)
+//   Z^T = E3 S             (A = E3; B = S from registers)
+// and Z is stored [mode][ld].  A 16x16 result leaves slot r of lane
+// (j + 16 q) holding row q + 4r (FP64) or 4q + r (FP32) of column j; step s of
+// a 16x16x4 product takes B[k][j] from lane j + 16 kq, so the K index of
+// (step s, lane group kq) is 4s + kq (FP64) or 4kq + s (FP32) and the A operand
+// (E) is read in that order.  Rows or columns past nc, and modes past b, are
+// masked or never stored.
+template <typename T>
+__device__ __forceinline__ void mode_chain(const T* __restrict__ Vs, const T* __restrict__ R, int ld, int b, int nc,
+                                           const T* __restrict__ E1, const T* __restrict__ E3,
+                                           const T* __restrict__ es, const cx<T>* __restrict__ lamv,
+                                           T* __restrict__ Z, int lane, int wave) {
+    using acc_t = typename Mfma<T>::acc_t;
+    constexpr bool f64 = sizeof(T) == 8;
+    if (wave >= 4 || 16 * wave >= b) return;
+    const int j = lane & 15, kq = lane >> 4;
+    const int mode = 16 * wave + j;
+    // 1. X^T = R^T V over the block's points
+    acc_t x;
+    for (int r = 0; r < 4; ++r) x[r] = (T)0;
+    const T fc = j < nc ? (T)1 : (T)0;
+    const int jc = j < nc ? j : nc - 1;
+    if (b == kMaxB) {
+#pragma unroll
+        for (int st = 0; st < kMaxB / 4; ++st) {
+            const int p = 4 * st + kq;
+            x = Mfma<T>::step(R[p * ld + jc] * fc, Vs[p * kLdsPad + mode], x);
+        }
+    } else {
+        for (int st = 0; 4 * st < b; ++st) {
+            const int p = 4 * st + kq;
+            const T fp = p < b ? fc : (T)0;
+            const int pc = p < b ? p : b - 1;
+            x = Mfma<T>::step(R[pc * ld + jc] * fp, Vs[pc * kLdsPad + mode], x);
+        }
+    }
+    // A operand of the two mixes: E[row j][k(st, kq)], zero outside nc x nc
+    auto e_at = [&](const T* E, int st) {
+        const int k = f64 ? 4 * st + kq : 4 * kq + st;
+        const bool in = j < nc && k < nc;
+        return in ? E[jc * nc + (k < nc ? k : nc - 1)] : (T)0;
+    };
+    // 2. Y = E1 X^T
+    acc_t y;
+    for (int r = 0; r < 4; ++r) y[r] = (T)0;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) y = Mfma<T>::step(e_at(E1, st), x[st], y);
+    // 3. scaling by 1 / (1 - e lam_p) of complex entries (re, im rows 2p, 2p + 1)
+    const T ev = es[mode < b ? mode : b - 1];
+    acc_t sv;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = Mfma<T>::row(lane, r);
+        T par;
+        if constexpr (f64) par = __shfl_xor(y[r], 16);   // row ^ 1 sits 16 lanes over
+        else par = y[r ^ 1];                              // row ^ 1 is the neighbouring slot
+        const bool im = row & 1;
+        const int pp = row >> 1;
+        const cx<T> lp = lamv[pp < (nc >> 1) ? pp : (nc >> 1) - 1];
+        const T xr = im ? par : y[r], xi = im ? y[r] : par;
+        const T dr = (T)1 - ev * lp.r, di = -ev * lp.i;   // 1 - e lam
+        const T sc = recip(dr * dr + di * di);
+        sv[r] = (im ? xi * dr - xr * di : xr * dr + xi * di) * sc * (row < nc ? (T)1 : (T)0);
+    }
+    // 4. Z^T = E3 S
+    acc_t z;
+    for (int r = 0; r < 4; ++r) z[r] = (T)0;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) z = Mfma<T>::step(e_at(E3, st), sv[st], z);
+    if (mode < b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = Mfma<T>::row(lane, r);
+            if (row < nc) Z[mode * ld + row] = z[r];
+        }
+    }
+}
+
 // Sum over aligned groups of G consecutive lanes (G = 1, 2, 4 or 8), returned
 // in every lane of the group: DPP moves within a quad (lanes ^ 1, ^ 2), then
 // between the two quads of a group of eight (row_half_mirror).  Every lane of
@@ -1035,11 +1119,13 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-10;
     double rprev = 0.0;
 
-    // ---- 1a. addresses (no loads yet); thread = residual item (point l, component m) ----
-    static_assert(kMaxB * kMaxNT <= kSweepThreads, "one residual item per thread");
-    const bool item = tid < b * NT;
-    const int t_it = item ? tid : 0;
-    const int l_it = t_it / NT, m_it = t_it - (t_it / NT) * NT;
+    // ---- 1a. addresses (no loads yet); thread = residual item (point l, component m):
+    //      eight lanes per point whatever NT is (lanes m >= NT idle), so that a point's
+    //      items are an aligned lane group inside one wave ----
+    constexpr int LPP = 8;
+    static_assert(kMaxNT <= LPP && kMaxB * LPP <= kSweepThreads, "one residual item per thread");
+    const bool item = (tid & (LPP - 1)) < NT && (tid / LPP) < b;
+    const int l_it = item ? tid / LPP : 0, m_it = item ? (tid & (LPP - 1)) : 0;
     const I3 lc_it = local_coords(g, l_it);
     const I3 gi_it = global_of_local(g, bc, lc_it);
     const int gj_it = point_index(g, gi_it);
@@ -1112,18 +1198,17 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     }
 
     // ---- 1c. consume into LDS ----
-    // a point's NT items are NT consecutive lanes when NT is a power of two: its
-    // constraint residual sigma = bs - sum_n s_n c_n is then a group sum
-    constexpr bool lane_groups = NT == 1 || NT == 2 || NT == 4 || NT == 8;
-    if constexpr (shared_tf && lane_groups) {
-        const double sm = (m_it & 1) ? -1.0 : 1.0;
-        const double sr = group_sum<NT>(sm * own.x), si = group_sum<NT>(sm * own.y);
+    // a point's items are one aligned group of LPP lanes: its constraint residual
+    // sigma = bs - sum_n s_n c_n is a group sum
+    if constexpr (shared_tf) {
+        const double sm = item ? ((m_it & 1) ? -1.0 : 1.0) : 0.0;
+        const double sr = group_sum<LPP>(sm * own.x), si = group_sum<LPP>(sm * own.y);
         if (item && m_it == 0) sgs[l_it] = make_double2(sgv.x - sr, sgv.y - si);
     }
     double2 halo = make_double2(0.0, 0.0);
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) halo = add2(halo, scl2((hmask >> dir) & 1 ? 1.0 : 0.0, hv[dir]));
-    if (item) cs[tid] = own;
+    if (item) cs[l_it * NT + m_it] = own;
     if (tid < b) {
         gidx[tid] = gjp;
         v0s[tid] = v0p;
@@ -1180,10 +1265,10 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         const double2 rho = sub2(rhsv, row);
         rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
         if (m == 0) {
-            if constexpr (shared_tf && lane_groups) sgl = sgs[l];   // the same rounding as the reduced system
+            if constexpr (shared_tf) sgl = sgs[l];   // the same rounding as the reduced system
             rs[l * NQ + NT] = C{(BT)sgl.x, (BT)sgl.y};
         }
-        if constexpr (shared_tf && lane_groups) {
+        if constexpr (shared_tf) {
             // reduced right-hand side (see below), sigma of the in-block neighbours from sgs
             double2 r = rho;
             const double2 sg = sgs[l];
@@ -1213,11 +1298,11 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         const double2 sg = make_double2((double)sv.r, (double)sv.i);
         if (m == 0) {
             double2 lin = make_double2(0.0, 0.0);
-#pragma unroll 1
+#pragma unroll 3
             for (int dir = 0; dir < 6; ++dir) {
                 const int ln = code_nb(g, lcode, l, dir);
-                const C sv = rs[(ln >= 0 ? ln : l) * NQ + NT];
-                lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, make_double2((double)sv.r, (double)sv.i)));
+                const C sn = rs[(ln >= 0 ? ln : l) * NQ + NT];
+                lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, make_double2((double)sn.r, (double)sn.i)));
             }
             const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l] + shift, sg));
             r = add2(r, scl2(to.U[0], asg));
@@ -1225,10 +1310,6 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
         xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
     };
-    if constexpr (shared_tf && !lane_groups) {
-        if (item) reduced_rhs();
-        __syncthreads();
-    }
     double r0n = 0.0;
     if (a.n_inner > 0) {
         double loc = 0.0;
@@ -1242,16 +1323,14 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
 
     const C* Mi = static_cast<const C*>(a.Minv);
     for (int pass = 0; pass <= a.n_inner; ++pass) {
-        // ---- 3a. rh[k][.] = sum_j V[j][k] in[j][.]  (matrix cores; in = the local
-        //      residual, or the reduced right-hand side of the shared factor) ----
-        {
-            const BT* in = STORED ? reinterpret_cast<const BT*>(rs) : reinterpret_cast<const BT*>(xb);
-            const auto acc = tile_gemm<BT, true, NC, N2>(Vs, in, b, lane, wave);
-            tile_store<BT>(reinterpret_cast<BT*>(rh), b, NC, N2, lane, wave, acc);
-        }
-        __syncthreads();
-        // ---- 3b. per-mode time solve ----
         if constexpr (STORED) {
+            // ---- 3a. rh[k][.] = sum_j V[j][k] rs[j][.]  (matrix cores) ----
+            {
+                const auto acc = tile_gemm<BT, true, NC, N2>(Vs, reinterpret_cast<const BT*>(rs), b, lane, wave);
+                tile_store<BT>(reinterpret_cast<BT*>(rh), b, NC, N2, lane, wave, acc);
+            }
+            __syncthreads();
+            // ---- 3b. per-mode time solve ----
             // stored inverses M(e_k)^{-1}; waves 0..3, thread (k, pg) computes rows pg, pg+4, pg+8
             const int k = tid & 63, pg = tid >> 6;
             const bool act = pg < 4;
@@ -1288,19 +1367,13 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                 }
             }
         } else {
-            // shared factor: M_r(e)^{-1} = E3 (I - e diag(lam))^{-1} E1
+            // ---- 3a + 3b. into the block eigenbasis and the per-mode solve
+            //      M_r(e)^{-1} = E3 (I - e diag(lam))^{-1} E1, chained per wave ----
             const BT* E1 = tfs;
             const BT* E3 = tfs + 4 * NT * NT;
             const C* lamv = reinterpret_cast<const C*>(tfs + 8 * NT * NT);
-            {
-                const auto acc = mode_mix<BT>(E1, reinterpret_cast<const BT*>(rh), b, NC, N2, lane, wave);
-                mode_mix_store<BT>(reinterpret_cast<BT*>(xb), b, NC, N2, lane, wave, acc);
-            }
-            __syncthreads();
-            {
-                const auto acc = mode_mix_scaled<BT>(E3, xb, es, lamv, b, NT, NQ, lane, wave);
-                mode_mix_store<BT>(reinterpret_cast<BT*>(rh), b, NC, N2, lane, wave, acc);
-            }
+            mode_chain<BT>(Vs, reinterpret_cast<const BT*>(xb), N2, b, NC, E1, E3, es, lamv,
+                           reinterpret_cast<BT*>(rh), lane, wave);
         }
         __syncthreads();
         // ---- 3c. back to points: xb[j][.] = sum_k V[j][k] rh[k][.] ----
@@ -1319,30 +1392,17 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                 dv = xb[l_it * NQ + m_it];
                 dl = xb[l_it * NQ + NT];
             }
-        } else if constexpr (lane_groups) {
+        } else {
             // every lane reads its own entry; dc_0 from a group sum (all lanes active)
             const C x = xb[l_it * NQ + m_it];
-            const BT sm = m_it == 0 ? (BT)0 : ((m_it & 1) ? (BT)-1 : (BT)1);
-            const BT sr = group_sum<NT>(sm * x.r), si = group_sum<NT>(sm * x.i);
+            const BT sm = (!item || m_it == 0) ? (BT)0 : ((m_it & 1) ? (BT)-1 : (BT)1);
+            const BT sr = group_sum<LPP>(sm * x.r), si = group_sum<LPP>(sm * x.i);
             if (m_it > 0) {
                 dv = x;
             } else {
                 const C sg = rs[l_it * NQ + NT];
                 dv = C{sg.r - sr, sg.i - si};
                 dl = x;
-            }
-        } else if (item) {
-            const int l = l_it, m = m_it;
-            if (m > 0) {
-                dv = xb[l * NQ + m];
-            } else {
-                dv = rs[l * NQ + NT];
-#pragma unroll 1
-                for (int j = 1; j < NT; ++j) {
-                    const C x = xb[l * NQ + j];
-                    dv = (j & 1) ? dv + x : dv - x;
-                }
-                dl = xb[l * NQ];
             }
         }
         if (last) {
