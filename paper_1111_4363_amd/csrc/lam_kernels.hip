@@ -1237,6 +1237,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __syncthreads();
 
     // ---- 2. local residual (FP64); the item (l, 0) also takes the constraint row of point l ----
+    const double shift = a.shift[blk];   // frozen-field eigenvalue shift of this block
     if (item) {
         const int l = l_it, m = m_it;
         double2 lap = add2(scl2(-2.0 * g.dim, own), halo);
@@ -1269,7 +1270,10 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             rs[l * NQ + NT] = C{(BT)sgl.x, (BT)sgl.y};
         }
         if constexpr (shared_tf) {
-            // reduced right-hand side (see below), sigma of the in-block neighbours from sgs
+            // right-hand side of the reduced system (dc_0 eliminated): rho - sigma K(e) e_0,
+            // i.e. + U_0 (A sigma) on component 0 (A: the block operator with the
+            // frozen-field shift, whose eigenvalues are e; sigma of the in-block
+            // neighbours from sgs) and, adjoint, + 2 i sigma on odd components
             double2 r = rho;
             const double2 sg = sgs[l];
             if (m == 0) {
@@ -1279,7 +1283,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                     const int ln = code_nb(g, lcode, l, dir);
                     lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, sgs[ln >= 0 ? ln : l]));
                 }
-                const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l] + a.shift[blk], sg));
+                const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l] + shift, sg));
                 r = add2(r, scl2(to.U[0], asg));
             }
             if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
@@ -1287,29 +1291,6 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         }
     }
     __syncthreads();
-    // right-hand side of the reduced system (dc_0 eliminated): rho - sigma K(e) e_0,
-    // i.e. + U_0 (A sigma) on component 0 (A: the block operator with the frozen-field
-    // shift, whose eigenvalues are e) and, adjoint, + 2 i sigma on odd components
-    const double shift = shared_tf ? a.shift[blk] : 0.0;
-    auto reduced_rhs = [&]() {
-        const int l = l_it, m = m_it;
-        const C rv = rs[l * NQ + m], sv = rs[l * NQ + NT];
-        double2 r = make_double2((double)rv.r, (double)rv.i);
-        const double2 sg = make_double2((double)sv.r, (double)sv.i);
-        if (m == 0) {
-            double2 lin = make_double2(0.0, 0.0);
-#pragma unroll 3
-            for (int dir = 0; dir < 6; ++dir) {
-                const int ln = code_nb(g, lcode, l, dir);
-                const C sn = rs[(ln >= 0 ? ln : l) * NQ + NT];
-                lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, make_double2((double)sn.r, (double)sn.i)));
-            }
-            const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l] + shift, sg));
-            r = add2(r, scl2(to.U[0], asg));
-        }
-        if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
-        xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
-    };
     double r0n = 0.0;
     if (a.n_inner > 0) {
         double loc = 0.0;
@@ -1414,54 +1395,38 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             }
             break;
         }
-        // inner pass: keep the state in LDS and update the local residual by K_bb delta
-        C* di = STORED ? xb : rh;
+        // inner pass: keep the state in LDS.  The correction solved the block system
+        // with the frozen field exactly, so the new local residual r - K_bb delta is
+        // the field's defect on this point alone:
+        //   row (l, m):  z_l (W delta_l)_m - shift U_m delta_lm,   constraint row: 0
+        // (written in place: no neighbour's correction is needed).  The reduced
+        // right-hand side of the next pass is that residual itself (sigma = 0).
         if (item) {
             const int l = l_it, m = m_it;
             cs[l * NT + m] = add2(cs[l * NT + m], make_double2((double)dv.r, (double)dv.i));
             if (m == 0) ls[l] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
-            if constexpr (!STORED) {
-                di[l * NQ + m] = dv;
-                if (m == 0) di[l * NQ + NT] = dl;
-            }
+            rh[l * NQ + m] = dv;   // this point's corrections, for its lane group
         }
-        if constexpr (!STORED) __syncthreads();
+        // a point's lanes are one group inside a wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double loc = 0.0;
         if (item) {
             const int l = l_it, m = m_it;
-            // y = (K_bb delta) on row (l, m); rolled loops keep the pass loop within 128 VGPRs
-            const C dvm = di[l * NQ + m];
-            C lap = rmul((BT)(-2.0 * g.dim), dvm);
+            C wd = C{0, 0};
+            if (a.field_on) {
 #pragma unroll 1
-            for (int dir = 0; dir < 6; ++dir) {
-                const int ln = code_nb(g, lcode, l, dir);
-                lap = lap + rmul(ln >= 0 ? (BT)1 : (BT)0, di[(ln >= 0 ? ln : l) * NQ + m]);
+                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)to.W[m * NT + n], rh[l * NQ + n]);
             }
-            const C hd = rmul((BT)(-g.kin), lap) + rmul((BT)v0s[l], dvm);
-            C tq = C{0, 0}, wd = C{0, 0}, sy = C{0, 0};
-#pragma unroll 1
-            for (int n = 0; n < NT; ++n) {
-                const C dn = di[l * NQ + n];
-                const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
-                tq = tq + rmul(cpl ? (BT)1 : (BT)0, dn);
-                if (a.field_on) wd = wd + rmul((BT)to.W[m * NT + n], dn);
-                sy = (n & 1) ? sy - dn : sy + dn;
-            }
-            const C tim = a.adjoint ? C{(BT)2 * tq.i, (BT)(-2) * tq.r} : C{(BT)(-2) * tq.i, (BT)2 * tq.r};
-            const BT sm = (m & 1) ? (BT)-1 : (BT)1;
-            const C y = tim - rmul((BT)to.U[m], hd) - rmul((BT)zs[l], wd) + rmul(sm, di[l * NQ + NT]);
-            rs[l * NQ + m] = rs[l * NQ + m] - y;
-            // multiplier row of point l
-            if (m == 0) rs[l * NQ + NT] = rs[l * NQ + NT] - sy;
-        }
-        __syncthreads();
-        if constexpr (!STORED) {
-            // the next pass's reduced right-hand side
-            if (item) reduced_rhs();
+            const C rn = rmul((BT)zs[l], wd) - rmul((BT)(shift * to.U[m]), dv);
+            rs[l * NQ + m] = rn;
+            if (m == 0) rs[l * NQ + NT] = C{0, 0};
+            if constexpr (shared_tf) xb[l * NQ + m] = rn;
+            loc = (double)rn.r * rn.r + (double)rn.i * rn.i;
         }
         {
             // stop the defect corrections once the local system is solved
-            double loc = 0.0;
-            for (int t = tid; t < b * NQ; t += kSweepThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
             const double tot = block_sum(loc, red);
             if (tid == 0) rnorm_sh = tot;
             __syncthreads();
