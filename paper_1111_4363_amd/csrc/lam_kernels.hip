@@ -844,35 +844,6 @@ __device__ __forceinline__ int code_nb(const LevelGeom& g, int lcode, int l, int
     return code == 0 ? -1 : l + (code == 1 ? step : wrap);
 }
 
-// Per-mode mixing on the matrix cores: Y[mode][.] = E X[mode][.] for every mode of
-// the block, with E a real n2 x n2 matrix (the real form of a complex n2/2 x n2/2
-// matrix acting on interleaved (re, im) values) and X, Y rows of n2 values, ld apart.
-// Wave w owns modes 16 (w % 4) .. and result rows 16 (w / 4) ..; operand loads
-// are unconditional (clamped index times a 0/1 factor).
-template <typename T>
-__device__ __forceinline__ typename Mfma<T>::acc_t mode_mix(const T* __restrict__ E, const T* __restrict__ X,
-                                                            int b, int n2, int ld, int lane, int wave) {
-    typename Mfma<T>::acc_t acc;
-    for (int r = 0; r < 4; ++r) acc[r] = (T)0;
-    const int nt = wave & 3, mt = wave >> 2;
-    if (16 * nt >= b || 16 * mt >= n2) return acc;
-    const int i = lane & 15, kq = lane >> 4;
-    const int mode = 16 * nt + i, row = 16 * mt + i;
-    const T fmode = mode < b ? (T)1 : (T)0;
-    const int modec = mode < b ? mode : b - 1, rowc = row < n2 ? row : n2 - 1;
-    const int ksteps = (n2 + 3) >> 2;
-#pragma unroll 5
-    for (int kk = 0; kk < ksteps; ++kk) {
-        const int k = 4 * kk + kq;
-        const T fk = k < n2 ? (T)1 : (T)0;
-        const int kc = k < n2 ? k : n2 - 1;
-        const T bv = X[modec * ld + kc] * (fmode * fk);
-        const T av = E[rowc * n2 + kc];
-        acc = Mfma<T>::step(av, bv, acc);
-    }
-    return acc;
-}
-
 // 1/d for normal, finite d: the hardware reciprocal estimate refined by
 // Newton-Raphson steps r <- r (2 - d r), each of which squares the relative
 // error (two steps in FP64, one in FP32 reach the last bit), without the
@@ -885,57 +856,6 @@ __device__ __forceinline__ double recip(double d) {
 __device__ __forceinline__ float recip(float d) {
     const float r = __builtin_amdgcn_rcpf(d);
     return r * (2.0f - d * r);
-}
-
-// mode_mix whose input is first multiplied by (I - e_k diag(lam))^{-1}: entry p
-// of mode k's vector becomes x_p / (1 - e_k lam_p).  Done on the operand
-// loads, so the scaled vector is never stored.  X holds nq complex entries per
-// mode, rows ldc apart.
-template <typename T>
-__device__ __forceinline__ typename Mfma<T>::acc_t mode_mix_scaled(const T* __restrict__ E, const cx<T>* __restrict__ X,
-                                                                   const T* __restrict__ es,
-                                                                   const cx<T>* __restrict__ lamv, int b, int nq,
-                                                                   int ldc, int lane, int wave) {
-    typename Mfma<T>::acc_t acc;
-    for (int r = 0; r < 4; ++r) acc[r] = (T)0;
-    const int n2 = 2 * nq;
-    const int nt = wave & 3, mt = wave >> 2;
-    if (16 * nt >= b || 16 * mt >= n2) return acc;
-    const int i = lane & 15, kq = lane >> 4;
-    const int mode = 16 * nt + i, row = 16 * mt + i;
-    const T fmode = mode < b ? (T)1 : (T)0;
-    const int modec = mode < b ? mode : b - 1, rowc = row < n2 ? row : n2 - 1;
-    const T ev = es[modec];
-    const int ksteps = (n2 + 3) >> 2;
-#pragma unroll 4
-    for (int kk = 0; kk < ksteps; ++kk) {
-        const int k = 4 * kk + kq;
-        const T fk = k < n2 ? (T)1 : (T)0;
-        const int kc = k < n2 ? k : n2 - 1;
-        const int p = kc >> 1;
-        const cx<T> x = X[modec * ldc + p];
-        const cx<T> lp = lamv[p];
-        const T dr = (T)1 - ev * lp.r, di = -ev * lp.i;   // 1 - e lam
-        const T sc = recip(dr * dr + di * di);
-        const T yr = (x.r * dr + x.i * di) * sc, yi = (x.i * dr - x.r * di) * sc;
-        const T bv = ((kc & 1) ? yi : yr) * (fmode * fk);
-        const T av = E[rowc * n2 + kc];
-        acc = Mfma<T>::step(av, bv, acc);
-    }
-    return acc;
-}
-
-template <typename T>
-__device__ __forceinline__ void mode_mix_store(T* __restrict__ Y, int b, int n2, int ld, int lane, int wave,
-                                               const typename Mfma<T>::acc_t& acc) {
-    const int nt = wave & 3, mt = wave >> 2;
-    if (16 * nt >= b || 16 * mt >= n2) return;
-    const int mode = 16 * nt + (lane & 15);
-    if (mode >= b) return;
-    for (int r = 0; r < 4; ++r) {
-        const int row = 16 * mt + Mfma<T>::row(lane, r);
-        if (row < n2) Y[mode * ld + row] = acc[r];
-    }
 }
 
 // The per-mode half of the shared-factor block solve, chained in the registers
@@ -951,11 +871,12 @@ __device__ __forceinline__ void mode_mix_store(T* __restrict__ Y, int b, int n2,
 // (step s, lane group kq) is 4s + kq (FP64) or 4kq + s (FP32) and the A operand
 // (E) is read in that order.  Rows or columns past nc, and modes past b, are
 // masked or never stored.
-template <typename T>
-__device__ __forceinline__ void mode_chain(const T* __restrict__ Vs, const T* __restrict__ R, int ld, int b, int nc,
+template <typename T, int LD, int NCOL>
+__device__ __forceinline__ void mode_chain(const T* __restrict__ Vs, const T* __restrict__ R, int b,
                                            const T* __restrict__ E1, const T* __restrict__ E3,
                                            const T* __restrict__ es, const cx<T>* __restrict__ lamv,
                                            T* __restrict__ Z, int lane, int wave) {
+    constexpr int ld = LD, nc = NCOL;
     using acc_t = typename Mfma<T>::acc_t;
     constexpr bool f64 = sizeof(T) == 8;
     if (wave >= 4 || 16 * wave >= b) return;
@@ -967,11 +888,12 @@ __device__ __forceinline__ void mode_chain(const T* __restrict__ Vs, const T* __
     const T fc = j < nc ? (T)1 : (T)0;
     const int jc = j < nc ? j : nc - 1;
     if (b == kMaxB) {
+        // one base address per operand, steps at compile-time offsets (folded into
+        // the LDS instructions, so no per-step address registers)
+        const T* rb = R + kq * ld + jc;
+        const T* vb = Vs + kq * kLdsPad + mode;
 #pragma unroll
-        for (int st = 0; st < kMaxB / 4; ++st) {
-            const int p = 4 * st + kq;
-            x = Mfma<T>::step(R[p * ld + jc] * fc, Vs[p * kLdsPad + mode], x);
-        }
+        for (int st = 0; st < kMaxB / 4; ++st) x = Mfma<T>::step(rb[4 * st * ld] * fc, vb[4 * st * kLdsPad], x);
     } else {
         for (int st = 0; 4 * st < b; ++st) {
             const int p = 4 * st + kq;
@@ -1353,8 +1275,8 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             const BT* E1 = tfs;
             const BT* E3 = tfs + 4 * NT * NT;
             const C* lamv = reinterpret_cast<const C*>(tfs + 8 * NT * NT);
-            mode_chain<BT>(Vs, reinterpret_cast<const BT*>(xb), N2, b, NC, E1, E3, es, lamv,
-                           reinterpret_cast<BT*>(rh), lane, wave);
+            mode_chain<BT, N2, NC>(Vs, reinterpret_cast<const BT*>(xb), b, E1, E3, es, lamv,
+                                   reinterpret_cast<BT*>(rh), lane, wave);
         }
         __syncthreads();
         // ---- 3c. back to points: xb[j][.] = sum_k V[j][k] rh[k][.] ----
