@@ -997,7 +997,8 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __shared__ C xb[kMaxB * NQ];   // E1 V^T r (shared factor), then the correction V y
     __shared__ BT tfs[TFR];        // shared time factor of this direction: E1, E3 real forms, lam
     __shared__ BT es[kMaxB];
-    __shared__ double2 sgs[kMaxB];  // constraint residual per point (shared factor, NT a power of two)
+    __shared__ double2 sgs[kMaxB];  // constraint residual per point (shared factor)
+    __shared__ double tos[NT + NT * NT];   // the time operators U, W (indexed per lane, so staged here)
     __shared__ double red[kSweepThreads / 64];
     __shared__ double rnorm_sh;
 
@@ -1040,6 +1041,38 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     // gains less than a factor 4 (the corrections have reached their rounding floor)
     const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-10;
     double rprev = 0.0;
+
+    // ---- 1. the block's eigenvectors and the shared time factor first: they depend on
+    //      the block id only, so their loads overlap the index arithmetic below ----
+    const double shift = a.shift[blk];   // frozen-field eigenvalue shift of this block
+    const int iw = tid - NT;
+    const double tov = tid < NT ? to.U[tid] : to.W[(iw >= 0 && iw < NT * NT) ? iw : 0];
+    BT vr[VPT];
+    {
+        const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
+        const int bb = b * b;
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) {
+            const int t = tid + r * kSweepThreads;
+            vr[r] = Vg[t < bb ? t : bb - 1];
+        }
+    }
+    BT tr[TPT];
+    BT ep = (BT)0;
+    if constexpr (shared_tf) {
+        const BT* tfg = static_cast<const BT*>(a.tf);
+        // the mixing pair of this direction (the adjoint pair follows the forward one),
+        // then its lam (after both pairs, forward first)
+        const int off_mix = a.adjoint ? 8 * NT * NT : 0;
+        const int off_lam = 16 * NT * NT + (a.adjoint ? 2 * NT : 0) - 8 * NT * NT;
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) {
+            const int t = tid + r * kSweepThreads;
+            const int tt = t < TFR ? t : TFR - 1;
+            tr[r] = tfg[tt < 8 * NT * NT ? off_mix + tt : off_lam + tt];
+        }
+        ep = (BT)(a.e[(size_t)blk * b + (tid < b ? tid : 0)] + shift);
+    }
 
     // ---- 1a. addresses (no loads yet); thread = residual item (point l, component m):
     //      eight lanes per point whatever NT is (lanes m >= NT idle), so that a point's
@@ -1092,34 +1125,8 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const double v0p = a.v0[gjp];
     const double2 lp = a.lam[gjp];
     const double2 sgv = scl2((a.bs && m_it == 0) ? 1.0 : 0.0, (a.bs ? a.bs : a.lam)[gj_it]);
-    BT vr[VPT];
-    {
-        const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
-        const int bb = b * b;
-#pragma unroll
-        for (int r = 0; r < VPT; ++r) {
-            const int t = tid + r * kSweepThreads;
-            vr[r] = Vg[t < bb ? t : bb - 1];
-        }
-    }
-    BT tr[TPT];
-    BT ep = (BT)0;
-    if constexpr (shared_tf) {
-        const BT* tfg = static_cast<const BT*>(a.tf);
-        // the mixing pair of this direction (the adjoint pair follows the forward one),
-        // then its lam (after both pairs, forward first)
-        const int off_mix = a.adjoint ? 8 * NT * NT : 0;
-        const int off_lam = 16 * NT * NT + (a.adjoint ? 2 * NT : 0) - 8 * NT * NT;
-#pragma unroll
-        for (int r = 0; r < TPT; ++r) {
-            const int t = tid + r * kSweepThreads;
-            const int tt = t < TFR ? t : TFR - 1;
-            tr[r] = tfg[tt < 8 * NT * NT ? off_mix + tt : off_lam + tt];
-        }
-        ep = (BT)(a.e[(size_t)blk * b + tp] + a.shift[blk]);
-    }
-
     // ---- 1c. consume into LDS ----
+    if (tid < NT + NT * NT) tos[tid] = tov;
     // a point's items are one aligned group of LPP lanes: its constraint residual
     // sigma = bs - sum_n s_n c_n is a group sum
     if constexpr (shared_tf) {
@@ -1159,7 +1166,6 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __syncthreads();
 
     // ---- 2. local residual (FP64); the item (l, 0) also takes the constraint row of point l ----
-    const double shift = a.shift[blk];   // frozen-field eigenvalue shift of this block
     if (item) {
         const int l = l_it, m = m_it;
         double2 lap = add2(scl2(-2.0 * g.dim, own), halo);
@@ -1178,12 +1184,12 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             const double2 cn = cs[l * NT + n];
             const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
             tq = add2(tq, scl2(cpl ? 1.0 : 0.0, cn));
-            if (a.field_on) wc = add2(wc, scl2(to.W[m * NT + n], cn));
+            if (a.field_on) wc = add2(wc, scl2(tos[NT + m * NT + n], cn));
             sgl = (n & 1) ? add2(sgl, cn) : sub2(sgl, cn);
         }
         const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
         const double sm = (m & 1) ? -1.0 : 1.0;
-        double2 row = sub2(sub2(tim, scl2(to.U[m], hc)), scl2(zs[l], wc));
+        double2 row = sub2(sub2(tim, scl2(tos[m], hc)), scl2(zs[l], wc));
         row = add2(row, scl2(sm, ls[l]));
         const double2 rho = sub2(rhsv, row);
         rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
@@ -1206,7 +1212,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                     lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, sgs[ln >= 0 ? ln : l]));
                 }
                 const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l] + shift, sg));
-                r = add2(r, scl2(to.U[0], asg));
+                r = add2(r, scl2(tos[0], asg));
             }
             if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
             xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
@@ -1339,9 +1345,9 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             C wd = C{0, 0};
             if (a.field_on) {
 #pragma unroll 1
-                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)to.W[m * NT + n], rh[l * NQ + n]);
+                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tos[NT + m * NT + n], rh[l * NQ + n]);
             }
-            const C rn = rmul((BT)zs[l], wd) - rmul((BT)(shift * to.U[m]), dv);
+            const C rn = rmul((BT)zs[l], wd) - rmul((BT)(shift * tos[m]), dv);
             rs[l * NQ + m] = rn;
             if (m == 0) rs[l * NQ + NT] = C{0, 0};
             if constexpr (shared_tf) xb[l * NQ + m] = rn;
