@@ -263,7 +263,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // Residual of item (point j, component m) of a group of points staged
 // together: every thread of the workgroup calls it (it holds a barrier).
 // cs holds the group's coefficients, slot = the thread's (point, m) position;
-// cj points at the item's point in cs.  Returns rho_jm; for m == 0 also the
+// cj points at the item's point in cs; tos (NT + NT^2 doubles of LDS) receives
+// U and W, which are indexed per lane.  Returns rho_jm; for m == 0 also the
 // constraint residual sigma_j (in *sg).
 template <int NT>
 __device__ __forceinline__ double2 residual_item(const LevelGeom& g, const TimeOps<NT>& to, int adjoint, int field_on,
@@ -271,8 +272,10 @@ __device__ __forceinline__ double2 residual_item(const LevelGeom& g, const TimeO
                                                  const double* __restrict__ v0, const double2* __restrict__ bc,
                                                  const double2* __restrict__ bg, const double2* __restrict__ bs,
                                                  int j, int m, bool slot, double2* cs, int cslot, const double2* cj,
-                                                 double2* sg) {
+                                                 double* tos, double2* sg) {
     const I3 i = point_coords(g, j);
+    const int t = threadIdx.x, iw = t - NT;
+    const double tov = t < NT ? to.U[t] : to.W[(iw >= 0 && iw < NT * NT) ? iw : 0];
     const double2 own = c[(size_t)j * NT + m];
     // neighbour loads issued unconditionally (clamped index, 0/1 weight)
     double2 nbv[6];
@@ -298,6 +301,7 @@ __device__ __forceinline__ double2 residual_item(const LevelGeom& g, const TimeO
     const double2 rhs = scl2((bc || bg) ? 1.0 : 0.0, *rbp);
     const double2 sgb = scl2((bs && m == 0) ? 1.0 : 0.0, (bs ? bs : lam)[j]);
     if (slot) cs[cslot] = own;
+    if (t < NT + NT * NT) tos[t] = tov;
     __syncthreads();
     double2 lap = scl2(-2.0 * g.dim, own);
 #pragma unroll
@@ -311,11 +315,11 @@ __device__ __forceinline__ double2 residual_item(const LevelGeom& g, const TimeO
     // forward: i * 2 tq ; adjoint: -i * 2 tq
     const double2 tim = adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
     const double2 hc = add2(scl2(-g.kin, lap), scl2(vj, own));
-    double2 row = sub2(tim, scl2(to.U[m], hc));
+    double2 row = sub2(tim, scl2(tos[m], hc));
     if (field_on) {
         double2 wc = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(to.W[m * NT + n], cj[n]));
+        for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(tos[NT + m * NT + n], cj[n]));
         row = sub2(row, scl2(zcoord(g, i), wc));
     }
     row = add2(row, scl2((m & 1) ? -1.0 : 1.0, lj));
@@ -340,6 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
                                                        double* __restrict__ partial) {
     constexpr int PW = kThreads / NT;  // points per workgroup
     __shared__ double2 cs[PW * NT];
+    __shared__ double tos[NT + NT * NT];
     __shared__ double red[kThreads / 64];
     const int t = threadIdx.x;
     const int lp = t / NT, m = t - lp * NT;
@@ -349,10 +354,10 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
     const int j = act ? (int)jw : 0;
     double2 sg = make_double2(0.0, 0.0);
     const double2 rho = residual_item<NT>(g, to, adjoint, field_on, c, lam, v0, bc, bg, bs, j, m, lp < PW, cs, t,
-                                          cs + (lp < PW ? lp : 0) * NT, &sg);
+                                          cs + (lp < PW ? lp : 0) * NT, tos, &sg);
     if (act) {
         if (rc) rc[(size_t)j * NT + m] = rho;
-        acc += to.U[m] * (rho.x * rho.x + rho.y * rho.y);
+        acc += tos[m] * (rho.x * rho.x + rho.y * rho.y);
         if (m == 0) {
             if (rs) rs[j] = sg;
             acc += sg.x * sg.x + sg.y * sg.y;
@@ -385,6 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(LevelGeom f, Lev
     static_assert(PT * kMaxNT <= kThreads, "one item per thread");
     __shared__ double2 cs[PT * NT];
     __shared__ double2 rb[PT * NQ];
+    __shared__ double tos[NT + NT * NT];
     const int t = threadIdx.x;
     const int lp = t / NT, m = t - lp * NT;
     const int dim = f.dim;
@@ -402,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(LevelGeom f, Lev
     const int j = inside ? point_index(f, fi) : 0;
     double2 sg = make_double2(0.0, 0.0);
     const double2 rho = residual_item<NT>(f, to, adjoint, field_on, c, lam, v0, bc, bg, bs, j, m, lp < PT, cs, t,
-                                          cs + (lp < PT ? lp : 0) * NT, &sg);
+                                          cs + (lp < PT ? lp : 0) * NT, tos, &sg);
     if (lp < PT) {
         rb[lp * NQ + m] = rho;
         if (m == 0) rb[lp * NQ + NT] = sg;
