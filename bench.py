@@ -134,7 +134,7 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
     # context creation = hierarchy + factorisation of every block of every level (once per run for a
     # static potential)
     prop = lam.Propagator(shape, cfg["h"], v0_t, cfg["n_t"], cfg["dt"], (cfg["block"],) * cfg["dim"],
-                          levels=cfg["levels"], nu_pre=1, nu_post=1, nu_coarse=2, precision=precision,
+                          levels=cfg["levels"], nu_pre=1, nu_post=1, nu_coarse=cfg["nu_coarse"], precision=precision,
                           tol=args.tol, max_cycles=60, pulse=pulse_of(cfg))
     torch.cuda.synchronize()
     factor_ms = (time.perf_counter() - t_f) * 1e3
@@ -190,7 +190,7 @@ def workload_string(cfg, tol):
                  "sin2+fourier": f", E0={p['e0']} sin^2 pulse + {p['n_coef']} Fourier amplitudes"}[p["kind"]]
     blocks = "x".join([str(cfg["block"])] * cfg["dim"])
     return (f"{cfg['name']} {shape} h={cfg['h']:g} {pot}{field}, N_t={cfg['n_t']}, dt={cfg['dt']}, "
-            f"{blocks} subvolumes, {cfg['levels']}-level V(1,1), tol {tol:g}")
+            f"{blocks} subvolumes, {cfg['levels']}-level V(1,1) with {cfg['nu_coarse']} coarsest sweep(s), tol {tol:g}")
 
 
 def main():
