@@ -1185,13 +1185,24 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         double2 tq = make_double2(0.0, 0.0);
         double2 wc = make_double2(0.0, 0.0);
         double2 sgl = sgv;
+        if (STORED || a.field_on) {
+            // every component: the field's W row, and (stored path) the constraint row
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            const double2 cn = cs[l * NT + n];
-            const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
-            tq = add2(tq, scl2(cpl ? 1.0 : 0.0, cn));
-            if (a.field_on) wc = add2(wc, scl2(tos[NT + m * NT + n], cn));
-            sgl = (n & 1) ? add2(sgl, cn) : sub2(sgl, cn);
+            for (int n = 0; n < NT; ++n) {
+                const double2 cn = cs[l * NT + n];
+                const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
+                tq = add2(tq, scl2(cpl ? 1.0 : 0.0, cn));
+                if (a.field_on) wc = add2(wc, scl2(tos[NT + m * NT + n], cn));
+                sgl = (n & 1) ? add2(sgl, cn) : sub2(sgl, cn);
+            }
+        } else {
+            // only the coupled components m + 1, m + 3, ... (adjoint m - 1, m - 3, ...)
+#pragma unroll
+            for (int k = 0; k < (NT + 1) / 2; ++k) {
+                const int n = a.adjoint ? m - 1 - 2 * k : m + 1 + 2 * k;
+                const bool in = n >= 0 && n < NT;
+                tq = add2(tq, scl2(in ? 1.0 : 0.0, cs[l * NT + (in ? n : m)]));
+            }
         }
         const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
         const double sm = (m & 1) ? -1.0 : 1.0;
