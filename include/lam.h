@@ -116,10 +116,13 @@ typedef struct {
     int n_inner;      /* most inner corrections of each subvolume solve when E(t) != 0
                          (the factor freezes the field at its step mean and block centre;
                          each block stops once its own residual fell by 1e-13 in FP64,
-                         1e-6 in FP32); -1 = automatic (16 with a field, 0 without) */
-    int time_factor;  /* how each mode's (n_t+1) time system is solved inside a sweep:
-                         LAM_TF_SHARED (0): one shared Schur factor per context, per-mode
-                         triangular solve (streams one eigenvalue per mode);
+                         1e-5 in FP32, or stops improving); -1 = automatic (16 with a
+                         field, 0 without) */
+    int time_factor;  /* how each mode's time system is solved inside a sweep:
+                         LAM_TF_SHARED (0): one factor shared by all modes (the n_t x n_t
+                         system left after each point's continuity row eliminates c_0,
+                         in the eigenbasis of its time operator; streams one eigenvalue
+                         per mode);
                          LAM_TF_STORED (1): stored per-mode inverses ((n_t+1)^2 complex per
                          mode, refactored when the step's mean field changes) */
 } lam_solver;

@@ -85,12 +85,9 @@ void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
 }
 
 // ---------------------------------------------------------------------------
-// Shared factor of the per-mode time systems.  M(e) = M0 - e D with
-// M0 = [[iQ^T, s], [s^T, 0]] and D = diag(U, 0), so M(e) = M0 (I - e G),
-// G = M0^{-1} D.  With the complex Schur form G = Z T Z^H (Z unitary, T upper
-// triangular): M(e)^{-1} = Z (I - e T)^{-1} B, B = Z^H M0^{-1}.  G has a 2x2
-// Jordan block at 0, so an eigenvector basis would be singular; the Schur
-// form stays unitary.  n <= 9: plain shifted QR on the full matrix.
+// Small dense complex linear algebra for the shared time factor of the
+// per-mode block systems (n <= 8): inverse, Householder QR and the complex
+// Schur form by shifted QR on the full matrix.
 // ---------------------------------------------------------------------------
 using cd = std::complex<double>;
 

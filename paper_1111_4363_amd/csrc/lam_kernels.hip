@@ -822,16 +822,21 @@ __global__ __launch_bounds__(64) void k_mode_factor(int b, TimeOps<NT> to, const
 }
 
 // ---------------------------------------------------------------------------
-// K3: relax every block of one colour.  One workgroup (4 waves) per block:
-//   1. issue every global load of the block (own coefficients, halo
-//      neighbours outside the block, right-hand side, lambda, V0,
-//      eigenvectors, eigenvalues, the shared time factor) before consuming
-//      any of them, so one memory latency covers the block;
-//   2. local residual r_U = (b - K x)_U from LDS and registers (FP64);
-//   3. delta = V (M(e_k)^{-1} (V^T r)) per mode k   [K_UU^{-1} r in factored form]
-//      (a) V^T r and (c) V d on the matrix cores, (b) the per-mode time solve;
-//   4. (field steps) corrections r <- r - K_UU delta, repeat 3, until the
-//      block's residual fell by 1e-13 (FP64) / 1e-6 (FP32), at most n_inner;
+// K3: relax every block of one colour.  One 512-thread workgroup per block,
+// eight lanes per grid point (a residual item (point, component) per lane):
+//   1. issue the block's global loads before consuming any of them (the
+//      eigenvectors, eigenvalues and time factor first, then own coefficients,
+//      halo neighbours outside the block, right-hand sides, lambda, V0), so one
+//      memory latency covers the block;
+//   2. local residual r_U = (b - K x)_U from LDS and registers (FP64), and the
+//      right-hand side of the reduced block system (dc_0 eliminated by each
+//      point's continuity row);
+//   3. delta = V (M_r(e_k)^{-1} (V^T r)) per mode k   [K_UU^{-1} r in factored
+//      form]: V^T r, the per-mode solve E3 (I - e diag(lam))^{-1} E1 chained in
+//      the registers of one wave per 16 modes, then V (.) on the matrix cores;
+//   4. (field steps) the new local residual is the frozen field's defect of
+//      delta, point by point; repeat 3 until the block's residual fell by 1e-13
+//      (FP64) / 1e-5 (FP32) or stops improving, at most n_inner times;
 //   5. write c_U += delta_c, lambda_U += delta_lambda.
 // BT is the precision of the factors and of step 3 (double, or float for the
 // mixed path); the state and the residual of step 2 are always FP64.
@@ -999,8 +1004,8 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __shared__ double zs[kMaxB];
     __shared__ int gidx[kMaxB];
     __shared__ C rs[kMaxB * NQ];   // local residual
-    __shared__ C rh[kMaxB * NQ];   // V^T r, then the per-mode solutions
-    __shared__ C xb[kMaxB * NQ];   // E1 V^T r (shared factor), then the correction V y
+    __shared__ C rh[kMaxB * NQ];   // per-mode solutions (stored path: V^T r first)
+    __shared__ C xb[kMaxB * NQ];   // reduced right-hand side (shared factor), then the correction V y
     __shared__ BT tfs[TFR];        // shared time factor of this direction: E1, E3 real forms, lam
     __shared__ BT es[kMaxB];
     __shared__ double2 sgs[kMaxB];  // constraint residual per point (shared factor)
