@@ -334,6 +334,7 @@ struct lam_ctx {
     double* h_norms = nullptr;    // pinned, mapped: N after each queued V-cycle of a solve (slot 0: N0)
     double* h_norms_dev = nullptr;
     int predict[2] = {0, 0};      // V-cycles the last forward / adjoint solve needed (0: none yet)
+    int solves[2] = {0, 0};       // forward / adjoint solves done
     std::vector<double> gl_x, gl_w;  // Gauss-Legendre nodes of the field quadrature
     double2* d_Gpart = nullptr;
     double2* d_G = nullptr;
@@ -563,12 +564,18 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
     double N0 = 0.0, N = 0.0;
     for (;;) {
         const int nb = std::min(batch, maxc - queued);
-        // norms after the last two cycles of the batch only: the last decides,
-        // the one before tells whether the next solve can use one cycle less
+        // norms after the last cycle of the batch (it decides) and, on every
+        // eighth solve of this kind, after the one before (whether the next solves
+        // can use one cycle less)
+        const bool probe = (c->solves[c->adjoint ? 1 : 0] & 7) == 0;
+        int first_norm = -1;   // the first cycle of this batch whose norm is queued
         for (int i = 0; i < nb; ++i) {
             LAMCHK(vcycle(c, 0));
             ++queued;
-            if (i >= nb - 2) LAMCHK(queue_norm(c, queued));
+            if (i == nb - 1 || (probe && i == nb - 2)) {
+                LAMCHK(queue_norm(c, queued));
+                if (first_norm < 0) first_norm = queued;
+            }
         }
         LAMCHK(wait_stream(c));
         N0 = c->h_norms[0];
@@ -582,7 +589,7 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
             break;
         }
         bool div = false;
-        for (int k = std::max(queued - nb + 1, queued - 1); k <= queued; ++k) {
+        for (int k = first_norm; first_norm >= 0 && k <= queued; ++k) {
             const double Nk = c->h_norms[k];
             if (!std::isfinite(Nk) || Nk > 1e12 * N0) {
                 div = true;
@@ -602,6 +609,7 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
         batch = 1;
     }
     if (conv > 0) predict = conv;
+    ++c->solves[c->adjoint ? 1 : 0];
     if (stats) {
         stats->cycles = queued;
         stats->resid0 = std::sqrt(N0);
