@@ -61,9 +61,10 @@ def setup(name, precision="fp64"):
         pulse = dict(kind=p["kind"], e0=p.get("e0", 0.0), omega=p.get("omega", 0.0), t_total=cfg["t_total"],
                      coef=list(coef))
     dev = torch.device("cuda:0")
+    # the configuration the benchmark times (coarsest-level sweeps included)
     prop = lam.Propagator(cfg["shape"], cfg["h"], torch.as_tensor(v0, device=dev), cfg["n_t"], cfg["dt"],
-                          (cfg["block"],) * cfg["dim"], levels=cfg["levels"], pulse=pulse, precision=precision,
-                          tol=1e-10, max_cycles=60)
+                          (cfg["block"],) * cfg["dim"], levels=cfg["levels"], nu_coarse=cfg["nu_coarse"],
+                          pulse=pulse, precision=precision, tol=1e-10, max_cycles=60)
     grid = G.Grid(cfg["shape"], cfg["h"])
     return cfg, v0, psi0, pulse, prop, grid, dev
 
