@@ -207,8 +207,12 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
 
 /* Propagate n_steps consecutive steps, step k starting at t0 + k dt, each
  * solved as by lam_solve_step: psi_in (device, P) -> psi_out (device, P); the
- * buffers may coincide.  The steps run back to back on the context stream
- * with no host round trip between them.  stats (may be NULL): cycles and
+ * buffers may coincide.  The steps run back to back on the context stream;
+ * the host waits only for each batch of norms.  When two consecutive steps
+ * both see no field, the next step's initial state and its N0 are queued
+ * ahead of the wait for the current step's last norms, into spare
+ * finest-level buffers (P (n_t + 2) complex values, allocated by the context
+ * on first use and kept until lam_destroy).  stats (may be NULL): cycles and
  * sweeps_fine summed over the steps, resid0/resid of the step with the
  * largest resid/resid0, t_factor_ms and t_solve_ms summed.  Stops at the first
  * step that does not return LAM_OK and returns its code (psi_out then holds

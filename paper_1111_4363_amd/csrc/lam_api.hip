@@ -334,6 +334,11 @@ struct lam_ctx {
     double* h_norms = nullptr;    // pinned, mapped: N after each queued V-cycle of a solve (slot 0: N0)
     double* h_norms_dev = nullptr;
     int predict[2] = {0, 0};      // V-cycles the last forward / adjoint solve needed (0: none yet)
+    // lam_propagate: the next step's initial state, built while the host waits
+    // for the norms of the current step's last V-cycles (finest level)
+    double2* d_c_next = nullptr;
+    double2* d_lam_next = nullptr;
+    double2* d_bs_next = nullptr;
     int solves[2] = {0, 0};       // forward / adjoint solves done
     std::vector<double> gl_x, gl_w;  // Gauss-Legendre nodes of the field quadrature
     double2* d_Gpart = nullptr;
@@ -424,6 +429,15 @@ int set_step(lam_ctx* c, double t0) {
     return LAM_OK;
 }
 
+// Whether the step starting at t0 sees no field (its time matrix is zero).
+bool field_free(const lam_ctx* c, double t0) {
+    double W[kMaxNT * kMaxNT];
+    time_matrix(c, t0, -1, W);
+    for (int k = 0; k < c->nt * c->nt; ++k)
+        if (W[k] != 0.0) return false;
+    return true;
+}
+
 int factor_level(lam_ctx* c, Level& L) {
     HIPCHK(launch_block_eig(L.g, L.d_v0, L.d_V, L.d_e, L.fp32 ? L.d_Vf : nullptr, c->st));
     L.factored_field = NAN;
@@ -488,15 +502,20 @@ int full_sweep(lam_ctx* c, int l) {
 // Wait for the work queued on the context stream (e.g. a norm reduction that
 // writes host memory): an event polled in a loop, so the host resumes as soon
 // as the work is done (a blocking stream synchronisation can add tens of
-// microseconds of wake-up latency to every V-cycle).
-int wait_stream(lam_ctx* c) {
-    HIPCHK(hipEventRecord(c->ev_norm, c->st));
+// microseconds of wake-up latency to every V-cycle).  wait_event polls
+// ev_norm as recorded earlier; wait_stream records it at the end of the queue.
+int wait_event(lam_ctx* c) {
     for (;;) {
         const hipError_t e = hipEventQuery(c->ev_norm);
         if (e == hipSuccess) break;
         if (e != hipErrorNotReady) return LAM_EHIP;
     }
     return LAM_OK;
+}
+
+int wait_stream(lam_ctx* c) {
+    HIPCHK(hipEventRecord(c->ev_norm, c->st));
+    return wait_event(c);
 }
 
 // N of the finest level for the context state (synchronises).
@@ -535,14 +554,20 @@ int vcycle(lam_ctx* c, int l) {
 }
 
 // V-cycles on the context state until sqrt(N/N0) <= tol.
-// Queue N of the finest level for the context state into h_norms[slot] (no wait).
-int queue_norm(lam_ctx* c, int slot) {
+// Queue N of the finest level for the context state into h_norms[slot] (no
+// wait); with `cx` given, for the forward state (cx, lx, bx) instead.
+int queue_norm(lam_ctx* c, int slot, const double2* cx = nullptr, const double2* lx = nullptr,
+               const double2* bx = nullptr) {
     Level& L = c->lv[0];
     const double2* bg = c->adjoint ? c->d_g : nullptr;
     const double2* bs = c->adjoint ? nullptr : L.d_bs;
+    if (cx) {
+        bg = nullptr;
+        bs = bx;
+    }
     int np = 0;
-    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, nullptr, bg,
-                           bs, nullptr, nullptr, c->d_partial, &np, c->st));
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, cx ? 0 : c->adjoint, c->field_on, cx ? cx : L.d_c,
+                           cx ? lx : L.d_lam, L.d_v0, nullptr, bg, bs, nullptr, nullptr, c->d_partial, &np, c->st));
     HIPCHK(launch_reduce(c->d_partial, np, 1, c->h_norms_dev + slot, c->st));
     return LAM_OK;
 }
@@ -554,10 +579,21 @@ int queue_norm(lam_ctx* c, int slot) {
 // host round trip per cycle would leave the GPU idle while the next cycle is
 // launched.  When a batch overshoots, the extra cycles only refine the state;
 // `cycles` reports the cycles run.
-int solve_loop(lam_ctx* c, lam_stats* stats) {
+// n0_slot >= 0: N0 of this (forward) solve is already queued into that slot.
+// next_out non-null (forward solves of lam_propagate whose next step has no
+// field, like this one): before each wait, the end state goes to next_out, the
+// next step's initial state to the context's d_*_next buffers and its N0 to
+// h_norms[next_slot], so that the GPU has work while the host reacts to the
+// norms; *next_ready tells whether that was done after the final cycle.
+int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out = nullptr, int next_slot = 0,
+               bool* next_ready = nullptr) {
     const int maxc = c->solver.max_cycles;
     int& predict = c->predict[c->adjoint ? 1 : 0];
-    LAMCHK(queue_norm(c, 0));
+    if (next_ready) *next_ready = false;
+    if (n0_slot < 0) {
+        n0_slot = 0;
+        LAMCHK(queue_norm(c, 0));
+    }
     int queued = 0, conv = -1;
     int rc = LAM_ENOCONV;
     int batch = std::min(predict, maxc);  // 0 on a context's first solve: look at N0 first
@@ -577,8 +613,16 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
                 if (first_norm < 0) first_norm = queued;
             }
         }
-        LAMCHK(wait_stream(c));
-        N0 = c->h_norms[0];
+        // the host waits for the norms only; queued after them, the next
+        // step's start keeps the GPU busy while the host reacts
+        HIPCHK(hipEventRecord(c->ev_norm, c->st));
+        if (next_out) {
+            Level& L = c->lv[0];
+            HIPCHK(launch_advance(c->nt, L.g.P, L.d_c, next_out, c->d_c_next, c->d_lam_next, c->d_bs_next, c->st));
+            LAMCHK(queue_norm(c, next_slot, c->d_c_next, c->d_lam_next, c->d_bs_next));
+        }
+        LAMCHK(wait_event(c));
+        N0 = c->h_norms[n0_slot];
         N = c->h_norms[queued];
         if (!std::isfinite(N0)) {
             rc = LAM_EDIVERGED;
@@ -586,6 +630,7 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
         }
         if (N0 == 0.0) {
             rc = LAM_OK;
+            if (next_ready) *next_ready = next_out != nullptr;
             break;
         }
         bool div = false;
@@ -603,6 +648,7 @@ int solve_loop(lam_ctx* c, lam_stats* stats) {
         }
         if (conv >= 0) {
             rc = LAM_OK;
+            if (next_ready) *next_ready = next_out != nullptr;
             break;
         }
         if (queued >= maxc) break;
@@ -701,6 +747,9 @@ void free_ctx(lam_ctx* c) {
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->ev_norm) (void)hipEventDestroy(c->ev_norm);
     if (c->h_norms) (void)hipHostFree(c->h_norms);
+    (void)hipFree(c->d_c_next);
+    (void)hipFree(c->d_lam_next);
+    (void)hipFree(c->d_bs_next);
     if (c->h_G) (void)hipHostFree(c->h_G);
     for (auto e : c->ev) (void)hipEventDestroy(e);
     delete c;
@@ -789,7 +838,7 @@ int build(lam_ctx* c, const double* v0_dev) {
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_red), sizeof(double), hipHostMallocMapped) != hipSuccess)
         return LAM_ENOMEM;
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_red_dev), c->h_red, 0));
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(double) * (c->solver.max_cycles + 2),
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(double) * (c->solver.max_cycles + 3),
                       hipHostMallocMapped) != hipSuccess)
         return LAM_ENOMEM;
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_norms_dev), c->h_norms, 0));
@@ -1021,16 +1070,39 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
     double worst = -1.0;
     int rc = LAM_OK;
     const lam_c64* src = psi_in;
+    int n0_slot = -1;  // >= 0: this step's initial state is in place and its N0 queued into that slot
     for (int k = 0; k < n_steps; ++k) {
-        LAMCHK(set_step(ctx, t0 + k * ctx->time.dt));
-        HIPCHK(launch_init_forward(ctx->nt, L.g.P, reinterpret_cast<const double2*>(src), L.d_c, L.d_lam, L.d_bs,
-                                   ctx->st));
+        const double tk = t0 + k * ctx->time.dt;
+        LAMCHK(set_step(ctx, tk));
+        if (n0_slot < 0)
+            HIPCHK(launch_init_forward(ctx->nt, L.g.P, reinterpret_cast<const double2*>(src), L.d_c, L.d_lam,
+                                       L.d_bs, ctx->st));
         ctx->adjoint = 0;
         ctx->have_state = 1;
+        // When neither this step nor the next sees a field, nothing changes
+        // between them but the state, and the next step's start is queued
+        // ahead of each wait for this step's norms.
+        const bool ahead = k + 1 < n_steps && !ctx->field_on && field_free(ctx, tk + ctx->time.dt);
+        if (ahead && !ctx->d_c_next) {
+            LAMCHK(dalloc(&ctx->d_c_next, (size_t)L.g.P * ctx->nt));
+            LAMCHK(dalloc(&ctx->d_lam_next, (size_t)L.g.P));
+            LAMCHK(dalloc(&ctx->d_bs_next, (size_t)L.g.P));
+        }
+        const int next_slot = ctx->solver.max_cycles + 1 + (k & 1);
+        bool ready = false;
         lam_stats st{};
-        rc = solve_loop(ctx, &st);
+        rc = solve_loop(ctx, &st, n0_slot, ahead ? reinterpret_cast<double2*>(psi_out) : nullptr, next_slot, &ready);
         if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
-        HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, reinterpret_cast<double2*>(psi_out), ctx->st));
+        n0_slot = -1;
+        if (ready) {
+            // psi_out holds this step's end state; the next step starts from the spare buffers
+            std::swap(L.d_c, ctx->d_c_next);
+            std::swap(L.d_lam, ctx->d_lam_next);
+            std::swap(L.d_bs, ctx->d_bs_next);
+            n0_slot = next_slot;
+        } else {
+            HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, reinterpret_cast<double2*>(psi_out), ctx->st));
+        }
         src = psi_out;
         tot.cycles += st.cycles;
         const double ratio = st.resid0 > 0.0 ? st.resid / st.resid0 : 0.0;

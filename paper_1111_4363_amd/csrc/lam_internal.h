@@ -114,6 +114,10 @@ hipError_t launch_init_zero(int nt, int P, double2* c, double2* lam, hipStream_t
 
 hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStream_t st);
 
+// psi = end state of c; (cn, lamn, bsn) = the next step's initial state from psi.
+hipError_t launch_advance(int nt, int P, const double2* c, double2* psi, double2* cn, double2* lamn, double2* bsn,
+                          hipStream_t st);
+
 hipError_t launch_copy_c2(const double2* src, double2* dst, size_t n, hipStream_t st);
 
 hipError_t launch_gradients(int nt, const LevelGeom& g, const double* U, const double2* cfwd,

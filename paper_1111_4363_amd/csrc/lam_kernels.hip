@@ -1436,6 +1436,26 @@ __global__ __launch_bounds__(kThreads) void k_end_eval(int P, const double2* __r
     psi[j] = acc;
 }
 
+// End of one step and start of the next in one pass: psi = x(t0 + dt) as in
+// k_end_eval, and the next step's initial state from it as in k_init_forward,
+// written to a second set of buffers (c is left as it is).
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_advance(int P, const double2* __restrict__ c,
+                                                      double2* __restrict__ psi, double2* __restrict__ cn,
+                                                      double2* __restrict__ lamn, double2* __restrict__ bsn) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= P) return;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc = add2(acc, c[(size_t)j * NT + n]);
+    psi[j] = acc;
+    cn[(size_t)j * NT] = acc;
+#pragma unroll
+    for (int n = 1; n < NT; ++n) cn[(size_t)j * NT + n] = make_double2(0.0, 0.0);
+    lamn[j] = make_double2(0.0, 0.0);
+    bsn[j] = acc;
+}
+
 __global__ __launch_bounds__(kThreads) void k_copy_c2(const double2* __restrict__ src, double2* __restrict__ dst,
                                                       size_t n) {
     const size_t k = (size_t)blockIdx.x * kThreads + threadIdx.x;
@@ -1616,6 +1636,13 @@ hipError_t launch_init_zero(int nt, int P, double2* c, double2* lam, hipStream_t
 hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStream_t st) {
     LAM_DISPATCH_NT(nt,
                     hipLaunchKernelGGL(k_end_eval<NT>, dim3(nblk_for(P)), dim3(kThreads), 0, st, P, c, psi));
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(int nt, int P, const double2* c, double2* psi, double2* cn, double2* lamn, double2* bsn,
+                          hipStream_t st) {
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_advance<NT>, dim3(nblk_for(P)), dim3(kThreads), 0, st, P, c, psi, cn,
+                                           lamn, bsn));
     return hipGetLastError();
 }
 

@@ -210,6 +210,49 @@ def test_native_propagate_matches_stepwise_and_edge_cases():
     prop.close()
 
 
+@pytest.mark.parametrize("pulse", [None, dict(kind="sin2", e0=0.05, omega=0.057, t_total=0.1)],
+                         ids=["no-field", "field-ends-mid-run"])
+def test_native_propagate_queued_next_step(pulse):
+    """Steps without a field have the next step's start queued ahead of each
+    wait (spare buffers swapped in when the step has converged).  Against the
+    oracle's direct steps and the step-by-step path: a run with no field, and
+    one whose pulse ends with the second step (the first two steps keep the
+    plain path); the in-place form; the context state after the run is the last
+    step's; a tiny max_cycles stops the run at its first step with that step's
+    result."""
+    import torch
+    from paper_1111_4363_amd import lam
+    case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=pulse)
+    note(f"native propagate, next step queued ahead {case}")
+    K = 7
+    psis = kkt.propagate(case.grid, case.v0, case.psi0, case.n_t, case.dt, K, case.field)
+    ref = np.abs(psis[-1]).max()
+    prop = case.prop(tol=1e-12, max_cycles=60)
+    psi_native, st = prop.propagate(t_c(case.psi0), K)
+    assert np.abs(n(psi_native) - psis[-1]).max() <= 1e-10 * ref
+    assert st[0]["resid"] <= 1e-12 * st[0]["resid0"] * 1.0001
+    cg, _ = prop.get_state()
+    assert np.abs(n(cg).reshape(-1, case.n_t).sum(axis=1) - n(psi_native)).max() <= 1e-14 * ref
+    seq, _ = prop.propagate(t_c(case.psi0), K, keep=True)
+    assert np.abs(n(psi_native) - n(seq[-1])).max() <= 1e-10 * ref
+    buf = t_c(case.psi0).clone()
+    assert prop._lib.lam_propagate(prop._ctx, 0.0, K, lam._ptr(buf, torch.complex128, case.npts),
+                                   lam._ptr(buf, torch.complex128, case.npts), None) == lam.LAM_OK
+    assert np.abs(n(buf) - psis[-1]).max() <= 1e-10 * ref
+    prop.close()
+    # two cycles cannot reach 1e-12: LAM_ENOCONV after the first step, psi_out = its end state
+    short = case.prop(tol=1e-12, max_cycles=2)
+    out = torch.zeros_like(t_c(case.psi0))
+    code = short._lib.lam_propagate(short._ctx, 0.0, K, lam._ptr(t_c(case.psi0), torch.complex128, case.npts),
+                                    lam._ptr(out, torch.complex128, case.npts), None)
+    assert code == lam.LAM_ENOCONV
+    short.close()
+    one = case.prop(tol=1e-12, max_cycles=2)
+    psi1, _ = one.solve_step(0.0, t_c(case.psi0), allow_noconv=True)
+    assert torch.equal(out, psi1)
+    one.close()
+
+
 def test_sweep_profiling_samples_every_kth_launch():
     """lam_profile(k) records the 1st, (k+1)-th, ... finest-level sweep launch."""
     case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2)
