@@ -187,6 +187,19 @@ __device__ __forceinline__ int neighbour(const LevelGeom& g, const I3& i, int ax
     return point_index(g, *gi);
 }
 
+// The same neighbour found from the point's own index and the axis stride, as
+// selects (no branches): j +- stride inside the grid, the opposite end of the
+// axis across a periodic boundary, -1 outside a Dirichlet grid.  AX and D are
+// compile-time, so the stride and the wrap offset are uniform values.
+template <int AX, int D>
+__device__ __forceinline__ int neighbour_of(const LevelGeom& g, const I3& i, int j) {
+    const int na = g.n[AX];
+    const int st = AX == 2 ? 1 : (AX == 1 ? g.n[2] : g.n[1] * g.n[2]);
+    const int v = comp(i, AX) + D;
+    const int wrap = g.periodic ? j - D * (na - 1) * st : -1;
+    return (unsigned)v < (unsigned)na ? j + D * st : wrap;
+}
+
 __device__ __forceinline__ double zcoord(const LevelGeom& g, const I3& i) {
     return (comp(i, g.fax) - 0.5 * (g.n[g.fax] - 1)) * g.h;
 }
@@ -278,21 +291,19 @@ __device__ __forceinline__ double2 residual_item(const LevelGeom& g, const TimeO
     const double tov = t < NT ? to.U[t] : to.W[(iw >= 0 && iw < NT * NT) ? iw : 0];
     const double2 own = c[(size_t)j * NT + m];
     // neighbour loads issued unconditionally (clamped index, 0/1 weight)
+    int nbq[6];
+    nbq[0] = neighbour_of<0, -1>(g, i, j);
+    nbq[1] = neighbour_of<0, 1>(g, i, j);
+    nbq[2] = g.dim > 1 ? neighbour_of<1, -1>(g, i, j) : -1;
+    nbq[3] = g.dim > 1 ? neighbour_of<1, 1>(g, i, j) : -1;
+    nbq[4] = g.dim > 2 ? neighbour_of<2, -1>(g, i, j) : -1;
+    nbq[5] = g.dim > 2 ? neighbour_of<2, 1>(g, i, j) : -1;
     double2 nbv[6];
     double nbw[6];
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) {
-        int nb = j;
-        nbw[dir] = 0.0;
-        if (dir < 2 * g.dim) {
-            I3 gi;
-            const int q = neighbour(g, i, dir >> 1, (dir & 1) ? 1 : -1, &gi);
-            if (q >= 0) {
-                nb = q;
-                nbw[dir] = 1.0;
-            }
-        }
-        nbv[dir] = c[(size_t)nb * NT + m];
+        nbw[dir] = nbq[dir] >= 0 ? 1.0 : 0.0;
+        nbv[dir] = c[(size_t)(nbq[dir] >= 0 ? nbq[dir] : j) * NT + m];
     }
     const double vj = v0[j];
     const double2 lj = lam[j];
@@ -384,7 +395,9 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(LevelGeom f, Lev
                                                                 const double2* __restrict__ bg,
                                                                 const double2* __restrict__ bs,
                                                                 double2* __restrict__ bcc, double2* __restrict__ bsc,
-                                                                double2* __restrict__ zc, double2* __restrict__ zl) {
+                                                                double2* __restrict__ zc, double2* __restrict__ zl,
+                                                                int t1, int t2, double rt1, double rt2) {
+    // t1, t2: tile counts along axes 1 and 2 (rt1, rt2: their reciprocals)
     constexpr int PT = 32;
     constexpr int NQ = NT + 1;
     static_assert(PT * kMaxNT <= kThreads, "one item per thread");
@@ -398,11 +411,12 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(LevelGeom f, Lev
     // tile extents (unused axes 1) and tile counts
     const int e0 = dim == 1 ? (1 << sl) : 2, e1 = dim == 1 ? 1 : (dim == 2 ? (1 << sl) : 2);
     const int e2 = dim == 3 ? (1 << sl) : 1;
-    const int t1 = (f.n[1] + e1 - 1) / e1, t2 = (f.n[2] + e2 - 1) / e2;
-    const int bz = (int)blockIdx.x % t2, byx = (int)blockIdx.x / t2;
-    const int by = byx % t1, bx = byx / t1;
+    const int le1 = dim == 1 ? 0 : (dim == 2 ? sl : 1), le2 = dim == 3 ? sl : 0;  // log2 e1, log2 e2
+    const int bid = (int)blockIdx.x;
+    const int byx = qdiv(bid, rt2), bz = bid - byx * t2;
+    const int bx = qdiv(byx, rt1), by = byx - bx * t1;
     // this thread's fine point
-    const int lz = lp % e2, ly = (lp / e2) % e1, lx = lp / (e1 * e2);
+    const int lz = lp & (e2 - 1), ly = (lp >> le2) & (e1 - 1), lx = lp >> (le1 + le2);
     const I3 fi{bx * e0 + lx, by * e1 + ly, bz * e2 + lz};
     const bool inside = lp < PT && fi.x < f.n[0] && fi.y < f.n[1] && fi.z < f.n[2];
     const int j = inside ? point_index(f, fi) : 0;
@@ -419,7 +433,8 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(LevelGeom f, Lev
     const int ncp = c0 * c1 * c2;
     if (t < ncp * NQ) {
         const int cp = t / NQ, n = t - cp * NQ;
-        const int cz = cp % c2, cy = (cp / c2) % c1, cx = cp / (c1 * c2);
+        const int lc1 = dim == 2 ? le1 - 1 : 0, lc2 = dim == 3 ? le2 - 1 : 0;  // log2 c1, log2 c2
+        const int cz = cp & (c2 - 1), cy = (cp >> lc2) & (c1 - 1), cx = cp >> (lc1 + lc2);
         const I3 ci{(bx * e0 >> 1) + cx, (by * e1 >> 1) + cy, (bz * e2 >> 1) + cz};
         // with unused axes of extent 1 the formulas above give coordinate 0 there
         const I3 cc{dim >= 1 ? ci.x : 0, dim >= 2 ? ci.y : 0, dim >= 3 ? ci.z : 0};
@@ -530,57 +545,48 @@ __global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg,
                                                       const double2* __restrict__ cc,
                                                       const double2* __restrict__ lc,
                                                       double2* __restrict__ cf, double2* __restrict__ lf) {
-    // one thread per (fine point, component): components 0..NT-1 of c, then lambda
+    // one thread per (fine point, component): components 0..NT-1 of c, then
+    // lambda; a workgroup takes kThreads / NQ consecutive fine points
     constexpr int NQ = NT + 1;
-    const size_t t = (size_t)blockIdx.x * kThreads + threadIdx.x;
-    if (t >= (size_t)f.P * NQ) return;
-    const int j = (int)(t / NQ), n = (int)(t - (size_t)j * NQ);
+    constexpr int PW = kThreads / NQ;
+    const int lp = (int)threadIdx.x / NQ, n = (int)threadIdx.x - lp * NQ;
+    const int j = (int)blockIdx.x * PW + lp;
+    if (lp >= PW || j >= f.P) return;
     const bool isc = n < NT;
     const double2* src = isc ? cc + n : lc;
     double2* dst = isc ? cf + (size_t)j * NT + n : lf + j;
     const int stride = isc ? NT : 1;
     const I3 i = point_coords(f, j);
-    // per axis: parent, nearer coarse neighbour, and whether that neighbour exists
-    int par[3], nb[3], ok[3];
+    // per axis: the parent's coordinate (its index Jp), the index offset to the
+    // nearer coarse neighbour (wrapped on a periodic grid; 0 with weight 0
+    // outside a Dirichlet grid) and the two weights
+    int Jp = 0, dJ[3];
+    double w0[3], w1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int ia = comp(i, a);
         const int nc = cg.n[a];
-        par[a] = ia >> 1;
-        nb[a] = (ia & 1) ? par[a] + 1 : par[a] - 1;
-        ok[a] = 1;
-        if (nb[a] < 0 || nb[a] >= nc) {
-            if (f.periodic)
-                nb[a] += nb[a] < 0 ? nc : -nc;
-            else
-                ok[a] = 0;
-        }
-        if (a >= f.dim) {  // unused axis: extent 1, no neighbour
-            par[a] = 0;
-            nb[a] = 0;
-            ok[a] = 0;
-        }
+        const int cst = a == 2 ? 1 : (a == 1 ? cg.n[2] : cg.n[1] * cg.n[2]);
+        const int ia = comp(i, a);
+        const int par = ia >> 1;
+        const int nb = (ia & 1) ? par + 1 : par - 1;
+        const bool inside = (unsigned)nb < (unsigned)nc;
+        const int nbw = inside ? nb : (f.periodic ? (nb < 0 ? nb + nc : nb - nc) : par);
+        const bool lin = !interp && a < f.dim;
+        Jp += par * cst;
+        dJ[a] = (nbw - par) * cst;
+        w0[a] = lin ? 0.75 : 1.0;
+        w1[a] = (lin && (inside || f.periodic)) ? 0.25 : 0.0;
     }
-    double2 acc = make_double2(0.0, 0.0);
     const int ncomb = interp ? 1 : (1 << f.dim);
-    // all parent loads issued unconditionally (clamped to the parent, weight 0 when unused)
+    // all loads issued unconditionally (unused combinations: the parent, weight 0),
+    // so that they are in flight together
+    double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
     for (int cmb = 0; cmb < 8; ++cmb) {
-        double w = cmb < ncomb ? 1.0 : 0.0;
-        int J3[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int bit = (cmb >> a) & 1;
-            J3[a] = par[a];
-            if (bit) {
-                if (ok[a]) J3[a] = nb[a];
-                else w = 0.0;
-                w *= 0.25;
-            } else {
-                w *= (interp || a >= f.dim) ? 1.0 : 0.75;
-            }
-        }
-        const int J = point_index(cg, I3{J3[0], J3[1], J3[2]});
+        const bool use = cmb < ncomb;
+        const int J = Jp + (use ? ((cmb & 1) ? dJ[0] : 0) + ((cmb & 2) ? dJ[1] : 0) + ((cmb & 4) ? dJ[2] : 0) : 0);
+        const double w = use ? ((cmb & 1) ? w1[0] : w0[0]) * ((cmb & 2) ? w1[1] : w0[1]) * ((cmb & 4) ? w1[2] : w0[2])
+                             : 0.0;
         acc = add2(acc, scl2(w, src[(size_t)J * stride]));
     }
     *dst = add2(*dst, acc);
@@ -1561,10 +1567,11 @@ hipError_t launch_residual_restrict(int nt, const LevelGeom& fine, const LevelGe
     const int sl = 6 - fine.dim;
     const int e0 = fine.dim == 1 ? (1 << sl) : 2, e1 = fine.dim == 1 ? 1 : (fine.dim == 2 ? (1 << sl) : 2);
     const int e2 = fine.dim == 3 ? (1 << sl) : 1;
-    const int nb = ((fine.n[0] + e0 - 1) / e0) * ((fine.n[1] + e1 - 1) / e1) * ((fine.n[2] + e2 - 1) / e2);
+    const int t1 = (fine.n[1] + e1 - 1) / e1, t2 = (fine.n[2] + e2 - 1) / e2;
+    const int nb = ((fine.n[0] + e0 - 1) / e0) * t1 * t2;
     LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_residual_restrict<NT>, dim3(nb), dim3(kThreads), 0, st, fine, coarse,
                                            make_ops<NT>(U, W), adjoint, field_on, c, lam, v0, bc, bg, bs, bcc, bsc,
-                                           zero_c, zero_l));
+                                           zero_c, zero_l, t1, t2, 1.0 / t1, 1.0 / t2));
     return hipGetLastError();
 }
 
@@ -1579,8 +1586,8 @@ hipError_t launch_restrict(int nt, const LevelGeom& fine, const LevelGeom& coars
 
 hipError_t launch_prolong(int nt, const LevelGeom& fine, const LevelGeom& coarse, int interp, const double2* cc,
                           const double2* lc, double2* cf, double2* lf, hipStream_t st) {
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_prolong<NT>, dim3(nblk_for((size_t)fine.P * (nt + 1))),
-                                           dim3(kThreads), 0, st, fine,
+    const int pw = kThreads / (nt + 1);
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_prolong<NT>, dim3((fine.P + pw - 1) / pw), dim3(kThreads), 0, st, fine,
                                            coarse, interp, cc, lc, cf, lf));
     return hipGetLastError();
 }
