@@ -212,7 +212,8 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
  * both see no field, the next step's initial state and its N0 are queued
  * ahead of the wait for the current step's last norms, into spare
  * finest-level buffers (P (n_t + 2) complex values, allocated by the context
- * on first use and kept until lam_destroy).  stats (may be NULL): cycles and
+ * on first use and kept until lam_destroy; if they cannot be allocated, the
+ * steps run without them).  stats (may be NULL): cycles and
  * sweeps_fine summed over the steps, resid0/resid of the step with the
  * largest resid/resid0, t_factor_ms and t_solve_ms summed.  Stops at the first
  * step that does not return LAM_OK and returns its code (psi_out then holds

@@ -719,6 +719,24 @@ int dalloc(T** p, size_t count) {
     return LAM_OK;
 }
 
+// The spare finest-level state of lam_propagate, allocated on first use: all
+// three buffers or none (on failure the steps run without them).
+bool alloc_next(lam_ctx* c) {
+    if (c->d_c_next && c->d_lam_next && c->d_bs_next) return true;
+    const size_t P = (size_t)c->lv[0].g.P;
+    bool ok = dalloc(&c->d_c_next, P * c->nt) == LAM_OK;
+    ok = ok && dalloc(&c->d_lam_next, P) == LAM_OK;
+    ok = ok && dalloc(&c->d_bs_next, P) == LAM_OK;
+    if (!ok) {
+        (void)hipFree(c->d_c_next);
+        (void)hipFree(c->d_lam_next);
+        c->d_c_next = nullptr;
+        c->d_lam_next = nullptr;
+        c->d_bs_next = nullptr;
+    }
+    return ok;
+}
+
 void free_ctx(lam_ctx* c) {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
@@ -1082,12 +1100,8 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
         // When neither this step nor the next sees a field, nothing changes
         // between them but the state, and the next step's start is queued
         // ahead of each wait for this step's norms.
-        const bool ahead = k + 1 < n_steps && !ctx->field_on && field_free(ctx, tk + ctx->time.dt);
-        if (ahead && !ctx->d_c_next) {
-            LAMCHK(dalloc(&ctx->d_c_next, (size_t)L.g.P * ctx->nt));
-            LAMCHK(dalloc(&ctx->d_lam_next, (size_t)L.g.P));
-            LAMCHK(dalloc(&ctx->d_bs_next, (size_t)L.g.P));
-        }
+        const bool ahead =
+            k + 1 < n_steps && !ctx->field_on && field_free(ctx, tk + ctx->time.dt) && alloc_next(ctx);
         const int next_slot = ctx->solver.max_cycles + 1 + (k & 1);
         bool ready = false;
         lam_stats st{};

@@ -210,35 +210,49 @@ def test_native_propagate_matches_stepwise_and_edge_cases():
     prop.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("pulse", [None, dict(kind="sin2", e0=0.05, omega=0.057, t_total=0.1)],
                          ids=["no-field", "field-ends-mid-run"])
-def test_native_propagate_queued_next_step(pulse):
+def test_native_propagate_queued_next_step(pulse, precision):
     """Steps without a field have the next step's start queued ahead of each
     wait (spare buffers swapped in when the step has converged).  Against the
     oracle's direct steps and the step-by-step path: a run with no field, and
     one whose pulse ends with the second step (the first two steps keep the
     plain path); the in-place form; the context state after the run is the last
-    step's; a tiny max_cycles stops the run at its first step with that step's
-    result."""
+    step's, and an adjoint step on the same context (its state buffers swapped
+    by the runs) matches the oracle's direct adjoint; a tiny max_cycles stops
+    the run at its first step with that step's result."""
     import torch
     from paper_1111_4363_amd import lam
     case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=pulse)
-    note(f"native propagate, next step queued ahead {case}")
+    note(f"native propagate, next step queued ahead {precision} {case}")
     K = 7
     psis = kkt.propagate(case.grid, case.v0, case.psi0, case.n_t, case.dt, K, case.field)
     ref = np.abs(psis[-1]).max()
-    prop = case.prop(tol=1e-12, max_cycles=60)
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    prop = case.prop(tol=1e-12, max_cycles=60, precision=precision)
     psi_native, st = prop.propagate(t_c(case.psi0), K)
-    assert np.abs(n(psi_native) - psis[-1]).max() <= 1e-10 * ref
+    assert np.abs(n(psi_native) - psis[-1]).max() <= tol * ref
     assert st[0]["resid"] <= 1e-12 * st[0]["resid0"] * 1.0001
     cg, _ = prop.get_state()
     assert np.abs(n(cg).reshape(-1, case.n_t).sum(axis=1) - n(psi_native)).max() <= 1e-14 * ref
     seq, _ = prop.propagate(t_c(case.psi0), K, keep=True)
-    assert np.abs(n(psi_native) - n(seq[-1])).max() <= 1e-10 * ref
+    assert np.abs(n(psi_native) - n(seq[-1])).max() <= tol * ref
     buf = t_c(case.psi0).clone()
     assert prop._lib.lam_propagate(prop._ctx, 0.0, K, lam._ptr(buf, torch.complex128, case.npts),
                                    lam._ptr(buf, torch.complex128, case.npts), None) == lam.LAM_OK
-    assert np.abs(n(buf) - psis[-1]).max() <= 1e-10 * ref
+    assert np.abs(n(buf) - psis[-1]).max() <= tol * ref
+    # adjoint step of the last step, on the context the runs above left behind
+    t_last = (K - 1) * case.dt
+    sysm = kkt.StepSystem(case.grid, case.v0, case.n_t, case.dt, t_last, case.field)
+    x = kkt.solve_direct(sysm.K, kkt.rhs(sysm, psis[-2]))
+    g_out = case.rng.normal(size=case.npts) + 1j * case.rng.normal(size=case.npts)
+    mu = A.adjoint_solve(sysm, A.adjoint_rhs(sysm, g_out))
+    g_in_ref, dv0_ref, _ = A.step_gradients(sysm, x, mu)
+    dv0 = torch.zeros(case.npts, dtype=torch.float64, device="cuda")
+    g_in, _ = prop.adjoint_step(t_last, t_c(psis[-2]), t_c(g_out), dv0)
+    assert np.abs(n(g_in) - g_in_ref).max() <= tol * np.abs(g_in_ref).max()
+    assert np.abs(n(dv0) - dv0_ref).max() <= tol * np.abs(dv0_ref).max()
     prop.close()
     # two cycles cannot reach 1e-12: LAM_ENOCONV after the first step, psi_out = its end state
     short = case.prop(tol=1e-12, max_cycles=2)
