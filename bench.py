@@ -221,7 +221,7 @@ def main():
                           "launches": 5}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the sharding design is described, not built).", file=sys.stderr)
         sys.exit(2)
 
