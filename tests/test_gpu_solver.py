@@ -26,6 +26,11 @@ PULSE_FOURIER = dict(kind="fourier", t_total=0.4, coef=[0.03, -0.02, 0.05])
     dict(shape=(32, 16), n_t=6, block=(4, 4), levels=2, h=0.2, pulse=PULSE_SIN2, interp="constant"),
     dict(shape=(64,), n_t=8, block=(8,), levels=3, h=0.3, potential="harmonic"),
     dict(shape=(8, 8, 16), n_t=3, block=(2, 2, 2), levels=2, h=0.3),
+    # ragged tiles of the fused residual-restriction (32 fine points: 2 x 16 in 2D,
+    # 2 x 2 x 8 in 3D, 32 in 1D), with a field and the constant interpolation
+    dict(shape=(16, 24), n_t=4, block=(4, 4), levels=2, h=0.2, pulse=PULSE_FOURIER),
+    dict(shape=(8, 8, 12), n_t=3, block=(2, 2, 2), levels=2, h=0.3, interp="constant"),
+    dict(shape=(40,), n_t=5, block=(4,), levels=2, h=0.3, potential="random"),
 ], ids=lambda c: f"{c['shape']}-L{c['levels']}")
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_vcycle_parity(cfg, adjoint):
