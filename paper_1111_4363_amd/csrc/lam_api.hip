@@ -554,20 +554,14 @@ int vcycle(lam_ctx* c, int l) {
 }
 
 // V-cycles on the context state until sqrt(N/N0) <= tol.
-// Queue N of the finest level for the context state into h_norms[slot] (no
-// wait); with `cx` given, for the forward state (cx, lx, bx) instead.
-int queue_norm(lam_ctx* c, int slot, const double2* cx = nullptr, const double2* lx = nullptr,
-               const double2* bx = nullptr) {
+// Queue N of the finest level for the context state into h_norms[slot] (no wait).
+int queue_norm(lam_ctx* c, int slot) {
     Level& L = c->lv[0];
     const double2* bg = c->adjoint ? c->d_g : nullptr;
     const double2* bs = c->adjoint ? nullptr : L.d_bs;
-    if (cx) {
-        bg = nullptr;
-        bs = bx;
-    }
     int np = 0;
-    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, cx ? 0 : c->adjoint, c->field_on, cx ? cx : L.d_c,
-                           cx ? lx : L.d_lam, L.d_v0, nullptr, bg, bs, nullptr, nullptr, c->d_partial, &np, c->st));
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, nullptr, bg,
+                           bs, nullptr, nullptr, c->d_partial, &np, c->st));
     HIPCHK(launch_reduce(c->d_partial, np, 1, c->h_norms_dev + slot, c->st));
     return LAM_OK;
 }
@@ -618,8 +612,10 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
         HIPCHK(hipEventRecord(c->ev_norm, c->st));
         if (next_out) {
             Level& L = c->lv[0];
-            HIPCHK(launch_advance(c->nt, L.g.P, L.d_c, next_out, c->d_c_next, c->d_lam_next, c->d_bs_next, c->st));
-            LAMCHK(queue_norm(c, next_slot, c->d_c_next, c->d_lam_next, c->d_bs_next));
+            int np = 0;
+            HIPCHK(launch_advance(c->nt, L.g, c->U[0], L.d_c, L.d_v0, next_out, c->d_c_next, c->d_lam_next,
+                                  c->d_bs_next, c->d_partial, &np, c->st));
+            HIPCHK(launch_reduce(c->d_partial, np, 1, c->h_norms_dev + next_slot, c->st));
         }
         LAMCHK(wait_event(c));
         N0 = c->h_norms[n0_slot];

@@ -114,9 +114,11 @@ hipError_t launch_init_zero(int nt, int P, double2* c, double2* lam, hipStream_t
 
 hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStream_t st);
 
-// psi = end state of c; (cn, lamn, bsn) = the next step's initial state from psi.
-hipError_t launch_advance(int nt, int P, const double2* c, double2* psi, double2* cn, double2* lamn, double2* bsn,
-                          hipStream_t st);
+// psi = end state of c; (cn, lamn, bsn) = the next step's initial state from
+// psi; partial = per-workgroup partials of that state's N0 for a step without
+// field (u0 = U_00; *nparts of them, residual_blocks(nt, P)).
+hipError_t launch_advance(int nt, const LevelGeom& g, double u0, const double2* c, const double* v0, double2* psi,
+                          double2* cn, double2* lamn, double2* bsn, double* partial, int* nparts, hipStream_t st);
 
 hipError_t launch_copy_c2(const double2* src, double2* dst, size_t n, hipStream_t st);
 

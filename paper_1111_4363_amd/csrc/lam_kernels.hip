@@ -1442,24 +1442,71 @@ __global__ __launch_bounds__(kThreads) void k_end_eval(int P, const double2* __r
     psi[j] = acc;
 }
 
-// End of one step and start of the next in one pass: psi = x(t0 + dt) as in
-// k_end_eval, and the next step's initial state from it as in k_init_forward,
-// written to a second set of buffers (c is left as it is).
+// End of one step and start of the next in one pass, with the norm N0 of the
+// next step's initial state (a step without field): psi = x(t0 + dt) as in
+// k_end_eval, the next initial state from it as in k_init_forward, written to
+// a second set of buffers (c is left as it is), and per-workgroup partials of
+// N0.  For that state only the rows (j, 0) have a residual, U_0 (H psi)_j: the
+// constraint residual vanishes exactly (c_j0 = psi_j) and the time couplings
+// see zero coefficients.  H psi = sum_n H c_n by linearity, so one thread per
+// (point, component) applies the stencil to its component (coalesced, as in
+// k_residual) and the workgroup sums over the components in LDS.
 template <int NT>
-__global__ __launch_bounds__(kThreads) void k_advance(int P, const double2* __restrict__ c,
-                                                      double2* __restrict__ psi, double2* __restrict__ cn,
-                                                      double2* __restrict__ lamn, double2* __restrict__ bsn) {
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    if (j >= P) return;
-    double2 acc = make_double2(0.0, 0.0);
+__global__ __launch_bounds__(kThreads) void k_advance(LevelGeom g, double u0, const double2* __restrict__ c,
+                                                      const double* __restrict__ v0, double2* __restrict__ psi,
+                                                      double2* __restrict__ cn, double2* __restrict__ lamn,
+                                                      double2* __restrict__ bsn, double* __restrict__ partial) {
+    constexpr int PW = kThreads / NT;  // points per workgroup
+    __shared__ double2 cs[PW * NT];
+    __shared__ double2 hs[PW * NT];
+    __shared__ double red[kThreads / 64];
+    const int t = threadIdx.x;
+    const int lp = t / NT, m = t - lp * NT;
+    const size_t jw = (size_t)blockIdx.x * PW + lp;
+    const bool act = lp < PW && jw < (size_t)g.P;
+    const int j = act ? (int)jw : 0;
+    const I3 i = point_coords(g, j);
+    const double2 own = c[(size_t)j * NT + m];
+    int nbq[6];
+    nbq[0] = neighbour_of<0, -1>(g, i, j);
+    nbq[1] = neighbour_of<0, 1>(g, i, j);
+    nbq[2] = g.dim > 1 ? neighbour_of<1, -1>(g, i, j) : -1;
+    nbq[3] = g.dim > 1 ? neighbour_of<1, 1>(g, i, j) : -1;
+    nbq[4] = g.dim > 2 ? neighbour_of<2, -1>(g, i, j) : -1;
+    nbq[5] = g.dim > 2 ? neighbour_of<2, 1>(g, i, j) : -1;
+    double2 nbv[6];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) acc = add2(acc, c[(size_t)j * NT + n]);
-    psi[j] = acc;
-    cn[(size_t)j * NT] = acc;
+    for (int dir = 0; dir < 6; ++dir) nbv[dir] = c[(size_t)(nbq[dir] >= 0 ? nbq[dir] : j) * NT + m];
+    const double vj = v0[j];
+    double2 lap = scl2(-2.0 * g.dim, own);
 #pragma unroll
-    for (int n = 1; n < NT; ++n) cn[(size_t)j * NT + n] = make_double2(0.0, 0.0);
-    lamn[j] = make_double2(0.0, 0.0);
-    bsn[j] = acc;
+    for (int dir = 0; dir < 6; ++dir) lap = add2(lap, scl2(nbq[dir] >= 0 ? 1.0 : 0.0, nbv[dir]));
+    const double2 hc = add2(scl2(-g.kin, lap), scl2(vj, own));
+    if (lp < PW) {
+        cs[t] = own;
+        hs[t] = hc;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    if (act) {
+        // psi in the order of k_end_eval
+        double2 ps = make_double2(0.0, 0.0), hp = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            ps = add2(ps, cs[lp * NT + n]);
+            hp = add2(hp, hs[lp * NT + n]);
+        }
+        cn[(size_t)j * NT + m] = m == 0 ? ps : make_double2(0.0, 0.0);
+        if (m == 0) {
+            psi[j] = ps;
+            lamn[j] = make_double2(0.0, 0.0);
+            bsn[j] = ps;
+            const double2 r = scl2(u0, hp);
+            acc = u0 * (r.x * r.x + r.y * r.y);
+        }
+    }
+    const double tot = block_sum(acc, red);
+    if (t == 0) partial[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(kThreads) void k_copy_c2(const double2* __restrict__ src, double2* __restrict__ dst,
@@ -1646,10 +1693,12 @@ hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_advance(int nt, int P, const double2* c, double2* psi, double2* cn, double2* lamn, double2* bsn,
-                          hipStream_t st) {
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_advance<NT>, dim3(nblk_for(P)), dim3(kThreads), 0, st, P, c, psi, cn,
-                                           lamn, bsn));
+hipError_t launch_advance(int nt, const LevelGeom& g, double u0, const double2* c, const double* v0, double2* psi,
+                          double2* cn, double2* lamn, double2* bsn, double* partial, int* nparts, hipStream_t st) {
+    const int nb = residual_blocks(nt, g.P);
+    if (nparts) *nparts = nb;
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_advance<NT>, dim3(nb), dim3(kThreads), 0, st, g, u0, c, v0, psi, cn,
+                                           lamn, bsn, partial));
     return hipGetLastError();
 }
 
