@@ -134,6 +134,8 @@ typedef struct {
     double resid;         /* sqrt(N) at the end */
     double t_factor_ms;   /* time spent refactoring subvolume time blocks this call */
     double t_solve_ms;    /* wall time of the call */
+    double resid0_last;   /* sqrt(N) of the initial guess of the last step solved */
+    double resid_last;    /* sqrt(N) at the end of the last step solved */
 } lam_stats;
 
 /* Create a propagator context: builds the level hierarchy (coarse grids with
@@ -215,7 +217,8 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
  * on first use and kept until lam_destroy; if they cannot be allocated, the
  * steps run without them).  stats (may be NULL): cycles and
  * sweeps_fine summed over the steps, resid0/resid of the step with the
- * largest resid/resid0, t_factor_ms and t_solve_ms summed.  Stops at the first
+ * largest resid/resid0, resid0_last/resid_last of the last step solved,
+ * t_factor_ms and t_solve_ms summed.  Stops at the first
  * step that does not return LAM_OK and returns its code (psi_out then holds
  * that step's result for LAM_ENOCONV); n_steps = 0 copies nothing and
  * returns LAM_OK. */

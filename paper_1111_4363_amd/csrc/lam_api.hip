@@ -656,6 +656,8 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
         stats->cycles = queued;
         stats->resid0 = std::sqrt(N0);
         stats->resid = std::sqrt(N);
+        stats->resid0_last = stats->resid0;
+        stats->resid_last = stats->resid;
     }
     return rc;
 }
@@ -1115,6 +1117,8 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
         }
         src = psi_out;
         tot.cycles += st.cycles;
+        tot.resid0_last = st.resid0;
+        tot.resid_last = st.resid;
         const double ratio = st.resid0 > 0.0 ? st.resid / st.resid0 : 0.0;
         if (ratio > worst) {
             worst = ratio;

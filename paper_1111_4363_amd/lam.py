@@ -65,7 +65,8 @@ class LamSolver(ctypes.Structure):
 
 class LamStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("sweeps_fine", ctypes.c_int), ("resid0", ctypes.c_double),
-                ("resid", ctypes.c_double), ("t_factor_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+                ("resid", ctypes.c_double), ("t_factor_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("resid0_last", ctypes.c_double), ("resid_last", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -53,6 +53,7 @@ int main(void) {
          sizeof(lam_grid), sizeof(lam_time), sizeof(lam_ham), sizeof(lam_solver), sizeof(lam_stats));
   P(lam_grid, h) P(lam_grid, block) P(lam_grid, interp) P(lam_ham, v0) P(lam_ham, coef)
   P(lam_ham, t_total) P(lam_solver, n_inner) P(lam_solver, time_factor) P(lam_stats, t_solve_ms)
+  P(lam_stats, resid_last)
   return 0;
 }
 ''')
@@ -74,6 +75,7 @@ int main(void) {
     assert int(out["lam_solver.n_inner"]) == lam.LamSolver.n_inner.offset
     assert int(out["lam_solver.time_factor"]) == lam.LamSolver.time_factor.offset
     assert int(out["lam_stats.t_solve_ms"]) == lam.LamStats.t_solve_ms.offset
+    assert int(out["lam_stats.resid_last"]) == lam.LamStats.resid_last.offset
 
 
 def test_binding_rejects_host_tensors_before_any_call():
