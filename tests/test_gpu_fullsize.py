@@ -93,11 +93,18 @@ def test_fullsize_residual_sampled(name):
     prop.close()
 
 
-@pytest.mark.parametrize("name", NAMES)
-def test_fullsize_sweep_sampled_blocks(name):
+SWEEP_RUNS = [(name, "fp64") for name in NAMES] + [("2d_softcoulomb", "mixed"), ("3d_laser", "mixed"),
+                                                      ("3d_large", "mixed")]
+
+
+@pytest.mark.parametrize("name,precision", SWEEP_RUNS)
+def test_fullsize_sweep_sampled_blocks(name, precision):
+    """Sampled subvolumes of one colour sweep against the exact local solves
+    (FP64: 1e-11 of the correction; mixed, FP32 local solves: 1e-4, as in the
+    small-size sweep parity); the other colour's points are left untouched."""
     import torch
-    cfg, v0, psi0, pulse, prop, grid, dev = setup(name)
-    note(f"full-size sweep {name} {cfg['shape']}")
+    cfg, v0, psi0, pulse, prop, grid, dev = setup(name, precision)
+    note(f"full-size sweep {name} {precision} {cfg['shape']}")
     nt, P = cfg["n_t"], grid.npts
     c, lam_ = W.random_state_device(P, nt, 12, dev, scale=0.1)
     psi_t = torch.as_tensor(psi0, device=dev)
@@ -133,7 +140,8 @@ def test_fullsize_sweep_sampled_blocks(name):
         Kbb = kkt.block_system(grid, v0, nt, cfg["dt"], t0, field, pts)
         delta = np.linalg.solve(Kbb, np.concatenate([r.ravel(), s]))
         err = np.abs((x_new - x_old) - delta).max()
-        assert err <= 1e-11 * np.abs(delta).max() + 64 * EPS * np.abs(x_old).max(), (name, err)
+        rel = 1e-11 if precision == "fp64" else 1e-4
+        assert err <= rel * np.abs(delta).max() + 64 * EPS * np.abs(x_old).max(), (name, err)
     prop.close()
 
 
