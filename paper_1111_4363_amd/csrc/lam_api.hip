@@ -1099,7 +1099,7 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
         // between them but the state, and the next step's start is queued
         // ahead of each wait for this step's norms.
         const bool ahead =
-            k + 1 < n_steps && !ctx->field_on && field_free(ctx, tk + ctx->time.dt) && alloc_next(ctx);
+            k + 1 < n_steps && !ctx->field_on && field_free(ctx, t0 + (k + 1) * ctx->time.dt) && alloc_next(ctx);
         const int next_slot = ctx->solver.max_cycles + 1 + (k & 1);
         bool ready = false;
         lam_stats st{};
