@@ -43,6 +43,29 @@ def test_initial_guess_meets_initial_condition_rows():
     assert np.abs(sigma).max() == 0.0
 
 
+@pytest.mark.parametrize("shape,periodic", [((8,), False), ((6, 5), False), ((4, 4), True), ((3, 4, 2), False)])
+def test_initial_guess_norm_closed_form(shape, periodic):
+    """Without a field, the initial guess c_j0 = psi_j (other coefficients and
+    lambda zero) leaves a residual only on the rows (j, 0), U_00 (H psi)_j: the
+    constraint rows vanish and the time couplings see zero coefficients, so
+    N0 = U_00^3 |H psi|^2 with H = T + V0 (the closed form the GPU library
+    uses for the next step's N0)."""
+    g = G.Grid(shape, 0.3, periodic=periodic)
+    rng = np.random.default_rng(11)
+    v0 = rng.normal(size=g.npts)
+    psi0 = rng.normal(size=g.npts) + 1j * rng.normal(size=g.npts)
+    n_t, dt = 5, 0.07
+    sysm = kkt.StepSystem(g, v0, n_t, dt)
+    r = kkt.residual(sysm.K, kkt.rhs(sysm, psi0), kkt.initial_guess(sysm, psi0))
+    rho, sigma = kkt.split(r, g.npts, n_t)
+    hpsi = G.hamiltonian(g, v0) @ psi0
+    assert np.abs(sigma).max() == 0.0
+    assert np.abs(rho[:, 1:]).max() <= 1e-12 * np.abs(hpsi).max()
+    np.testing.assert_allclose(rho[:, 0], dt * hpsi, rtol=0, atol=1e-12 * np.abs(hpsi).max())
+    n0 = kkt.residual_norm(sysm, r)
+    assert abs(n0 - dt ** 3 * np.sum(np.abs(hpsi) ** 2)) <= 1e-12 * n0
+
+
 def test_residual_norm_weights():
     g = G.Grid((2,), 1.0)
     sysm = kkt.StepSystem(g, np.zeros(2), 2, 0.3)
