@@ -277,6 +277,28 @@ def test_native_propagate_queued_next_step(pulse, precision):
     one.close()
 
 
+@pytest.mark.parametrize("cfg", [
+    dict(shape=(64,), n_t=8, block=(8,), levels=2, h=0.3, potential="harmonic"),
+    dict(shape=(16, 16), n_t=4, block=(4, 4), levels=2, h=0.3, periodic=True),
+    dict(shape=(8, 8, 8), n_t=6, block=(4, 4, 4), levels=2, h=0.3),
+], ids=lambda c: f"{c['shape']}-p{c.get('periodic', False)}")
+def test_queued_step_across_grids(cfg):
+    """The queued-ahead start of field-free steps on 1D, periodic 2D and 3D
+    grids: the run matches the step-by-step path, and the last step's N0 (from
+    the same pass as its initial state) the plain residual of that guess."""
+    case = Case(**cfg)
+    note(f"queued step {case}")
+    K = 4
+    prop = case.prop(tol=1e-12, max_cycles=60)
+    psi_native, st = prop.propagate(t_c(case.psi0), K)
+    seq, _ = prop.propagate(t_c(case.psi0), K, keep=True)
+    ref = np.abs(n(seq[-1])).max()
+    assert np.abs(n(psi_native) - n(seq[-1])).max() <= 1e-10 * ref
+    _, st1 = prop.solve_step((K - 1) * case.dt, seq[-2])
+    assert abs(st[0]["resid0_last"] - st1["resid0"]) <= 1e-9 * st1["resid0"]
+    prop.close()
+
+
 def test_sweep_profiling_samples_every_kth_launch():
     """lam_profile(k) records the 1st, (k+1)-th, ... finest-level sweep launch."""
     case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2)
