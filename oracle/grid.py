@@ -21,7 +21,8 @@ Readings (the paper's own test uses Legendre finite elements):
   relaxation to the least action solution": relaxations over non-overlapping
   volumes of a local Lagrangian are independent).
 
-Parity: pinned (tests/test_oracle_grid.py).
+Parity: pinned (tests/test_oracle_grid.py; the Dirichlet and periodic boundary
+rows of the interpolation in tests/test_oracle_pointwise.py).
 """
 from dataclasses import dataclass
 
@@ -153,10 +154,6 @@ def interpolation(grid, kind="linear"):
     for m in mats[1:]:
         out = sp.kron(out, m, format="csr")
     return sp.csr_matrix(out)
-
-
-def coarsen_potential(grid, v0):
-    return restriction(grid) @ np.asarray(v0, dtype=float).ravel()
 
 
 # ---------------------------------------------------------------------------

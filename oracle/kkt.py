@@ -26,7 +26,10 @@ The residual is the full system residual b - K x (the multiplier term is part
 of it; at a solution of the constrained problem the paper's r_jm alone is not
 zero).  N weights the stationarity rows with U and the constraint rows with 1.
 
-Parity: pinned (tests/test_oracle_kkt.py, tests/test_oracle_physics.py).
+Parity: pinned.  The assembly by brute force from the action and by closed
+forms of the step (tests/test_oracle_kkt.py, tests/test_oracle_physics.py);
+the pointwise checkers residual_at_points and block_system against the rows
+and sub-matrices of the assembled system (tests/test_oracle_pointwise.py).
 """
 from dataclasses import dataclass, field as dc_field
 
