@@ -62,6 +62,7 @@ extern "C" {
 
 #define LAM_MAX_NT     8    /* largest number of Legendre time functions */
 #define LAM_MAX_BLOCK  64   /* largest number of grid points in one subvolume */
+#define LAM_MAX_INNER  32   /* largest n_inner (inner passes of one subvolume solve) */
 
 #define LAM_PULSE_NONE          0
 #define LAM_PULSE_SIN2          1  /* E = e0 sin^2(pi t/T) cos(omega t) on [0,T] */
@@ -113,18 +114,21 @@ typedef struct {
     int precision;    /* LAM_FP64 or LAM_MIXED */
     double tol;       /* stop when sqrt(N / N0) <= tol (N: residual norm, N0: at the start) */
     int max_cycles;   /* V-cycle limit per solve */
-    int n_inner;      /* most inner corrections of each subvolume solve when E(t) != 0
-                         (the factor freezes the field at its step mean and block centre;
-                         each block stops once its own residual fell by 1e-13 in FP64,
-                         1e-5 in FP32, or stops improving); -1 = automatic (16 with a
-                         field, 0 without) */
+    int n_inner;      /* most inner corrections of each subvolume solve when E(t) != 0,
+                         0..LAM_MAX_INNER or -1 = automatic (16 with a field, 0 without).
+                         The factor of a subvolume takes the field's full time matrix W
+                         at one dipole coordinate zf, the centre of its slab of
+                         subvolumes along the field axis; the corrections remove the
+                         rest, (z - zf) W, point by point.  Each subvolume stops once its
+                         own residual fell by 1e-13 in FP64, 1e-5 in FP32, or stops
+                         improving (lam_pass_stats counts both) */
     int time_factor;  /* how each mode's time system is solved inside a sweep:
                          LAM_TF_SHARED (0): one factor shared by all modes (the n_t x n_t
                          system left after each point's continuity row eliminates c_0,
                          in the eigenbasis of its time operator; streams one eigenvalue
                          per mode);
                          LAM_TF_STORED (1): stored per-mode inverses ((n_t+1)^2 complex per
-                         mode, refactored when the step's mean field changes) */
+                         mode, refactored for every step with a field) */
 } lam_solver;
 
 typedef struct {
@@ -132,7 +136,7 @@ typedef struct {
     int sweeps_fine;      /* full sweeps (both colours) on the finest level */
     double resid0;        /* sqrt(N) of the initial guess */
     double resid;         /* sqrt(N) at the end */
-    double t_factor_ms;   /* time spent refactoring subvolume time blocks this call */
+    double t_factor_ms;   /* host time spent on time factors (field steps) this call */
     double t_solve_ms;    /* wall time of the call */
     double resid0_last;   /* sqrt(N) of the initial guess of the last step solved */
     double resid_last;    /* sqrt(N) at the end of the last step solved */
@@ -152,7 +156,11 @@ int lam_create(const lam_grid* grid, const lam_time* time, const lam_ham* ham,
 int lam_destroy(lam_ctx* ctx);
 
 /* Replace the Fourier pulse amplitudes (host array of n_coef values, n_coef
- * must equal the count given at create). */
+ * must equal the count given at create): the coefficients of the dipole
+ * field E(t) in the time-dependent local potential V(x, t) of the action
+ * (Sec. "Review of the Least Action Principle", the V_ijnm term of
+ * Eq. (stationaryphase)).  Field matrices and factors are rebuilt on next use;
+ * a loaded state keeps its step. */
 int lam_set_pulse(lam_ctx* ctx, int n_coef, const double* coef);
 
 /* Replace V0 (device, one FP64 per finest point) and refactor every level. */
@@ -186,11 +194,15 @@ int lam_set_adjoint_state(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c
 /* Copy the finest-level state (c: P*n_t, lam: P; device) out of the context. */
 int lam_get_state(lam_ctx* ctx, lam_c64* c, lam_c64* lam);
 
-/* One colour of subvolume relaxation on level `level` (0 = finest) of the
- * context state: every subvolume of that colour (parity of the sum of its box
- * coordinates) is replaced by x_U + K_UU^{-1} (b - K x)_U with the exterior
- * held fixed (Sec. "Iterative relaxation to the least action solution").
- * Subvolumes of one colour do not share a face, so they run in parallel. */
+/* One colour of subvolume relaxation of the context state on the finest
+ * level (level must be 0; a coarse level relaxes a correction problem whose
+ * right-hand side only a V-cycle produces, so other levels are LAM_EINVAL):
+ * every subvolume of that colour (parity of the sum of its box coordinates)
+ * is replaced by x_U + K_UU^{-1} (b - K x)_U with the exterior held fixed
+ * (Sec. "Iterative relaxation to the least action solution").  Subvolumes of
+ * one colour do not share a face, so they run in parallel.  Acts on the step
+ * of the loaded state (lam_set_state / lam_set_adjoint_state), whatever step a
+ * residual call looked at since. */
 int lam_relax_sweep(lam_ctx* ctx, int level, int colour);
 
 /* One V-cycle on the context state (Eqs. (residual_rough), (correction_fine)):
@@ -199,8 +211,11 @@ int lam_relax_sweep(lam_ctx* ctx, int level, int colour);
  * norm (host, may be NULL) receives N of the finest level afterwards. */
 int lam_vcycle(lam_ctx* ctx, double* norm);
 
-/* Propagate one step from t0: psi_in (device, P) -> psi_out (device, P,
- * psi_out_j = sum_n c_jn).  V-cycles from the initial guess c_j0 = psi_in_j,
+/* Propagate one step from t0 (Sec. "Review of the Least Action Principle":
+ * the least-action solution of one step, continued from its initial value;
+ * Sec. "Multigrid Relaxation" for the V-cycles): psi_in (device, P) ->
+ * psi_out (device, P, psi_out_j = sum_n c_jn, every T_n being 1 at the end of
+ * the step).  V-cycles from the initial guess c_j0 = psi_in_j,
  * c_jn = 0 (n >= 1), lambda = 0 until sqrt(N/N0) <= tol.  stats may be NULL.
  * Returns LAM_ENOCONV (psi_out written) if max_cycles is reached,
  * LAM_EDIVERGED if the norm becomes non-finite or grows by more than 1e6. */
@@ -208,14 +223,16 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
                    lam_stats* stats);
 
 /* Propagate n_steps consecutive steps, step k starting at t0 + k dt, each
- * solved as by lam_solve_step: psi_in (device, P) -> psi_out (device, P); the
+ * solved as by lam_solve_step (the step-by-step propagation of Sec. "Review
+ * of the Least Action Principle", each step's end value the next one's
+ * initial condition): psi_in (device, P) -> psi_out (device, P); the
  * buffers may coincide.  The steps run back to back on the context stream;
- * the host waits only for each batch of norms.  When two consecutive steps
- * both see no field, the next step's initial state and its N0 are queued
- * ahead of the wait for the current step's last norms, into spare
- * finest-level buffers (P (n_t + 2) complex values, allocated by the context
- * on first use and kept until lam_destroy; if they cannot be allocated, the
- * steps run without them).  stats (may be NULL): cycles and
+ * the host waits only for each batch of norms.  The next step's initial state
+ * and its N0 (with its field) are queued ahead of the wait for the current
+ * step's last norms, into spare finest-level buffers (P (n_t + 2) complex
+ * values, allocated by the context on first use and kept until lam_destroy;
+ * if they cannot be allocated, the steps run without them), and the host
+ * builds the next step's time factor records during that wait.  stats (may be NULL): cycles and
  * sweeps_fine summed over the steps, resid0/resid of the step with the
  * largest resid/resid0, resid0_last/resid_last of the last step solved,
  * t_factor_ms and t_solve_ms summed.  Stops at the first
@@ -225,7 +242,12 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
 int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, lam_c64* psi_out,
                   lam_stats* stats);
 
-/* Backward pass of one step for a real loss L.  psi_in: the step's initial
+/* Backward pass of one step for a real loss L: the adjoint of the step's
+ * linear system (Sec. "Review of the Least Action Principle", Eqs.
+ * (stationaryphase) and the initial-condition rows; the adjoint is the
+ * conjugate-transposed system, solved by the relaxation of Sec. "Iterative
+ * relaxation to the least action solution" and the V-cycles of Sec.
+ * "Multigrid Relaxation").  psi_in: the step's initial
  * wavefunction (device checkpoint; the forward solve is recomputed from it).
  * g_out = dL/dpsi_out^* (device, P).  Solves K^H mu = E^H g_out with the same
  * relaxation and multigrid machinery, then
@@ -256,6 +278,14 @@ int lam_level_shape(const lam_ctx* ctx, int level, int* n);
  * row-major [point][mode]) and eigenvalues (host, bpts) of the real symmetric
  * spatial block operator T_U + diag(V0_U).  For tests of the block factor. */
 int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, double* vals);
+
+/* Inner passes of the subvolume solves on `level`: hist (host, LAM_MAX_INNER
+ * + 2 entries) receives in hist[p] the number of subvolumes whose last solve
+ * took p inner corrections (0 without field) and in hist[LAM_MAX_INNER + 1]
+ * the number whose last solve stopped with its local residual above the
+ * tolerance (pass limit reached, or corrections that stopped improving).
+ * Synchronises the stream.  For measurements and tests. */
+int lam_pass_stats(lam_ctx* ctx, int level, long long* hist);
 
 /* Timing of finest-level sweep launches with HIP events on the context
  * stream.  enable = k > 0 starts recording (clearing previous records) the

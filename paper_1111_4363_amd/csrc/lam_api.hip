@@ -45,9 +45,10 @@ struct Level {
     float* d_Vf = nullptr;      // FP32 copy (mixed path)
     double2* d_Minv = nullptr;  // per-mode time-system inverses
     float2* d_Minvf = nullptr;
-    double* d_shift = nullptr;  // per-block eigenvalue shift (frozen field)
-    std::vector<double> zc;     // block centre coordinate along the field axis
-    double factored_field = NAN;
+    unsigned char* d_passes = nullptr;  // per block: inner passes of its last solve
+    int nslab = 0;              // blocks along the field axis
+    std::vector<double> zslab;  // centre coordinate of each slab along the field axis
+    size_t tf_off = 0;          // first record of this level in the slab factor tables
     bool fp32 = false;
 };
 
@@ -85,214 +86,274 @@ void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
 }
 
 // ---------------------------------------------------------------------------
-// Small dense complex linear algebra for the shared time factor of the
-// per-mode block systems (n <= 8): inverse, Householder QR and the complex
-// Schur form by shifted QR on the full matrix.
+// Small dense complex linear algebra for the time factors of the per-mode
+// block systems (n <= 8): fixed-size arrays, no allocation.
 // ---------------------------------------------------------------------------
 using cd = std::complex<double>;
+constexpr int kTN = kMaxNT;   // leading dimension of the small matrices
 
-// In-place inverse of an n x n row-major complex matrix (Gauss-Jordan, partial pivoting).
-bool invert_small(int n, cd* A) {
-    std::vector<int> piv(n);
+// In-place inverse of an n x n complex matrix (stride kTN; Gauss-Jordan with
+// partial pivoting).  Returns false for an exactly singular pivot.
+bool invert_small(int n, cd (*A)[kTN]) {
+    int piv[kTN];
     for (int col = 0; col < n; ++col) {
         int p = col;
         for (int r = col + 1; r < n; ++r)
-            if (std::abs(A[r * n + col]) > std::abs(A[p * n + col])) p = r;
+            if (std::abs(A[r][col]) > std::abs(A[p][col])) p = r;
         piv[col] = p;
-        if (std::abs(A[p * n + col]) == 0.0) return false;
+        if (std::abs(A[p][col]) == 0.0) return false;
         if (p != col)
-            for (int k = 0; k < n; ++k) std::swap(A[col * n + k], A[p * n + k]);
-        const cd inv = 1.0 / A[col * n + col];
-        A[col * n + col] = 1.0;
-        for (int k = 0; k < n; ++k) A[col * n + k] *= inv;
+            for (int k = 0; k < n; ++k) std::swap(A[col][k], A[p][k]);
+        const cd inv = 1.0 / A[col][col];
+        A[col][col] = 1.0;
+        for (int k = 0; k < n; ++k) A[col][k] *= inv;
         for (int r = 0; r < n; ++r) {
             if (r == col) continue;
-            const cd f = A[r * n + col];
-            A[r * n + col] = 0.0;
-            for (int k = 0; k < n; ++k) A[r * n + k] -= f * A[col * n + k];
+            const cd f = A[r][col];
+            A[r][col] = 0.0;
+            for (int k = 0; k < n; ++k) A[r][k] -= f * A[col][k];
         }
     }
     for (int col = n - 1; col >= 0; --col)
         if (piv[col] != col)
-            for (int r = 0; r < n; ++r) std::swap(A[r * n + col], A[r * n + piv[col]]);
+            for (int r = 0; r < n; ++r) std::swap(A[r][col], A[r][piv[col]]);
     return true;
 }
 
-// Householder QR of the leading m x m block of A (stride n): A = Q R.
-void householder_qr(int m, int n, const cd* A, cd* Q, cd* R) {
+// Complex Schur form H = Z T Z^H of the m x m matrix H (overwritten by the
+// upper triangular T; Z unitary): Householder reduction to Hessenberg form,
+// then single-shift QR sweeps of Givens rotations with Wilkinson shifts and
+// deflation of negligible subdiagonal entries.  false if it does not converge.
+bool schur_small(int m, cd (*H)[kTN], cd (*Z)[kTN]) {
     for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) {
-            R[i * m + j] = A[i * n + j];
-            Q[i * m + j] = (i == j) ? 1.0 : 0.0;
-        }
-    std::vector<cd> v(m);
-    for (int k = 0; k + 1 < m; ++k) {
-        double nx = 0.0;
-        for (int i = k; i < m; ++i) nx += std::norm(R[i * m + k]);
-        nx = std::sqrt(nx);
-        if (nx == 0.0) continue;
-        const cd x0 = R[k * m + k];
-        const cd alpha = (std::abs(x0) > 0.0) ? -(x0 / std::abs(x0)) * nx : cd(-nx);
-        double nv = 0.0;
-        for (int i = k; i < m; ++i) {
-            v[i] = R[i * m + k] - (i == k ? alpha : cd(0.0));
-            nv += std::norm(v[i]);
-        }
-        nv = std::sqrt(nv);
-        if (nv == 0.0) continue;
-        for (int i = k; i < m; ++i) v[i] /= nv;
-        for (int j = 0; j < m; ++j) {  // R <- (I - 2 v v^H) R
-            cd dot = 0.0;
-            for (int i = k; i < m; ++i) dot += std::conj(v[i]) * R[i * m + j];
-            for (int i = k; i < m; ++i) R[i * m + j] -= 2.0 * v[i] * dot;
-        }
-        for (int i = 0; i < m; ++i) {  // Q <- Q (I - 2 v v^H)
-            cd dot = 0.0;
-            for (int j = k; j < m; ++j) dot += Q[i * m + j] * v[j];
-            for (int j = k; j < m; ++j) Q[i * m + j] -= 2.0 * dot * std::conj(v[j]);
-        }
-    }
-}
-
-// Complex Schur form of the n x n matrix A (row-major, overwritten by T); Z unitary.
-bool schur_small(int n, cd* A, cd* Z) {
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) Z[i * n + j] = (i == j) ? 1.0 : 0.0;
+        for (int j = 0; j < m; ++j) Z[i][j] = (i == j) ? 1.0 : 0.0;
     double nrm = 0.0;
-    for (int k = 0; k < n * n; ++k) nrm += std::norm(A[k]);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) nrm += std::norm(H[i][j]);
     nrm = std::sqrt(nrm);
     if (nrm == 0.0) return true;
-    std::vector<cd> Q(n * n), R(n * n), tmp(n * n);
-    for (int m = n; m > 1; --m) {
-        bool done = false;
-        for (int it = 0; it < 300 && !done; ++it) {
-            double off = 0.0;
-            for (int j = 0; j + 1 < m; ++j) off += std::norm(A[(m - 1) * n + j]);
-            if (std::sqrt(off) <= 1e-15 * nrm) {
-                for (int j = 0; j + 1 < m; ++j) A[(m - 1) * n + j] = 0.0;
-                done = true;
-                break;
+    // Hessenberg: reflector I - 2 v v^H / (v^H v) zeroes H[k+2.., k]
+    for (int k = 0; k + 2 < m; ++k) {
+        cd v[kTN];
+        double xn = 0.0;
+        for (int i = k + 1; i < m; ++i) xn += std::norm(H[i][k]);
+        xn = std::sqrt(xn);
+        if (xn == 0.0) continue;
+        const cd x0 = H[k + 1][k];
+        const cd ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cd(1.0);
+        double vn = 0.0;
+        for (int i = k + 1; i < m; ++i) {
+            v[i] = H[i][k] + (i == k + 1 ? ph * xn : cd(0.0));
+            vn += std::norm(v[i]);
+        }
+        if (vn == 0.0) continue;
+        for (int j = 0; j < m; ++j) {  // H <- P H
+            cd d = 0.0;
+            for (int i = k + 1; i < m; ++i) d += std::conj(v[i]) * H[i][j];
+            d *= 2.0 / vn;
+            for (int i = k + 1; i < m; ++i) H[i][j] -= v[i] * d;
+        }
+        for (int i = 0; i < m; ++i) {  // H <- H P, Z <- Z P
+            cd d = 0.0, e = 0.0;
+            for (int j = k + 1; j < m; ++j) {
+                d += H[i][j] * v[j];
+                e += Z[i][j] * v[j];
             }
-            const cd a = A[(m - 2) * n + m - 2], b = A[(m - 2) * n + m - 1];
-            const cd c = A[(m - 1) * n + m - 2], d = A[(m - 1) * n + m - 1];
-            const cd tr = 0.5 * (a + d);
-            const cd disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
-            cd mu = (std::abs(tr + disc - d) < std::abs(tr - disc - d)) ? tr + disc : tr - disc;
-            if (it % 11 == 10) mu += 0.75 * std::abs(c);
-            for (int i = 0; i < m; ++i) A[i * n + i] -= mu;
-            householder_qr(m, n, A, Q.data(), R.data());
-            for (int i = 0; i < m; ++i)  // A[:m,:m] = R Q + mu I
-                for (int j = 0; j < m; ++j) {
-                    cd acc = 0.0;
-                    for (int k = 0; k < m; ++k) acc += R[i * m + k] * Q[k * m + j];
-                    A[i * n + j] = acc + (i == j ? mu : cd(0.0));
-                }
-            for (int j = m; j < n; ++j) {  // A[:m, m:] = Q^H A[:m, m:]
-                for (int i = 0; i < m; ++i) {
-                    cd acc = 0.0;
-                    for (int k = 0; k < m; ++k) acc += std::conj(Q[k * m + i]) * A[k * n + j];
-                    tmp[i] = acc;
-                }
-                for (int i = 0; i < m; ++i) A[i * n + j] = tmp[i];
-            }
-            for (int i = 0; i < n; ++i) {  // Z[:, :m] = Z[:, :m] Q
-                for (int j = 0; j < m; ++j) {
-                    cd acc = 0.0;
-                    for (int k = 0; k < m; ++k) acc += Z[i * n + k] * Q[k * m + j];
-                    tmp[j] = acc;
-                }
-                for (int j = 0; j < m; ++j) Z[i * n + j] = tmp[j];
+            d *= 2.0 / vn;
+            e *= 2.0 / vn;
+            for (int j = k + 1; j < m; ++j) {
+                H[i][j] -= d * std::conj(v[j]);
+                Z[i][j] -= e * std::conj(v[j]);
             }
         }
-        if (!done) return false;
+        for (int i = k + 2; i < m; ++i) H[i][k] = 0.0;
+    }
+    const double eps = 1e-16;
+    int hi = m - 1, iter = 0;
+    while (hi > 0) {
+        // the active window [lo, hi] ends at the first negligible subdiagonal entry
+        int lo = hi;
+        while (lo > 0) {
+            const double s = std::abs(H[lo][lo]) + std::abs(H[lo - 1][lo - 1]);
+            if (std::abs(H[lo][lo - 1]) <= eps * (s > 0.0 ? s : nrm)) {
+                H[lo][lo - 1] = 0.0;
+                break;
+            }
+            --lo;
+        }
+        if (lo == hi) {
+            --hi;
+            iter = 0;
+            continue;
+        }
+        if (++iter > 60) return false;
+        // Wilkinson shift from the trailing 2 x 2 block (an exceptional one now and then)
+        const cd a = H[hi - 1][hi - 1], b = H[hi - 1][hi], c = H[hi][hi - 1], d = H[hi][hi];
+        const cd tr = 0.5 * (a + d);
+        const cd disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
+        cd mu = (std::abs(tr + disc - d) < std::abs(tr - disc - d)) ? tr + disc : tr - disc;
+        if (iter % 10 == 0) mu += 0.75 * std::abs(c);
+        for (int i = lo; i <= hi; ++i) H[i][i] -= mu;
+        double cs[kTN];
+        cd sn[kTN];
+        for (int k = lo; k < hi; ++k) {  // H - mu I = Q R: rotations from the left
+            const cd x = H[k][k], y = H[k + 1][k];
+            const double r = std::sqrt(std::norm(x) + std::norm(y));
+            double cc;
+            cd ss;
+            if (r == 0.0) {
+                cc = 1.0;
+                ss = 0.0;
+            } else if (std::abs(x) == 0.0) {
+                cc = 0.0;
+                ss = std::conj(y) / r;
+            } else {
+                cc = std::abs(x) / r;
+                ss = (x / std::abs(x)) * std::conj(y) / r;
+            }
+            cs[k] = cc;
+            sn[k] = ss;
+            for (int j = k; j < m; ++j) {
+                const cd u = H[k][j], w = H[k + 1][j];
+                H[k][j] = cc * u + ss * w;
+                H[k + 1][j] = -std::conj(ss) * u + cc * w;
+            }
+        }
+        for (int k = lo; k < hi; ++k) {  // R Q: the same rotations from the right, and into Z
+            const double cc = cs[k];
+            const cd ss = sn[k];
+            const int top = std::min(k + 2, hi);
+            for (int i = 0; i <= top; ++i) {
+                const cd u = H[i][k], w = H[i][k + 1];
+                H[i][k] = cc * u + std::conj(ss) * w;
+                H[i][k + 1] = -ss * u + cc * w;
+            }
+            for (int i = 0; i < m; ++i) {
+                const cd u = Z[i][k], w = Z[i][k + 1];
+                Z[i][k] = cc * u + std::conj(ss) * w;
+                Z[i][k + 1] = -ss * u + cc * w;
+            }
+        }
+        for (int i = lo; i <= hi; ++i) H[i][i] += mu;
     }
     return true;
 }
 
-// Shared time factor of the block systems with c_0 eliminated.  Per point the
-// constraint sum_n s_n dc_n = sigma (s_n = (-1)^n) fixes dc_0 = sigma -
+// Time factor of the block systems of one direction with c_0 eliminated.  Per
+// point the constraint sum_n s_n dc_n = sigma (s_n = (-1)^n) fixes dc_0 = sigma -
 // sum_{j>=1} s_j dc_j, so the unknowns of a block mode are x = (dlam, dc_1 ..
 // dc_{nt-1}) and its nt rows read M_r(e) x = rho - sigma K(e) e_0 with
-// K(e) = M0c - e U (M0c: the time coupling, i 2 on (m, k), k > m, k - m odd;
-// adjoint: its conjugate transpose) and
+//   K(e) = M0c - e U - zf W
+// (M0c: the time coupling, i 2 on (m, k), k > m, k - m odd; adjoint: its
+// conjugate transpose; W: the field's time matrix of the step, taken at the
+// dipole coordinate zf; W = null for no field) and
 //   M_r(e)[:, 0] = s,   M_r(e)[:, j] = K(e)[:, j] - s_j K(e)[:, 0]   (j >= 1).
 // Split M_r(e) = M_r0 - e D_r (D_r[:, 0] = 0, D_r[:, j] = U_j e_j - s_j U_0 e_0)
-// and diagonalise G = M_r0^{-1} D_r = S diag(lam) S^{-1}: its eigenvalues are
-// simple (0 is one of them, with eigenvector e_0), so
+// and diagonalise G = M_r0^{-1} D_r = S diag(lam) S^{-1}.  G's first column is
+// zero, so e_0 is an eigenvector with eigenvalue 0 and the others come from the
+// trailing block G22: for G22 u = lam u (lam != 0) the eigenvector of G is
+// (g12 . u / lam, u) with g12 = G[0, 1..].  With simple eigenvalues
 //   M_r(e)^{-1} = S (I - e diag(lam))^{-1} S^{-1} M_r0^{-1}.
-// Eigenvectors from the complex Schur form G = Z T Z^H by back substitution.
 // Outputs (row-major, nt x nt complex): E3 = S, E1 = S^{-1} M_r0^{-1}, and lam.
-// Returns false if G S = S diag(lam) fails to 1e-12.
-bool time_factor(int nt, const double* U, bool adjoint, cd* E1, cd* E3, cd* lam) {
+// Returns false if an eigenvalue of G22 is zero or repeated or G S = S diag(lam)
+// fails to 1e-12.
+bool time_factor(int nt, const double* U, const double* W, double zf, bool adjoint, cd* E1, cd* E3, cd* lam) {
     const int n = nt;
-    std::vector<cd> M0c(n * n, 0.0), Mr0(n * n, 0.0), Dr(n * n, 0.0), Minv(n * n), G(n * n, 0.0), T(n * n),
-        Z(n * n);
+    cd K0[kTN][kTN], Mr0[kTN][kTN], Dr[kTN][kTN], Minv[kTN][kTN], G[kTN][kTN];
     for (int m = 0; m < n; ++m)
-        for (int k = 0; k < n; ++k)
+        for (int k = 0; k < n; ++k) {
+            K0[m][k] = 0.0;
+            Dr[m][k] = 0.0;
+        }
+    for (int m = 0; m < n; ++m)
+        for (int k = 0; k < n; ++k) {
             if (k > m && ((k - m) & 1)) {
-                if (!adjoint) M0c[m * n + k] = cd(0.0, 2.0);
-                else M0c[k * n + m] = cd(0.0, -2.0);
+                if (!adjoint) K0[m][k] += cd(0.0, 2.0);
+                else K0[k][m] += cd(0.0, -2.0);
             }
+            if (W) K0[m][k] -= zf * W[m * n + k];
+        }
     auto sgn = [](int j) { return (j & 1) ? -1.0 : 1.0; };
     for (int m = 0; m < n; ++m) {
-        Mr0[m * n + 0] = sgn(m);
-        for (int j = 1; j < n; ++j) Mr0[m * n + j] = M0c[m * n + j] - sgn(j) * M0c[m * n + 0];
+        Mr0[m][0] = sgn(m);
+        for (int j = 1; j < n; ++j) Mr0[m][j] = K0[m][j] - sgn(j) * K0[m][0];
     }
     for (int j = 1; j < n; ++j) {
-        Dr[j * n + j] += U[j];
-        Dr[0 * n + j] -= sgn(j) * U[0];
+        Dr[j][j] += U[j];
+        Dr[0][j] -= sgn(j) * U[0];
     }
-    Minv = Mr0;
-    if (!invert_small(n, Minv.data())) return false;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Minv[i][j] = Mr0[i][j];
+    if (!invert_small(n, Minv)) return false;
+    double gn = 0.0;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             cd acc = 0.0;
-            for (int k = 0; k < n; ++k) acc += Minv[i * n + k] * Dr[k * n + j];
-            G[i * n + j] = acc;
+            for (int k = 0; k < n; ++k) acc += Minv[i][k] * Dr[k][j];
+            G[i][j] = acc;
+            gn = std::max(gn, std::abs(acc));
         }
-    T = G;
-    if (!schur_small(n, T.data(), Z.data())) return false;
-    std::vector<cd> S(n * n, 0.0), w(n);
-    for (int k = 0; k < n; ++k) {
-        const cd lk = T[k * n + k];
-        for (int i = 0; i < n; ++i) w[i] = 0.0;
-        w[k] = 1.0;
-        for (int i = k - 1; i >= 0; --i) {
-            cd acc = 0.0;
-            for (int m = i + 1; m <= k; ++m) acc += T[i * n + m] * w[m];
-            const cd den = T[i * n + i] - lk;
-            if (std::abs(den) < 1e-12 * std::max(std::abs(lk), std::abs(T[i * n + i]))) return false;
-            w[i] = -acc / den;
+    cd S[kTN][kTN], lv[kTN];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) S[i][j] = (i == j && j == 0) ? 1.0 : 0.0;
+    lv[0] = 0.0;
+    const int m = n - 1;
+    if (m > 0) {
+        cd T[kTN][kTN], Z[kTN][kTN];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) T[i][j] = G[i + 1][j + 1];
+        if (!schur_small(m, T, Z)) return false;
+        for (int k = 0; k < m; ++k) {
+            const cd lk = T[k][k];
+            if (!(std::abs(lk) > 1e-12 * std::max(gn, 1e-300))) return false;
+            cd w[kTN];
+            for (int i = 0; i < m; ++i) w[i] = 0.0;
+            w[k] = 1.0;
+            for (int i = k - 1; i >= 0; --i) {
+                cd acc = 0.0;
+                for (int j = i + 1; j <= k; ++j) acc += T[i][j] * w[j];
+                const cd den = T[i][i] - lk;
+                if (std::abs(den) < 1e-12 * std::max(std::abs(lk), std::abs(T[i][i]))) return false;
+                w[i] = -acc / den;
+            }
+            cd v[kTN];
+            cd g12u = 0.0;
+            for (int i = 0; i < m; ++i) {
+                cd acc = 0.0;
+                for (int j = 0; j <= k; ++j) acc += Z[i][j] * w[j];
+                v[i + 1] = acc;
+            }
+            for (int i = 0; i < m; ++i) g12u += G[0][i + 1] * v[i + 1];
+            v[0] = g12u / lk;
+            double nv = 0.0;
+            for (int i = 0; i < n; ++i) nv += std::norm(v[i]);
+            nv = std::sqrt(nv);
+            for (int i = 0; i < n; ++i) S[i][k + 1] = v[i] / nv;
+            lv[k + 1] = lk;
         }
-        double nv = 0.0;
-        std::vector<cd> v(n, 0.0);
-        for (int i = 0; i < n; ++i) {
-            for (int m = 0; m <= k; ++m) v[i] += Z[i * n + m] * w[m];
-            nv += std::norm(v[i]);
-        }
-        nv = std::sqrt(nv);
-        for (int i = 0; i < n; ++i) S[i * n + k] = v[i] / nv;
-        lam[k] = lk;
     }
     // check G S = S diag(lam)
-    double gn = 0.0, err = 0.0;
-    for (int k = 0; k < n * n; ++k) gn = std::max(gn, std::abs(G[k]));
+    double err = 0.0;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             cd gs = 0.0;
-            for (int k = 0; k < n; ++k) gs += G[i * n + k] * S[k * n + j];
-            err = std::max(err, std::abs(gs - S[i * n + j] * lam[j]));
+            for (int k = 0; k < n; ++k) gs += G[i][k] * S[k][j];
+            err = std::max(err, std::abs(gs - S[i][j] * lv[j]));
         }
     if (!(err <= 1e-12 * std::max(gn, 1.0))) return false;
-    std::vector<cd> Sinv = S;
-    if (!invert_small(n, Sinv.data())) return false;
+    cd Sinv[kTN][kTN];
     for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Sinv[i][j] = S[i][j];
+    if (!invert_small(n, Sinv)) return false;
+    for (int i = 0; i < n; ++i) {
+        lam[i] = lv[i];
         for (int j = 0; j < n; ++j) {
-            E3[i * n + j] = S[i * n + j];
+            E3[i * n + j] = S[i][j];
             cd acc = 0.0;
-            for (int k = 0; k < n; ++k) acc += Sinv[i * n + k] * Minv[k * n + j];
+            for (int k = 0; k < n; ++k) acc += Sinv[i][k] * Minv[k][j];
             E1[i * n + j] = acc;
         }
+    }
     return true;
 }
 
@@ -318,7 +379,6 @@ struct lam_ctx {
     // current step
     double t0 = NAN;
     double W[kMaxNT * kMaxNT] = {};
-    double Ebar = 0.0;
     int field_on = 0;
     int n_inner = 0;
     int have_state = 0;
@@ -345,8 +405,28 @@ struct lam_ctx {
     double2* d_G = nullptr;
     double2* h_G = nullptr;       // pinned
     double2* d_cf = nullptr;      // forward coefficients kept for the gradients
-    double2* d_tf = nullptr;      // shared time factor (real forms of E1, E3, E3^H, E1^H; eigenvalues), FP64
-    float2* d_tff = nullptr;      // and its FP32 copy
+    // time factor records (layout in lam_internal.h): TS reals each
+    int TS = 0;
+    double* d_tf0 = nullptr;      // without field: the forward record, then the adjoint one (FP64)
+    float* d_tf0f = nullptr;      // and their FP32 copies
+    std::vector<double> h_tf0[2]; // host copies (the fallback of a slab factor)
+    size_t nslab_total = 0;       // slabs over all levels
+    // with a field: per direction, one record per slab of every level (FP64), then
+    // their FP32 copies; rebuilt on the host for every step and copied in stream order
+    unsigned char* d_tfs[2] = {nullptr, nullptr};
+    double tf_t[2] = {NAN, NAN};  // step whose records d_tfs[dir] hold
+    double mf_t = NAN;            // stored per-mode inverses: step with a field they were built
+                                  // for (-inf: without field; NaN: none)
+    struct Stage {                // pinned host staging of one step's records
+        unsigned char* h = nullptr;
+        hipEvent_t ev = nullptr;  // recorded after the copy that reads h
+        double t = NAN;
+        int dir = -1;
+    } stage[2];
+    int stage_next = 0;
+    double prep_t = NAN;          // a step whose records the next wait should prepare on the host
+    int prep_dir = 0;
+    double state_t0 = NAN;        // step of the state loaded in the context
     // profiling of finest-level sweeps
     int prof = 0;                 // record every prof-th finest-level sweep launch (0: off)
     long prof_count = 0;
@@ -397,51 +477,132 @@ void time_matrix(const lam_ctx* c, double t0, int q, double* W) {
     }
 }
 
-int refactor_modes(lam_ctx* c, Level& L) {
-    if (L.factored_field == c->Ebar) return LAM_OK;
-    std::vector<double> sh(L.nblocks);
-    for (int b = 0; b < L.nblocks; ++b) sh[b] = c->Ebar * L.zc[b];
-    // make sure no queued sweep still reads the previous shifts, then upload
-    HIPCHK(hipStreamSynchronize(c->st));
-    HIPCHK(hipMemcpy(L.d_shift, sh.data(), sizeof(double) * L.nblocks, hipMemcpyHostToDevice));
-    if (c->solver.time_factor == LAM_TF_STORED)
-        HIPCHK(launch_mode_factor(c->nt, L.nblocks, L.g.bpts, c->U, L.d_e, L.d_shift, L.d_Minv,
-                                  L.fp32 ? L.d_Minvf : nullptr, c->st));
-    L.factored_field = c->Ebar;
+bool any_nonzero(const double* W, int n) {
+    for (int k = 0; k < n; ++k)
+        if (W[k] != 0.0) return true;
+    return false;
+}
+
+// Real form (2n x 2n, acting on interleaved re/im) of an n x n complex matrix.
+void real_form(int n, const cd* M, double* out) {
+    const int n2 = 2 * n;
+    for (int r = 0; r < n2; ++r)
+        for (int q = 0; q < n2; ++q) {
+            const cd m = M[(r >> 1) * n + (q >> 1)];
+            const int a = r & 1, cc = q & 1;
+            out[r * n2 + q] = (a == cc) ? m.real() : (a == 0 ? -m.imag() : m.imag());
+        }
+}
+
+// One time factor record (layout in lam_internal.h) of direction dir with the
+// field's time matrix W (null: none) taken at zf.  false if the factor fails.
+bool make_record(const lam_ctx* c, const double* W, double zf, int dir, double* rec) {
+    const int n = c->nt;
+    cd E1[kTN * kTN], E3[kTN * kTN], lam[kTN];
+    if (!time_factor(n, c->U, W, zf, dir != 0, E1, E3, lam)) return false;
+    real_form(n, E1, rec);
+    real_form(n, E3, rec + 4 * n * n);
+    for (int k = 0; k < n; ++k) {
+        rec[8 * n * n + 2 * k] = lam[k].real();
+        rec[8 * n * n + 2 * k + 1] = lam[k].imag();
+    }
+    rec[tf_record_reals(n)] = zf;
+    rec[tf_record_reals(n) + 1] = 0.0;
+    return true;
+}
+
+size_t tf_table_bytes(const lam_ctx* c) { return c->nslab_total * (size_t)c->TS * (sizeof(double) + sizeof(float)); }
+
+// Build on the host the records of step t (direction dir) for every slab of
+// every level, into a staging buffer (reused if it already holds them).  A
+// slab whose factor fails takes the record without field (zf = 0), so its
+// inner passes correct the whole field term.
+int prepare_tables(lam_ctx* c, double t, int dir) {
+    for (auto& s : c->stage)
+        if (s.t == t && s.dir == dir) return LAM_OK;
+    auto& s = c->stage[c->stage_next];
+    c->stage_next ^= 1;
+    HIPCHK(hipEventSynchronize(s.ev));  // the copy that last read this buffer is done
+    s.t = NAN;
+    double W[kMaxNT * kMaxNT];
+    time_matrix(c, t, -1, W);
+    const int TS = c->TS;
+    double* h64 = reinterpret_cast<double*>(s.h);
+    float* h32 = reinterpret_cast<float*>(s.h + c->nslab_total * (size_t)TS * sizeof(double));
+    for (const auto& L : c->lv)
+        for (int k = 0; k < L.nslab; ++k) {
+            double* rec = h64 + (L.tf_off + k) * (size_t)TS;
+            if (!make_record(c, W, L.zslab[k], dir, rec))
+                std::copy(c->h_tf0[dir].begin(), c->h_tf0[dir].end(), rec);
+            float* rf = h32 + (L.tf_off + k) * (size_t)TS;
+            for (int i = 0; i < TS; ++i) rf[i] = (float)rec[i];
+        }
+    s.t = t;
+    s.dir = dir;
     return LAM_OK;
 }
 
-// Select the step starting at t0: field matrix, mean field, inner-pass count.
-int set_step(lam_ctx* c, double t0) {
+// Make d_tfs[dir] hold the records of step t (a copy queued on the stream:
+// kernels queued before it still read the previous records).
+int upload_tables(lam_ctx* c, double t, int dir) {
+    if (c->tf_t[dir] == t) return LAM_OK;
+    LAMCHK(prepare_tables(c, t, dir));
+    for (auto& s : c->stage)
+        if (s.t == t && s.dir == dir) {
+            HIPCHK(hipMemcpyAsync(c->d_tfs[dir], s.h, tf_table_bytes(c), hipMemcpyHostToDevice, c->st));
+            HIPCHK(hipEventRecord(s.ev, c->st));
+            c->tf_t[dir] = t;
+            return LAM_OK;
+        }
+    return LAM_EINVAL;
+}
+
+// Stored per-mode inverses (LAM_TF_STORED) for the current step: with the
+// field at each slab's zf (records of direction dir), or without field.
+int stored_factors(lam_ctx* c, int dir) {
+    if (c->solver.time_factor != LAM_TF_STORED) return LAM_OK;
+    const double want = c->field_on ? c->t0 : -INFINITY;
+    if (c->mf_t == want) return LAM_OK;
+    for (auto& L : c->lv) {
+        const double* tf = c->field_on ? reinterpret_cast<const double*>(c->d_tfs[dir]) + L.tf_off * (size_t)c->TS
+                                       : nullptr;
+        HIPCHK(launch_mode_factor(c->nt, L.g, c->U, c->field_on ? c->W : nullptr, L.d_e, tf, c->TS, L.d_Minv,
+                                  L.fp32 ? L.d_Minvf : nullptr, c->st));
+    }
+    c->mf_t = want;
+    return LAM_OK;
+}
+
+// Select the step starting at t0 for solves of direction dir (0 forward, 1
+// adjoint): its field matrix, inner-pass count and time factor records.
+int set_step(lam_ctx* c, double t0, int dir) {
     if (!(c->t0 == t0)) {
         time_matrix(c, t0, -1, c->W);
         c->t0 = t0;
     }
     const int nt = c->nt;
-    int on = 0;
-    for (int k = 0; k < nt * nt; ++k) on |= (c->W[k] != 0.0);
+    const bool on = any_nonzero(c->W, nt * nt);
     c->field_on = on;
-    c->Ebar = c->W[0] / c->U[0];
     c->n_inner = c->solver.n_inner >= 0 ? c->solver.n_inner : (on ? 16 : 0);
     auto t_a = std::chrono::steady_clock::now();
-    for (auto& L : c->lv) LAMCHK(refactor_modes(c, L));
+    if (on) LAMCHK(upload_tables(c, t0, dir));
+    LAMCHK(stored_factors(c, dir));
     c->t_factor_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
     return LAM_OK;
 }
 
-// Whether the step starting at t0 sees no field (its time matrix is zero).
-bool field_free(const lam_ctx* c, double t0) {
-    double W[kMaxNT * kMaxNT];
-    time_matrix(c, t0, -1, W);
-    for (int k = 0; k < c->nt * c->nt; ++k)
-        if (W[k] != 0.0) return false;
-    return true;
+// Whether the step starting at t0 sees a field (its time matrix is nonzero); W (may be null) receives it.
+bool step_field(const lam_ctx* c, double t0, double* W) {
+    double Wl[kMaxNT * kMaxNT];
+    double* w = W ? W : Wl;
+    time_matrix(c, t0, -1, w);
+    return any_nonzero(w, c->nt * c->nt);
 }
 
 int factor_level(lam_ctx* c, Level& L) {
     HIPCHK(launch_block_eig(L.g, L.d_v0, L.d_V, L.d_e, L.fp32 ? L.d_Vf : nullptr, c->st));
-    L.factored_field = NAN;
-    return refactor_modes(c, L);
+    c->mf_t = NAN;  // stored per-mode inverses depend on the eigenvalues
+    return LAM_OK;
 }
 
 int sweep(lam_ctx* c, int l, int colour) {
@@ -469,9 +630,19 @@ int sweep(lam_ctx* c, int l, int colour) {
         a.Minv = L.fp32 ? static_cast<const void*>(L.d_Minvf) : static_cast<const void*>(L.d_Minv);
     else
         a.Minv = nullptr;
-    a.tf = L.fp32 ? static_cast<const void*>(c->d_tff) : static_cast<const void*>(c->d_tf);
+    const int dir = c->adjoint ? 1 : 0;
+    if (c->field_on) {
+        const size_t off = L.tf_off * (size_t)c->TS;
+        const double* t64 = reinterpret_cast<const double*>(c->d_tfs[dir]);
+        const float* t32 = reinterpret_cast<const float*>(c->d_tfs[dir] + c->nslab_total * (size_t)c->TS * sizeof(double));
+        a.tf = L.fp32 ? static_cast<const void*>(t32 + off) : static_cast<const void*>(t64 + off);
+        a.tf_stride = c->TS;
+    } else {
+        a.tf = L.fp32 ? static_cast<const void*>(c->d_tf0f + dir * c->TS) : static_cast<const void*>(c->d_tf0 + dir * c->TS);
+        a.tf_stride = 0;
+    }
     a.e = L.d_e;
-    a.shift = L.d_shift;
+    a.passes = L.d_passes;
     a.adjoint = c->adjoint;
     a.n_inner = c->n_inner;
     a.field_on = c->field_on ? 1 : 0;
@@ -580,7 +751,7 @@ int queue_norm(lam_ctx* c, int slot) {
 // h_norms[next_slot], so that the GPU has work while the host reacts to the
 // norms; *next_ready tells whether that was done after the final cycle.
 int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out = nullptr, int next_slot = 0,
-               bool* next_ready = nullptr) {
+               bool* next_ready = nullptr, const double* next_W = nullptr) {
     const int maxc = c->solver.max_cycles;
     int& predict = c->predict[c->adjoint ? 1 : 0];
     if (next_ready) *next_ready = false;
@@ -613,9 +784,15 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
         if (next_out) {
             Level& L = c->lv[0];
             int np = 0;
-            HIPCHK(launch_advance(c->nt, L.g, c->U[0], L.d_c, L.d_v0, next_out, c->d_c_next, c->d_lam_next,
+            HIPCHK(launch_advance(c->nt, L.g, c->U, next_W, L.d_c, L.d_v0, next_out, c->d_c_next, c->d_lam_next,
                                   c->d_bs_next, c->d_partial, &np, c->st));
             HIPCHK(launch_reduce(c->d_partial, np, 1, c->h_norms_dev + next_slot, c->st));
+        }
+        // the host builds the next step's time factor records while the GPU works
+        if (!std::isnan(c->prep_t)) {
+            const double tp = c->prep_t;
+            c->prep_t = NAN;
+            LAMCHK(prepare_tables(c, tp, c->prep_dir));
         }
         LAMCHK(wait_event(c));
         N0 = c->h_norms[n0_slot];
@@ -678,7 +855,7 @@ int validate(const lam_grid* g, const lam_time* t, const lam_ham* h, const lam_s
     if (h->n_coef < 0 || (h->n_coef > 0 && !h->coef)) return LAM_EINVAL;
     if (!h->v0) return LAM_EINVAL;
     if (s->precision != LAM_FP64 && s->precision != LAM_MIXED) return LAM_EINVAL;
-    if (s->max_cycles < 0 || !(s->tol >= 0.0) || s->n_inner < -1) return LAM_EINVAL;
+    if (s->max_cycles < 0 || !(s->tol >= 0.0) || s->n_inner < -1 || s->n_inner > LAM_MAX_INNER) return LAM_EINVAL;
     if (s->time_factor != LAM_TF_SHARED && s->time_factor != LAM_TF_STORED) return LAM_EINVAL;
     long bpts = 1;
     for (int a = 0; a < g->dim; ++a) {
@@ -750,7 +927,7 @@ void free_ctx(lam_ctx* c) {
         (void)hipFree(L.d_Vf);
         (void)hipFree(L.d_Minv);
         (void)hipFree(L.d_Minvf);
-        (void)hipFree(L.d_shift);
+        (void)hipFree(L.d_passes);
     }
     (void)hipFree(c->d_g);
     (void)hipFree(c->d_partial);
@@ -758,8 +935,13 @@ void free_ctx(lam_ctx* c) {
     (void)hipFree(c->d_Gpart);
     (void)hipFree(c->d_G);
     (void)hipFree(c->d_cf);
-    (void)hipFree(c->d_tf);
-    (void)hipFree(c->d_tff);
+    (void)hipFree(c->d_tf0);
+    (void)hipFree(c->d_tf0f);
+    for (auto* p : c->d_tfs) (void)hipFree(p);
+    for (auto& s : c->stage) {
+        if (s.h) (void)hipHostFree(s.h);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+    }
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->ev_norm) (void)hipEventDestroy(c->ev_norm);
     if (c->h_norms) (void)hipHostFree(c->h_norms);
@@ -802,9 +984,8 @@ int build(lam_ctx* c, const double* v0_dev) {
         }
         L.nblocks = g.nblk[0] * g.nblk[1] * g.nblk[2];
         L.fp32 = c->solver.precision == LAM_MIXED && (l < gr.levels - 1 || gr.levels == 1);
-        // colour lists and block centres along the field axis
+        // colour lists
         std::vector<int> col[2];
-        L.zc.resize(L.nblocks);
         for (int b = 0; b < L.nblocks; ++b) {
             int bc[3] = {0, 0, 0}, t = b;
             for (int a = gr.dim - 1; a >= 0; --a) {
@@ -812,9 +993,19 @@ int build(lam_ctx* c, const double* v0_dev) {
                 t /= g.nblk[a];
             }
             col[(bc[0] + bc[1] + bc[2]) & 1].push_back(b);
+        }
+        // slabs of blocks along the field axis and their centre coordinates, rounded
+        // to FP32 so that both precisions' factor records hold the same zf exactly
+        {
             const int a = g.fax;
-            const double centre_index = bc[a] * g.bdim[a] + 0.5 * (g.bdim[a] - 1);
-            L.zc[b] = (centre_index - 0.5 * (g.n[a] - 1)) * g.h;
+            L.nslab = g.nblk[a];
+            L.zslab.resize(L.nslab);
+            for (int k = 0; k < L.nslab; ++k) {
+                const double centre_index = k * g.bdim[a] + 0.5 * (g.bdim[a] - 1);
+                L.zslab[k] = (double)(float)((centre_index - 0.5 * (g.n[a] - 1)) * g.h);
+            }
+            L.tf_off = c->nslab_total;
+            c->nslab_total += L.nslab;
         }
         for (int k = 0; k < 2; ++k) {
             L.ncol[k] = (int)col[k].size();
@@ -834,7 +1025,8 @@ int build(lam_ctx* c, const double* v0_dev) {
         LAMCHK(dalloc(&L.d_e, L.nblocks * B));
         const bool stored = c->solver.time_factor == LAM_TF_STORED;
         if (stored) LAMCHK(dalloc(&L.d_Minv, L.nblocks * B * (nt + 1) * (nt + 1)));
-        LAMCHK(dalloc(&L.d_shift, (size_t)L.nblocks));
+        LAMCHK(dalloc(&L.d_passes, (size_t)L.nblocks));
+        HIPCHK(hipMemsetAsync(L.d_passes, 0, (size_t)L.nblocks, c->st));
         if (L.fp32) {
             LAMCHK(dalloc(&L.d_Vf, L.nblocks * B * B));
             if (stored) LAMCHK(dalloc(&L.d_Minvf, L.nblocks * B * (nt + 1) * (nt + 1)));
@@ -863,44 +1055,30 @@ int build(lam_ctx* c, const double* v0_dev) {
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
         return LAM_ENOMEM;
     {
-        // shared time factor, as reals: the real forms (2n x 2n, acting on interleaved
-        // re/im) of E1, E3 of the forward direction, then of the adjoint direction,
-        // then lam (n complex) of each direction; n = nt
-        const int n = nt, n2 = 2 * n;
-        std::vector<double> h;
-        h.reserve(4 * n2 * n2 + 4 * n);
-        auto expand = [&](const std::vector<cd>& M) {
-            for (int r = 0; r < n2; ++r)
-                for (int q = 0; q < n2; ++q) {
-                    const int p = r >> 1, a = r & 1, qq = q >> 1, cc = q & 1;
-                    const cd m = M[p * n + qq];
-                    double v;
-                    if (a == 0 && cc == 0) v = m.real();
-                    else if (a == 0 && cc == 1) v = -m.imag();
-                    else if (a == 1 && cc == 0) v = m.imag();
-                    else v = m.real();
-                    h.push_back(v);
-                }
-        };
-        std::vector<cd> E1(n * n), E3(n * n), lam_f(n), lam_a(n);
-        if (!time_factor(nt, c->U, false, E1.data(), E3.data(), lam_f.data())) return LAM_EINVAL;
-        expand(E1);
-        expand(E3);
-        if (!time_factor(nt, c->U, true, E1.data(), E3.data(), lam_a.data())) return LAM_EINVAL;
-        expand(E1);
-        expand(E3);
-        for (const auto* lv : {&lam_f, &lam_a})
-            for (const cd& v : *lv) {
-                h.push_back(v.real());
-                h.push_back(v.imag());
-            }
+        // time factor records without field (forward, adjoint), and the per-slab
+        // tables and staging buffers for steps with a field
+        const int TS = tf_record_stride(nt);
+        c->TS = TS;
+        std::vector<double> h(2 * TS);
+        for (int dir = 0; dir < 2; ++dir) {
+            if (!make_record(c, nullptr, 0.0, dir, h.data() + dir * TS)) return LAM_EINVAL;
+            c->h_tf0[dir].assign(h.begin() + dir * TS, h.begin() + (dir + 1) * TS);
+        }
         std::vector<float> hf(h.begin(), h.end());
-        LAMCHK(dalloc(&c->d_tf, h.size() / 2));
-        LAMCHK(dalloc(&c->d_tff, hf.size() / 2));
-        HIPCHK(hipMemcpy(c->d_tf, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(c->d_tff, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice));
+        LAMCHK(dalloc(&c->d_tf0, h.size()));
+        LAMCHK(dalloc(&c->d_tf0f, hf.size()));
+        HIPCHK(hipMemcpy(c->d_tf0, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->d_tf0f, hf.data(), sizeof(float) * hf.size(), hipMemcpyHostToDevice));
+        const size_t tb = tf_table_bytes(c);
+        for (int dir = 0; dir < 2; ++dir) LAMCHK(dalloc(&c->d_tfs[dir], tb));
+        for (auto& s : c->stage) {
+            if (hipHostMalloc(reinterpret_cast<void**>(&s.h), tb) != hipSuccess) {
+                s.h = nullptr;
+                return LAM_ENOMEM;
+            }
+            HIPCHK(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+        }
     }
-    c->Ebar = 0.0;
     for (auto& L : c->lv) LAMCHK(factor_level(c, L));
     HIPCHK(hipStreamSynchronize(c->st));
     return LAM_OK;
@@ -945,7 +1123,12 @@ int lam_destroy(lam_ctx* ctx) {
 int lam_set_pulse(lam_ctx* ctx, int n_coef, const double* coef) {
     if (!ctx || n_coef != (int)ctx->coef.size() || (n_coef > 0 && !coef)) return LAM_EINVAL;
     ctx->coef.assign(coef, coef + n_coef);
-    ctx->t0 = NAN;  // field matrices must be recomputed
+    // field matrices, time factor records and stored inverses must be rebuilt
+    ctx->t0 = NAN;
+    ctx->tf_t[0] = ctx->tf_t[1] = NAN;
+    for (auto& s : ctx->stage) s.t = NAN;
+    ctx->mf_t = NAN;
+    if (ctx->have_state) LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
     return LAM_OK;
 }
 
@@ -956,6 +1139,7 @@ int lam_set_potential(lam_ctx* ctx, const double* v0) {
         HIPCHK(launch_average_potential(ctx->lv[l - 1].g, ctx->lv[l].g, ctx->lv[l - 1].d_v0, ctx->lv[l].d_v0,
                                         ctx->st));
     for (auto& L : ctx->lv) LAMCHK(factor_level(ctx, L));
+    if (ctx->have_state) LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
     HIPCHK(hipStreamSynchronize(ctx->st));
     return LAM_OK;
 }
@@ -963,10 +1147,12 @@ int lam_set_potential(lam_ctx* ctx, const double* v0) {
 int lam_residual_action(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c, const lam_c64* lam,
                         lam_c64* rho, lam_c64* sigma, double* norm) {
     if (!ctx || bad_ptr(psi0) || bad_ptr(c) || bad_ptr(lam)) return LAM_EINVAL;
-    LAMCHK(set_step(ctx, t0));
+    // the step's field matrix, without touching the step of the context's state
+    double W[kMaxNT * kMaxNT];
+    const int on = step_field(ctx, t0, W) ? 1 : 0;
     Level& L = ctx->lv[0];
     int np = 0;
-    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, ctx->W, 0, ctx->field_on, reinterpret_cast<const double2*>(c),
+    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, W, 0, on, reinterpret_cast<const double2*>(c),
                            reinterpret_cast<const double2*>(lam), L.d_v0, nullptr, nullptr,
                            reinterpret_cast<const double2*>(psi0), reinterpret_cast<double2*>(rho),
                            reinterpret_cast<double2*>(sigma), norm ? ctx->d_partial : nullptr, &np, ctx->st));
@@ -981,10 +1167,11 @@ int lam_residual_action(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_
 int lam_residual_adjoint(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c, const lam_c64* mu_lam,
                          lam_c64* rho, lam_c64* sigma, double* norm) {
     if (!ctx || bad_ptr(g) || bad_ptr(mu_c) || bad_ptr(mu_lam)) return LAM_EINVAL;
-    LAMCHK(set_step(ctx, t0));
+    double W[kMaxNT * kMaxNT];
+    const int on = step_field(ctx, t0, W) ? 1 : 0;
     Level& L = ctx->lv[0];
     int np = 0;
-    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, ctx->W, 1, ctx->field_on, reinterpret_cast<const double2*>(mu_c),
+    HIPCHK(launch_residual(ctx->nt, L.g, ctx->U, W, 1, on, reinterpret_cast<const double2*>(mu_c),
                            reinterpret_cast<const double2*>(mu_lam), L.d_v0, nullptr,
                            reinterpret_cast<const double2*>(g), nullptr, reinterpret_cast<double2*>(rho),
                            reinterpret_cast<double2*>(sigma), norm ? ctx->d_partial : nullptr, &np, ctx->st));
@@ -998,7 +1185,7 @@ int lam_residual_adjoint(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c6
 
 int lam_set_state(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c, const lam_c64* lam) {
     if (!ctx || bad_ptr(psi0) || bad_ptr(c) || bad_ptr(lam)) return LAM_EINVAL;
-    LAMCHK(set_step(ctx, t0));
+    LAMCHK(set_step(ctx, t0, 0));
     Level& L = ctx->lv[0];
     const size_t P = L.g.P;
     HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(psi0), L.d_bs, P, ctx->st));
@@ -1006,12 +1193,13 @@ int lam_set_state(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c
     HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(lam), L.d_lam, P, ctx->st));
     ctx->adjoint = 0;
     ctx->have_state = 1;
+    ctx->state_t0 = t0;
     return LAM_OK;
 }
 
 int lam_set_adjoint_state(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c, const lam_c64* mu_lam) {
     if (!ctx || bad_ptr(g) || bad_ptr(mu_c) || bad_ptr(mu_lam)) return LAM_EINVAL;
-    LAMCHK(set_step(ctx, t0));
+    LAMCHK(set_step(ctx, t0, 1));
     Level& L = ctx->lv[0];
     const size_t P = L.g.P;
     HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(g), ctx->d_g, P, ctx->st));
@@ -1019,6 +1207,7 @@ int lam_set_adjoint_state(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c
     HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(mu_lam), L.d_lam, P, ctx->st));
     ctx->adjoint = 1;
     ctx->have_state = 1;
+    ctx->state_t0 = t0;
     return LAM_OK;
 }
 
@@ -1040,12 +1229,15 @@ int lam_relax_sweep(lam_ctx* ctx, int level, int colour) {
         // produced by a V-cycle, so only the finest level is addressable on its own
         return LAM_EINVAL;
     }
+    // the step of the loaded state (a residual call may have looked at another one)
+    LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
     return sweep(ctx, level, colour);
 }
 
 int lam_vcycle(lam_ctx* ctx, double* norm) {
     if (!ctx) return LAM_EINVAL;
     if (!ctx->have_state) return LAM_ESTATE;
+    LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
     LAMCHK(vcycle(ctx, 0));
     if (norm) LAMCHK(norm0(ctx, norm));
     return LAM_OK;
@@ -1056,12 +1248,13 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
     const auto t_a = std::chrono::steady_clock::now();
     ctx->t_factor_ms = 0.0;
     const int sw0 = ctx->sweeps_fine;
-    LAMCHK(set_step(ctx, t0));
+    LAMCHK(set_step(ctx, t0, 0));
     Level& L = ctx->lv[0];
     HIPCHK(launch_init_forward(ctx->nt, L.g.P, reinterpret_cast<const double2*>(psi_in), L.d_c, L.d_lam, L.d_bs,
                                ctx->st));
     ctx->adjoint = 0;
     ctx->have_state = 1;
+    ctx->state_t0 = t0;
     const int rc = solve_loop(ctx, stats);
     if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
     HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, reinterpret_cast<double2*>(psi_out), ctx->st));
@@ -1089,21 +1282,31 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
     int n0_slot = -1;  // >= 0: this step's initial state is in place and its N0 queued into that slot
     for (int k = 0; k < n_steps; ++k) {
         const double tk = t0 + k * ctx->time.dt;
-        LAMCHK(set_step(ctx, tk));
+        LAMCHK(set_step(ctx, tk, 0));
         if (n0_slot < 0)
             HIPCHK(launch_init_forward(ctx->nt, L.g.P, reinterpret_cast<const double2*>(src), L.d_c, L.d_lam,
                                        L.d_bs, ctx->st));
         ctx->adjoint = 0;
         ctx->have_state = 1;
-        // When neither this step nor the next sees a field, nothing changes
-        // between them but the state, and the next step's start is queued
-        // ahead of each wait for this step's norms.
-        const bool ahead =
-            k + 1 < n_steps && !ctx->field_on && field_free(ctx, t0 + (k + 1) * ctx->time.dt) && alloc_next(ctx);
+        ctx->state_t0 = tk;
+        // The next step's start (its initial state and N0, with its field) is
+        // queued ahead of each wait for this step's norms, and while the GPU works
+        // the host builds the next step's time factor records.
+        double Wn[kMaxNT * kMaxNT];
+        const double tn = t0 + (k + 1) * ctx->time.dt;
+        const bool has_next = k + 1 < n_steps;
+        const bool next_field = has_next && step_field(ctx, tn, Wn);
+        if (next_field) {
+            ctx->prep_t = tn;
+            ctx->prep_dir = 0;
+        }
+        const bool ahead = has_next && alloc_next(ctx);
         const int next_slot = ctx->solver.max_cycles + 1 + (k & 1);
         bool ready = false;
         lam_stats st{};
-        rc = solve_loop(ctx, &st, n0_slot, ahead ? reinterpret_cast<double2*>(psi_out) : nullptr, next_slot, &ready);
+        rc = solve_loop(ctx, &st, n0_slot, ahead ? reinterpret_cast<double2*>(psi_out) : nullptr, next_slot, &ready,
+                        next_field ? Wn : nullptr);
+        ctx->prep_t = NAN;
         if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
         n0_slot = -1;
         if (ready) {
@@ -1143,19 +1346,27 @@ int lam_adjoint_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, const lam_c
     const auto t_a = std::chrono::steady_clock::now();
     ctx->t_factor_ms = 0.0;
     const int sw0 = ctx->sweeps_fine;
-    LAMCHK(set_step(ctx, t0));
+    LAMCHK(set_step(ctx, t0, 0));
     Level& L = ctx->lv[0];
     const int nt = ctx->nt;
     const size_t P = L.g.P;
-    // 1. recompute the forward solution of this step from its checkpoint
+    // 1. recompute the forward solution of this step from its checkpoint (the host
+    //    builds the adjoint time factor records meanwhile)
     HIPCHK(launch_init_forward(nt, (int)P, reinterpret_cast<const double2*>(psi_in), L.d_c, L.d_lam, L.d_bs,
                                ctx->st));
     ctx->adjoint = 0;
     ctx->have_state = 1;
+    ctx->state_t0 = t0;
+    if (ctx->field_on) {
+        ctx->prep_t = t0;
+        ctx->prep_dir = 1;
+    }
     int rc = solve_loop(ctx, nullptr);
+    ctx->prep_t = NAN;
     if (rc != LAM_OK) return rc;
     HIPCHK(launch_copy_c2(L.d_c, ctx->d_cf, P * nt, ctx->st));
     // 2. adjoint solve K^H mu = E^H g_out from mu = 0
+    LAMCHK(set_step(ctx, t0, 1));
     HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(g_out), ctx->d_g, P, ctx->st));
     HIPCHK(launch_init_zero(nt, (int)P, L.d_c, L.d_lam, ctx->st));
     ctx->adjoint = 1;
@@ -1226,6 +1437,20 @@ int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, dou
     HIPCHK(hipStreamSynchronize(ctx->st));
     HIPCHK(hipMemcpy(vecs, L.d_V + block * B * B, sizeof(double) * B * B, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(vals, L.d_e + block * B, sizeof(double) * B, hipMemcpyDeviceToHost));
+    return LAM_OK;
+}
+
+int lam_pass_stats(lam_ctx* ctx, int level, long long* hist) {
+    if (!ctx || !hist || level < 0 || level >= ctx->L) return LAM_EINVAL;
+    const Level& L = ctx->lv[level];
+    std::vector<unsigned char> h((size_t)L.nblocks);
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    HIPCHK(hipMemcpy(h.data(), L.d_passes, h.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < LAM_MAX_INNER + 2; ++k) hist[k] = 0;
+    for (const unsigned char v : h) {
+        hist[std::min(v & 0x7f, LAM_MAX_INNER)]++;
+        if (v & 0x80) hist[LAM_MAX_INNER + 1]++;
+    }
     return LAM_OK;
 }
 

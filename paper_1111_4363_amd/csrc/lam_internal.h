@@ -57,14 +57,26 @@ struct SweepArgs {
     const double2* bs;        // constraint right-hand side [P], may be null (= 0)
     const void* V;            // [nblocks][bpts][bpts] eigenvectors (double or float)
     const void* Minv;         // [nblocks][NT+1][NT+1][bpts] mode inverses (double2 or float2), or null:
-    const void* tf;           // shared time factor: real forms of E1, E3 (forward), E1, E3 (adjoint),
-                              // then lam of each direction
+    const void* tf;           // time factor records of this level and direction (double or float),
+                              // one per slab of blocks along the field axis (layout below)
+    int tf_stride;            // reals from one slab's record to the next; 0: one record for all
+    int pad2_;
     const double* e;          // [nblocks][bpts] eigenvalues of the block operators
-    const double* shift;      // [nblocks] frozen-field eigenvalue shift
+    unsigned char* passes;    // [nblocks] inner passes of each block's last solve (bit 7: its
+                              // local system was left unsolved); may be null
     int adjoint;
     int n_inner;
     int field_on;             // W (the field's time matrix) is nonzero this step
 };
+
+// A time factor record (reals of the factor's precision): the real forms
+// (2 n_t x 2 n_t, acting on interleaved re/im) of E1 and E3, then lam (n_t
+// complex), then the dipole coordinate zf the factor was built for, then one
+// pad entry.  See time_factor() in lam_api.hip.
+constexpr int tf_record_reals(int nt) { return 8 * nt * nt + 2 * nt; }   // E1, E3, lam
+constexpr int tf_record_stride(int nt) { return tf_record_reals(nt) + 2; } // + zf + pad
+
+constexpr int kMaxInner = 32;   // most inner passes of one subvolume solve
 
 // Workgroups (and norm partials) of a residual launch over P points.
 inline int residual_blocks(int nt, int P) {
@@ -101,8 +113,11 @@ hipError_t launch_average_potential(const LevelGeom& fine, const LevelGeom& coar
 hipError_t launch_block_eig(const LevelGeom& g, const double* v0, double* V, double* e, float* Vf,
                             hipStream_t st);
 
-hipError_t launch_mode_factor(int nt, int nblocks, int bpts, const double* U, const double* e,
-                              const double* shift, double2* Minv, float2* Minvf, hipStream_t st);
+// Per-mode inverses of the full time systems of every block of a level, with
+// the field's time matrix W taken at the zf of each block's slab record in tf
+// (FP64 records, stride tf_stride; tf null or W null: no field).
+hipError_t launch_mode_factor(int nt, const LevelGeom& g, const double* U, const double* W, const double* e,
+                              const double* tf, int tf_stride, double2* Minv, float2* Minvf, hipStream_t st);
 
 hipError_t launch_sweep(int nt, int mixed, const SweepArgs& a, const double* U, const double* W,
                         int nblocks_colour, hipStream_t st);
@@ -115,10 +130,12 @@ hipError_t launch_init_zero(int nt, int P, double2* c, double2* lam, hipStream_t
 hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStream_t st);
 
 // psi = end state of c; (cn, lamn, bsn) = the next step's initial state from
-// psi; partial = per-workgroup partials of that state's N0 for a step without
-// field (u0 = U_00; *nparts of them, residual_blocks(nt, P)).
-hipError_t launch_advance(int nt, const LevelGeom& g, double u0, const double2* c, const double* v0, double2* psi,
-                          double2* cn, double2* lamn, double2* bsn, double* partial, int* nparts, hipStream_t st);
+// psi; partial = per-workgroup partials of that state's N0 (U, W: the time
+// operators of the next step, W null without field; *nparts of them,
+// residual_blocks(nt, P)).
+hipError_t launch_advance(int nt, const LevelGeom& g, const double* U, const double* W, const double2* c,
+                          const double* v0, double2* psi, double2* cn, double2* lamn, double2* bsn,
+                          double* partial, int* nparts, hipStream_t st);
 
 hipError_t launch_copy_c2(const double2* src, double2* dst, size_t n, hipStream_t st);
 

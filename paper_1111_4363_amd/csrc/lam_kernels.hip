@@ -4,9 +4,11 @@
 // c[j][n] (interleaved re/im), one complex multiplier lam[j], one real V0[j].
 // Grid points are in C order over the axes.  Per subvolume ("block"): the
 // eigenvectors of its real symmetric spatial operator [point][mode] (FP64, and
-// an FP32 copy for the mixed path), its eigenvalues and a frozen-field shift.
-// One time factor shared by all blocks (the eigenbasis form of the n_t x n_t
-// time system left once each point's continuity row has eliminated dc_0).
+// an FP32 copy for the mixed path) and its eigenvalues.  Time factors (the
+// eigenbasis form of the n_t x n_t time system left once each point's
+// continuity row has eliminated dc_0): one record shared by all blocks for a
+// step without field, and with a field one per slab of blocks along the field
+// axis, built with the field's time matrix at the slab's centre coordinate.
 // Optionally, per mode, the inverse of the full (n_t+1) x (n_t+1) system,
 // stored [block][row][col][mode] so that one wave reads 64 modes of one entry
 // as a contiguous segment.
@@ -742,27 +744,31 @@ __global__ __launch_bounds__(kSweepThreads) void k_block_eig(LevelGeom g, const 
 
 // ---------------------------------------------------------------------------
 // K2b: per block and mode, invert the time system of eigenvalue e,
-//   M(e) = [[ iQ^T - e U, s ], [ s^T, 0 ]],  s_n = (-1)^n,
+//   M(e) = [[ iQ^T - e U - zf W, s ], [ s^T, 0 ]],  s_n = (-1)^n,
+// (zf: the dipole coordinate of the block's slab record; W = 0 without field)
 // by in-place Gauss-Jordan with partial pivoting.  One thread per mode; the
 // matrix lives in LDS, interleaved across the 64 threads of the workgroup.
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(64) void k_mode_factor(int b, TimeOps<NT> to, const double* __restrict__ e,
-                                                    const double* __restrict__ shift,
+__global__ __launch_bounds__(64) void k_mode_factor(LevelGeom g, TimeOps<NT> to, const double* __restrict__ e,
+                                                    const double* __restrict__ tf, int tf_stride,
                                                     double2* __restrict__ Minv, float2* __restrict__ Minvf) {
     constexpr int NQ = NT + 1;
     __shared__ double2 M[NQ * NQ * 64];
     const int blk = blockIdx.x;
     const int k = threadIdx.x;
+    const int b = g.bpts;
     if (k >= b) return;
-    const double ev = e[(size_t)blk * b + k] + (shift ? shift[blk] : 0.0);
+    const double ev = e[(size_t)blk * b + k];
+    const double zf = tf ? tf[(size_t)comp(block_coords(g, blk), g.fax) * tf_stride + tf_record_reals(NT)] : 0.0;
 #define MAT(r, cc) M[((r) * NQ + (cc)) * 64 + k]
     for (int m = 0; m < NQ; ++m)
         for (int n = 0; n < NQ; ++n) {
             double2 v = make_double2(0.0, 0.0);
             if (m < NT && n < NT) {
                 if (n > m && ((n - m) & 1)) v.y = 2.0;  // i Q_nm
-                if (m == n) v.x = -ev * to.U[m];
+                v.x = -zf * to.W[m * NT + n];
+                if (m == n) v.x -= ev * to.U[m];
             } else if (m < NT && n == NT) {
                 v.x = (m & 1) ? -1.0 : 1.0;
             } else if (m == NT && n < NT) {
@@ -1000,7 +1006,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     // mode (dlam, dc_1 .. dc_{NT-1}), so the eigenbasis transforms take NC = 2 NT
     // real columns; the stored inverses act on all NQ components
     constexpr int NC = STORED ? N2 : 2 * NT;
-    constexpr int TFR = 8 * NT * NT + 2 * NT;                // reals of the two mixing matrices and lam
+    constexpr int TFR = tf_record_reals(NT);                 // reals of the two mixing matrices and lam
     constexpr int TPT = (TFR + kSweepThreads - 1) / kSweepThreads;
     using C = cx<BT>;
     __shared__ BT Vs[kMaxB * kLdsPad];
@@ -1059,9 +1065,13 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-10;
     double rprev = 0.0;
 
-    // ---- 1. the block's eigenvectors and the shared time factor first: they depend on
-    //      the block id only, so their loads overlap the index arithmetic below ----
-    const double shift = a.shift[blk];   // frozen-field eigenvalue shift of this block
+    // ---- 1. the block's eigenvectors and time factor record first: they depend on
+    //      the block id only, so their loads overlap the index arithmetic below.  The
+    //      record is its slab's (blocks along the field axis share one): the factor of
+    //      the block system with the field's time matrix taken at the dipole
+    //      coordinate zf of the record ----
+    const BT* tfg = static_cast<const BT*>(a.tf) + (size_t)comp(bc, g.fax) * a.tf_stride;
+    const double zf = (double)tfg[TFR];
     const int iw = tid - NT;
     const double tov = tid < NT ? to.U[tid] : to.W[(iw >= 0 && iw < NT * NT) ? iw : 0];
     BT vr[VPT];
@@ -1077,18 +1087,12 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     BT tr[TPT];
     BT ep = (BT)0;
     if constexpr (shared_tf) {
-        const BT* tfg = static_cast<const BT*>(a.tf);
-        // the mixing pair of this direction (the adjoint pair follows the forward one),
-        // then its lam (after both pairs, forward first)
-        const int off_mix = a.adjoint ? 8 * NT * NT : 0;
-        const int off_lam = 16 * NT * NT + (a.adjoint ? 2 * NT : 0) - 8 * NT * NT;
 #pragma unroll
         for (int r = 0; r < TPT; ++r) {
             const int t = tid + r * kSweepThreads;
-            const int tt = t < TFR ? t : TFR - 1;
-            tr[r] = tfg[tt < 8 * NT * NT ? off_mix + tt : off_lam + tt];
+            tr[r] = tfg[t < TFR ? t : TFR - 1];
         }
-        ep = (BT)(a.e[(size_t)blk * b + (tid < b ? tid : 0)] + shift);
+        ep = (BT)a.e[(size_t)blk * b + (tid < b ? tid : 0)];
     }
 
     // ---- 1a. addresses (no loads yet); thread = residual item (point l, component m):
@@ -1226,10 +1230,11 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             rs[l * NQ + NT] = C{(BT)sgl.x, (BT)sgl.y};
         }
         if constexpr (shared_tf) {
-            // right-hand side of the reduced system (dc_0 eliminated): rho - sigma K(e) e_0,
-            // i.e. + U_0 (A sigma) on component 0 (A: the block operator with the
-            // frozen-field shift, whose eigenvalues are e; sigma of the in-block
-            // neighbours from sgs) and, adjoint, + 2 i sigma on odd components
+            // right-hand side of the reduced system (dc_0 eliminated): rho - sigma K(e) e_0
+            // with K(e) = (time coupling) - e U - zf W, i.e. + U_0 (A sigma) on component 0
+            // (A: the block operator, whose eigenvalues are e; sigma of the in-block
+            // neighbours from sgs), + zf W_m0 sigma on every component and, adjoint,
+            // + 2 i sigma on odd components
             double2 r = rho;
             const double2 sg = sgs[l];
             if (m == 0) {
@@ -1239,9 +1244,10 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                     const int ln = code_nb(g, lcode, l, dir);
                     lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, sgs[ln >= 0 ? ln : l]));
                 }
-                const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l] + shift, sg));
+                const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l], sg));
                 r = add2(r, scl2(tos[0], asg));
             }
+            if (a.field_on) r = add2(r, scl2(zf * tos[NT + m * NT], sg));
             if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
             xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
         }
@@ -1349,12 +1355,15 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                 a.c[(size_t)gj_it * NT + m] = add2(cs[l * NT + m], make_double2((double)dv.r, (double)dv.i));
                 if (m == 0) a.lam[gj_it] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
             }
+            // the cap was reached: with a field the last correction is left unchecked
+            if (a.passes && tid == 0)
+                a.passes[blk] = (unsigned char)(pass | ((a.n_inner > 0 && a.field_on) ? 0x80 : 0));
             break;
         }
         // inner pass: keep the state in LDS.  The correction solved the block system
-        // with the frozen field exactly, so the new local residual r - K_bb delta is
-        // the field's defect on this point alone:
-        //   row (l, m):  z_l (W delta_l)_m - shift U_m delta_lm,   constraint row: 0
+        // with the field taken at zf exactly, so the new local residual r - K_bb delta
+        // is the rest of the field's term on this point alone:
+        //   row (l, m):  (z_l - zf) (W delta_l)_m,   constraint row: 0
         // (written in place: no neighbour's correction is needed).  The reduced
         // right-hand side of the next pass is that residual itself (sigma = 0).
         if (item) {
@@ -1375,7 +1384,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
 #pragma unroll 1
                 for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tos[NT + m * NT + n], rh[l * NQ + n]);
             }
-            const C rn = rmul((BT)zs[l], wd) - rmul((BT)(shift * tos[m]), dv);
+            const C rn = rmul((BT)(zs[l] - zf), wd);
             rs[l * NQ + m] = rn;
             if (m == 0) rs[l * NQ + NT] = C{0, 0};
             if constexpr (shared_tf) xb[l * NQ + m] = rn;
@@ -1387,10 +1396,12 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             if (tid == 0) rnorm_sh = tot;
             __syncthreads();
             const double rn = rnorm_sh;
-            const bool done = rn <= inner_tol2 * r0n || rn > 0.0625 * (pass > 0 ? rprev : r0n);
+            const bool solved = rn <= inner_tol2 * r0n;
+            const bool done = solved || rn > 0.0625 * (pass > 0 ? rprev : r0n);
             rprev = rn;
             __syncthreads();
             if (done) {
+                if (a.passes && tid == 0) a.passes[blk] = (unsigned char)(pass | (solved ? 0 : 0x80));
                 // ---- 5. write back (after an early stop of the passes) ----
                 for (int t = tid; t < b * NT; t += kSweepThreads) {
                     const int l = t / NT, n = t - l * NT;
@@ -1443,16 +1454,18 @@ __global__ __launch_bounds__(kThreads) void k_end_eval(int P, const double2* __r
 }
 
 // End of one step and start of the next in one pass, with the norm N0 of the
-// next step's initial state (a step without field): psi = x(t0 + dt) as in
-// k_end_eval, the next initial state from it as in k_init_forward, written to
-// a second set of buffers (c is left as it is), and per-workgroup partials of
-// N0.  For that state only the rows (j, 0) have a residual, U_0 (H psi)_j: the
-// constraint residual vanishes exactly (c_j0 = psi_j) and the time couplings
-// see zero coefficients.  H psi = sum_n H c_n by linearity, so one thread per
-// (point, component) applies the stencil to its component (coalesced, as in
-// k_residual) and the workgroup sums over the components in LDS.
+// next step's initial state: psi = x(t0 + dt) as in k_end_eval, the next
+// initial state from it as in k_init_forward, written to a second set of
+// buffers (c is left as it is), and per-workgroup partials of N0.  For that
+// state the constraint residual vanishes exactly (c_j0 = psi_j) and the time
+// couplings see zero coefficients, so row (j, m) holds U_0 (H psi)_j for m = 0
+// plus z_j W_m0 psi_j (the next step's field; zero without one).
+// H psi = sum_n H c_n by linearity, so one thread per (point, component)
+// applies the stencil to its component (coalesced, as in k_residual) and the
+// workgroup sums over the components in LDS.
 template <int NT>
-__global__ __launch_bounds__(kThreads) void k_advance(LevelGeom g, double u0, const double2* __restrict__ c,
+__global__ __launch_bounds__(kThreads) void k_advance(LevelGeom g, TimeOps<NT> to, int field_on,
+                                                      const double2* __restrict__ c,
                                                       const double* __restrict__ v0, double2* __restrict__ psi,
                                                       double2* __restrict__ cn, double2* __restrict__ lamn,
                                                       double2* __restrict__ bsn, double* __restrict__ partial) {
@@ -1497,13 +1510,14 @@ __global__ __launch_bounds__(kThreads) void k_advance(LevelGeom g, double u0, co
             hp = add2(hp, hs[lp * NT + n]);
         }
         cn[(size_t)j * NT + m] = m == 0 ? ps : make_double2(0.0, 0.0);
+        double2 r = scl2(field_on ? zcoord(g, i) * to.W[m * NT] : 0.0, ps);
         if (m == 0) {
             psi[j] = ps;
             lamn[j] = make_double2(0.0, 0.0);
             bsn[j] = ps;
-            const double2 r = scl2(u0, hp);
-            acc = u0 * (r.x * r.x + r.y * r.y);
+            r = add2(scl2(to.U[0], hp), r);
         }
+        acc = to.U[m] * (r.x * r.x + r.y * r.y);
     }
     const double tot = block_sum(acc, red);
     if (t == 0) partial[blockIdx.x] = tot;
@@ -1652,10 +1666,11 @@ hipError_t launch_block_eig(const LevelGeom& g, const double* v0, double* V, dou
     return hipGetLastError();
 }
 
-hipError_t launch_mode_factor(int nt, int nblocks, int bpts, const double* U, const double* e, const double* shift,
-                              double2* Minv, float2* Minvf, hipStream_t st) {
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_mode_factor<NT>, dim3(nblocks), dim3(64), 0, st, bpts,
-                                           make_ops<NT>(U, nullptr), e, shift, Minv, Minvf));
+hipError_t launch_mode_factor(int nt, const LevelGeom& g, const double* U, const double* W, const double* e,
+                              const double* tf, int tf_stride, double2* Minv, float2* Minvf, hipStream_t st) {
+    const int nblocks = g.nblk[0] * g.nblk[1] * g.nblk[2];
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_mode_factor<NT>, dim3(nblocks), dim3(64), 0, st, g,
+                                           make_ops<NT>(U, W), e, tf, tf_stride, Minv, Minvf));
     return hipGetLastError();
 }
 
@@ -1693,12 +1708,13 @@ hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_advance(int nt, const LevelGeom& g, double u0, const double2* c, const double* v0, double2* psi,
-                          double2* cn, double2* lamn, double2* bsn, double* partial, int* nparts, hipStream_t st) {
+hipError_t launch_advance(int nt, const LevelGeom& g, const double* U, const double* W, const double2* c,
+                          const double* v0, double2* psi, double2* cn, double2* lamn, double2* bsn,
+                          double* partial, int* nparts, hipStream_t st) {
     const int nb = residual_blocks(nt, g.P);
     if (nparts) *nparts = nb;
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_advance<NT>, dim3(nb), dim3(kThreads), 0, st, g, u0, c, v0, psi, cn,
-                                           lamn, bsn, partial));
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_advance<NT>, dim3(nb), dim3(kThreads), 0, st, g, make_ops<NT>(U, W),
+                                           W ? 1 : 0, c, v0, psi, cn, lamn, bsn, partial));
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "liblam.so")
 LAM_OK, LAM_EINVAL, LAM_ENOMEM, LAM_EHIP, LAM_ENOCONV, LAM_EDIVERGED, LAM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 LAM_MAX_NT = 8
 LAM_MAX_BLOCK = 64
+LAM_MAX_INNER = 32
 PULSE = {"none": 0, "sin2": 1, "fourier": 2, "sin2+fourier": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 INTERP = {"linear": 0, "constant": 1}
@@ -98,6 +99,7 @@ SIGNATURES = {
     "lam_prolong_add": (_I, [_P, _I, _P, _P, _P, _P]),
     "lam_level_shape": (_I, [_P, _I, _PI]),
     "lam_block_factor": (_I, [_P, _I, _I, _PD, _PD]),
+    "lam_pass_stats": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
     "lam_profile": (_I, [_P, _I]),
     "lam_profile_read": (_I, [_P, _PI, _PD]),
     "lam_strerror": (ctypes.c_char_p, [_I]),
@@ -206,6 +208,9 @@ class Propagator:
         s = LamSolver(PRECISION[precision], float(tol), int(max_cycles), int(n_inner), TIME_FACTOR[time_factor])
         self.levels = int(levels)
         self.precision = precision
+        # what the context holds (the autograd function restores its own inputs)
+        self._v0_held = v0.detach().clone()
+        self._coef_held = list(coef)
         h_ctx = ctypes.c_void_p()
         _check(lib.lam_create(ctypes.byref(g), ctypes.byref(t), ctypes.byref(ham), ctypes.byref(s),
                               _stream_handle(self.stream), ctypes.byref(h_ctx)), "lam_create")
@@ -233,11 +238,23 @@ class Propagator:
         coef = [float(a) for a in coef]
         arr = (ctypes.c_double * max(1, len(coef)))(*coef)
         _check(self._lib.lam_set_pulse(self._ctx, len(coef), arr), "lam_set_pulse")
+        self._coef_held = coef
 
     def set_potential(self, v0):
         v0 = v0.contiguous()
         _check(self._lib.lam_set_potential(self._ctx, _ptr(v0, torch.float64, self.npts, "v0")),
                "lam_set_potential")
+        self._v0_held = v0.detach().clone()
+
+    def hold(self, v0, coef):
+        """Make the context hold potential v0 and pulse amplitudes coef, calling
+        lam_set_potential / lam_set_pulse only for what differs from what it holds."""
+        v0 = v0.detach().contiguous()
+        if v0.shape != self._v0_held.shape or not torch.equal(v0, self._v0_held):
+            self.set_potential(v0)
+        coef = [float(a) for a in coef]
+        if self.n_coef and coef != self._coef_held:
+            self.set_pulse(coef)
 
     def residual_action(self, t0, psi0, c, lam, want_fields=True):
         P, nt = self.npts, self.n_t
@@ -356,6 +373,13 @@ class Propagator:
         import numpy as np
         return np.array(vecs[:]).reshape(b, b), np.array(vals[:])
 
+    def pass_stats(self, level=0):
+        """(histogram of inner passes of the last solve of every subvolume on the level,
+        number of subvolumes left unsolved): lam_pass_stats."""
+        hist = (ctypes.c_longlong * (LAM_MAX_INNER + 2))()
+        _check(self._lib.lam_pass_stats(self._ctx, int(level), hist), "lam_pass_stats")
+        return [int(hist[k]) for k in range(LAM_MAX_INNER + 1)], int(hist[LAM_MAX_INNER + 1])
+
     def profile(self, enable):
         _check(self._lib.lam_profile(self._ctx, int(enable)), "lam_profile")
 
@@ -403,9 +427,9 @@ class LeastActionPropagate(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, psi0, v0, coef, prop, n_steps, t_start):
-        prop.set_potential(v0.detach().contiguous())
-        if prop.n_coef:
-            prop.set_pulse(coef.detach().cpu().tolist())
+        ctx.v0 = v0.detach().contiguous().clone()
+        ctx.coef = [float(a) for a in coef.detach().cpu().tolist()] if prop.n_coef else []
+        prop.hold(ctx.v0, ctx.coef)
         psis, _ = prop.propagate(psi0.detach().contiguous(), int(n_steps), float(t_start), keep=True)
         ctx.prop = prop
         ctx.n_steps = int(n_steps)
@@ -417,6 +441,9 @@ class LeastActionPropagate(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         prop = ctx.prop
+        # the system this forward solved: another forward on the same Propagator
+        # since then may have replaced the potential or the pulse
+        prop.hold(ctx.v0, ctx.coef)
         # torch passes 2 dL/dpsi^*; the library works with dL/dpsi^*
         g = (0.5 * grad_out).contiguous()
         dv0 = torch.zeros(prop.npts, dtype=torch.float64, device=prop.device)
