@@ -1,18 +1,22 @@
 """Benchmark of the least-action relaxation path on one MI355X.
 
-Workload: the 2D soft-Coulomb problem, 512 x 512 points, h = 0.2,
-V = -1/sqrt(r^2 + 1), N_t = 8 Legendre time functions, dt = 0.05, 8 x 8
-subvolumes, 5-level V(1,1) cycles, random-phase Gaussian initial state
-(seed 0), steps solved to sqrt(N/N0) <= 1e-10.  A "step" is one propagation
-time step: every kernel of the path (residual, colour sweeps on all levels,
-projection, interpolation, coarse sweeps, step I/O) until the tolerance.
+Headline workload (the largest single-GPU configuration): 3d_large, a 3D
+256^3 grid, h = 0.25, soft-Coulomb V0 = -1/sqrt(r^2 + 1) plus a dipole field
+E(t) = 0.1 sin^2(pi t/T) cos(0.057 t) + 32 Fourier sine amplitudes
+(N(0, 0.02^2), seed 0), N_t = 8 Legendre time functions, dt = 0.05, 4^3
+subvolumes, 6-level V(1,1) cycles, Gaussian initial state, steps solved to
+sqrt(N/N0) <= 1e-10.  A "step" is one propagation time step: every kernel of
+the path (residual, colour sweeps on all levels, projection, interpolation,
+coarse sweeps, step I/O) until the tolerance, inputs resident in HBM.
 
 value: finest-level Munknowns*sweeps/s = P * N_t * (finest full sweeps done
-in the timed steps) / (wall time of the timed steps) / 1e6, FP64 path.
-The mixed path (FP32 subvolume solves) is reported next to it, with the
-time to reach the 1e-10 residual per step for both.
+in the timed steps) / (wall time of the timed steps) / 1e6, on the mixed path
+(FP32 subvolume solves, FP64 state, residual, transfers and coarsest level),
+which is what the workload names.  The FP64 path is reported next to it, with
+the time to reach the 1e-10 residual per step for both, the adjoint step, and
+the 2D soft-Coulomb 512^2 workload as an extra block.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512] [--levels 5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 import argparse
 import hashlib
@@ -28,17 +32,21 @@ METRIC = "Munknowns·sweeps/s + time-to-action-residual 1e-10 (FP64 vs mixed) pe
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1111_4363_amd", "csrc", "lam_kernels.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "sweep_counters.json")
+HEADLINE = "3d_large"
 
 
 def sweep_launch_bytes(shape, block, n_t, colour, precision):
     """Algorithmic HBM bytes of one finest-level colour launch (forward step).
 
     Per block of b points: its eigenvectors, b^2 reals (8 B FP64, 4 B mixed),
-    its b eigenvalues (FP64) and frozen-field shift (8 B), its id (4 B).  Per
-    own point: read c (N_t complex FP64), lambda, the constraint right-hand
-    side (complex) and V0 (real); write c and lambda.  Per distinct halo point
-    of the launch: read c (N_t complex).  The shared time factor (3 (N_t+1)^2
-    complex, under 4 KB) is read once per launch and not counted.
+    its b eigenvalues (FP64), its id (4 B, only when the colour's blocks come
+    from a table: an odd block count along the last axis) and its inner-pass
+    count (1 B written).  Per own point: read c (N_t complex FP64), lambda,
+    the constraint right-hand side (complex) and V0 (real); write c and
+    lambda.  Per distinct halo point of the launch: read c (N_t complex).
+    The time factor records (one per slab of blocks along the field axis, or
+    one for the whole launch; a few hundred KB at most) are read once per
+    launch and not counted.
     """
     import numpy as np
     nblk = [s // b for s, b in zip(shape, block)]
@@ -46,15 +54,17 @@ def sweep_launch_bytes(shape, block, n_t, colour, precision):
     rb = 8 if precision == "fp64" else 4
     coords = np.indices(nblk).reshape(len(nblk), -1).T
     ncol = int(np.sum(coords.sum(axis=1) % 2 == colour))
-    per_block = b * b * rb + b * 8 + 8 + 4
+    per_block = b * b * rb + b * 8 + (4 if nblk[-1] % 2 else 0) + 1
     per_point = (n_t * 16 + 16 + 16 + 8) + (n_t * 16 + 16)
     # distinct halo points: points outside a colour block, face-adjacent to one
     owner_colour = np.zeros(shape, dtype=np.int8)
-    idx = np.indices(shape)
+    idx = np.indices(shape, dtype=np.int16)
     for a in range(len(shape)):
         owner_colour += (idx[a] // block[a]).astype(np.int8)
+    del idx
     owner_colour %= 2
     inside = owner_colour == colour
+    del owner_colour
     halo = np.zeros(shape, bool)
     for a in range(len(shape)):
         for d in (-1, 1):
@@ -68,8 +78,9 @@ def sweep_launch_bytes(shape, block, n_t, colour, precision):
     return ncol * (per_block + b * per_point) + nhalo * n_t * 16, ncol
 
 
-def counters_for_current_kernel():
-    """Traffic per launch from committed rocprofv3 counters, if taken on this kernel source."""
+def counters_for_current_kernel(key):
+    """Traffic per launch from committed rocprofv3 counters (entry `key`, e.g.
+    "3d_large/mixed"), if they were taken on this kernel source."""
     if not os.path.exists(COUNTERS):
         return None
     try:
@@ -79,30 +90,56 @@ def counters_for_current_kernel():
             digest = hashlib.sha256(f.read()).hexdigest()
         if rec.get("kernel_source_sha256") != digest:
             return None
-        return rec.get("traffic_bytes_per_launch")
+        ent = rec.get("entries", {}).get(key)
+        return ent.get("traffic_bytes_per_launch") if ent else None
     except Exception:
         return None
 
 
-def cpu_baseline(budget_s=20.0):
-    """The oracle's plain-loop colour sweeps on a 64 x 64 window of the workload."""
-    import numpy as np
+def threads_in_use():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def field_of(cfg):
+    """The workload's field E(t) as a host function for the oracle (None without)."""
+    import workloads as W
+    from oracle import timebasis as tb
+    p = cfg["pulse"]
+    if not p:
+        return None
+    parts = []
+    if p["kind"] in ("sin2", "sin2+fourier"):
+        parts.append(tb.pulse_sin2_cos(p["e0"], p["omega"], cfg["t_total"]))
+    if p["kind"] in ("fourier", "sin2+fourier"):
+        parts.append(tb.pulse_fourier_sine(list(W.pulse_coefficients(cfg)), cfg["t_total"]))
+    return parts[0] if len(parts) == 1 else (lambda t: parts[0](t) + parts[1](t))
+
+
+def cpu_baseline(name, budget_s=15.0):
+    """The oracle, untuned, on a window of the workload: plain-loop colour sweeps
+    (dense local solves of its subvolumes) on a 16^3 (3D) or 64^2 (2D) window,
+    and its direct step solve on an 8^3 (3D) or 32^2 (2D) window, median of 3."""
+    import numpy as np
     import workloads as W
     from oracle import grid as G
     from oracle import kkt, relax
-    cfg = W.config("2d_softcoulomb", n=64)
+    threads = threads_in_use()
+    full = W.config(name)
+    field = field_of(full)
+    t0 = 0.35 * full["t_total"]
+    win = 16 if full["dim"] == 3 else 64
+    cfg = W.config(name, n=win)
     v0 = W.potential(cfg)
     psi0 = W.initial_state(cfg, v0)
     g = G.Grid(cfg["shape"], cfg["h"])
-    sysm = kkt.StepSystem(g, v0, cfg["n_t"], cfg["dt"])
+    sysm = kkt.StepSystem(g, v0, cfg["n_t"], cfg["dt"], t0, field)
     b = kkt.rhs(sysm, psi0)
     x = kkt.initial_guess(sysm, psi0)
-    bl = G.blocks(g, (cfg["block"],) * 2)
+    bl = G.blocks(g, (cfg["block"],) * cfg["dim"])
     sweeps = 0
     t_a = time.perf_counter()
     while True:
@@ -112,9 +149,29 @@ def cpu_baseline(budget_s=20.0):
             break
     dt = time.perf_counter() - t_a
     value = g.npts * cfg["n_t"] * sweeps / dt / 1e6
+    # direct solve of one step (assembly + factorisation + solve) on a smaller window
+    dwin = 8 if full["dim"] == 3 else 32
+    dcfg = W.config(name, n=dwin)
+    dv0 = W.potential(dcfg)
+    dpsi = W.initial_state(dcfg, dv0)
+    dg = G.Grid(dcfg["shape"], dcfg["h"])
+    times = []
+    for _ in range(3):
+        t_b = time.perf_counter()
+        kkt.step(dg, dv0, dpsi, dcfg["n_t"], dcfg["dt"], t0, field)
+        times.append(time.perf_counter() - t_b)
+    t_direct = float(np.median(times))
+    unknowns = dg.npts * (dcfg["n_t"] + 1)
+    shape = "x".join(str(k) for k in cfg["shape"])
+    dshape = "x".join(str(k) for k in dcfg["shape"])
     return {"value": value, "unit": "Munknowns·sweeps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sweeps} full colour sweeps (plain-loop dense local solves) of the same workload's "
-                      f"8x8 subvolumes on a 64x64 window (64 of its 4096 blocks), {dt:.1f} s"}
+            "sample": f"{sweeps} full colour sweeps (plain-loop dense local solves of the "
+                      f"{cfg['block']}^{cfg['dim']} subvolumes, field on) of the same workload on a {shape} "
+                      f"window, {dt:.1f} s",
+            "direct_step": {"window": dshape, "unknowns": unknowns, "s_per_step_median_of_3": t_direct,
+                            "munknowns_per_s": unknowns / t_direct / 1e6,
+                            "method": "assembly + dense LAPACK (<= 6000 unknowns) or SuperLU solve of the "
+                                      "step system, the oracle's kkt.step"}}
 
 
 def pulse_of(cfg):
@@ -127,7 +184,7 @@ def pulse_of(cfg):
                 coef=list(W.pulse_coefficients(cfg)))
 
 
-def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
+def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam, adjoint_steps=0):
     shape = cfg["shape"]
     torch.cuda.synchronize()
     t_f = time.perf_counter()
@@ -138,14 +195,15 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
                           tol=args.tol, max_cycles=60, pulse=pulse_of(cfg))
     torch.cuda.synchronize()
     factor_ms = (time.perf_counter() - t_f) * 1e3
-    psi = psi0_t.clone()
+    # warm-up steps from the start of the pulse, then the timed steps again from the initial
+    # state at t = 0: the timed region is the workload's own steps (with a field, its pulse)
     t = 0.0
     if args.warmup:
-        psi, _ = prop.propagate(psi, args.warmup, t_start=t)
-        t += args.warmup * cfg["dt"]
+        prop.propagate(psi0_t.clone(), args.warmup, t_start=t)
+    psi = psi0_t.clone()
     torch.cuda.synchronize()
     # HIP events around every 8th finest-level sweep launch of the timed steps (a sample: each
-    # event record costs stream time, so recording all 16 launches of a step would slow it ~5%)
+    # event record costs stream time)
     prop.profile(8)
     torch.cuda.synchronize()
     # the timed steps run back to back inside one lam_propagate call
@@ -156,6 +214,11 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
     st = stl[0]
     launches, sweep_ms = prop.profile_read()
     prop.profile(0)
+    # inner passes per subvolume: one more step solved at mid-pulse, outside the timed region
+    # (the statistics describe each subvolume's last solve)
+    prop.solve_step(0.5 * cfg["t_total"], psi0_t)
+    hist, unsolved = prop.pass_stats(0)
+    nblk = sum(hist)
     sweeps = st["sweeps_fine"]
     P = 1
     for s in shape:
@@ -163,8 +226,7 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
     value = P * cfg["n_t"] * sweeps / elapsed / 1e6
     kernel_rate = P * cfg["n_t"] * 0.5 / (sweep_ms / launches / 1e3) / 1e6 if sweep_ms > 0 else None
     norm = float(torch.sum(torch.abs(psi) ** 2).item()) * cfg["h"] ** cfg["dim"]
-    prop.close()
-    return {
+    out = {
         "value": value,
         "ms_per_step": elapsed / args.steps * 1e3,
         "time_to_residual_ms": st["t_solve_ms"] / args.steps,
@@ -174,9 +236,27 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam):
         "sweep_launches": launches,
         "sweep_kernel_ms_avg": sweep_ms / launches if launches else None,
         "sweep_kernel_munk_sweeps_per_s": kernel_rate,
+        "inner_passes_finest_mean": (sum(k * c for k, c in enumerate(hist)) / nblk) if nblk else 0.0,
+        "inner_passes_finest_max": max([k for k, c in enumerate(hist) if c] + [0]),
+        "subvolumes_unsolved_finest": unsolved,
         "norm_after": norm,
         "factor_ms": factor_ms,
     }
+    if adjoint_steps:
+        # backward steps of a loss of the final state (lam_adjoint_step: the step's forward
+        # solve recomputed from its checkpoint, then the adjoint solve and the gradients)
+        g = (psi / torch.sqrt(torch.sum(torch.abs(psi) ** 2))).contiguous()
+        dv0 = torch.zeros(P, dtype=torch.float64, device=psi.device)
+        dcoef = [0.0] * prop.n_coef
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        for k in range(adjoint_steps):
+            t_k = (args.steps - 1 - k) * cfg["dt"]
+            g, _ = prop.adjoint_step(t_k, psi, g, dv0, dcoef)
+        torch.cuda.synchronize()
+        out["adjoint_ms_per_step"] = (time.perf_counter() - t_b) / adjoint_steps * 1e3
+    prop.close()
+    return out
 
 
 def workload_string(cfg, tol):
@@ -193,17 +273,51 @@ def workload_string(cfg, tol):
             f"{blocks} subvolumes, {cfg['levels']}-level V(1,1) with {cfg['nu_coarse']} coarsest sweep(s), tol {tol:g}")
 
 
+def roofline_of(cfg, prec, r, traffic):
+    import numpy as np
+    blocks = (cfg["block"],) * cfg["dim"]
+    nb0, ncol0 = sweep_launch_bytes(cfg["shape"], blocks, cfg["n_t"], 0, prec)
+    nb1, ncol1 = sweep_launch_bytes(cfg["shape"], blocks, cfg["n_t"], 1, prec)
+    bytes_per_launch = 0.5 * (nb0 + nb1)
+    avg = r["sweep_kernel_ms_avg"]
+    achieved = bytes_per_launch / (avg * 1e-3) / 1e9 if avg else None
+    # matrix-core work issued per launch and block solve: the two block transforms (points x
+    # modes by the 2 N_t reals of the reduced block system) and the two per-mode mixes (modes x
+    # 2 N_t by 2 N_t x 2 N_t), each over 16x16 output tiles with 16x16x4 steps, once per
+    # solve (1 + the inner passes)
+    b = int(np.prod(blocks))
+    nc = 2 * cfg["n_t"]
+    tiles = -(-b // 16) * -(-nc // 16)
+    mfma_per_solve = 2 * tiles * 4 * (-(-b // 16)) + 2 * tiles * ((nc + 3) // 4)
+    solves = 1.0 + r["inner_passes_finest_mean"]
+    mfma_flops = 0.5 * (ncol0 + ncol1) * mfma_per_solve * solves * 2 * 16 * 16 * 4
+    mfma_peak = 78.6 if prec == "fp64" else 157.3
+    mfma_tf = mfma_flops / (avg * 1e-3) / 1e12 if avg else None
+    kern = f"k_sweep<{cfg['n_t']}, {'double' if prec == 'fp64' else 'float'}, false>"
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic,
+            "kernel": f"{kern} (finest level, {ncol0 + ncol1} subvolumes per full sweep)",
+            "bytes_per_launch": bytes_per_launch,
+            "mfma": {"achieved": mfma_tf, "peak": mfma_peak, "unit": "TFLOP/s",
+                     "frac": (mfma_tf / mfma_peak) if mfma_tf else None,
+                     "note": "matrix-core FLOPs issued (16x16 tiles, padding included, inner passes counted)"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="2d_softcoulomb",
-                    help="2d_softcoulomb (the headline, default), 1d_harmonic, 3d_laser, 2d_adjoint, 3d_large")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=HEADLINE,
+                    help="3d_large (the headline, default), 2d_softcoulomb, 1d_harmonic, 3d_laser, 2d_adjoint")
     ap.add_argument("--n", type=int, default=None, help="points per axis (default: the workload's)")
     ap.add_argument("--levels", type=int, default=None, help="multigrid levels (default: the workload's)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 2D soft-Coulomb extra block")
+    ap.add_argument("--adjoint-steps", type=int, default=2,
+                    help="backward steps timed on the headline precision (0: none)")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
@@ -232,49 +346,47 @@ def main():
     import workloads as W
 
     lam.load_library()
-    cfg = W.config(args.workload, n=args.n, levels=args.levels)
-    v0 = W.potential(cfg)
-    psi0 = W.initial_state(cfg, v0)
     dev = torch.device("cuda:0")
-    v0_t = torch.as_tensor(v0, dtype=torch.float64, device=dev)
-    psi0_t = torch.as_tensor(psi0, dtype=torch.complex128, device=dev)
 
-    res = {}
-    for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
-        print(f"[bench] {prec}: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
-        res[prec] = run_precision(args, prec, v0_t, psi0_t, cfg, torch, lam)
-    main_prec = "fp64" if "fp64" in res else "mixed"
+    def run_workload(name, n=None, levels=None, precisions=("fp64", "mixed"), adjoint_for=None):
+        cfg = W.config(name, n=n, levels=levels)
+        v0 = W.potential(cfg)
+        psi0 = W.initial_state(cfg, v0)
+        v0_t = torch.as_tensor(v0, dtype=torch.float64, device=dev)
+        psi0_t = torch.as_tensor(psi0, dtype=torch.complex128, device=dev)
+        res = {}
+        for prec in precisions:
+            print(f"[bench] {name} {prec}: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
+                  flush=True)
+            res[prec] = run_precision(args, prec, v0_t, psi0_t, cfg, torch, lam,
+                                      adjoint_steps=args.adjoint_steps if prec == adjoint_for else 0)
+        del v0_t, psi0_t
+        torch.cuda.empty_cache()
+        return cfg, res
+
+    precs = ("fp64", "mixed") if args.precision == "both" else (args.precision,)
+    # the headline precision: mixed for workloads that name it (a field and FP32 block solves), else FP64
+    main_prec = "mixed" if ("mixed" in precs and args.workload in ("3d_large", "3d_laser")) else precs[0]
+    if main_prec not in precs:
+        main_prec = precs[0]
+    cfg, res = run_workload(args.workload, args.n, args.levels, precs, adjoint_for=main_prec)
     r = res[main_prec]
+    full_size = args.n is None and args.levels is None
+    traffic = counters_for_current_kernel(f"{args.workload}/{main_prec}") if full_size else None
+    roofline = roofline_of(cfg, main_prec, r, traffic)
 
-    blocks = (cfg["block"],) * cfg["dim"]
-    nb0, ncol0 = sweep_launch_bytes(cfg["shape"], blocks, cfg["n_t"], 0, main_prec)
-    nb1, ncol1 = sweep_launch_bytes(cfg["shape"], blocks, cfg["n_t"], 1, main_prec)
-    bytes_per_launch = 0.5 * (nb0 + nb1)
-    achieved = bytes_per_launch / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9 if r["sweep_kernel_ms_avg"] else None
-    traffic = counters_for_current_kernel() if (args.workload == "2d_softcoulomb" and args.n is None) else None
-    # matrix-core work issued per launch: per block, the two block transforms (points x modes
-    # by the 2 N_t reals of the reduced block system) and the two per-mode mixes (modes x
-    # 2 N_t by 2 N_t x 2 N_t), each over 16x16 output tiles with 16x16x4 steps
-    b = int(np.prod(blocks))
-    nc = 2 * cfg["n_t"]
-    tiles = -(-b // 16) * -(-nc // 16)
-    mfma_per_block = 2 * tiles * 4 * (-(-b // 16)) + 2 * tiles * ((nc + 3) // 4)
-    mfma_flops = 0.5 * (ncol0 + ncol1) * mfma_per_block * 2 * 16 * 16 * 4
-    mfma_peak = 78.6 if main_prec == "fp64" else 157.3
-    mfma_tf = mfma_flops / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e12 if r["sweep_kernel_ms_avg"] else None
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": traffic,
-                "kernel": f"k_sweep<{cfg['n_t']}, {'double' if main_prec == 'fp64' else 'float'}, false> (finest level)",
-                "bytes_per_launch": bytes_per_launch,
-                "mfma": {"achieved": mfma_tf, "peak": mfma_peak, "unit": "TFLOP/s",
-                         "frac": (mfma_tf / mfma_peak) if mfma_tf else None,
-                         "note": "matrix-core FLOPs issued (16x16 tiles, padding included)"}}
+    extra = None
+    if not args.no_extra and args.workload == HEADLINE and full_size:
+        c2, r2 = run_workload("2d_softcoulomb", precisions=precs)
+        p2 = "fp64" if "fp64" in r2 else precs[0]
+        extra = {"2d_softcoulomb": {"config": workload_string(c2, args.tol), "precisions": r2,
+                                    "roofline": roofline_of(c2, p2, r2[p2],
+                                                            counters_for_current_kernel(f"2d_softcoulomb/{p2}"))}}
 
     cpu = None
-    if not args.no_cpu_baseline and args.workload == "2d_softcoulomb":
+    if not args.no_cpu_baseline and full_size:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(args.workload)
 
     out = {
         "metric": METRIC,
@@ -289,13 +401,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": workload_string(cfg, args.tol),
+        "config": {"workload": workload_string(cfg, args.tol), "precision": main_prec,
                    "grid": list(cfg["shape"]), "n_t": cfg["n_t"], "levels": cfg["levels"],
                    "unknowns_per_step": int(np.prod(cfg["shape"])) * (cfg["n_t"] + 1)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_residual_ms": {p: res[p]["time_to_residual_ms"] for p in res},
         "precisions": res,
+        "extra": extra,
     }
     print(json.dumps(out))
 
