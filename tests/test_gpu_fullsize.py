@@ -145,9 +145,69 @@ def test_fullsize_sweep_sampled_blocks(name, precision):
     prop.close()
 
 
-@pytest.mark.parametrize("name,precision", [("2d_softcoulomb", "fp64"), ("2d_softcoulomb", "mixed"),
-                                            ("3d_laser", "mixed"), ("3d_large", "mixed"),
-                                            ("1d_harmonic", "fp64")])
+ADJOINT_SWEEP_RUNS = [("2d_adjoint", "fp64"), ("2d_adjoint", "mixed"), ("3d_large", "fp64"), ("3d_large", "mixed")]
+
+
+@pytest.mark.parametrize("name,precision", ADJOINT_SWEEP_RUNS)
+def test_fullsize_adjoint_sweep_sampled_blocks(name, precision):
+    """The adjoint system K^H mu = E^H g at full size: sampled subvolumes of one
+    colour sweep against the exact local solves of K^H restricted to them (the
+    conjugate transpose of K's block), right-hand side from the oracle's adjoint
+    residual rows (FP64: 1e-11 of the correction; mixed: 1e-4); the other
+    colour's points untouched.  Also: every subvolume's local system solved."""
+    import torch
+    cfg, v0, psi0, pulse, prop, grid, dev = setup(name, precision)
+    note(f"full-size adjoint sweep {name} {precision} {cfg['shape']}")
+    nt, P = cfg["n_t"], grid.npts
+    mu_c, mu_l = W.random_state_device(P, nt, 21, dev, scale=0.1)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(22)
+    g_t = torch.randn(P, dtype=torch.complex128, device=dev, generator=gen)
+    t0 = 0.35 * cfg["t_total"]
+    prop.set_adjoint_state(t0, g_t, mu_c, mu_l)
+    block = (cfg["block"],) * cfg["dim"]
+    nblk = [s // b for s, b in zip(cfg["shape"], block)]
+    rng = np.random.default_rng(23)
+    picks = set([0, int(np.prod(nblk)) - 1])
+    while len(picks) < 8:
+        picks.add(int(rng.integers(np.prod(nblk))))
+    idx_all = np.arange(P).reshape(cfg["shape"])
+    samples = []
+    for bid in sorted(picks):
+        bc = np.unravel_index(bid, nblk)
+        sl = tuple(slice(k * b, (k + 1) * b) for k, b in zip(bc, block))
+        samples.append((int(sum(bc)) % 2, idx_all[sl].ravel()))
+    allpts = np.concatenate([p for _, p in samples])
+    nbh = neighbourhood(grid, allpts)
+    c_old, l_old, g_rows = Rows(mu_c, nt, nbh), Rows(mu_l, 1, nbh), Rows(g_t, 1, nbh)
+    prop.relax_sweep(0)
+    c_new_t, l_new_t = prop.get_state()
+    c_new, l_new = Rows(c_new_t, nt, allpts), Rows(l_new_t, 1, allpts)
+    hist, unsolved = prop.pass_stats(0)
+    assert unsolved == 0
+    field = field_fn(pulse)
+    zeros = np.zeros(P, complex)
+
+    class G1:
+        def __getitem__(self, j):
+            return g_rows[j]
+    for colour, pts in samples:
+        x_old = np.concatenate([np.array([c_old[j] for j in pts]).ravel(), np.array([l_old[j] for j in pts])])
+        x_new = np.concatenate([np.array([c_new[j] for j in pts]).ravel(), np.array([l_new[j] for j in pts])])
+        if colour == 1:
+            assert np.array_equal(x_new, x_old)
+            continue
+        r, s = kkt.residual_at_points(grid, v0, nt, cfg["dt"], t0, field, c_old, l_old, zeros, pts,
+                                      stat_rhs=G1(), adjoint=True)
+        Kbb = kkt.block_system(grid, v0, nt, cfg["dt"], t0, field, pts)
+        delta = np.linalg.solve(Kbb.conj().T, np.concatenate([r.ravel(), s]))
+        err = np.abs((x_new - x_old) - delta).max()
+        rel = 1e-11 if precision == "fp64" else 1e-4
+        assert err <= rel * np.abs(delta).max() + 64 * EPS * np.abs(x_old).max(), (name, err)
+    prop.close()
+
+
+@pytest.mark.parametrize("name,precision", [(nm, pr) for nm in NAMES for pr in ("fp64", "mixed")])
 def test_fullsize_step_converges(name, precision):
     """One step in the bench configuration: the library's FP64 residual reaches
     sqrt(N/N0) <= 1e-10, and the oracle's residual on 1000 sampled points of the
@@ -160,8 +220,15 @@ def test_fullsize_step_converges(name, precision):
     nt, P = cfg["n_t"], grid.npts
     t0 = 0.5 * cfg["t_total"]
     psi_out, st = prop.solve_step(t0, torch.as_tensor(psi0, device=dev))
-    note(f"cycles={st['cycles']} ratio={st['resid'] / st['resid0']:.2e} ms={st['t_solve_ms']:.1f}")
+    hist, unsolved = prop.pass_stats(0)
+    passes = max([k for k, c_ in enumerate(hist) if c_] + [0])
+    note(f"cycles={st['cycles']} ratio={st['resid'] / st['resid0']:.2e} ms={st['t_solve_ms']:.1f} "
+         f"finest inner passes max={passes} unsolved={unsolved}")
     assert st["resid"] <= 1e-10 * st["resid0"]
+    # every finest subvolume's local system solved; with the field's full time matrix in
+    # the slab factor, at most 3 corrections (FP64, to 1e-13) or 1 (FP32, to 1e-5)
+    assert unsolved == 0
+    assert passes <= (3 if precision == "fp64" else 1)
     c_t, l_t = prop.get_state()
     pts = np.random.default_rng(7).choice(P, size=min(P, 1000), replace=False)
     nbh = neighbourhood(grid, pts)
