@@ -59,10 +59,12 @@ extern "C" {
 #define LAM_ENOCONV    -4   /* tolerance not reached within max_cycles (outputs still written) */
 #define LAM_EDIVERGED  -5   /* residual norm non-finite or grew by more than 1e6 */
 #define LAM_ESTATE     -6   /* call needs a state that was never set (lam_set_state) */
+#define LAM_ETOOBIG    -7   /* input larger than a no-allocation call's fixed scratch */
 
 #define LAM_MAX_NT     8    /* largest number of Legendre time functions */
 #define LAM_MAX_BLOCK  64   /* largest number of grid points in one subvolume */
 #define LAM_MAX_INNER  32   /* largest n_inner (inner passes of one subvolume solve) */
+#define LAM_NOALLOC_SCRATCH_BYTES (4u << 20)  /* fixed device scratch per GPU (4 MiB) */
 
 #define LAM_PULSE_NONE          0
 #define LAM_PULSE_SIN2          1  /* E = e0 sin^2(pi t/T) cos(omega t) on [0,T] */
@@ -278,6 +280,26 @@ int lam_level_shape(const lam_ctx* ctx, int level, int* n);
  * row-major [point][mode]) and eigenvalues (host, bpts) of the real symmetric
  * spatial block operator T_U + diag(V0_U).  For tests of the block factor. */
 int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, double* vals);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the residual
+ * of lam_residual_action without a context and without any allocation or host
+ * synchronisation.  grid, time, ham: as for lam_create (validated the same way;
+ * ham->v0 is read by the kernels, so it must stay valid until the stream has
+ * run them; ham->coef is read during the call); solver settings play no part.
+ * psi0, c, lam: device inputs (P, P*n_t, P complex); rho, sigma: device outputs
+ * (may be NULL).  norm (device, one double, may be NULL) receives N, computed
+ * through a fixed device scratch array of LAM_NOALLOC_SCRATCH_BYTES per GPU
+ * holding one FP64 partial sum per group of floor(256 / n_t) points: so
+ * P <= 524288 * floor(256 / n_t) points (16,777,216 at n_t = 8); a larger grid
+ * with norm != NULL is LAM_ETOOBIG and nothing runs.  All work is queued on hip_stream (a hipStream_t
+ * of the current device; NULL = the null stream).  Every call on one GPU uses
+ * that GPU's one scratch array, and every partial it reads is written by the
+ * same call first: calls whose work overlaps on one GPU (different streams)
+ * race and must be ordered by the caller. */
+int lam_residual_action_noalloc(const lam_grid* grid, const lam_time* time, const lam_ham* ham, double t0,
+                                const lam_c64* psi0, const lam_c64* c, const lam_c64* lam, lam_c64* rho,
+                                lam_c64* sigma, double* norm, void* hip_stream);
 
 /* Inner passes of the subvolume solves on `level`: hist (host, LAM_MAX_INNER
  * + 2 entries) receives in hist[p] the number of subvolumes whose last solve

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -52,10 +53,10 @@ struct Level {
     bool fp32 = false;
 };
 
+constexpr int kGL = 48;   // Gauss-Legendre nodes of the field quadrature
+
 // Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_N.
-void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
-    x.assign(N, 0.0);
-    w.assign(N, 0.0);
+void gauss_legendre(int N, double* x, double* w) {
     for (int i = 0; i < N; ++i) {
         double z = std::cos(M_PI * (i + 0.75) / (N + 0.5));
         double dp = 1.0;
@@ -83,6 +84,16 @@ void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
         x[i] = z;
         w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
+}
+
+// The field quadrature's nodes, computed once.
+struct GaussNodes {
+    double x[kGL], w[kGL];
+    GaussNodes() { gauss_legendre(kGL, x, w); }
+};
+const GaussNodes& gauss_nodes() {
+    static const GaussNodes g;
+    return g;
 }
 
 // ---------------------------------------------------------------------------
@@ -400,7 +411,6 @@ struct lam_ctx {
     double2* d_lam_next = nullptr;
     double2* d_bs_next = nullptr;
     int solves[2] = {0, 0};       // forward / adjoint solves done
-    std::vector<double> gl_x, gl_w;  // Gauss-Legendre nodes of the field quadrature
     double2* d_Gpart = nullptr;
     double2* d_G = nullptr;
     double2* h_G = nullptr;       // pinned
@@ -438,8 +448,8 @@ struct lam_ctx {
 
 namespace {
 
-double field_value(const lam_ctx* c, double t) {
-    const lam_ham& h = c->ham;
+// E(t) of the pulse h with Fourier amplitudes coef[0..ncoef).
+double field_value(const lam_ham& h, const double* coef, int ncoef, double t) {
     if (h.pulse_kind == LAM_PULSE_NONE) return 0.0;
     if (t < 0.0 || t > h.t_total) return 0.0;
     double e = 0.0;
@@ -448,33 +458,35 @@ double field_value(const lam_ctx* c, double t) {
         e += h.e0 * s * s * std::cos(h.omega * t);
     }
     if (h.pulse_kind == LAM_PULSE_FOURIER || h.pulse_kind == LAM_PULSE_SIN2_FOURIER) {
-        for (size_t q = 0; q < c->coef.size(); ++q) e += c->coef[q] * std::sin((q + 1) * M_PI * t / h.t_total);
+        for (int q = 0; q < ncoef; ++q) e += coef[q] * std::sin((q + 1) * M_PI * t / h.t_total);
     }
     return e;
 }
 
 // W_nm = int_{t0}^{t0+dt} T_n T_m f(t) dt for f = E (q < 0) or the q-th sine.
-void time_matrix(const lam_ctx* c, double t0, int q, double* W) {
-    const int nt = c->nt;
-    const double dt = c->time.dt;
-    const std::vector<double>& x = c->gl_x;
-    const std::vector<double>& w = c->gl_w;
+void time_matrix(const lam_ham& h, const double* coef, int ncoef, int nt, double dt, double t0, int q,
+                 double* W) {
+    const GaussNodes& gl = gauss_nodes();
     for (int k = 0; k < nt * nt; ++k) W[k] = 0.0;
     double P[kMaxNT];
-    for (size_t k = 0; k < x.size(); ++k) {
-        const double t = t0 + 0.5 * dt * (x[k] + 1.0);
+    for (int k = 0; k < kGL; ++k) {
+        const double t = t0 + 0.5 * dt * (gl.x[k] + 1.0);
         double f;
         if (q < 0) {
-            f = field_value(c, t);
+            f = field_value(h, coef, ncoef, t);
         } else {
-            f = (t < 0.0 || t > c->ham.t_total) ? 0.0 : std::sin((q + 1) * M_PI * t / c->ham.t_total);
+            f = (t < 0.0 || t > h.t_total) ? 0.0 : std::sin((q + 1) * M_PI * t / h.t_total);
         }
         if (f == 0.0) continue;
-        legendre_values(nt, x[k], P);
-        const double wk = 0.5 * dt * w[k] * f;
+        legendre_values(nt, gl.x[k], P);
+        const double wk = 0.5 * dt * gl.w[k] * f;
         for (int n = 0; n < nt; ++n)
             for (int m = 0; m < nt; ++m) W[n * nt + m] += wk * P[n] * P[m];
     }
+}
+
+void time_matrix(const lam_ctx* c, double t0, int q, double* W) {
+    time_matrix(c->ham, c->coef.data(), (int)c->coef.size(), c->nt, c->time.dt, t0, q, W);
 }
 
 bool any_nonzero(const double* W, int n) {
@@ -953,6 +965,34 @@ void free_ctx(lam_ctx* c) {
     delete c;
 }
 
+// Geometry of level l of a (validated) grid.
+LevelGeom level_geom(const lam_grid& gr, const lam_ham& ham, int l) {
+    LevelGeom g{};
+    g.dim = gr.dim;
+    g.P = 1;
+    g.nblk[0] = g.nblk[1] = g.nblk[2] = 1;
+    g.bdim[0] = g.bdim[1] = g.bdim[2] = 1;
+    g.n[0] = g.n[1] = g.n[2] = 1;
+    for (int a = 0; a < gr.dim; ++a) {
+        g.n[a] = gr.n[a] >> l;
+        g.bdim[a] = gr.block[a];
+        g.nblk[a] = g.n[a] / g.bdim[a];
+        g.P *= g.n[a];
+    }
+    g.h = gr.h * std::ldexp(1.0, l);
+    g.periodic = gr.periodic;
+    g.fax = ham.field_axis;
+    g.kin = 1.0 / (2.0 * ham.mass * g.h * g.h);
+    g.bpts = g.bdim[0] * g.bdim[1] * g.bdim[2];
+    g.rbp = 1.0f / (float)g.bpts;
+    for (int a = 0; a < 3; ++a) {
+        g.rn[a] = 1.0 / g.n[a];
+        g.rnb[a] = 1.0 / g.nblk[a];
+        g.rbd[a] = 1.0f / (float)g.bdim[a];
+    }
+    return g;
+}
+
 int build(lam_ctx* c, const double* v0_dev) {
     const lam_grid& gr = c->grid;
     const int nt = c->nt;
@@ -960,28 +1000,7 @@ int build(lam_ctx* c, const double* v0_dev) {
     for (int l = 0; l < gr.levels; ++l) {
         Level& L = c->lv[l];
         LevelGeom& g = L.g;
-        g.dim = gr.dim;
-        g.P = 1;
-        g.nblk[0] = g.nblk[1] = g.nblk[2] = 1;
-        g.bdim[0] = g.bdim[1] = g.bdim[2] = 1;
-        g.n[0] = g.n[1] = g.n[2] = 1;
-        for (int a = 0; a < gr.dim; ++a) {
-            g.n[a] = gr.n[a] >> l;
-            g.bdim[a] = gr.block[a];
-            g.nblk[a] = g.n[a] / g.bdim[a];
-            g.P *= g.n[a];
-        }
-        g.h = gr.h * std::ldexp(1.0, l);
-        g.periodic = gr.periodic;
-        g.fax = c->ham.field_axis;
-        g.kin = 1.0 / (2.0 * c->ham.mass * g.h * g.h);
-        g.bpts = g.bdim[0] * g.bdim[1] * g.bdim[2];
-        g.rbp = 1.0f / (float)g.bpts;
-        for (int a = 0; a < 3; ++a) {
-            g.rn[a] = 1.0 / g.n[a];
-            g.rnb[a] = 1.0 / g.nblk[a];
-            g.rbd[a] = 1.0f / (float)g.bdim[a];
-        }
+        g = level_geom(gr, c->ham, l);
         L.nblocks = g.nblk[0] * g.nblk[1] * g.nblk[2];
         L.fp32 = c->solver.precision == LAM_MIXED && (l < gr.levels - 1 || gr.levels == 1);
         // colour lists
@@ -1050,7 +1069,6 @@ int build(lam_ctx* c, const double* v0_dev) {
                       hipHostMallocMapped) != hipSuccess)
         return LAM_ENOMEM;
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_norms_dev), c->h_norms, 0));
-    gauss_legendre(48, c->gl_x, c->gl_w);
     HIPCHK(hipEventCreateWithFlags(&c->ev_norm, hipEventDisableTiming));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
         return LAM_ENOMEM;
@@ -1081,6 +1099,38 @@ int build(lam_ctx* c, const double* v0_dev) {
     }
     for (auto& L : c->lv) LAMCHK(factor_level(c, L));
     HIPCHK(hipStreamSynchronize(c->st));
+    return LAM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of lam_residual_action_noalloc: the per-workgroup
+// partial sums of its norm reduction.  Each GPU the library runs on holds its
+// own copy until the process ends; host code uses the address looked up per
+// device below, never the array's name.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[LAM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per device).
+int scratch_address(double** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return LAM_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return LAM_EHIP;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
     return LAM_OK;
 }
 
@@ -1440,6 +1490,33 @@ int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, dou
     return LAM_OK;
 }
 
+int lam_residual_action_noalloc(const lam_grid* grid, const lam_time* time, const lam_ham* ham, double t0,
+                                const lam_c64* psi0, const lam_c64* c, const lam_c64* lam, lam_c64* rho,
+                                lam_c64* sigma, double* norm, void* hip_stream) {
+    const lam_solver any_solver{LAM_FP64, 0.0, 0, -1, LAM_TF_SHARED};
+    LAMCHK(validate(grid, time, ham, &any_solver));
+    if (bad_ptr(psi0) || bad_ptr(c) || bad_ptr(lam)) return LAM_EINVAL;
+    const int nt = time->n_t;
+    const LevelGeom g = level_geom(*grid, *ham, 0);
+    double U[kMaxNT], W[kMaxNT * kMaxNT];
+    for (int m = 0; m < nt; ++m) U[m] = time->dt / (2.0 * m + 1.0);
+    time_matrix(*ham, ham->coef, ham->n_coef, nt, time->dt, t0, -1, W);
+    const int on = any_nonzero(W, nt * nt) ? 1 : 0;
+    double* partial = nullptr;
+    if (norm) {
+        if ((size_t)residual_blocks(nt, g.P) > LAM_NOALLOC_SCRATCH_BYTES / sizeof(double)) return LAM_ETOOBIG;
+        LAMCHK(scratch_address(&partial));
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int np = 0;
+    HIPCHK(launch_residual(nt, g, U, W, 0, on, reinterpret_cast<const double2*>(c),
+                           reinterpret_cast<const double2*>(lam), ham->v0, nullptr, nullptr,
+                           reinterpret_cast<const double2*>(psi0), reinterpret_cast<double2*>(rho),
+                           reinterpret_cast<double2*>(sigma), partial, &np, st));
+    if (norm) HIPCHK(launch_reduce(partial, np, 1, norm, st));
+    return LAM_OK;
+}
+
 int lam_pass_stats(lam_ctx* ctx, int level, long long* hist) {
     if (!ctx || !hist || level < 0 || level >= ctx->L) return LAM_EINVAL;
     const Level& L = ctx->lv[level];
@@ -1487,6 +1564,7 @@ const char* lam_strerror(int code) {
         case LAM_ENOCONV: return "tolerance not reached within max_cycles";
         case LAM_EDIVERGED: return "residual norm diverged";
         case LAM_ESTATE: return "no state loaded";
+        case LAM_ETOOBIG: return "input larger than the fixed scratch of a no-allocation call";
         default: return "unknown error";
     }
 }

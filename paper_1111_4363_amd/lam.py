@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblam.so")
 
 LAM_OK, LAM_EINVAL, LAM_ENOMEM, LAM_EHIP, LAM_ENOCONV, LAM_EDIVERGED, LAM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+LAM_ETOOBIG = -7
 LAM_MAX_NT = 8
 LAM_MAX_BLOCK = 64
 LAM_MAX_INNER = 32
@@ -100,6 +101,8 @@ SIGNATURES = {
     "lam_level_shape": (_I, [_P, _I, _PI]),
     "lam_block_factor": (_I, [_P, _I, _I, _PD, _PD]),
     "lam_pass_stats": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
+    "lam_residual_action_noalloc": (_I, [ctypes.POINTER(LamGrid), ctypes.POINTER(LamTime), ctypes.POINTER(LamHam),
+                                         _D, _P, _P, _P, _P, _P, _P, _P]),
     "lam_profile": (_I, [_P, _I]),
     "lam_profile_read": (_I, [_P, _PI, _PD]),
     "lam_strerror": (ctypes.c_char_p, [_I]),
@@ -169,6 +172,56 @@ def _pulse_fields(pulse):
         float(pulse.get("t_total", 0.0)), coef
 
 
+def _describe(shape, h, v0, n_t, dt, block, levels=1, nu_pre=1, nu_post=1, nu_coarse=2, interp="linear",
+              periodic=False, mass=1.0, field_axis=-1, pulse=None):
+    """The lam_grid, lam_time and lam_ham structs (and the host array the last points to)."""
+    shape = tuple(int(s) for s in shape)
+    block = tuple(int(b) for b in block)
+    dim = len(shape)
+    if dim not in (1, 2, 3) or len(block) != dim:
+        raise ValueError("shape and block must have the same rank 1, 2 or 3")
+    npts = 1
+    for s in shape:
+        npts *= s
+    g = LamGrid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = shape[a] if a < dim else 1
+        g.block[a] = block[a] if a < dim else 1
+    g.h, g.periodic, g.levels = float(h), int(bool(periodic)), int(levels)
+    g.nu_pre, g.nu_post, g.nu_coarse, g.interp = int(nu_pre), int(nu_post), int(nu_coarse), INTERP[interp]
+    t = LamTime(int(n_t), float(dt))
+    kind, e0, omega, t_total, coef = _pulse_fields(pulse)
+    carr = (ctypes.c_double * max(1, len(coef)))(*coef)
+    ham = LamHam()
+    ham.mass = float(mass)
+    ham.v0 = _ptr(v0, torch.float64, npts, "v0")
+    ham.field_axis = int(field_axis) % dim
+    ham.pulse_kind, ham.e0, ham.omega, ham.t_total = kind, e0, omega, t_total
+    ham.n_coef = len(coef)
+    ham.coef = carr
+    return g, t, ham, carr, coef, npts
+
+
+def residual_action_noalloc(shape, h, v0, n_t, dt, t0, psi0, c, lam, rho=None, sigma=None, norm=None,
+                            block=None, periodic=False, mass=1.0, field_axis=-1, pulse=None, stream=None):
+    """lam_residual_action_noalloc: the action residual without a context or any
+    device allocation.  v0, psi0, c, lam: device inputs; rho, sigma: device outputs
+    or None; norm: a device float64 tensor of one element or None.  Returns the
+    library's code (0 on success); nothing is raised."""
+    lib = load_library()
+    block = block if block is not None else (1,) * len(shape)
+    v0 = v0.contiguous()
+    g, t, ham, carr, _, P = _describe(shape, h, v0, n_t, dt, block, periodic=periodic, mass=mass,
+                                      field_axis=field_axis, pulse=pulse)
+    nt = int(n_t)
+    return lib.lam_residual_action_noalloc(
+        ctypes.byref(g), ctypes.byref(t), ctypes.byref(ham), float(t0), _ptr(psi0, torch.complex128, P, "psi0"),
+        _ptr(c, torch.complex128, P * nt, "c"), _ptr(lam, torch.complex128, P, "lam"),
+        _ptr(rho, torch.complex128, P * nt, "rho"), _ptr(sigma, torch.complex128, P, "sigma"),
+        _ptr(norm, torch.float64, 1, "norm"), _stream_handle(stream))
+
+
 class Propagator:
     """One liblam context: a grid, a time basis, a Hamiltonian and a solver."""
 
@@ -176,35 +229,14 @@ class Propagator:
                  interp="linear", periodic=False, mass=1.0, field_axis=-1, pulse=None,
                  precision="fp64", tol=1e-10, max_cycles=50, n_inner=-1, time_factor="shared", stream=None):
         lib = load_library()
-        shape = tuple(int(s) for s in shape)
-        block = tuple(int(b) for b in block)
-        dim = len(shape)
-        if dim not in (1, 2, 3) or len(block) != dim:
-            raise ValueError("shape and block must have the same rank 1, 2 or 3")
-        self.shape, self.block, self.n_t, self.dt, self.h = shape, block, int(n_t), float(dt), float(h)
-        self.npts = 1
-        for s in shape:
-            self.npts *= s
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
-        g = LamGrid()
-        g.dim = dim
-        for a in range(3):
-            g.n[a] = shape[a] if a < dim else 1
-            g.block[a] = block[a] if a < dim else 1
-        g.h, g.periodic, g.levels = float(h), int(bool(periodic)), int(levels)
-        g.nu_pre, g.nu_post, g.nu_coarse, g.interp = int(nu_pre), int(nu_post), int(nu_coarse), INTERP[interp]
-        t = LamTime(int(n_t), float(dt))
-        kind, e0, omega, t_total, coef = _pulse_fields(pulse)
-        self.n_coef = len(coef)
-        self._coef = (ctypes.c_double * max(1, len(coef)))(*coef)
         v0 = v0.contiguous()
-        ham = LamHam()
-        ham.mass = float(mass)
-        ham.v0 = _ptr(v0, torch.float64, self.npts, "v0")
-        ham.field_axis = int(field_axis) % dim
-        ham.pulse_kind, ham.e0, ham.omega, ham.t_total = kind, e0, omega, t_total
-        ham.n_coef = len(coef)
-        ham.coef = self._coef
+        g, t, ham, self._coef, coef, self.npts = _describe(shape, h, v0, n_t, dt, block, levels, nu_pre, nu_post,
+                                                           nu_coarse, interp, periodic, mass, field_axis, pulse)
+        self.shape = tuple(int(s) for s in shape)
+        self.block = tuple(int(b) for b in block)
+        self.n_t, self.dt, self.h = int(n_t), float(dt), float(h)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.n_coef = len(coef)
         s = LamSolver(PRECISION[precision], float(tol), int(max_cycles), int(n_inner), TIME_FACTOR[time_factor])
         self.levels = int(levels)
         self.precision = precision

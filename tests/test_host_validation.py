@@ -59,3 +59,38 @@ def test_null_output_pointer():
 
 def test_destroy_accepts_null():
     assert lam.load_library().lam_destroy(None) == lam.LAM_OK
+
+
+def _noalloc(n, n_t, with_norm=True, dim=3):
+    """lam_residual_action_noalloc on a grid description only: the host-side
+    checks run before any device call, so dummy (never dereferenced) pointers do."""
+    lib = lam.load_library()
+    g = lam.LamGrid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = n if a < dim else 1
+        g.block[a] = 1
+    g.h, g.levels = 0.25, 1
+    g.nu_pre = g.nu_post = g.nu_coarse = 1
+    t = lam.LamTime(n_t, 0.05)
+    dummy = ctypes.c_double(0.0)
+    p = ctypes.cast(ctypes.pointer(dummy), ctypes.c_void_p)
+    h = lam.LamHam()
+    h.mass, h.v0, h.field_axis = 1.0, p, dim - 1
+    norm = p if with_norm else None
+    return lib.lam_residual_action_noalloc(ctypes.byref(g), ctypes.byref(t), ctypes.byref(h), 0.0, p, p, p, None,
+                                           None, norm, None)
+
+
+def test_noalloc_residual_rejects_grids_beyond_its_scratch():
+    """The fixed 4 MiB scratch holds one partial sum per floor(256/n_t) points:
+    512^3 points at n_t = 8 need 4 Mi partials, and the call refuses before
+    touching any pointer (LAM_ETOOBIG, named by lam_strerror)."""
+    assert _noalloc(512, 8) == lam.LAM_ETOOBIG
+    assert _noalloc(336, 4) == lam.LAM_ETOOBIG       # 37.9M points / 64 per partial = 592704 > 524288
+    assert "scratch" in lam.strerror(lam.LAM_ETOOBIG)
+
+
+def test_noalloc_residual_validates_like_create():
+    assert _noalloc(16, 0) == lam.LAM_EINVAL          # n_t out of range
+    assert _noalloc(16, 9) == lam.LAM_EINVAL
