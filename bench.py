@@ -191,7 +191,8 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam, adjoint_steps=
     # context creation = hierarchy + factorisation of every block of every level (once per run for a
     # static potential)
     prop = lam.Propagator(shape, cfg["h"], v0_t, cfg["n_t"], cfg["dt"], (cfg["block"],) * cfg["dim"],
-                          levels=cfg["levels"], nu_pre=1, nu_post=1, nu_coarse=cfg["nu_coarse"], precision=precision,
+                          levels=cfg["levels"], nu_pre=1, nu_post=1, nu_coarse=cfg["nu_coarse"],
+                          coarse_reduction=cfg["coarse_reduction"], precision=precision,
                           tol=args.tol, max_cycles=60, pulse=pulse_of(cfg))
     torch.cuda.synchronize()
     factor_ms = (time.perf_counter() - t_f) * 1e3
@@ -236,6 +237,8 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam, adjoint_steps=
         "sweep_launches": launches,
         "sweep_kernel_ms_avg": sweep_ms / launches if launches else None,
         "sweep_kernel_munk_sweeps_per_s": kernel_rate,
+        "coarsest_sweeps_per_cycle": st["coarse_sweeps"] / max(1, st["cycles"]),
+        "coarsest_solves_short_of_reduction": st["coarse_unmet"],
         "inner_passes_finest_mean": (sum(k * c for k, c in enumerate(hist)) / nblk) if nblk else 0.0,
         "inner_passes_finest_max": max([k for k, c in enumerate(hist) if c] + [0]),
         "subvolumes_unsolved_finest": unsolved,
@@ -270,7 +273,8 @@ def workload_string(cfg, tol):
                  "sin2+fourier": f", E0={p['e0']} sin^2 pulse + {p['n_coef']} Fourier amplitudes"}[p["kind"]]
     blocks = "x".join([str(cfg["block"])] * cfg["dim"])
     return (f"{cfg['name']} {shape} h={cfg['h']:g} {pot}{field}, N_t={cfg['n_t']}, dt={cfg['dt']}, "
-            f"{blocks} subvolumes, {cfg['levels']}-level V(1,1) with {cfg['nu_coarse']} coarsest sweep(s), tol {tol:g}")
+            f"{blocks} subvolumes, {cfg['levels']}-level V(1,1), coarsest level swept to a "
+            f"{1 / cfg['coarse_reduction']:.0e} reduction (at most {cfg['nu_coarse']} sweeps), tol {tol:g}")
 
 
 def roofline_of(cfg, prec, r, traffic):

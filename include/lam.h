@@ -91,7 +91,8 @@ typedef struct {
                          must be even at all levels but the coarsest */
     int nu_pre;       /* full sweeps before the coarse correction */
     int nu_post;      /* full sweeps after it */
-    int nu_coarse;    /* full sweeps that make the coarsest-level solve */
+    int nu_coarse;    /* full sweeps of the coarsest-level solve (its maximum when the
+                         solver's coarse_reduction > 0) */
     int interp;       /* 0: cell-centred tensor-linear interpolation,
                          1: piecewise constant (projection * interpolation = identity) */
 } lam_grid;
@@ -131,6 +132,11 @@ typedef struct {
                          per mode);
                          LAM_TF_STORED (1): stored per-mode inverses ((n_t+1)^2 complex per
                          mode, refactored for every step with a field) */
+    double coarse_reduction;  /* the coarsest-level solve of each V-cycle: 0 = exactly
+                         grid.nu_coarse full sweeps; in (0, 1) = full sweeps until the
+                         coarsest residual norm sqrt(N) has fallen by this factor from
+                         its value at the start of the solve, at most grid.nu_coarse
+                         (decided on the device; lam_stats counts sweeps and misses) */
 } lam_solver;
 
 typedef struct {
@@ -142,6 +148,9 @@ typedef struct {
     double t_solve_ms;    /* wall time of the call */
     double resid0_last;   /* sqrt(N) of the initial guess of the last step solved */
     double resid_last;    /* sqrt(N) at the end of the last step solved */
+    int coarse_sweeps;    /* full sweeps of the coarsest-level solves (coarse_reduction > 0) */
+    int coarse_unmet;     /* V-cycles whose coarsest solve stopped at nu_coarse sweeps before
+                             reaching coarse_reduction */
 } lam_stats;
 
 /* Create a propagator context: builds the level hierarchy (coarse grids with

@@ -19,8 +19,11 @@ Sec. "Multigrid Relaxation", Eqs. (residual_rough) and (correction_fine): the
 residual is projected to the coarse level, a correction is found there and
 interpolated back.  The coarse operator is the step system rediscretised on
 the coarse grid (same N_t, dt, field; potential averaged over children).
-V-cycle with nu_pre / nu_post sweeps around the coarse correction and
-nu_coarse sweeps as the coarsest-level solve.
+V-cycle with nu_pre / nu_post sweeps around the coarse correction.  The
+coarsest-level solve (the coarse inverse of Eq. (correction_fine)) is either
+nu_coarse sweeps, or sweeps repeated until the coarsest residual norm has
+fallen by a given factor (at most nu_coarse of them), or the direct solve of
+the coarsest system.
 
 The adjoint variants use K^H at every level with the same transfers.
 
@@ -120,21 +123,51 @@ def prolong(level, xc):
     return kkt.join(level.I @ cc, level.I @ lc)
 
 
-def reference_vcycle(levels, l, x, b, nu_pre=1, nu_post=1, nu_coarse=2, adjoint=False):
+def coarsest_solve(lev, K, b, x, nu_coarse, coarse_reduction=None, direct=False):
+    """The coarsest-level solve; returns (x, full sweeps done).
+
+    direct: x = K^{-1} b.  coarse_reduction None: nu_coarse full sweeps.
+    Otherwise full sweeps until sqrt(N / N0) <= coarse_reduction, N0 the norm
+    at the start, checked after every sweep, at most nu_coarse sweeps.
+    """
+    P, n_t = lev.grid.npts, lev.system.n_t
+    if direct:
+        return kkt.solve_direct(K, b), 0
+    if coarse_reduction is None:
+        for _ in range(nu_coarse):
+            x = reference_sweep(K, b, x, lev.blocks, P, n_t)
+        return x, nu_coarse
+    n0 = kkt.residual_norm(lev.system, b - K @ x)
+    if n0 == 0.0:
+        return x, 0
+    done = 0
+    for _ in range(nu_coarse):
+        x = reference_sweep(K, b, x, lev.blocks, P, n_t)
+        done += 1
+        if kkt.residual_norm(lev.system, b - K @ x) <= coarse_reduction ** 2 * n0:
+            break
+    return x, done
+
+
+def reference_vcycle(levels, l, x, b, nu_pre=1, nu_post=1, nu_coarse=2, adjoint=False, coarse_reduction=None,
+                     coarse_direct=False, counts=None):
+    """One V-cycle; counts (a list, optional) receives the coarsest sweeps done."""
     lev = levels[l]
     K = operator(lev, adjoint)
     P, n_t = lev.grid.npts, lev.system.n_t
     x = np.array(x, dtype=complex)
     if l == len(levels) - 1:
-        for _ in range(nu_coarse):
-            x = reference_sweep(K, b, x, lev.blocks, P, n_t)
+        x, done = coarsest_solve(lev, K, b, x, nu_coarse, coarse_reduction, coarse_direct)
+        if counts is not None:
+            counts.append(done)
         return x
     for _ in range(nu_pre):
         x = reference_sweep(K, b, x, lev.blocks, P, n_t)
     r = b - K @ x
     bc = restrict(lev, r)
     xc = np.zeros_like(bc)
-    xc = reference_vcycle(levels, l + 1, xc, bc, nu_pre, nu_post, nu_coarse, adjoint)
+    xc = reference_vcycle(levels, l + 1, xc, bc, nu_pre, nu_post, nu_coarse, adjoint, coarse_reduction,
+                          coarse_direct, counts)
     x = x + prolong(lev, xc)
     for _ in range(nu_post):
         x = reference_sweep(K, b, x, lev.blocks, P, n_t)

@@ -437,6 +437,13 @@ struct lam_ctx {
     double prep_t = NAN;          // a step whose records the next wait should prepare on the host
     int prep_dir = 0;
     double state_t0 = NAN;        // step of the state loaded in the context
+    // iterated coarsest-level solve
+    CoarseCtl* d_ctl = nullptr;
+    int* h_citers = nullptr;      // pinned, mapped: per queued V-cycle, coarsest sweeps run | reached << 30
+    int* h_citers_dev = nullptr;
+    int coarse_launch = 0;        // coarsest iterations queued per V-cycle (learned; at most nu_coarse)
+    int coarse_sweeps = 0;        // coarsest full sweeps run / V-cycles whose coarsest solve missed its
+    int coarse_unmet = 0;         // reduction, since the current call started
     // profiling of finest-level sweeps
     int prof = 0;                 // record every prof-th finest-level sweep launch (0: off)
     long prof_count = 0;
@@ -617,9 +624,10 @@ int factor_level(lam_ctx* c, Level& L) {
     return LAM_OK;
 }
 
-int sweep(lam_ctx* c, int l, int colour) {
+int sweep(lam_ctx* c, int l, int colour, const int* skip = nullptr) {
     Level& L = c->lv[l];
     SweepArgs a{};
+    a.skip = skip;
     a.g = L.g;
     a.blocks = L.d_blocks[colour];
     a.colour = colour;
@@ -675,11 +683,63 @@ int sweep(lam_ctx* c, int l, int colour) {
     return LAM_OK;
 }
 
-int full_sweep(lam_ctx* c, int l) {
-    LAMCHK(sweep(c, l, 0));
-    LAMCHK(sweep(c, l, 1));
+int full_sweep(lam_ctx* c, int l, const int* skip = nullptr) {
+    LAMCHK(sweep(c, l, 0, skip));
+    LAMCHK(sweep(c, l, 1, skip));
     if (l == 0) c->sweeps_fine++;
     return LAM_OK;
+}
+
+// The coarsest-level solve of a V-cycle (Eq. (correction_fine): the coarse
+// correction solves the coarse system for the projected residual).  Without a
+// reduction target: exactly nu_coarse full sweeps.  With one (solver
+// coarse_reduction > 0): full sweeps until the coarsest residual norm has
+// fallen by that factor, at most nu_coarse.  The decision is taken on the
+// device: after each full sweep a residual and its sum update the control
+// block, and once the target is reached the remaining queued launches of the
+// solve do nothing.  The host queues as many iterations as the previous
+// V-cycles needed plus one (at most nu_coarse), learning from the counts the
+// reductions leave in mapped host memory (slot: this V-cycle's, -1 for none).
+int coarsest_solve(lam_ctx* c, int l, int slot) {
+    const double red = c->solver.coarse_reduction;
+    if (!(red > 0.0)) {
+        for (int s = 0; s < c->grid.nu_coarse; ++s) LAMCHK(full_sweep(c, l));
+        return LAM_OK;
+    }
+    Level& L = c->lv[l];
+    const double2* bc = l == 0 ? nullptr : L.d_bc;
+    const double2* bg = (l == 0 && c->adjoint) ? c->d_g : nullptr;
+    const double2* bs = (l == 0 && c->adjoint) ? nullptr : L.d_bs;
+    const int* done = &c->d_ctl->done;
+    int np = 0;
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, bc, bg, bs,
+                           nullptr, nullptr, c->d_partial, &np, c->st));
+    HIPCHK(launch_reduce_ctl(c->d_partial, np, c->d_ctl, 1, 0.0, nullptr, c->st));
+    const int n_it = std::min(c->grid.nu_coarse, std::max(1, c->coarse_launch));
+    for (int it = 0; it < n_it; ++it) {
+        LAMCHK(full_sweep(c, l, done));
+        HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, bc, bg, bs,
+                               nullptr, nullptr, c->d_partial, &np, c->st, done));
+        HIPCHK(launch_reduce_ctl(c->d_partial, np, c->d_ctl, 0, red * red,
+                                 (it == n_it - 1 && slot >= 0) ? c->h_citers_dev + slot : nullptr, c->st));
+    }
+    return LAM_OK;
+}
+
+// Account for the coarsest solves of V-cycles [first, last] (their slots).
+void note_coarsest(lam_ctx* c, int first, int last) {
+    if (!(c->solver.coarse_reduction > 0.0)) return;
+    int used = 0;
+    for (int k = first; k <= last; ++k) {
+        const int v = c->h_citers[k];
+        const int it = v & 0x3fffffff;
+        const bool met = (v >> 30) & 1;
+        c->coarse_sweeps += it;
+        if (!met) c->coarse_unmet++;
+        // a solve that ran every queued iteration without reaching the target asks for all
+        used = std::max(used, met ? it : c->grid.nu_coarse);
+    }
+    c->coarse_launch = std::min(c->grid.nu_coarse, used + 1);
 }
 
 // Wait for the work queued on the context stream (e.g. a norm reduction that
@@ -715,11 +775,8 @@ int norm0(lam_ctx* c, double* out) {
     return LAM_OK;
 }
 
-int vcycle(lam_ctx* c, int l) {
-    if (l == c->L - 1) {
-        for (int s = 0; s < c->grid.nu_coarse; ++s) LAMCHK(full_sweep(c, l));
-        return LAM_OK;
-    }
+int vcycle(lam_ctx* c, int l, int slot = -1) {
+    if (l == c->L - 1) return coarsest_solve(c, l, slot);
     for (int s = 0; s < c->grid.nu_pre; ++s) LAMCHK(full_sweep(c, l));
     Level& F = c->lv[l];
     Level& C = c->lv[l + 1];
@@ -730,7 +787,7 @@ int vcycle(lam_ctx* c, int l) {
     const double2* bs = (l == 0 && c->adjoint) ? nullptr : F.d_bs;
     HIPCHK(launch_residual_restrict(c->nt, F.g, C.g, c->U, c->W, c->adjoint, c->field_on, F.d_c, F.d_lam, F.d_v0, bc,
                                     bg, bs, C.d_bc, C.d_bs, C.d_c, C.d_lam, c->st));
-    LAMCHK(vcycle(c, l + 1));
+    LAMCHK(vcycle(c, l + 1, slot));
     HIPCHK(launch_prolong(c->nt, F.g, C.g, c->grid.interp, C.d_c, C.d_lam, F.d_c, F.d_lam, c->st));
     for (int s = 0; s < c->grid.nu_post; ++s) LAMCHK(full_sweep(c, l));
     return LAM_OK;
@@ -774,6 +831,7 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
     int queued = 0, conv = -1;
     int rc = LAM_ENOCONV;
     int batch = std::min(predict, maxc);  // 0 on a context's first solve: look at N0 first
+    const int cs0 = c->coarse_sweeps, cu0 = c->coarse_unmet;
     double N0 = 0.0, N = 0.0;
     for (;;) {
         const int nb = std::min(batch, maxc - queued);
@@ -783,7 +841,7 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
         const bool probe = (c->solves[c->adjoint ? 1 : 0] & 7) == 0;
         int first_norm = -1;   // the first cycle of this batch whose norm is queued
         for (int i = 0; i < nb; ++i) {
-            LAMCHK(vcycle(c, 0));
+            LAMCHK(vcycle(c, 0, queued + 1));
             ++queued;
             if (i == nb - 1 || (probe && i == nb - 2)) {
                 LAMCHK(queue_norm(c, queued));
@@ -807,6 +865,7 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
             LAMCHK(prepare_tables(c, tp, c->prep_dir));
         }
         LAMCHK(wait_event(c));
+        if (nb > 0) note_coarsest(c, queued - nb + 1, queued);
         N0 = c->h_norms[n0_slot];
         N = c->h_norms[queued];
         if (!std::isfinite(N0)) {
@@ -847,6 +906,8 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
         stats->resid = std::sqrt(N);
         stats->resid0_last = stats->resid0;
         stats->resid_last = stats->resid;
+        stats->coarse_sweeps = c->coarse_sweeps - cs0;
+        stats->coarse_unmet = c->coarse_unmet - cu0;
     }
     return rc;
 }
@@ -868,6 +929,7 @@ int validate(const lam_grid* g, const lam_time* t, const lam_ham* h, const lam_s
     if (!h->v0) return LAM_EINVAL;
     if (s->precision != LAM_FP64 && s->precision != LAM_MIXED) return LAM_EINVAL;
     if (s->max_cycles < 0 || !(s->tol >= 0.0) || s->n_inner < -1 || s->n_inner > LAM_MAX_INNER) return LAM_EINVAL;
+    if (!(s->coarse_reduction >= 0.0 && s->coarse_reduction < 1.0)) return LAM_EINVAL;
     if (s->time_factor != LAM_TF_SHARED && s->time_factor != LAM_TF_STORED) return LAM_EINVAL;
     long bpts = 1;
     for (int a = 0; a < g->dim; ++a) {
@@ -957,6 +1019,8 @@ void free_ctx(lam_ctx* c) {
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->ev_norm) (void)hipEventDestroy(c->ev_norm);
     if (c->h_norms) (void)hipHostFree(c->h_norms);
+    if (c->h_citers) (void)hipHostFree(c->h_citers);
+    (void)hipFree(c->d_ctl);
     (void)hipFree(c->d_c_next);
     (void)hipFree(c->d_lam_next);
     (void)hipFree(c->d_bs_next);
@@ -1069,6 +1133,14 @@ int build(lam_ctx* c, const double* v0_dev) {
                       hipHostMallocMapped) != hipSuccess)
         return LAM_ENOMEM;
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_norms_dev), c->h_norms, 0));
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_citers), sizeof(int) * (c->solver.max_cycles + 3),
+                      hipHostMallocMapped) != hipSuccess)
+        return LAM_ENOMEM;
+    std::memset(c->h_citers, 0, sizeof(int) * (c->solver.max_cycles + 3));
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_citers_dev), c->h_citers, 0));
+    LAMCHK(dalloc(&c->d_ctl, 1));
+    HIPCHK(hipMemsetAsync(c->d_ctl, 0, sizeof(CoarseCtl), c->st));
+    c->coarse_launch = gr.nu_coarse;
     HIPCHK(hipEventCreateWithFlags(&c->ev_norm, hipEventDisableTiming));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
         return LAM_ENOMEM;
@@ -1370,6 +1442,8 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
         }
         src = psi_out;
         tot.cycles += st.cycles;
+        tot.coarse_sweeps += st.coarse_sweeps;
+        tot.coarse_unmet += st.coarse_unmet;
         tot.resid0_last = st.resid0;
         tot.resid_last = st.resid;
         const double ratio = st.resid0 > 0.0 ? st.resid / st.resid0 : 0.0;
@@ -1493,7 +1567,7 @@ int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, dou
 int lam_residual_action_noalloc(const lam_grid* grid, const lam_time* time, const lam_ham* ham, double t0,
                                 const lam_c64* psi0, const lam_c64* c, const lam_c64* lam, lam_c64* rho,
                                 lam_c64* sigma, double* norm, void* hip_stream) {
-    const lam_solver any_solver{LAM_FP64, 0.0, 0, -1, LAM_TF_SHARED};
+    const lam_solver any_solver{LAM_FP64, 0.0, 0, -1, LAM_TF_SHARED, 0.0};
     LAMCHK(validate(grid, time, ham, &any_solver));
     if (bad_ptr(psi0) || bad_ptr(c) || bad_ptr(lam)) return LAM_EINVAL;
     const int nt = time->n_t;

@@ -64,9 +64,21 @@ struct SweepArgs {
     const double* e;          // [nblocks][bpts] eigenvalues of the block operators
     unsigned char* passes;    // [nblocks] inner passes of each block's last solve (bit 7: its
                               // local system was left unsolved); may be null
+    const int* skip;          // when non-null and nonzero at launch, the launch does nothing
     int adjoint;
     int n_inner;
     int field_on;             // W (the field's time matrix) is nonzero this step
+};
+
+// Control of the iterated coarsest-level solve (device memory): the norm N of
+// the coarsest residual when the solve started and after the latest sweep,
+// whether the reduction is reached (the remaining launches of the solve then
+// do nothing) and the number of full sweeps that ran.
+struct CoarseCtl {
+    double n0;
+    double n;
+    int done;
+    int iters;
 };
 
 // A time factor record (reals of the factor's precision): the real forms
@@ -87,12 +99,21 @@ inline int residual_blocks(int nt, int P) {
 // ---- launchers (lam_kernels.hip) -------------------------------------------
 // All return hipSuccess or the launch error.
 
+// skip (may be null): when it points to a nonzero value at launch, the launch does nothing.
 hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const double* W, int adjoint,
                            int field_on, const double2* c, const double2* lam, const double* v0, const double2* bc,
                            const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
-                           int* nparts, hipStream_t st);
+                           int* nparts, hipStream_t st, const int* skip = nullptr);
 
 hipError_t launch_reduce(const double* partial, int nparts, int width, double* out, hipStream_t st);
+
+// Sum of the partials into the coarsest-solve control: start = 1 opens a solve
+// (n0 = n = sum, done = (sum == 0), iters = 0); start = 0 closes one full sweep
+// unless the solve is already done (iters + 1, n = sum, done = n <= thr2 n0).
+// iters_out (may be null, e.g. mapped host memory) receives iters and, in bit
+// 30, whether the reduction was reached.
+hipError_t launch_reduce_ctl(const double* partial, int nparts, CoarseCtl* ctl, int start, double thr2,
+                             int* iters_out, hipStream_t st);
 
 hipError_t launch_residual_restrict(int nt, const LevelGeom& fine, const LevelGeom& coarse, const double* U,
                                     const double* W, int adjoint, int field_on, const double2* c,

@@ -354,7 +354,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
                                                        const double2* __restrict__ bg,
                                                        const double2* __restrict__ bs,
                                                        double2* __restrict__ rc, double2* __restrict__ rs,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, const int* __restrict__ skip) {
+    if (skip && *skip) return;
     constexpr int PW = kThreads / NT;  // points per workgroup
     __shared__ double2 cs[PW * NT];
     __shared__ double tos[NT + NT * NT];
@@ -479,6 +480,39 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double* __restr
     for (; k < nparts; k += kReduceThreads) acc[0] += partial[k];
     const double tot = block_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), red);
     if (threadIdx.x == 0) out[0] = tot;
+}
+
+// The same sum, closing one step of the iterated coarsest-level solve (see
+// launch_reduce_ctl).
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_ctl(const double* __restrict__ partial, int nparts,
+                                                               CoarseCtl* __restrict__ ctl, int start, double thr2,
+                                                               int* __restrict__ iters_out) {
+    __shared__ double red[kReduceThreads / 64];
+    if (!start && ctl->done) {
+        if (threadIdx.x == 0 && iters_out) *iters_out = ctl->iters | (1 << 30);
+        return;
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = threadIdx.x;
+    for (; k + 3 * kReduceThreads < nparts; k += 4 * kReduceThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += partial[k + u * kReduceThreads];
+    }
+    for (; k < nparts; k += kReduceThreads) acc[0] += partial[k];
+    const double tot = block_sum((acc[0] + acc[1]) + (acc[2] + acc[3]), red);
+    if (threadIdx.x == 0) {
+        if (start) {
+            ctl->n0 = tot;
+            ctl->n = tot;
+            ctl->done = tot == 0.0 ? 1 : 0;
+            ctl->iters = 0;
+        } else {
+            ctl->iters += 1;
+            ctl->n = tot;
+            ctl->done = tot <= thr2 * ctl->n0 ? 1 : 0;
+        }
+        if (iters_out) *iters_out = ctl->iters | (ctl->done ? (1 << 30) : 0);
+    }
 }
 
 // One workgroup per output element w: out[w] = sum_p partial[p * width + w].
@@ -999,6 +1033,8 @@ constexpr int sweep_waves_per_simd() { return STORED ? 2 : 4; }
 
 template <int NT, typename BT, bool STORED>
 __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())) void k_sweep(SweepArgs a, TimeOps<NT> to) {
+    // a finished coarsest-level solve: the rest of its launches do nothing
+    if (a.skip && *a.skip) return;
     constexpr int NQ = NT + 1;
     constexpr int N2 = 2 * NQ;                               // reals per point / mode
     constexpr int VPT = kMaxB * kMaxB / kSweepThreads;       // eigenvector entries per thread
@@ -1601,12 +1637,19 @@ inline int nblk_for(size_t n) { return (int)((n + kThreads - 1) / kThreads); }
 hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const double* W, int adjoint,
                            int field_on, const double2* c, const double2* lam, const double* v0, const double2* bc,
                            const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
-                           int* nparts, hipStream_t st) {
+                           int* nparts, hipStream_t st, const int* skip) {
     const int nb = residual_blocks(nt, g.P);
     if (nparts) *nparts = nb;
     LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_residual<NT>, dim3(nb), dim3(kThreads), 0, st, g,
                                            make_ops<NT>(U, W), adjoint, field_on, c, lam, v0, bc, bg, bs, rc,
-                                           rs, partial));
+                                           rs, partial, skip));
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_ctl(const double* partial, int nparts, CoarseCtl* ctl, int start, double thr2,
+                             int* iters_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_ctl, dim3(1), dim3(kReduceThreads), 0, st, partial, nparts, ctl, start, thr2,
+                       iters_out);
     return hipGetLastError();
 }
 

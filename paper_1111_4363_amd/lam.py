@@ -62,13 +62,14 @@ class LamHam(ctypes.Structure):
 
 class LamSolver(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_cycles", ctypes.c_int),
-                ("n_inner", ctypes.c_int), ("time_factor", ctypes.c_int)]
+                ("n_inner", ctypes.c_int), ("time_factor", ctypes.c_int), ("coarse_reduction", ctypes.c_double)]
 
 
 class LamStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("sweeps_fine", ctypes.c_int), ("resid0", ctypes.c_double),
                 ("resid", ctypes.c_double), ("t_factor_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
-                ("resid0_last", ctypes.c_double), ("resid_last", ctypes.c_double)]
+                ("resid0_last", ctypes.c_double), ("resid_last", ctypes.c_double),
+                ("coarse_sweeps", ctypes.c_int), ("coarse_unmet", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -227,7 +228,8 @@ class Propagator:
 
     def __init__(self, shape, h, v0, n_t, dt, block, levels=1, nu_pre=1, nu_post=1, nu_coarse=2,
                  interp="linear", periodic=False, mass=1.0, field_axis=-1, pulse=None,
-                 precision="fp64", tol=1e-10, max_cycles=50, n_inner=-1, time_factor="shared", stream=None):
+                 precision="fp64", tol=1e-10, max_cycles=50, n_inner=-1, time_factor="shared", coarse_reduction=0.0,
+                 stream=None):
         lib = load_library()
         v0 = v0.contiguous()
         g, t, ham, self._coef, coef, self.npts = _describe(shape, h, v0, n_t, dt, block, levels, nu_pre, nu_post,
@@ -237,7 +239,8 @@ class Propagator:
         self.n_t, self.dt, self.h = int(n_t), float(dt), float(h)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.n_coef = len(coef)
-        s = LamSolver(PRECISION[precision], float(tol), int(max_cycles), int(n_inner), TIME_FACTOR[time_factor])
+        s = LamSolver(PRECISION[precision], float(tol), int(max_cycles), int(n_inner), TIME_FACTOR[time_factor],
+                      float(coarse_reduction))
         self.levels = int(levels)
         self.precision = precision
         # what the context holds (the autograd function restores its own inputs)

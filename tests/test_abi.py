@@ -37,7 +37,7 @@ def test_binding_covers_every_declared_symbol():
 
 
 def test_strerror_names_every_code():
-    for code in [0, -1, -2, -3, -4, -5, -6]:
+    for code in [0, -1, -2, -3, -4, -5, -6, -7]:
         assert lam.strerror(code) not in ("", "unknown error")
 
 
@@ -52,8 +52,8 @@ int main(void) {
   printf("lam_grid %zu\nlam_time %zu\nlam_ham %zu\nlam_solver %zu\nlam_stats %zu\n",
          sizeof(lam_grid), sizeof(lam_time), sizeof(lam_ham), sizeof(lam_solver), sizeof(lam_stats));
   P(lam_grid, h) P(lam_grid, block) P(lam_grid, interp) P(lam_ham, v0) P(lam_ham, coef)
-  P(lam_ham, t_total) P(lam_solver, n_inner) P(lam_solver, time_factor) P(lam_stats, t_solve_ms)
-  P(lam_stats, resid_last)
+  P(lam_ham, t_total) P(lam_solver, n_inner) P(lam_solver, time_factor) P(lam_solver, coarse_reduction)
+  P(lam_stats, t_solve_ms) P(lam_stats, resid_last) P(lam_stats, coarse_unmet)
   return 0;
 }
 ''')
@@ -76,6 +76,8 @@ int main(void) {
     assert int(out["lam_solver.time_factor"]) == lam.LamSolver.time_factor.offset
     assert int(out["lam_stats.t_solve_ms"]) == lam.LamStats.t_solve_ms.offset
     assert int(out["lam_stats.resid_last"]) == lam.LamStats.resid_last.offset
+    assert int(out["lam_solver.coarse_reduction"]) == lam.LamSolver.coarse_reduction.offset
+    assert int(out["lam_stats.coarse_unmet"]) == lam.LamStats.coarse_unmet.offset
 
 
 def test_binding_rejects_host_tensors_before_any_call():

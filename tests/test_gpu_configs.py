@@ -33,7 +33,8 @@ def make_prop(cfg, v0, precision, tol, max_cycles=80):
                      coef=list(W.pulse_coefficients(cfg)))
     return lam.Propagator(cfg["shape"], cfg["h"], torch.as_tensor(v0, device="cuda"), cfg["n_t"], cfg["dt"],
                           (cfg["block"],) * cfg["dim"], levels=cfg["levels"], nu_coarse=cfg["nu_coarse"],
-                          pulse=pulse, precision=precision, tol=tol, max_cycles=max_cycles)
+                          coarse_reduction=cfg["coarse_reduction"], pulse=pulse, precision=precision, tol=tol,
+                          max_cycles=max_cycles)
 
 
 def population(g_t, w):

@@ -64,6 +64,7 @@ def setup(name, precision="fp64"):
     # the configuration the benchmark times (coarsest-level sweeps included)
     prop = lam.Propagator(cfg["shape"], cfg["h"], torch.as_tensor(v0, device=dev), cfg["n_t"], cfg["dt"],
                           (cfg["block"],) * cfg["dim"], levels=cfg["levels"], nu_coarse=cfg["nu_coarse"],
+                          coarse_reduction=cfg["coarse_reduction"],
                           pulse=pulse, precision=precision, tol=1e-10, max_cycles=60)
     grid = G.Grid(cfg["shape"], cfg["h"])
     return cfg, v0, psi0, pulse, prop, grid, dev

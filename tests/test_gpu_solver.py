@@ -61,6 +61,70 @@ def test_vcycle_parity(cfg, adjoint):
     prop.close()
 
 
+@pytest.mark.parametrize("cfg", [
+    dict(shape=(32, 32), n_t=4, block=(4, 4), levels=3, h=0.2),
+    dict(shape=(8, 8, 16), n_t=6, block=(2, 2, 2), levels=2, h=0.3, pulse=PULSE_SIN2),
+    dict(shape=(64,), n_t=8, block=(8,), levels=1, h=0.3, potential="harmonic"),
+], ids=lambda c: f"{c['shape']}-L{c['levels']}")
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_vcycle_parity_iterated_coarsest_solve(cfg, adjoint):
+    """The coarsest solve iterated on the device until its residual fell by 1e3
+    (at most 6 sweeps) against the oracle's V-cycle with the same rule; on one
+    level the 'coarsest' level is the fine grid itself."""
+    case = Case(**cfg)
+    note(f"vcycle iterated coarsest adjoint={adjoint} {case}")
+    t0 = 0.1
+    H = relax.build_hierarchy(case.grid, case.v0, case.n_t, case.dt, case.block, case.levels, t0=t0,
+                              field=case.field, interp=case.interp)
+    sysm = H[0].system
+    c, lam = case.random_state(0.1)
+    x = kkt.join(c, lam)
+    prop = case.prop(nu_pre=1, nu_post=1, nu_coarse=6, coarse_reduction=1e-3, n_inner=(8 if case.field else -1))
+    if adjoint:
+        b = A.adjoint_rhs(sysm, case.psi0)
+        prop.set_adjoint_state(t0, t_c(case.psi0), t_c(c), t_c(lam))
+    else:
+        b = kkt.rhs(sysm, case.psi0)
+        prop.set_state(t0, t_c(case.psi0), t_c(c), t_c(lam))
+    counts = []
+    x_ref = relax.reference_vcycle(H, 0, x, b, 1, 1, 6, adjoint=adjoint, coarse_reduction=1e-3, counts=counts)
+    prop.vcycle()
+    cg, lg = prop.get_state()
+    x_gpu = np.concatenate([n(cg), n(lg)])
+    assert np.abs(x_gpu - x_ref).max() <= 1e-10 * np.abs(x_ref).max()
+    assert 1 <= counts[0] <= 6
+    prop.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_with_iterated_coarsest_counts_its_sweeps(precision):
+    """A step of the 2D workload reduced to 64^2 (3 levels) with the iterated
+    coarsest solve: coefficients against the oracle's direct solve, every coarsest
+    solve reached its reduction, and the coarsest sweeps the library reports equal
+    the oracle's count for the same V-cycles (FP64 decisions on both sides)."""
+    case = Case(shape=(64, 64), h=0.2, n_t=8, block=(8, 8), levels=3)
+    note(f"solve with iterated coarsest {precision} {case}")
+    t0 = 0.0
+    sysm = kkt.StepSystem(case.grid, case.v0, case.n_t, case.dt, t0, case.field)
+    b = kkt.rhs(sysm, case.psi0)
+    x_ref = kkt.solve_direct(sysm.K, b)
+    prop = case.prop(precision=precision, tol=1e-10, max_cycles=40, nu_coarse=4, coarse_reduction=1e-3)
+    _, st = prop.solve_step(t0, t_c(case.psi0))
+    cg, _ = prop.get_state()
+    c_ref, _ = kkt.split(x_ref, case.npts, case.n_t)
+    target = 1e-10 if precision == "fp64" else 1e-8
+    assert np.abs(n(cg).reshape(-1, case.n_t) - c_ref).max() <= target * np.abs(c_ref).max()
+    assert st["coarse_unmet"] == 0 and st["coarse_sweeps"] >= st["cycles"]
+    if precision == "fp64":
+        H = relax.build_hierarchy(case.grid, case.v0, case.n_t, case.dt, case.block, case.levels, t0=t0)
+        x = kkt.initial_guess(sysm, case.psi0)
+        counts = []
+        for _ in range(st["cycles"]):
+            x = relax.reference_vcycle(H, 0, x, b, 1, 1, 4, coarse_reduction=1e-3, counts=counts)
+        assert st["coarse_sweeps"] == sum(counts), (st["coarse_sweeps"], counts)
+    prop.close()
+
+
 SOLVE_CASES = [
     # the 1D workload at its full size
     dict(shape=(256,), h=40 / 256, n_t=8, block=(8,), levels=1, potential="harmonic", nu_coarse=2),

@@ -113,10 +113,10 @@ def test_coarse_operator_is_rediscretisation():
 
 
 def test_coarsest_level_sweeps_reduce_residual_by_a_thousand():
-    """Reading of the coarsest solve: nu_coarse = 2 colour sweeps on the 2D workload's
-    coarsest level (512^2 coarsened four times: 32^2, h = 3.2, kappa = dt/(2h^2) ~ 0.0024)
-    reduce a random right-hand side's residual norm by at least 1e3, the reduction the
-    direct coarse solve would be replaced by."""
+    """On the 2D workload's coarsest level (512^2 coarsened four times: 32^2, h = 3.2,
+    kappa = dt/(2h^2) ~ 0.0024) two colour sweeps reduce a random right-hand side's
+    residual norm by at least 1e3, the reduction the iterated coarsest solve asks for:
+    it needs at most two of its four sweeps there."""
     g = G.Grid((32, 32), 3.2)
     r2 = sum(c ** 2 for c in g.coords()).ravel()
     v0 = -1.0 / np.sqrt(r2 + 1.0)
@@ -129,3 +129,64 @@ def test_coarsest_level_sweeps_reduce_residual_by_a_thousand():
     for _ in range(2):
         x = relax.reference_sweep(sysm.K, b, x, bl, g.npts, 8)
     assert kkt.residual_norm(sysm, b - sysm.K @ x) <= 1e-6 * N0
+
+
+def _coarse_problem(n=16, h=3.2, n_t=8, block=(8, 8), seed=5):
+    g = G.Grid((n, n), h)
+    r2 = sum(c ** 2 for c in g.coords()).ravel()
+    v0 = -1.0 / np.sqrt(r2 + 1.0)
+    H = relax.build_hierarchy(g, v0, n_t, 0.05, block, 1)
+    sysm = H[0].system
+    rng = np.random.default_rng(seed)
+    b = rng.normal(size=sysm.size) + 1j * rng.normal(size=sysm.size)
+    return H[0], sysm, b
+
+
+def test_iterated_coarsest_solve_converges_to_the_direct_coarse_solution():
+    """Sweeps repeated to a tiny reduction reach the coarse system's direct
+    solution, the coarse inverse of Eq. (correction_fine)."""
+    lev, sysm, b = _coarse_problem(n=16, block=(4, 4))
+    x, done = relax.coarsest_solve(lev, sysm.K, b, np.zeros_like(b), 60, coarse_reduction=1e-13)
+    xd = kkt.solve_direct(sysm.K, b)
+    assert np.abs(x - xd).max() <= 1e-11 * np.abs(xd).max()
+    assert 1 < done < 60
+
+
+def test_iterated_coarsest_solve_stops_at_the_first_sweep_that_meets_the_reduction():
+    lev, sysm, b = _coarse_problem(n=16, block=(4, 4), seed=6)
+    P, n_t = lev.grid.npts, sysm.n_t
+    n0 = kkt.residual_norm(sysm, b)
+    for red in (1e-2, 1e-5, 1e-8):
+        x, done = relax.coarsest_solve(lev, sysm.K, b, np.zeros_like(b), 40, coarse_reduction=red)
+        assert kkt.residual_norm(sysm, b - sysm.K @ x) <= red ** 2 * n0
+        # the same number of plain sweeps, and one fewer: the count is the first that meets it
+        xs = np.zeros_like(b)
+        for k in range(done):
+            prev = xs
+            xs = relax.reference_sweep(sysm.K, b, xs, lev.blocks, P, n_t)
+        np.testing.assert_array_equal(xs, x)
+        assert done == 1 or kkt.residual_norm(sysm, b - sysm.K @ prev) > red ** 2 * n0
+    # the cap: a reduction out of reach stops after nu_coarse sweeps
+    _, done = relax.coarsest_solve(lev, sysm.K, b, np.zeros_like(b), 2, coarse_reduction=1e-30)
+    assert done == 2
+
+
+def test_vcycles_with_the_iterated_coarsest_solve_converge_like_a_direct_coarse_solve():
+    """The reading of the coarsest solve: sweeps to a 1e-3 reduction in place of
+    the direct coarse solve leave the V-cycle's convergence unchanged (2D
+    soft-Coulomb, h = 0.2, N_t = 8, three levels, kappa = 0.625): every cycle's
+    residual ratio within a factor 1.5 of the direct variant's."""
+    g, v0, psi0, sysm = _setup((32, 32), h=0.2, n_t=8)
+    H = relax.build_hierarchy(g, v0, 8, 0.05, (4, 4), 3)
+    b = kkt.rhs(sysm, psi0)
+    x0 = kkt.initial_guess(sysm, psi0)
+    n0 = kkt.residual_norm(sysm, b - sysm.K @ x0)
+    hist = {}
+    for name, kw in (("direct", dict(coarse_direct=True)), ("iterated", dict(coarse_reduction=1e-3, nu_coarse=8))):
+        x, h = x0, []
+        for _ in range(4):
+            x = relax.reference_vcycle(H, 0, x, b, 1, 1, **kw)
+            h.append(np.sqrt(kkt.residual_norm(sysm, b - sysm.K @ x) / n0))
+        hist[name] = np.array(h)
+    assert hist["direct"][-1] < 1e-9
+    assert np.all(hist["iterated"] <= 1.5 * hist["direct"]) and np.all(hist["direct"] <= 1.5 * hist["iterated"])

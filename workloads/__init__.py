@@ -60,11 +60,10 @@ def config(name, n=None, levels=None, steps=None):
         cfg["steps"] = int(steps)
     cfg["shape"] = (cfg["n"],) * cfg["dim"]
     cfg["t_total"] = cfg["steps"] * cfg["dt"]
-    # full sweeps on the coarsest level of a V-cycle: one when it is a coarse grid
-    # (its problem is dominated by the time coupling, so one sweep leaves the
-    # cycle's contraction unchanged), two when the coarsest level is the fine grid
-    # itself (levels = 1: those sweeps are the whole smoother)
-    cfg["nu_coarse"] = 2 if cfg["levels"] == 1 else 1
+    # the coarsest-level solve of a V-cycle: colour sweeps until its residual norm
+    # has fallen by 1e3, at most four of them
+    cfg["nu_coarse"] = 4
+    cfg["coarse_reduction"] = 1e-3
     return cfg
 
 
