@@ -174,6 +174,41 @@ def cpu_baseline(name, budget_s=15.0):
                                       "step system, the oracle's kkt.step"}}
 
 
+def oracle_direct_2d(sizes=(64, 128), repeats=3):
+    """The oracle's direct solve of one step of the 2D soft-Coulomb workload
+    (same h, dt, N_t, potential, state) at reduced sizes: SuperLU factorisation
+    (COLAMD) and solve timed separately, median of `repeats`."""
+    import numpy as np
+    import scipy.sparse.linalg as spla
+    import workloads as W
+    from oracle import grid as G
+    from oracle import kkt
+    out = {"workload": "2d_softcoulomb", "threads": threads_in_use(), "cores": os.cpu_count(),
+           "method": "scipy.sparse.linalg.splu (SuperLU, COLAMD) of the assembled step system", "sizes": {}}
+    for n in sizes:
+        cfg = W.config("2d_softcoulomb", n=n)
+        v0 = W.potential(cfg)
+        psi0 = W.initial_state(cfg, v0)
+        g = G.Grid(cfg["shape"], cfg["h"])
+        sysm = kkt.StepSystem(g, v0, cfg["n_t"], cfg["dt"])
+        b = kkt.rhs(sysm, psi0)
+        Kc = sysm.K.tocsc()
+        tf, ts = [], []
+        for _ in range(repeats):
+            t_a = time.perf_counter()
+            lu = spla.splu(Kc, permc_spec="COLAMD")
+            tf.append(time.perf_counter() - t_a)
+            t_a = time.perf_counter()
+            x = lu.solve(b)
+            ts.append(time.perf_counter() - t_a)
+        res = float(np.abs(sysm.K @ x - b).max())
+        out["sizes"][f"{n}x{n}"] = {"unknowns": sysm.size, "factor_s": float(np.median(tf)),
+                                    "solve_s": float(np.median(ts)), "max_residual": res}
+        print(f"[oracle-direct] {n}^2: factor {np.median(tf):.2f} s, solve {np.median(ts):.3f} s",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def pulse_of(cfg):
     """The workload's pulse as Propagator arguments (None without a field)."""
     import workloads as W
@@ -325,7 +360,13 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
+    ap.add_argument("--oracle-direct", action="store_true",
+                    help="only time the oracle's direct step solve (SuperLU factor and solve, median of 3) "
+                         "of the 2D soft-Coulomb workload at 64^2 and 128^2, on the host")
     args = ap.parse_args()
+    if args.oracle_direct:
+        print(json.dumps(oracle_direct_2d()))
+        return
     if args.copy_probe:
         import torch
         n = (1 << 30) // 8
