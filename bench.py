@@ -209,6 +209,72 @@ def oracle_direct_2d(sizes=(64, 128), repeats=3):
     return out
 
 
+# Relaxation variants over groups of 2^d elements (Sec. "Convergence"): each
+# element relaxed separately (blocks of edge e), the group relaxed
+# simultaneously (blocks of edge 2e), or separately after a correction found
+# on the coarse grid whose element is the group (one more level: the residual
+# projected, the coarse element relaxed, the correction interpolated, then the
+# fine elements relaxed separately; the paper's intergrid-transfer variant).
+VARIANT_PROBLEMS = {
+    "2d": dict(workload="2d_softcoulomb", n=256, edge=4),
+    "3d": dict(workload="3d_laser", n=128, edge=2),
+}
+
+
+def relaxation_variants(torch, lam, precision="fp64", iters=6, problems=("2d", "3d")):
+    """Residual reduction per iteration and GPU time per iteration of the three
+    variants, from the same initial guess of one step (the workloads' potential,
+    h, dt and N_t, without field)."""
+    import numpy as np
+    import workloads as W
+    out = {}
+    dev = torch.device("cuda:0")
+    for key in problems:
+        spec = VARIANT_PROBLEMS[key]
+        cfg = W.config(spec["workload"], n=spec["n"])
+        v0 = W.potential(cfg)
+        psi0 = W.initial_state(cfg, v0)
+        d, e = cfg["dim"], spec["edge"]
+        v0_t = torch.as_tensor(v0, device=dev)
+        psi_t = torch.as_tensor(psi0, device=dev)
+        P, nt = int(np.prod(cfg["shape"])), cfg["n_t"]
+        c0 = torch.zeros(P * nt, dtype=torch.complex128, device=dev)
+        c0.view(P, nt)[:, 0] = psi_t
+        l0 = torch.zeros(P, dtype=torch.complex128, device=dev)
+        res = {}
+        for name, block, levels, (pre, post, coarse) in (
+                ("separate", e, 1, (0, 0, 1)),
+                ("simultaneous", 2 * e, 1, (0, 0, 1)),
+                ("intergrid", e, 2, (0, 1, 1))):
+            prop = lam.Propagator(cfg["shape"], cfg["h"], v0_t, nt, cfg["dt"], (block,) * d, levels=levels,
+                                  nu_pre=pre, nu_post=post, nu_coarse=coarse, precision=precision)
+            _, _, n0 = prop.residual_action(0.0, psi_t, c0, l0, want_fields=False)
+            prop.set_state(0.0, psi_t, c0, l0)
+            prop.vcycle(norm=False)                       # warm-up
+            prop.set_state(0.0, psi_t, c0, l0)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(prop.stream)
+            for _ in range(iters):
+                prop.vcycle(norm=False)
+            ev[1].record(prop.stream)
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / iters
+            c, l_ = prop.get_state()
+            _, _, nk = prop.residual_action(0.0, psi_t, c, l_, want_fields=False)
+            rate = (nk / n0) ** (0.5 / iters)
+            res[name] = {"block": "x".join([str(block)] * d), "levels": levels, "ms_per_iteration": ms,
+                         "residual_ratio_per_iteration": rate,
+                         "decades_per_ms": -np.log10(rate) / ms if rate > 0 else None}
+            prop.close()
+        sep = res["separate"]["ms_per_iteration"]
+        for r in res.values():
+            r["cost_vs_separate"] = r["ms_per_iteration"] / sep
+        out[key] = {"problem": f"{spec['workload']} at {'x'.join(str(k) for k in cfg['shape'])}, h={cfg['h']}, "
+                               f"N_t={nt}, dt={cfg['dt']}, no field, {precision}", "variants": res}
+    return out
+
+
 def pulse_of(cfg):
     """The workload's pulse as Propagator arguments (None without a field)."""
     import workloads as W
@@ -363,7 +429,16 @@ def main():
     ap.add_argument("--oracle-direct", action="store_true",
                     help="only time the oracle's direct step solve (SuperLU factor and solve, median of 3) "
                          "of the 2D soft-Coulomb workload at 64^2 and 128^2, on the host")
+    ap.add_argument("--variants", action="store_true",
+                    help="only measure the relaxation variants over groups of 2^d elements (separate, "
+                         "simultaneous, intergrid transfer): residual ratio and time per iteration")
     args = ap.parse_args()
+    if args.variants:
+        import torch
+        from paper_1111_4363_amd import lam
+        lam.load_library()
+        print(json.dumps({p: relaxation_variants(torch, lam, p) for p in ("fp64", "mixed")}))
+        return
     if args.oracle_direct:
         print(json.dumps(oracle_direct_2d()))
         return

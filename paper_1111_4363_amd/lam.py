@@ -337,7 +337,12 @@ class Propagator:
     def relax_sweep(self, colour, level=0):
         _check(self._lib.lam_relax_sweep(self._ctx, int(level), int(colour)), "lam_relax_sweep")
 
-    def vcycle(self):
+    def vcycle(self, norm=True):
+        """One V-cycle; returns N afterwards (synchronises), or None with norm=False
+        (queued on the stream only)."""
+        if not norm:
+            _check(self._lib.lam_vcycle(self._ctx, None), "lam_vcycle")
+            return None
         N = ctypes.c_double()
         _check(self._lib.lam_vcycle(self._ctx, ctypes.byref(N)), "lam_vcycle")
         return N.value
