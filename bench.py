@@ -275,6 +275,39 @@ def relaxation_variants(torch, lam, precision="fp64", iters=6, problems=("2d", "
     return out
 
 
+# (kappa, nu) regimes of the paper's convergence maps (Sec. "Convergence")
+PW_REGIMES = [(0.0, 0.0), (0.1, 0.0), (1.0, 0.0), (10.0, 0.0), (0.0, 1.0), (0.0, -1.0), (1.0, 1.0), (1.0, -1.0)]
+
+
+def plane_wave_maps(torch, lam, npts=128, kmax=8.0, bases=((3, 3), (4, 4), (6, 6))):
+    """The plane-wave convergence maps on an npts x npts grid of (k, w) in
+    [-kmax, kmax]^2 (cell centres), for every regime, basis size and mode: the
+    fraction of trial waves whose residual norm falls (ratio < 1) and falls ten
+    times (< 0.1), the median log10 of the ratio, and the GPU time of the map."""
+    import numpy as np
+    grid = [-kmax + 2 * kmax * (j + 0.5) / npts for j in range(npts)]
+    out = []
+    for mode in ("one", "simultaneous", "intergrid"):
+        for nx, nt in bases:
+            for kappa, nu in PW_REGIMES:
+                torch.cuda.synchronize()
+                t_a = time.perf_counter()
+                rr, ar = lam.plane_wave_map(nx, nt, mode, kappa, nu, grid, grid)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t_a) * 1e3
+                r = rr.cpu().numpy().ravel()
+                a = ar.cpu().numpy().ravel()
+                ok = np.isfinite(r)
+                lr = np.log10(r[ok])
+                out.append({"mode": mode, "n_x": nx, "n_t": nt, "kappa": kappa, "nu": nu,
+                            "frac_resid_below_1": float(np.mean(r[ok] < 1.0)),
+                            "frac_resid_below_0.1": float(np.mean(r[ok] < 0.1)),
+                            "median_log10_resid_ratio": float(np.median(lr)),
+                            "median_log10_action_ratio": float(np.median(np.log10(a[np.isfinite(a)]))),
+                            "ms_per_map": ms, "points": npts * npts})
+    return out
+
+
 def pulse_of(cfg):
     """The workload's pulse as Propagator arguments (None without a field)."""
     import workloads as W
@@ -432,7 +465,16 @@ def main():
     ap.add_argument("--variants", action="store_true",
                     help="only measure the relaxation variants over groups of 2^d elements (separate, "
                          "simultaneous, intergrid transfer): residual ratio and time per iteration")
+    ap.add_argument("--plane-wave", action="store_true",
+                    help="only compute the Legendre-element plane-wave convergence maps (128 x 128 trial "
+                         "waves per regime, basis and mode) and summarise them")
     args = ap.parse_args()
+    if args.plane_wave:
+        import torch
+        from paper_1111_4363_amd import lam
+        lam.load_library()
+        print(json.dumps(plane_wave_maps(torch, lam)))
+        return
     if args.variants:
         import torch
         from paper_1111_4363_amd import lam

@@ -310,6 +310,46 @@ int lam_residual_action_noalloc(const lam_grid* grid, const lam_time* time, cons
                                 const lam_c64* psi0, const lam_c64* c, const lam_c64* lam, lam_c64* rho,
                                 lam_c64* sigma, double* norm, void* hip_stream);
 
+/* ---- The plane-wave relaxation experiment in the Legendre element basis ----
+ * Sec. "Implementation with Legendre Polynomials" (element matrices O, U, Q, T,
+ * transfers, continuity) and Sec. "Convergence" (the experiment).  A regime is
+ * the dimensionless element operator of Eq. (leastaction_dimensionless),
+ *   i O_ij Q_nm - 2 kappa T_ij U_nm - nu O_ij U_nm,
+ * on n_x x n_t Legendre functions per element (1..8 each), and a relaxation mode:
+ *   LAM_PW_ONE           one element [-1, 1];
+ *   LAM_PW_SIMULTANEOUS  two elements [-1, 0], [0, 1] relaxed at once;
+ *   LAM_PW_INTERGRID     two elements: the parent element's correction (Galerkin
+ *                        problem of Eq. (residual_rough), Eq. (correction_fine)),
+ *                        then each element with its interface held fixed.
+ * (elements x n_x x n_t <= LAM_PW_MAX_UNKNOWNS).  T_ij is the closed form the
+ * paper prints, (j(j+1) - i(i+1))/2 for i > j, i - j even, read as the entry of
+ * trial i in test row j. */
+#define LAM_PW_ONE           0
+#define LAM_PW_SIMULTANEOUS  1
+#define LAM_PW_INTERGRID     2
+#define LAM_PW_MAX_UNKNOWNS  72
+
+typedef struct {
+    int n_x, n_t;        /* Legendre functions per element in space and in time */
+    int mode;            /* LAM_PW_* */
+    double kappa, nu;    /* kinetic and potential action parameters */
+} lam_pw_regime;
+
+/* For every trial f = exp(i(k x + w t)) of the grid (k[ik], w[iw]) (host arrays
+ * of nk and nw values; x, t in [-1, 1]): project f onto the element(s) (L2,
+ * continuous across the interface), relax once in the correction form with the
+ * correction zero at the initial time and at both ends (and continuous inside),
+ * and write sqrt(N_after / N_before) to resid_ratio[iw * nk + ik] and
+ * |S_after| / |S_before| to action_ratio[iw * nk + ik] (device, FP64), where
+ * N = r^H (O (x) U) r is the norm of the residual r = -A C (without multiplier
+ * terms) and S = C^H A C the action.  A trial whose residual or action is zero
+ * gives NaN.  The call builds the regime's matrices on the host, copies them to
+ * a device buffer it allocates, runs the kernel on hip_stream (NULL = null
+ * stream), synchronises it and frees the buffer.  Errors: LAM_EINVAL (sizes,
+ * mode, pointers, a singular reduced system), LAM_ENOMEM, LAM_EHIP. */
+int lam_plane_wave_map(const lam_pw_regime* regime, int nk, const double* k, int nw, const double* w,
+                       double* resid_ratio, double* action_ratio, void* hip_stream);
+
 /* Inner passes of the subvolume solves on `level`: hist (host, LAM_MAX_INNER
  * + 2 entries) receives in hist[p] the number of subvolumes whose last solve
  * took p inner corrections (0 without field) and in hist[LAM_MAX_INNER + 1]

@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/lam_kernels.hip", "csrc/lam_api.hip"]
+SOURCES = ["csrc/lam_kernels.hip", "csrc/lam_api.hip", "csrc/lam_planewave.hip"]
 LIB = os.path.join(HERE, "liblam.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -65,6 +65,15 @@ class LamSolver(ctypes.Structure):
                 ("n_inner", ctypes.c_int), ("time_factor", ctypes.c_int), ("coarse_reduction", ctypes.c_double)]
 
 
+class LamPWRegime(ctypes.Structure):
+    _fields_ = [("n_x", ctypes.c_int), ("n_t", ctypes.c_int), ("mode", ctypes.c_int), ("kappa", ctypes.c_double),
+                ("nu", ctypes.c_double)]
+
+
+PW_MODE = {"one": 0, "simultaneous": 1, "intergrid": 2}
+LAM_PW_MAX_UNKNOWNS = 72
+
+
 class LamStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("sweeps_fine", ctypes.c_int), ("resid0", ctypes.c_double),
                 ("resid", ctypes.c_double), ("t_factor_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
@@ -102,6 +111,7 @@ SIGNATURES = {
     "lam_level_shape": (_I, [_P, _I, _PI]),
     "lam_block_factor": (_I, [_P, _I, _I, _PD, _PD]),
     "lam_pass_stats": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
+    "lam_plane_wave_map": (_I, [ctypes.POINTER(LamPWRegime), _I, _PD, _I, _PD, _P, _P, _P]),
     "lam_residual_action_noalloc": (_I, [ctypes.POINTER(LamGrid), ctypes.POINTER(LamTime), ctypes.POINTER(LamHam),
                                          _D, _P, _P, _P, _P, _P, _P, _P]),
     "lam_profile": (_I, [_P, _I]),
@@ -221,6 +231,23 @@ def residual_action_noalloc(shape, h, v0, n_t, dt, t0, psi0, c, lam, rho=None, s
         _ptr(c, torch.complex128, P * nt, "c"), _ptr(lam, torch.complex128, P, "lam"),
         _ptr(rho, torch.complex128, P * nt, "rho"), _ptr(sigma, torch.complex128, P, "sigma"),
         _ptr(norm, torch.float64, 1, "norm"), _stream_handle(stream))
+
+
+def plane_wave_map(n_x, n_t, mode, kappa, nu, k, w, stream=None, device="cuda"):
+    """lam_plane_wave_map: residual-norm and action ratios of one relaxation of the
+    trial exp(i(k x + w t)) for every (w, k) of the grid; returns two device float64
+    tensors of shape (len(w), len(k))."""
+    lib = load_library()
+    k = [float(v) for v in k]
+    w = [float(v) for v in w]
+    rg = LamPWRegime(int(n_x), int(n_t), PW_MODE[mode], float(kappa), float(nu))
+    rr = torch.empty((len(w), len(k)), dtype=torch.float64, device=device)
+    ar = torch.empty_like(rr)
+    ka = (ctypes.c_double * len(k))(*k)
+    wa = (ctypes.c_double * len(w))(*w)
+    _check(lib.lam_plane_wave_map(ctypes.byref(rg), len(k), ka, len(w), wa, _ptr(rr, torch.float64),
+                                  _ptr(ar, torch.float64), _stream_handle(stream)), "lam_plane_wave_map")
+    return rr, ar
 
 
 class Propagator:

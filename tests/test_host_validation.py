@@ -95,3 +95,19 @@ def test_noalloc_residual_rejects_grids_beyond_its_scratch():
 def test_noalloc_residual_validates_like_create():
     assert _noalloc(16, 0) == lam.LAM_EINVAL          # n_t out of range
     assert _noalloc(16, 9) == lam.LAM_EINVAL
+
+
+def _pw(n_x=3, n_t=3, mode=0, kappa=1.0, nu=0.0, nk=4):
+    lib = lam.load_library()
+    rg = lam.LamPWRegime(n_x, n_t, mode, kappa, nu)
+    k = (ctypes.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    dummy = ctypes.c_double(0.0)
+    p = ctypes.cast(ctypes.pointer(dummy), ctypes.c_void_p)
+    return lib.lam_plane_wave_map(ctypes.byref(rg), nk, k, 4, k, p, p, None)
+
+
+@pytest.mark.parametrize("over", [dict(n_x=0), dict(n_x=9), dict(n_t=9), dict(mode=3), dict(mode=-1),
+                                  dict(mode=1, n_x=8, n_t=8),          # 2 x 64 unknowns > 72
+                                  dict(kappa=float("inf")), dict(nk=0)])
+def test_plane_wave_map_rejects_invalid_regimes_before_any_device_call(over):
+    assert _pw(**over) == lam.LAM_EINVAL
