@@ -64,6 +64,7 @@ extern "C" {
 #define LAM_MAX_NT     8    /* largest number of Legendre time functions */
 #define LAM_MAX_BLOCK  64   /* largest number of grid points in one subvolume */
 #define LAM_MAX_INNER  32   /* largest n_inner (inner passes of one subvolume solve) */
+#define LAM_MAX_SPLIT  8    /* largest max_split (sub-steps of dt / 256) */
 #define LAM_NOALLOC_SCRATCH_BYTES (4u << 20)  /* fixed device scratch per GPU (4 MiB) */
 
 #define LAM_PULSE_NONE          0
@@ -137,6 +138,21 @@ typedef struct {
                          coarsest residual norm sqrt(N) has fallen by this factor from
                          its value at the start of the solve, at most grid.nu_coarse
                          (decided on the device; lam_stats counts sweeps and misses) */
+    int max_split;    /* time-step splitting, 0..LAM_MAX_SPLIT (0 = off).  Halving the
+                         step halves both dimensionless parameters of the least-action
+                         equations (kappa = p_max^2 dt / 2, nu = V dt; Sec. "Implementation
+                         with Legendre Polynomials", after Eq. (leastaction_dimensionless)),
+                         which brings relaxation back into its convergent regime.  With
+                         max_split > 0 a solve is abandoned as soon as its residual norm
+                         grows (a checked V-cycle ends above N0, or above the one checked
+                         before it while sqrt(N / N0) > 100 tol), diverges or misses tol
+                         after max_cycles, and the
+                         step is then done as two steps of half its length, each of which
+                         may split again, down to dt / 2^max_split.  The result is the
+                         state after the sub-steps; lam_stats reports how many were solved
+                         and the deepest halving used.  Forward steps (lam_solve_step,
+                         lam_propagate) and adjoint steps (lam_adjoint_step, which splits
+                         the same way its forward recomputation does) */
 } lam_solver;
 
 typedef struct {
@@ -151,6 +167,9 @@ typedef struct {
     int coarse_sweeps;    /* full sweeps of the coarsest-level solves (coarse_reduction > 0) */
     int coarse_unmet;     /* V-cycles whose coarsest solve stopped at nu_coarse sweeps before
                              reaching coarse_reduction */
+    int substeps;         /* steps solved, counting each sub-step of a split step (1 per
+                             unsplit step) */
+    int split_depth;      /* the deepest halving used: sub-steps of dt / 2^split_depth */
 } lam_stats;
 
 /* Create a propagator context: builds the level hierarchy (coarse grids with

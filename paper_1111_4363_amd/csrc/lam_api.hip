@@ -386,9 +386,16 @@ struct lam_ctx {
     int L = 0;
     std::vector<Level> lv;
     std::vector<double> coef;
-    double U[kMaxNT] = {};
+    double U[kMaxNT] = {};        // U_mm of the current step length dt_cur
+    // time-step splitting: steps in progress have length dt_cur = dt / 2^depth
+    int depth = 0;
+    double dt_cur = 0.0;
+    int state_depth = 0;          // depth of the state loaded in the context
+    std::vector<double2*> d_split; // per depth: the state between two halves, then the
+                                   // adjoint right-hand side between them (2P each)
     // current step
     double t0 = NAN;
+    int W_depth = 0;              // depth whose step length W was built for
     double W[kMaxNT * kMaxNT] = {};
     int field_on = 0;
     int n_inner = 0;
@@ -417,21 +424,24 @@ struct lam_ctx {
     double2* d_cf = nullptr;      // forward coefficients kept for the gradients
     // time factor records (layout in lam_internal.h): TS reals each
     int TS = 0;
-    double* d_tf0 = nullptr;      // without field: the forward record, then the adjoint one (FP64)
+    double* d_tf0 = nullptr;      // without field, per depth 0..max_split: the forward record,
+                                  // then the adjoint one (FP64)
     float* d_tf0f = nullptr;      // and their FP32 copies
-    std::vector<double> h_tf0[2]; // host copies (the fallback of a slab factor)
+    std::vector<std::vector<double>> h_tf0;  // host copies, [2 depth + dir] (the fallback of a slab factor)
     size_t nslab_total = 0;       // slabs over all levels
     // with a field: per direction, one record per slab of every level (FP64), then
     // their FP32 copies; rebuilt on the host for every step and copied in stream order
     unsigned char* d_tfs[2] = {nullptr, nullptr};
-    double tf_t[2] = {NAN, NAN};  // step whose records d_tfs[dir] hold
+    double tf_t[2] = {NAN, NAN};  // step (start, depth) whose records d_tfs[dir] hold
+    int tf_depth[2] = {0, 0};
     double mf_t = NAN;            // stored per-mode inverses: step with a field they were built
-                                  // for (-inf: without field; NaN: none)
+    int mf_depth = 0;             // for (-inf: without field; NaN: none), and its depth
     struct Stage {                // pinned host staging of one step's records
         unsigned char* h = nullptr;
         hipEvent_t ev = nullptr;  // recorded after the copy that reads h
         double t = NAN;
         int dir = -1;
+        int depth = 0;
     } stage[2];
     int stage_next = 0;
     double prep_t = NAN;          // a step whose records the next wait should prepare on the host
@@ -493,7 +503,7 @@ void time_matrix(const lam_ham& h, const double* coef, int ncoef, int nt, double
 }
 
 void time_matrix(const lam_ctx* c, double t0, int q, double* W) {
-    time_matrix(c->ham, c->coef.data(), (int)c->coef.size(), c->nt, c->time.dt, t0, q, W);
+    time_matrix(c->ham, c->coef.data(), (int)c->coef.size(), c->nt, c->dt_cur, t0, q, W);
 }
 
 bool any_nonzero(const double* W, int n) {
@@ -538,7 +548,7 @@ size_t tf_table_bytes(const lam_ctx* c) { return c->nslab_total * (size_t)c->TS 
 // inner passes correct the whole field term.
 int prepare_tables(lam_ctx* c, double t, int dir) {
     for (auto& s : c->stage)
-        if (s.t == t && s.dir == dir) return LAM_OK;
+        if (s.t == t && s.dir == dir && s.depth == c->depth) return LAM_OK;
     auto& s = c->stage[c->stage_next];
     c->stage_next ^= 1;
     HIPCHK(hipEventSynchronize(s.ev));  // the copy that last read this buffer is done
@@ -551,26 +561,30 @@ int prepare_tables(lam_ctx* c, double t, int dir) {
     for (const auto& L : c->lv)
         for (int k = 0; k < L.nslab; ++k) {
             double* rec = h64 + (L.tf_off + k) * (size_t)TS;
-            if (!make_record(c, W, L.zslab[k], dir, rec))
-                std::copy(c->h_tf0[dir].begin(), c->h_tf0[dir].end(), rec);
+            if (!make_record(c, W, L.zslab[k], dir, rec)) {
+                const auto& fb = c->h_tf0[2 * c->depth + dir];
+                std::copy(fb.begin(), fb.end(), rec);
+            }
             float* rf = h32 + (L.tf_off + k) * (size_t)TS;
             for (int i = 0; i < TS; ++i) rf[i] = (float)rec[i];
         }
     s.t = t;
     s.dir = dir;
+    s.depth = c->depth;
     return LAM_OK;
 }
 
 // Make d_tfs[dir] hold the records of step t (a copy queued on the stream:
 // kernels queued before it still read the previous records).
 int upload_tables(lam_ctx* c, double t, int dir) {
-    if (c->tf_t[dir] == t) return LAM_OK;
+    if (c->tf_t[dir] == t && c->tf_depth[dir] == c->depth) return LAM_OK;
     LAMCHK(prepare_tables(c, t, dir));
     for (auto& s : c->stage)
-        if (s.t == t && s.dir == dir) {
+        if (s.t == t && s.dir == dir && s.depth == c->depth) {
             HIPCHK(hipMemcpyAsync(c->d_tfs[dir], s.h, tf_table_bytes(c), hipMemcpyHostToDevice, c->st));
             HIPCHK(hipEventRecord(s.ev, c->st));
             c->tf_t[dir] = t;
+            c->tf_depth[dir] = c->depth;
             return LAM_OK;
         }
     return LAM_EINVAL;
@@ -581,7 +595,7 @@ int upload_tables(lam_ctx* c, double t, int dir) {
 int stored_factors(lam_ctx* c, int dir) {
     if (c->solver.time_factor != LAM_TF_STORED) return LAM_OK;
     const double want = c->field_on ? c->t0 : -INFINITY;
-    if (c->mf_t == want) return LAM_OK;
+    if (c->mf_t == want && c->mf_depth == c->depth) return LAM_OK;
     for (auto& L : c->lv) {
         const double* tf = c->field_on ? reinterpret_cast<const double*>(c->d_tfs[dir]) + L.tf_off * (size_t)c->TS
                                        : nullptr;
@@ -589,15 +603,27 @@ int stored_factors(lam_ctx* c, int dir) {
                                   L.fp32 ? L.d_Minvf : nullptr, c->st));
     }
     c->mf_t = want;
+    c->mf_depth = c->depth;
     return LAM_OK;
+}
+
+// Steps of length dt / 2^d from now on (U and, through the step length, every
+// field matrix and time factor record; the records without field are kept per
+// depth, the others are rebuilt on demand, keyed by their depth).
+void set_depth(lam_ctx* c, int d) {
+    if (c->depth == d && c->dt_cur > 0.0) return;
+    c->depth = d;
+    c->dt_cur = std::ldexp(c->time.dt, -d);
+    for (int m = 0; m < c->nt; ++m) c->U[m] = c->dt_cur / (2.0 * m + 1.0);
 }
 
 // Select the step starting at t0 for solves of direction dir (0 forward, 1
 // adjoint): its field matrix, inner-pass count and time factor records.
 int set_step(lam_ctx* c, double t0, int dir) {
-    if (!(c->t0 == t0)) {
+    if (!(c->t0 == t0 && c->W_depth == c->depth)) {
         time_matrix(c, t0, -1, c->W);
         c->t0 = t0;
+        c->W_depth = c->depth;
     }
     const int nt = c->nt;
     const bool on = any_nonzero(c->W, nt * nt);
@@ -658,7 +684,8 @@ int sweep(lam_ctx* c, int l, int colour, const int* skip = nullptr) {
         a.tf = L.fp32 ? static_cast<const void*>(t32 + off) : static_cast<const void*>(t64 + off);
         a.tf_stride = c->TS;
     } else {
-        a.tf = L.fp32 ? static_cast<const void*>(c->d_tf0f + dir * c->TS) : static_cast<const void*>(c->d_tf0 + dir * c->TS);
+        const size_t off = (2 * (size_t)c->depth + dir) * c->TS;
+        a.tf = L.fp32 ? static_cast<const void*>(c->d_tf0f + off) : static_cast<const void*>(c->d_tf0 + off);
         a.tf_stride = 0;
     }
     a.e = L.d_e;
@@ -814,6 +841,11 @@ int queue_norm(lam_ctx* c, int slot) {
 // launched.  When a batch overshoots, the extra cycles only refine the state;
 // `cycles` reports the cycles run.
 // n0_slot >= 0: N0 of this (forward) solve is already queued into that slot.
+// While the step may still be split (depth < max_split), a solve whose checked
+// norm ends above N0, or above the norm checked before it while still far from
+// tol (above 100 tol, clear of the rounding floor), is abandoned at once
+// (LAM_EDIVERGED): it is leaving the convergent regime, and the shorter steps
+// will be solved instead.
 // next_out non-null (forward solves of lam_propagate whose next step has no
 // field, like this one): before each wait, the end state goes to next_out, the
 // next step's initial state to the context's d_*_next buffers and its N0 to
@@ -832,7 +864,8 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
     int rc = LAM_ENOCONV;
     int batch = std::min(predict, maxc);  // 0 on a context's first solve: look at N0 first
     const int cs0 = c->coarse_sweeps, cu0 = c->coarse_unmet;
-    double N0 = 0.0, N = 0.0;
+    const bool may_split = c->depth < c->solver.max_split;
+    double N0 = 0.0, N = 0.0, Nchk = -1.0;
     for (;;) {
         const int nb = std::min(batch, maxc - queued);
         // norms after the last cycle of the batch (it decides) and, on every
@@ -878,12 +911,18 @@ int solve_loop(lam_ctx* c, lam_stats* stats, int n0_slot = -1, double2* next_out
             break;
         }
         bool div = false;
+        if (Nchk < 0.0) Nchk = N0;
         for (int k = first_norm; first_norm >= 0 && k <= queued; ++k) {
             const double Nk = c->h_norms[k];
             if (!std::isfinite(Nk) || Nk > 1e12 * N0) {
                 div = true;
                 break;
             }
+            if (may_split && (Nk > N0 || (Nk > Nchk && std::sqrt(Nk / N0) > 100.0 * c->solver.tol))) {
+                div = true;
+                break;
+            }
+            Nchk = Nk;
             if (conv < 0 && std::sqrt(Nk / N0) <= c->solver.tol) conv = k;
         }
         if (div) {
@@ -930,6 +969,7 @@ int validate(const lam_grid* g, const lam_time* t, const lam_ham* h, const lam_s
     if (s->precision != LAM_FP64 && s->precision != LAM_MIXED) return LAM_EINVAL;
     if (s->max_cycles < 0 || !(s->tol >= 0.0) || s->n_inner < -1 || s->n_inner > LAM_MAX_INNER) return LAM_EINVAL;
     if (!(s->coarse_reduction >= 0.0 && s->coarse_reduction < 1.0)) return LAM_EINVAL;
+    if (s->max_split < 0 || s->max_split > LAM_MAX_SPLIT) return LAM_EINVAL;
     if (s->time_factor != LAM_TF_SHARED && s->time_factor != LAM_TF_STORED) return LAM_EINVAL;
     long bpts = 1;
     for (int a = 0; a < g->dim; ++a) {
@@ -1024,6 +1064,7 @@ void free_ctx(lam_ctx* c) {
     (void)hipFree(c->d_c_next);
     (void)hipFree(c->d_lam_next);
     (void)hipFree(c->d_bs_next);
+    for (auto* p : c->d_split) (void)hipFree(p);
     if (c->h_G) (void)hipHostFree(c->h_G);
     for (auto e : c->ev) (void)hipEventDestroy(e);
     delete c;
@@ -1145,15 +1186,23 @@ int build(lam_ctx* c, const double* v0_dev) {
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_G), sizeof(double2) * nt * nt) != hipSuccess)
         return LAM_ENOMEM;
     {
-        // time factor records without field (forward, adjoint), and the per-slab
-        // tables and staging buffers for steps with a field
+        // time factor records without field (forward, adjoint) for every step
+        // length dt / 2^d a split may use, and the per-slab tables and staging
+        // buffers for steps with a field
         const int TS = tf_record_stride(nt);
         c->TS = TS;
-        std::vector<double> h(2 * TS);
-        for (int dir = 0; dir < 2; ++dir) {
-            if (!make_record(c, nullptr, 0.0, dir, h.data() + dir * TS)) return LAM_EINVAL;
-            c->h_tf0[dir].assign(h.begin() + dir * TS, h.begin() + (dir + 1) * TS);
+        const int nd = c->solver.max_split + 1;
+        std::vector<double> h(2 * (size_t)nd * TS);
+        c->h_tf0.resize(2 * nd);
+        for (int d = 0; d < nd; ++d) {
+            set_depth(c, d);
+            for (int dir = 0; dir < 2; ++dir) {
+                double* rec = h.data() + (2 * d + dir) * (size_t)TS;
+                if (!make_record(c, nullptr, 0.0, dir, rec)) return LAM_EINVAL;
+                c->h_tf0[2 * d + dir].assign(rec, rec + TS);
+            }
         }
+        set_depth(c, 0);
         std::vector<float> hf(h.begin(), h.end());
         LAMCHK(dalloc(&c->d_tf0, h.size()));
         LAMCHK(dalloc(&c->d_tf0f, hf.size()));
@@ -1172,6 +1221,154 @@ int build(lam_ctx* c, const double* v0_dev) {
     for (auto& L : c->lv) LAMCHK(factor_level(c, L));
     HIPCHK(hipStreamSynchronize(c->st));
     return LAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Steps, split in halves while their solves fail (solver max_split > 0).
+// ---------------------------------------------------------------------------
+
+// Statistics of the solves of one call: the work of every solve (including the
+// abandoned ones), and for the accepted (sub-)steps the worst ratio of final to
+// initial residual (resid0 / resid), the last step's, their count and the
+// deepest halving.
+struct Totals {
+    lam_stats s{};
+    double worst = -1.0;
+    void work(const lam_stats& st) {
+        s.cycles += st.cycles;
+        s.coarse_sweeps += st.coarse_sweeps;
+        s.coarse_unmet += st.coarse_unmet;
+    }
+    void accept(const lam_stats& st, int depth) {
+        s.resid0_last = st.resid0;
+        s.resid_last = st.resid;
+        const double ratio = st.resid0 > 0.0 ? st.resid / st.resid0 : 0.0;
+        if (ratio > worst) {
+            worst = ratio;
+            s.resid0 = st.resid0;
+            s.resid = st.resid;
+        }
+        s.substeps += 1;
+        s.split_depth = std::max(s.split_depth, depth);
+    }
+};
+
+bool splittable(const lam_ctx* c, int rc, int depth) {
+    return (rc == LAM_EDIVERGED || rc == LAM_ENOCONV) && depth < c->solver.max_split;
+}
+
+// The two buffers of halving depth d (allocated on first use).
+int split_buffers(lam_ctx* c, int d, double2** mid, double2** gmid) {
+    if ((int)c->d_split.size() <= d) c->d_split.resize(d + 1, nullptr);
+    const size_t P = (size_t)c->lv[0].g.P;
+    if (!c->d_split[d]) LAMCHK(dalloc(&c->d_split[d], 2 * P));
+    *mid = c->d_split[d];
+    *gmid = c->d_split[d] + P;
+    return LAM_OK;
+}
+
+int forward_halves(lam_ctx* c, double t0, int depth, const double2* psi_in, double2* psi_out, Totals& tot);
+
+// The forward step [t0, t0 + dt / 2^depth) from psi_in to psi_out.  A solve that
+// fails while a further halving is allowed is replaced by the two halves.
+// psi_in may be psi_out, or the finest level's constraint right-hand side
+// (which holds the step's initial state and is not written by its solve).
+int forward_split(lam_ctx* c, double t0, int depth, const double2* psi_in, double2* psi_out, Totals& tot) {
+    set_depth(c, depth);
+    LAMCHK(set_step(c, t0, 0));
+    Level& L = c->lv[0];
+    HIPCHK(launch_init_forward(c->nt, L.g.P, psi_in, L.d_c, L.d_lam, L.d_bs, c->st));
+    c->adjoint = 0;
+    c->have_state = 1;
+    c->state_t0 = t0;
+    c->state_depth = depth;
+    lam_stats st{};
+    const int rc = solve_loop(c, &st);
+    tot.work(st);
+    if (splittable(c, rc, depth)) return forward_halves(c, t0, depth + 1, psi_in, psi_out, tot);
+    if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
+    tot.accept(st, depth);
+    HIPCHK(launch_end_eval(c->nt, L.g.P, L.d_c, psi_out, c->st));
+    return rc;
+}
+
+// Two steps of length dt / 2^depth from t0 (the halves of a step of twice that).
+int forward_halves(lam_ctx* c, double t0, int depth, const double2* psi_in, double2* psi_out, Totals& tot) {
+    const int r1 = forward_split(c, t0, depth, psi_in, psi_out, tot);
+    if (r1 != LAM_OK && r1 != LAM_ENOCONV) return r1;
+    const int r2 = forward_split(c, t0 + std::ldexp(c->time.dt, -depth), depth, psi_out, psi_out, tot);
+    return r2 != LAM_OK ? r2 : r1;
+}
+
+// The adjoint of the forward step [t0, t0 + dt / 2^depth) from psi_in (the
+// forward solve is recomputed first, and decides whether the step splits, as
+// it did going forward): g_in = the adjoint state at the step's start for
+// g_out at its end, gradients accumulated.  A split step's adjoint runs
+// through its halves in reverse, with the state between them recomputed.
+int adjoint_split(lam_ctx* c, double t0, int depth, const double2* psi_in, const double2* g_out, double2* g_in,
+                  double* dL_dv0, double* dL_dcoef, Totals& tot) {
+    set_depth(c, depth);
+    LAMCHK(set_step(c, t0, 0));
+    Level& L = c->lv[0];
+    const int nt = c->nt;
+    const size_t P = L.g.P;
+    // 1. recompute the forward solution of this step from its checkpoint (the host
+    //    builds the adjoint time factor records meanwhile)
+    HIPCHK(launch_init_forward(nt, (int)P, psi_in, L.d_c, L.d_lam, L.d_bs, c->st));
+    c->adjoint = 0;
+    c->have_state = 1;
+    c->state_t0 = t0;
+    c->state_depth = depth;
+    if (c->field_on) {
+        c->prep_t = t0;
+        c->prep_dir = 1;
+    }
+    int rc = solve_loop(c, nullptr);
+    c->prep_t = NAN;
+    if (splittable(c, rc, depth)) {
+        double2 *mid, *gmid;
+        LAMCHK(split_buffers(c, depth + 1, &mid, &gmid));
+        Totals fwd;
+        rc = forward_split(c, t0, depth + 1, psi_in, mid, fwd);
+        if (rc != LAM_OK) return rc;
+        const double th = t0 + std::ldexp(c->time.dt, -(depth + 1));
+        LAMCHK(adjoint_split(c, th, depth + 1, mid, g_out, gmid, dL_dv0, dL_dcoef, tot));
+        return adjoint_split(c, t0, depth + 1, psi_in, gmid, g_in, dL_dv0, dL_dcoef, tot);
+    }
+    if (rc != LAM_OK) return rc;
+    HIPCHK(launch_copy_c2(L.d_c, c->d_cf, P * nt, c->st));
+    // 2. adjoint solve K^H mu = E^H g_out from mu = 0
+    LAMCHK(set_step(c, t0, 1));
+    HIPCHK(launch_copy_c2(g_out, c->d_g, P, c->st));
+    HIPCHK(launch_init_zero(nt, (int)P, L.d_c, L.d_lam, c->st));
+    c->adjoint = 1;
+    lam_stats st{};
+    rc = solve_loop(c, &st);
+    tot.work(st);
+    if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
+    tot.accept(st, depth);
+    // 3. gradients
+    int np = 0;
+    const bool want_coef = dL_dcoef && !c->coef.empty() &&
+                           (c->ham.pulse_kind == LAM_PULSE_FOURIER || c->ham.pulse_kind == LAM_PULSE_SIN2_FOURIER);
+    HIPCHK(launch_gradients(nt, L.g, c->U, c->d_cf, L.d_c, dL_dv0, want_coef ? c->d_Gpart : nullptr, &np, c->st));
+    HIPCHK(launch_copy_c2(L.d_lam, g_in, P, c->st));
+    if (want_coef) {
+        HIPCHK(launch_reduce_c2(c->d_Gpart, np, nt * nt, c->d_G, c->st));
+        HIPCHK(hipMemcpyAsync(c->h_G, c->d_G, sizeof(double2) * nt * nt, hipMemcpyDeviceToHost, c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (want_coef) {
+        double Wq[kMaxNT * kMaxNT];
+        for (size_t q = 0; q < c->coef.size(); ++q) {
+            time_matrix(c, t0, (int)q, Wq);
+            double acc = 0.0;
+            for (int m = 0; m < nt; ++m)
+                for (int n = 0; n < nt; ++n) acc += Wq[m * nt + n] * c->h_G[m * nt + n].x;
+            dL_dcoef[q] += 2.0 * acc;
+        }
+    }
+    return rc;
 }
 
 }  // namespace
@@ -1227,7 +1424,7 @@ int lam_create(const lam_grid* grid, const lam_time* time, const lam_ham* ham, c
     c->coef.assign(ham->coef, ham->coef + ham->n_coef);
     c->ham.coef = nullptr;
     c->ham.v0 = nullptr;
-    for (int m = 0; m < c->nt; ++m) c->U[m] = time->dt / (2.0 * m + 1.0);
+    set_depth(c, 0);
     const int r = build(c, ham->v0);
     if (r != LAM_OK) {
         free_ctx(c);
@@ -1250,7 +1447,11 @@ int lam_set_pulse(lam_ctx* ctx, int n_coef, const double* coef) {
     ctx->tf_t[0] = ctx->tf_t[1] = NAN;
     for (auto& s : ctx->stage) s.t = NAN;
     ctx->mf_t = NAN;
-    if (ctx->have_state) LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
+    if (ctx->have_state) {
+        set_depth(ctx, ctx->state_depth);
+        LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
+        set_depth(ctx, 0);
+    }
     return LAM_OK;
 }
 
@@ -1261,7 +1462,11 @@ int lam_set_potential(lam_ctx* ctx, const double* v0) {
         HIPCHK(launch_average_potential(ctx->lv[l - 1].g, ctx->lv[l].g, ctx->lv[l - 1].d_v0, ctx->lv[l].d_v0,
                                         ctx->st));
     for (auto& L : ctx->lv) LAMCHK(factor_level(ctx, L));
-    if (ctx->have_state) LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
+    if (ctx->have_state) {
+        set_depth(ctx, ctx->state_depth);
+        LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
+        set_depth(ctx, 0);
+    }
     HIPCHK(hipStreamSynchronize(ctx->st));
     return LAM_OK;
 }
@@ -1307,6 +1512,7 @@ int lam_residual_adjoint(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c6
 
 int lam_set_state(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c, const lam_c64* lam) {
     if (!ctx || bad_ptr(psi0) || bad_ptr(c) || bad_ptr(lam)) return LAM_EINVAL;
+    set_depth(ctx, 0);
     LAMCHK(set_step(ctx, t0, 0));
     Level& L = ctx->lv[0];
     const size_t P = L.g.P;
@@ -1316,11 +1522,13 @@ int lam_set_state(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c
     ctx->adjoint = 0;
     ctx->have_state = 1;
     ctx->state_t0 = t0;
+    ctx->state_depth = 0;
     return LAM_OK;
 }
 
 int lam_set_adjoint_state(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c, const lam_c64* mu_lam) {
     if (!ctx || bad_ptr(g) || bad_ptr(mu_c) || bad_ptr(mu_lam)) return LAM_EINVAL;
+    set_depth(ctx, 0);
     LAMCHK(set_step(ctx, t0, 1));
     Level& L = ctx->lv[0];
     const size_t P = L.g.P;
@@ -1330,6 +1538,7 @@ int lam_set_adjoint_state(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c
     ctx->adjoint = 1;
     ctx->have_state = 1;
     ctx->state_t0 = t0;
+    ctx->state_depth = 0;
     return LAM_OK;
 }
 
@@ -1352,17 +1561,22 @@ int lam_relax_sweep(lam_ctx* ctx, int level, int colour) {
         return LAM_EINVAL;
     }
     // the step of the loaded state (a residual call may have looked at another one)
+    set_depth(ctx, ctx->state_depth);
     LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
-    return sweep(ctx, level, colour);
+    const int rc = sweep(ctx, level, colour);
+    set_depth(ctx, 0);
+    return rc;
 }
 
 int lam_vcycle(lam_ctx* ctx, double* norm) {
     if (!ctx) return LAM_EINVAL;
     if (!ctx->have_state) return LAM_ESTATE;
+    set_depth(ctx, ctx->state_depth);
     LAMCHK(set_step(ctx, ctx->state_t0, ctx->adjoint));
-    LAMCHK(vcycle(ctx, 0));
-    if (norm) LAMCHK(norm0(ctx, norm));
-    return LAM_OK;
+    int rc = vcycle(ctx, 0);
+    if (rc == LAM_OK && norm) rc = norm0(ctx, norm);
+    set_depth(ctx, 0);
+    return rc;
 }
 
 int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_out, lam_stats* stats) {
@@ -1370,18 +1584,14 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
     const auto t_a = std::chrono::steady_clock::now();
     ctx->t_factor_ms = 0.0;
     const int sw0 = ctx->sweeps_fine;
-    LAMCHK(set_step(ctx, t0, 0));
-    Level& L = ctx->lv[0];
-    HIPCHK(launch_init_forward(ctx->nt, L.g.P, reinterpret_cast<const double2*>(psi_in), L.d_c, L.d_lam, L.d_bs,
-                               ctx->st));
-    ctx->adjoint = 0;
-    ctx->have_state = 1;
-    ctx->state_t0 = t0;
-    const int rc = solve_loop(ctx, stats);
+    Totals tot;
+    const int rc = forward_split(ctx, t0, 0, reinterpret_cast<const double2*>(psi_in),
+                                 reinterpret_cast<double2*>(psi_out), tot);
+    set_depth(ctx, 0);
     if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
-    HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, reinterpret_cast<double2*>(psi_out), ctx->st));
     LAMCHK(wait_stream(ctx));
     if (stats) {
+        *stats = tot.s;
         stats->sweeps_fine = ctx->sweeps_fine - sw0;
         stats->t_factor_ms = ctx->t_factor_ms;
         stats->t_solve_ms =
@@ -1392,18 +1602,20 @@ int lam_solve_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, lam_c64* psi_
 
 int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, lam_c64* psi_out,
                   lam_stats* stats) {
-    if (!ctx || bad_ptr(psi_in) || bad_ptr(psi_out) || n_steps < 0) return LAM_EINVAL;
+    if (!ctx || bad_ptr(psi_in) || bad_ptr(psi_out)) return LAM_EINVAL;
+    if (n_steps < 0) return LAM_EINVAL;
     const auto t_a = std::chrono::steady_clock::now();
     ctx->t_factor_ms = 0.0;
     const int sw0 = ctx->sweeps_fine;
     Level& L = ctx->lv[0];
-    lam_stats tot{};
-    double worst = -1.0;
+    Totals tot;
     int rc = LAM_OK;
     const lam_c64* src = psi_in;
+    double2* out = reinterpret_cast<double2*>(psi_out);
     int n0_slot = -1;  // >= 0: this step's initial state is in place and its N0 queued into that slot
     for (int k = 0; k < n_steps; ++k) {
         const double tk = t0 + k * ctx->time.dt;
+        set_depth(ctx, 0);
         LAMCHK(set_step(ctx, tk, 0));
         if (n0_slot < 0)
             HIPCHK(launch_init_forward(ctx->nt, L.g.P, reinterpret_cast<const double2*>(src), L.d_c, L.d_lam,
@@ -1411,6 +1623,7 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
         ctx->adjoint = 0;
         ctx->have_state = 1;
         ctx->state_t0 = tk;
+        ctx->state_depth = 0;
         // The next step's start (its initial state and N0, with its field) is
         // queued ahead of each wait for this step's norms, and while the GPU works
         // the host builds the next step's time factor records.
@@ -1426,40 +1639,38 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
         const int next_slot = ctx->solver.max_cycles + 1 + (k & 1);
         bool ready = false;
         lam_stats st{};
-        rc = solve_loop(ctx, &st, n0_slot, ahead ? reinterpret_cast<double2*>(psi_out) : nullptr, next_slot, &ready,
-                        next_field ? Wn : nullptr);
+        rc = solve_loop(ctx, &st, n0_slot, ahead ? out : nullptr, next_slot, &ready, next_field ? Wn : nullptr);
         ctx->prep_t = NAN;
-        if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
+        tot.work(st);
         n0_slot = -1;
-        if (ready) {
-            // psi_out holds this step's end state; the next step starts from the spare buffers
-            std::swap(L.d_c, ctx->d_c_next);
-            std::swap(L.d_lam, ctx->d_lam_next);
-            std::swap(L.d_bs, ctx->d_bs_next);
-            n0_slot = next_slot;
+        if (splittable(ctx, rc, 0)) {
+            // the step again as two halves, from its initial state (the finest
+            // level's constraint right-hand side: the failed solve left it intact)
+            rc = forward_halves(ctx, tk, 1, L.d_bs, out, tot);
+            set_depth(ctx, 0);
+            if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
         } else {
-            HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, reinterpret_cast<double2*>(psi_out), ctx->st));
+            if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
+            tot.accept(st, 0);
+            if (ready) {
+                // psi_out holds this step's end state; the next step starts from the spare buffers
+                std::swap(L.d_c, ctx->d_c_next);
+                std::swap(L.d_lam, ctx->d_lam_next);
+                std::swap(L.d_bs, ctx->d_bs_next);
+                n0_slot = next_slot;
+            } else {
+                HIPCHK(launch_end_eval(ctx->nt, L.g.P, L.d_c, out, ctx->st));
+            }
         }
         src = psi_out;
-        tot.cycles += st.cycles;
-        tot.coarse_sweeps += st.coarse_sweeps;
-        tot.coarse_unmet += st.coarse_unmet;
-        tot.resid0_last = st.resid0;
-        tot.resid_last = st.resid;
-        const double ratio = st.resid0 > 0.0 ? st.resid / st.resid0 : 0.0;
-        if (ratio > worst) {
-            worst = ratio;
-            tot.resid0 = st.resid0;
-            tot.resid = st.resid;
-        }
         if (rc != LAM_OK) break;
     }
     LAMCHK(wait_stream(ctx));
     if (stats) {
-        tot.sweeps_fine = ctx->sweeps_fine - sw0;
-        tot.t_factor_ms = ctx->t_factor_ms;
-        tot.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
-        *stats = tot;
+        *stats = tot.s;
+        stats->sweeps_fine = ctx->sweeps_fine - sw0;
+        stats->t_factor_ms = ctx->t_factor_ms;
+        stats->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
     }
     return rc;
 }
@@ -1470,55 +1681,14 @@ int lam_adjoint_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, const lam_c
     const auto t_a = std::chrono::steady_clock::now();
     ctx->t_factor_ms = 0.0;
     const int sw0 = ctx->sweeps_fine;
-    LAMCHK(set_step(ctx, t0, 0));
-    Level& L = ctx->lv[0];
-    const int nt = ctx->nt;
-    const size_t P = L.g.P;
-    // 1. recompute the forward solution of this step from its checkpoint (the host
-    //    builds the adjoint time factor records meanwhile)
-    HIPCHK(launch_init_forward(nt, (int)P, reinterpret_cast<const double2*>(psi_in), L.d_c, L.d_lam, L.d_bs,
-                               ctx->st));
-    ctx->adjoint = 0;
-    ctx->have_state = 1;
-    ctx->state_t0 = t0;
-    if (ctx->field_on) {
-        ctx->prep_t = t0;
-        ctx->prep_dir = 1;
-    }
-    int rc = solve_loop(ctx, nullptr);
-    ctx->prep_t = NAN;
-    if (rc != LAM_OK) return rc;
-    HIPCHK(launch_copy_c2(L.d_c, ctx->d_cf, P * nt, ctx->st));
-    // 2. adjoint solve K^H mu = E^H g_out from mu = 0
-    LAMCHK(set_step(ctx, t0, 1));
-    HIPCHK(launch_copy_c2(reinterpret_cast<const double2*>(g_out), ctx->d_g, P, ctx->st));
-    HIPCHK(launch_init_zero(nt, (int)P, L.d_c, L.d_lam, ctx->st));
-    ctx->adjoint = 1;
-    rc = solve_loop(ctx, stats);
+    Totals tot;
+    const int rc = adjoint_split(ctx, t0, 0, reinterpret_cast<const double2*>(psi_in),
+                                 reinterpret_cast<const double2*>(g_out), reinterpret_cast<double2*>(g_in), dL_dv0,
+                                 dL_dcoef, tot);
+    set_depth(ctx, 0);
     if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
-    // 3. gradients
-    int np = 0;
-    const bool want_coef = dL_dcoef && !ctx->coef.empty() &&
-                           (ctx->ham.pulse_kind == LAM_PULSE_FOURIER || ctx->ham.pulse_kind == LAM_PULSE_SIN2_FOURIER);
-    HIPCHK(launch_gradients(nt, L.g, ctx->U, ctx->d_cf, L.d_c, dL_dv0, want_coef ? ctx->d_Gpart : nullptr, &np,
-                            ctx->st));
-    HIPCHK(launch_copy_c2(L.d_lam, reinterpret_cast<double2*>(g_in), P, ctx->st));
-    if (want_coef) {
-        HIPCHK(launch_reduce_c2(ctx->d_Gpart, np, nt * nt, ctx->d_G, ctx->st));
-        HIPCHK(hipMemcpyAsync(ctx->h_G, ctx->d_G, sizeof(double2) * nt * nt, hipMemcpyDeviceToHost, ctx->st));
-    }
-    HIPCHK(hipStreamSynchronize(ctx->st));
-    if (want_coef) {
-        double Wq[kMaxNT * kMaxNT];
-        for (size_t q = 0; q < ctx->coef.size(); ++q) {
-            time_matrix(ctx, t0, (int)q, Wq);
-            double acc = 0.0;
-            for (int m = 0; m < nt; ++m)
-                for (int n = 0; n < nt; ++n) acc += Wq[m * nt + n] * ctx->h_G[m * nt + n].x;
-            dL_dcoef[q] += 2.0 * acc;
-        }
-    }
     if (stats) {
+        *stats = tot.s;
         stats->sweeps_fine = ctx->sweeps_fine - sw0;
         stats->t_factor_ms = ctx->t_factor_ms;
         stats->t_solve_ms =

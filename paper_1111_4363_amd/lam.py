@@ -26,6 +26,7 @@ LAM_ETOOBIG = -7
 LAM_MAX_NT = 8
 LAM_MAX_BLOCK = 64
 LAM_MAX_INNER = 32
+LAM_MAX_SPLIT = 8
 PULSE = {"none": 0, "sin2": 1, "fourier": 2, "sin2+fourier": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 INTERP = {"linear": 0, "constant": 1}
@@ -62,7 +63,8 @@ class LamHam(ctypes.Structure):
 
 class LamSolver(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_cycles", ctypes.c_int),
-                ("n_inner", ctypes.c_int), ("time_factor", ctypes.c_int), ("coarse_reduction", ctypes.c_double)]
+                ("n_inner", ctypes.c_int), ("time_factor", ctypes.c_int), ("coarse_reduction", ctypes.c_double),
+                ("max_split", ctypes.c_int)]
 
 
 class LamPWRegime(ctypes.Structure):
@@ -78,7 +80,8 @@ class LamStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("sweeps_fine", ctypes.c_int), ("resid0", ctypes.c_double),
                 ("resid", ctypes.c_double), ("t_factor_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("resid0_last", ctypes.c_double), ("resid_last", ctypes.c_double),
-                ("coarse_sweeps", ctypes.c_int), ("coarse_unmet", ctypes.c_int)]
+                ("coarse_sweeps", ctypes.c_int), ("coarse_unmet", ctypes.c_int), ("substeps", ctypes.c_int),
+                ("split_depth", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -256,7 +259,7 @@ class Propagator:
     def __init__(self, shape, h, v0, n_t, dt, block, levels=1, nu_pre=1, nu_post=1, nu_coarse=2,
                  interp="linear", periodic=False, mass=1.0, field_axis=-1, pulse=None,
                  precision="fp64", tol=1e-10, max_cycles=50, n_inner=-1, time_factor="shared", coarse_reduction=0.0,
-                 stream=None):
+                 max_split=0, stream=None):
         lib = load_library()
         v0 = v0.contiguous()
         g, t, ham, self._coef, coef, self.npts = _describe(shape, h, v0, n_t, dt, block, levels, nu_pre, nu_post,
@@ -267,7 +270,7 @@ class Propagator:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.n_coef = len(coef)
         s = LamSolver(PRECISION[precision], float(tol), int(max_cycles), int(n_inner), TIME_FACTOR[time_factor],
-                      float(coarse_reduction))
+                      float(coarse_reduction), int(max_split))
         self.levels = int(levels)
         self.precision = precision
         # what the context holds (the autograd function restores its own inputs)

@@ -31,7 +31,8 @@ def _create(**over):
     h.t_total = over.get("t_total", 1.0)
     h.n_coef = over.get("n_coef", 0)
     s = lam.LamSolver(over.get("precision", 0), over.get("tol", 1e-10), over.get("max_cycles", 10),
-                      over.get("n_inner", -1), over.get("time_factor", 0), over.get("coarse_reduction", 0.0))
+                      over.get("n_inner", -1), over.get("time_factor", 0), over.get("coarse_reduction", 0.0),
+                      over.get("max_split", 0))
     out = ctypes.c_void_p()
     return lib.lam_create(ctypes.byref(g), ctypes.byref(t), ctypes.byref(h), ctypes.byref(s), None,
                           ctypes.byref(out))
@@ -48,6 +49,7 @@ def _create(**over):
     dict(field_axis=2), dict(pulse_kind=7), dict(pulse_kind=1, t_total=0.0), dict(n_coef=3),
     dict(precision=2), dict(tol=-1.0), dict(n_inner=-2), dict(interp=3), dict(v0=None), dict(time_factor=2),
     dict(n_inner=33), dict(coarse_reduction=-0.1), dict(coarse_reduction=1.0), dict(coarse_reduction=float("nan")),
+    dict(max_split=-1), dict(max_split=9),
 ])
 def test_invalid_arguments_are_rejected(over):
     assert _create(**over) == lam.LAM_EINVAL

@@ -190,3 +190,41 @@ def test_vcycles_with_the_iterated_coarsest_solve_converge_like_a_direct_coarse_
         hist[name] = np.array(h)
     assert hist["direct"][-1] < 1e-9
     assert np.all(hist["iterated"] <= 1.5 * hist["direct"]) and np.all(hist["direct"] <= 1.5 * hist["iterated"])
+
+
+def _vcycle_history(dt, n=64, levels=3, cycles=8):
+    """sqrt(N/N0) after each V-cycle of the 1D harmonic-oscillator step with
+    h = 40/256 (kappa = dt / (2 h^2)), N_t = 8, subvolumes of 8 points."""
+    h = 40.0 / 256
+    grid = G.Grid((n,), h)
+    x = (np.arange(n) - 0.5 * (n - 1)) * h
+    v0 = 0.5 * x * x
+    psi0 = np.exp(-0.5 * (x - 1.0) ** 2 + 0.5j * x)
+    levs = relax.build_hierarchy(grid, v0, 8, dt, (8,), levels)
+    sysm = levs[0].system
+    _, hist = relax.solve_by_vcycles(levs, kkt.initial_guess(sysm, psi0), kkt.rhs(sysm, psi0), tol=1e-10,
+                                     max_cycles=cycles, nu_coarse=2)
+    return np.array(hist)
+
+
+def test_halving_the_step_halves_both_dimensionless_parameters():
+    """Without a field the step operator is affine in dt: the time coupling i Q
+    does not depend on it, the kinetic and potential blocks (kappa, nu of Eq.
+    (leastaction_dimensionless)) scale with it, so K(dt) - K(dt/2) = 2 (K(dt/2) - K(dt/4))
+    and the dt-proportional part at dt/2 is half that at dt."""
+    grid = G.Grid((12,), 0.3)
+    v0 = np.linspace(-1.0, 2.0, 12)
+    K = [kkt.StepSystem(grid, v0, 5, dt, 0.0, None).K.toarray() for dt in (0.4, 0.2, 0.1)]
+    np.testing.assert_allclose(K[0] - K[1], 2.0 * (K[1] - K[2]), atol=1e-13)
+    assert np.abs(K[0] - K[1]).max() > 0.01
+
+
+def test_time_step_splitting_recovers_convergence():
+    """The paper's remedy for a step outside the convergent regime: at kappa = 10.2
+    and 5.1 (dt = 0.5, 0.25) the V-cycles' residual grows within a few cycles, at
+    kappa = 2.56 (dt = 0.125, two halvings) it falls below 1e-6 in eight."""
+    for dt in (0.5, 0.25):
+        h = _vcycle_history(dt)
+        assert h[-1] > 1.0 and np.any(np.diff(h[1:]) > 0)
+    h = _vcycle_history(0.125)
+    assert h[-1] < 1e-6 and np.all(np.diff(h) < 0)
