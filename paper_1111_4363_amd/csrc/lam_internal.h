@@ -12,7 +12,8 @@ namespace lam {
 constexpr int kMaxNT = LAM_MAX_NT;
 constexpr int kMaxB = LAM_MAX_BLOCK;
 constexpr int kThreads = 256;
-constexpr int kSweepThreads = 512;   // the colour sweep: 8 waves per block
+constexpr int kSweepThreads = 512;   // the colour sweep: 8 waves per block, one lane per (point, component)
+constexpr int kPairThreads = 256;    // its FP32 shared-factor form: 4 waves per block, two components per lane
 constexpr int kLdsPad = kMaxB + 1;   // row stride of per-block matrices in LDS
 
 // Geometry of one level, passed by value to kernels.

@@ -1450,6 +1450,364 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     }
 }
 
+// The FP32 shared-factor colour sweep with two time components per lane: four
+// lanes per point (lane q of a point takes m = q and m = q + 4), so a 64-point
+// block is one wave per SIMD.  The per-point index arithmetic is done once for
+// two components, every wave takes part in the matrix-core steps, and at 168
+// registers three blocks share a compute unit (LDS: under 50 KB each).  The
+// arithmetic of each item is that of k_sweep<NT, float, false>.
+template <int NT>
+__global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, TimeOps<NT> to) {
+    using BT = float;
+    using C = cx<BT>;
+    // a finished coarsest-level solve: the rest of its launches do nothing
+    if (a.skip && *a.skip) return;
+    constexpr int THR = kPairThreads;
+    constexpr int NW = THR / 64;                             // waves per block
+    constexpr int NQ = NT + 1;
+    constexpr int N2 = 2 * NQ;                               // reals per point / mode
+    constexpr int NC = 2 * NT;                               // real columns of the reduced system
+    constexpr int VPT = kMaxB * kMaxB / THR;                 // eigenvector entries per thread
+    constexpr int TFR = tf_record_reals(NT);                 // reals of the two mixing matrices and lam
+    constexpr int TPT = (TFR + THR - 1) / THR;
+    constexpr int LPP = 4, IPL = 2;                          // lanes per point, items per lane
+    static_assert(kMaxNT <= LPP * IPL && kMaxB * LPP == THR && NW == 4, "every residual item has a lane");
+    __shared__ BT Vs[kMaxB * kLdsPad];
+    __shared__ double2 cs[kMaxB * NT];
+    __shared__ double2 ls[kMaxB];
+    __shared__ double v0s[kMaxB];
+    __shared__ double zs[kMaxB];
+    __shared__ int gidx[kMaxB];
+    __shared__ C rs[kMaxB * NQ];   // local residual
+    __shared__ C rh[kMaxB * NQ];   // per-mode solutions
+    __shared__ C xb[kMaxB * NQ];   // reduced right-hand side, then the correction V y
+    __shared__ BT tfs[TFR];        // shared time factor of this direction: E1, E3 real forms, lam
+    __shared__ BT es[kMaxB];
+    __shared__ double2 sgs[kMaxB];  // constraint residual per point
+    __shared__ double tos[NT + NT * NT];   // the time operators U, W (indexed per lane, so staged here)
+    __shared__ double red[NW];
+    __shared__ double rnorm_sh;
+
+    {
+        // touch every 64-byte line of the sweep arguments at once (see k_sweep)
+        const auto* kp = (const __attribute__((address_space(4))) int*)__builtin_amdgcn_kernarg_segment_ptr();
+        constexpr int kEnd = (int)sizeof(SweepArgs);
+        int t = kp[kEnd / 4 - 1];
+#pragma unroll
+        for (int off = 0; off < kEnd; off += 64) t ^= kp[off / 4];
+        asm volatile("" ::"s"(t));
+    }
+    const LevelGeom& g = a.g;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    // block of this workgroup (as in k_sweep)
+    const int dim = g.dim, colour = a.colour, half = a.half_last, nb1 = g.nblk[1], nb2 = g.nblk[2];
+    const int idx = (int)blockIdx.x;
+    const int line = idx / half, i = idx - line * half;
+    const int lead0 = dim == 3 ? line / nb1 : line;
+    const int lead1 = dim == 3 ? line - lead0 * nb1 : 0;
+    const int last = 2 * i + ((colour + lead0 + lead1) & 1);
+    I3 bc{dim == 1 ? last : lead0, dim == 2 ? last : (dim == 3 ? lead1 : 0), dim == 3 ? last : 0};
+    int blk = (bc.x * nb1 + bc.y) * nb2 + bc.z;
+    if (!a.arith_blocks) {
+        blk = a.blocks[idx];
+        bc = block_coords(g, blk);
+    }
+    const int b = g.bpts;
+    const int nd = 2 * g.dim;
+    const double inner_tol2 = 1e-10;   // FP32: about what FP32 corrections resolve (in norm, 1e-5)
+    double rprev = 0.0;
+
+    // ---- 1. eigenvectors and the slab's time factor record (see k_sweep) ----
+    const BT* tfg = static_cast<const BT*>(a.tf) + (size_t)comp(bc, g.fax) * a.tf_stride;
+    const double zf = (double)tfg[TFR];
+    const int iw = tid - NT;
+    const double tov = tid < NT ? to.U[tid] : to.W[(iw >= 0 && iw < NT * NT) ? iw : 0];
+    BT vr[VPT];
+    {
+        const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
+        const int bb = b * b;
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) {
+            const int t = tid + r * THR;
+            vr[r] = Vg[t < bb ? t : bb - 1];
+        }
+    }
+    BT tr[TPT];
+#pragma unroll
+    for (int r = 0; r < TPT; ++r) {
+        const int t = tid + r * THR;
+        tr[r] = tfg[t < TFR ? t : TFR - 1];
+    }
+    const BT ep = (BT)a.e[(size_t)blk * b + (tid < b ? tid : 0)];
+
+    // ---- 1a. addresses: thread = point l = tid / 4 and the items (l, q), (l, q + 4)
+    //      (q = tid % 4; items past NT or the block are idle and load a clamped,
+    //      valid address) ----
+    const int l_it = tid / LPP < b ? tid / LPP : 0;
+    const int q_it = tid & (LPP - 1);
+    bool item[IPL];
+    int m_it[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        item[k] = q_it + LPP * k < NT && tid / LPP < b;
+        m_it[k] = item[k] ? q_it + LPP * k : 0;
+    }
+    const I3 lc_it = local_coords(g, l_it);
+    const I3 gi_it = global_of_local(g, bc, lc_it);
+    const int gj_it = point_index(g, gi_it);
+    int hidx[6], hmask = 0, lcode = 0;
+#pragma unroll
+    for (int dir = 0; dir < 6; ++dir) {
+        const int ax = dir >> 1;
+        const bool up = dir & 1;
+        const int la = comp(lc_it, ax), ga = comp(gi_it, ax);
+        const int bd = g.bdim[ax], na = g.n[ax];
+        const int gstr = ax == 0 ? g.n[1] * g.n[2] : (ax == 1 ? g.n[2] : 1);
+        const bool used = dir < nd;
+        const bool inside = up ? la + 1 < bd : la > 0;
+        const bool self_wrap = g.periodic && g.nblk[ax] == 1;
+        const bool edge = up ? ga + 1 >= na : ga == 0;
+        const int gstep = up ? gstr : -gstr;
+        lcode |= (!used ? 0 : (inside ? 1 : (self_wrap ? 2 : 0))) << (2 * dir);
+        const bool halo = used && !inside && !self_wrap && (!edge || g.periodic);
+        const int hw = edge ? gj_it - (up ? 1 : -1) * (na - 1) * gstr : gj_it + gstep;
+        hidx[dir] = halo ? hw : gj_it;
+        hmask |= (halo ? 1 : 0) << dir;
+    }
+    const int tp = tid < b ? tid : 0;
+    const I3 gip = global_of_local(g, bc, local_coords(g, tp));
+    const int gjp = point_index(g, gip);
+
+    // ---- 1b. loads, all in flight together ----
+    double2 own[IPL], hv[IPL][6], rhsv[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        own[k] = a.c[(size_t)gj_it * NT + m_it[k]];
+#pragma unroll
+        for (int dir = 0; dir < 6; ++dir) hv[k][dir] = a.c[(size_t)hidx[dir] * NT + m_it[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        const double2* rbp = a.bc ? a.bc + (size_t)gj_it * NT + m_it[k]
+                                  : (a.bg ? a.bg + gj_it : a.c + (size_t)gj_it * NT + m_it[k]);
+        rhsv[k] = scl2((a.bc || a.bg) ? 1.0 : 0.0, *rbp);
+    }
+    const double v0p = a.v0[gjp];
+    const double2 lp = a.lam[gjp];
+    // the point's constraint right-hand side (lane q = 0 holds m = 0)
+    const double2 sgv = scl2((a.bs && q_it == 0) ? 1.0 : 0.0, (a.bs ? a.bs : a.lam)[gj_it]);
+    // ---- 1c. consume into LDS; sigma = bs - sum_n s_n c_n as a sum over the point's lanes ----
+    if (tid < NT + NT * NT) tos[tid] = tov;
+    {
+        double pr = 0.0, pi = 0.0;
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            const double sm = item[k] ? ((m_it[k] & 1) ? -1.0 : 1.0) : 0.0;
+            pr += sm * own[k].x;
+            pi += sm * own[k].y;
+        }
+        const double sr = group_sum<LPP>(pr), si = group_sum<LPP>(pi);
+        if (tid / LPP < b && q_it == 0) sgs[l_it] = make_double2(sgv.x - sr, sgv.y - si);
+    }
+    double2 halo[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        halo[k] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int dir = 0; dir < 6; ++dir) halo[k] = add2(halo[k], scl2((hmask >> dir) & 1 ? 1.0 : 0.0, hv[k][dir]));
+        if (item[k]) cs[l_it * NT + m_it[k]] = own[k];
+    }
+    if (tid < b) {
+        gidx[tid] = gjp;
+        v0s[tid] = v0p;
+        ls[tid] = lp;
+        zs[tid] = zcoord(g, gip);
+        es[tid] = ep;
+    }
+    {
+        const int bb = b * b;
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) {
+            const int t = tid + r * THR;
+            if (t < bb) {
+                const int j = qdiv_small(t, g.rbp), k = t - j * b;
+                Vs[j * kLdsPad + k] = vr[r];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < TPT; ++r) {
+        const int t = tid + r * THR;
+        if (t < TFR) tfs[t] = tr[r];
+    }
+    __syncthreads();
+
+    // ---- 2. local residual (FP64) and the reduced right-hand side (see k_sweep) ----
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        if (!item[k]) continue;
+        const int l = l_it, m = m_it[k];
+        double2 lap = add2(scl2(-2.0 * g.dim, own[k]), halo[k]);
+#pragma unroll
+        for (int dir = 0; dir < 6; ++dir) {
+            const int ln = code_nb(g, lcode, l, dir);
+            lap = add2(lap, scl2(ln >= 0 ? 1.0 : 0.0, cs[(ln >= 0 ? ln : l) * NT + m]));
+        }
+        const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], own[k]));
+        double2 tq = make_double2(0.0, 0.0);
+        double2 wc = make_double2(0.0, 0.0);
+        if (a.field_on) {
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const double2 cn = cs[l * NT + n];
+                const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
+                tq = add2(tq, scl2(cpl ? 1.0 : 0.0, cn));
+                wc = add2(wc, scl2(tos[NT + m * NT + n], cn));
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < (NT + 1) / 2; ++kk) {
+                const int n = a.adjoint ? m - 1 - 2 * kk : m + 1 + 2 * kk;
+                const bool in = n >= 0 && n < NT;
+                tq = add2(tq, scl2(in ? 1.0 : 0.0, cs[l * NT + (in ? n : m)]));
+            }
+        }
+        const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
+        const double sm = (m & 1) ? -1.0 : 1.0;
+        double2 row = sub2(sub2(tim, scl2(tos[m], hc)), scl2(zs[l], wc));
+        row = add2(row, scl2(sm, ls[l]));
+        const double2 rho = sub2(rhsv[k], row);
+        rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
+        const double2 sg = sgs[l];
+        if (m == 0) rs[l * NQ + NT] = C{(BT)sg.x, (BT)sg.y};
+        double2 r = rho;
+        if (m == 0) {
+            double2 lin = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int dir = 0; dir < 6; ++dir) {
+                const int ln = code_nb(g, lcode, l, dir);
+                lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, sgs[ln >= 0 ? ln : l]));
+            }
+            const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l], sg));
+            r = add2(r, scl2(tos[0], asg));
+        }
+        if (a.field_on) r = add2(r, scl2(zf * tos[NT + m * NT], sg));
+        if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
+        xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
+    }
+    __syncthreads();
+    double r0n = 0.0;
+    if (a.n_inner > 0) {
+        double loc = 0.0;
+        for (int t = tid; t < b * NQ; t += THR) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
+        const double tot = block_sum(loc, red);
+        if (tid == 0) rnorm_sh = tot;
+        __syncthreads();
+        r0n = rnorm_sh;
+        __syncthreads();
+    }
+
+    for (int pass = 0; pass <= a.n_inner; ++pass) {
+        // ---- 3a + 3b. into the block eigenbasis and the per-mode solve, one wave per
+        //      16 modes (all four waves) ----
+        const BT* E1 = tfs;
+        const BT* E3 = tfs + 4 * NT * NT;
+        const C* lamv = reinterpret_cast<const C*>(tfs + 8 * NT * NT);
+        mode_chain<BT, N2, NC>(Vs, reinterpret_cast<const BT*>(xb), b, E1, E3, es, lamv, reinterpret_cast<BT*>(rh),
+                               lane, wave);
+        __syncthreads();
+        // ---- 3c. back to points: xb[j][.] = sum_k V[j][k] rh[k][.] (one 16-row tile per wave) ----
+        {
+            const auto acc = tile_gemm<BT, false, NC, N2>(Vs, reinterpret_cast<const BT*>(rh), b, lane, wave);
+            tile_store<BT>(reinterpret_cast<BT*>(xb), b, NC, N2, lane, wave, acc);
+        }
+        __syncthreads();
+        // ---- 4. corrections: xb[l] holds (dlam, dc_1 .. dc_{NT-1}), dc_0 = sigma -
+        //      sum_{j>=1} s_j dc_j as a sum over the point's lanes ----
+        const bool last = pass == a.n_inner;
+        C dv[IPL], dl = C{0, 0};
+        {
+            C x[IPL];
+            BT pr = (BT)0, pi = (BT)0;
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) {
+                x[k] = xb[l_it * NQ + m_it[k]];
+                const BT sm = (!item[k] || m_it[k] == 0) ? (BT)0 : ((m_it[k] & 1) ? (BT)-1 : (BT)1);
+                pr += sm * x[k].r;
+                pi += sm * x[k].i;
+            }
+            const BT sr = group_sum<LPP>(pr), si = group_sum<LPP>(pi);
+            const C sg = rs[l_it * NQ + NT];
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) dv[k] = m_it[k] > 0 ? x[k] : C{sg.r - sr, sg.i - si};
+            dl = x[0];   // used by the lane holding m = 0 only
+        }
+        if (last) {
+            // the last possible pass writes the updated state straight to HBM
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) {
+                if (!item[k]) continue;
+                const int l = l_it, m = m_it[k];
+                a.c[(size_t)gj_it * NT + m] = add2(cs[l * NT + m], make_double2((double)dv[k].r, (double)dv[k].i));
+                if (m == 0) a.lam[gj_it] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
+            }
+            if (a.passes && tid == 0)
+                a.passes[blk] = (unsigned char)(pass | ((a.n_inner > 0 && a.field_on) ? 0x80 : 0));
+            break;
+        }
+        // inner pass (see k_sweep): the state stays in LDS, the new local residual is
+        // (z_l - zf) (W delta_l)_m on row (l, m) and 0 on the constraint rows
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            if (!item[k]) continue;
+            const int l = l_it, m = m_it[k];
+            cs[l * NT + m] = add2(cs[l * NT + m], make_double2((double)dv[k].r, (double)dv[k].i));
+            if (m == 0) ls[l] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
+            rh[l * NQ + m] = dv[k];
+        }
+        // a point's lanes are one group inside a wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double loc = 0.0;
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            if (!item[k]) continue;
+            const int l = l_it, m = m_it[k];
+            C wd = C{0, 0};
+            if (a.field_on) {
+#pragma unroll 1
+                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tos[NT + m * NT + n], rh[l * NQ + n]);
+            }
+            const C rn = rmul((BT)(zs[l] - zf), wd);
+            rs[l * NQ + m] = rn;
+            if (m == 0) rs[l * NQ + NT] = C{0, 0};
+            xb[l * NQ + m] = rn;
+            loc += (double)rn.r * rn.r + (double)rn.i * rn.i;
+        }
+        {
+            const double tot = block_sum(loc, red);
+            if (tid == 0) rnorm_sh = tot;
+            __syncthreads();
+            const double rn = rnorm_sh;
+            const bool solved = rn <= inner_tol2 * r0n;
+            const bool done = solved || rn > 0.0625 * (pass > 0 ? rprev : r0n);
+            rprev = rn;
+            __syncthreads();
+            if (done) {
+                if (a.passes && tid == 0) a.passes[blk] = (unsigned char)(pass | (solved ? 0 : 0x80));
+                for (int t = tid; t < b * NT; t += THR) {
+                    const int l = t / NT, n = t - l * NT;
+                    a.c[(size_t)gidx[l] * NT + n] = cs[t];
+                }
+                for (int l = tid; l < b; l += THR) a.lam[gidx[l]] = ls[l];
+                break;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K11: step I/O and the adjoint right-hand side.
 // ---------------------------------------------------------------------------
@@ -1723,6 +2081,9 @@ hipError_t launch_sweep(int nt, int mixed, const SweepArgs& a, const double* U, 
     const dim3 grid(nblocks_colour), threads(kSweepThreads);
     if (mixed && a.Minv) {
         LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, float, true>), grid, threads, 0, st, a, make_ops<NT>(U, W)));
+    } else if (mixed && (nt == 8 || nt <= 4)) {
+        // two components per lane (for N_t = 5..7 its registers would spill)
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_sweep_pair<NT>, grid, dim3(kPairThreads), 0, st, a, make_ops<NT>(U, W)));
     } else if (mixed) {
         LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, float, false>), grid, threads, 0, st, a, make_ops<NT>(U, W)));
     } else if (a.Minv) {
