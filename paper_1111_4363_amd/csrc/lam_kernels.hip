@@ -1455,8 +1455,10 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
 // block is one wave per SIMD.  The per-point index arithmetic is done once for
 // two components, every wave takes part in the matrix-core steps, and at 168
 // registers three blocks share a compute unit (LDS: under 50 KB each).  The
-// arithmetic of each item is that of k_sweep<NT, float, false>.
-template <int NT>
+// arithmetic of each item is that of k_sweep<NT, float, false>.  CUBE4: the
+// level is 3D with 4 x 4 x 4 blocks, known at compile time (the block
+// geometry's divisions become shifts and its tests constants).
+template <int NT, bool CUBE4>
 __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, TimeOps<NT> to) {
     using BT = float;
     using C = cx<BT>;
@@ -1498,10 +1500,32 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         asm volatile("" ::"s"(t));
     }
     const LevelGeom& g = a.g;
+    // the block geometry (compile-time for CUBE4): extents, local coordinates of
+    // block point l, global coordinates, in-block neighbour from its 2-bit code
+    const int gdim = CUBE4 ? 3 : g.dim;
+    auto bdim = [&](int ax) { return CUBE4 ? 4 : g.bdim[ax]; };
+    auto local_of = [&](int l) {
+        if constexpr (CUBE4) return I3{l >> 4, (l >> 2) & 3, l & 3};
+        else return local_coords(g, l);
+    };
+    auto global_of = [&](const I3& blk3, const I3& lc) {
+        return I3{blk3.x * bdim(0) + lc.x, blk3.y * bdim(1) + lc.y, blk3.z * bdim(2) + lc.z};
+    };
+    auto nb_of = [&](int lcode, int l, int dir) {
+        if constexpr (CUBE4) {
+            const int ax = dir >> 1;
+            const bool up = dir & 1;
+            const int lstr = ax == 0 ? 16 : (ax == 1 ? 4 : 1);
+            const int code = (lcode >> (2 * dir)) & 3;
+            return code == 0 ? -1 : l + (code == 1 ? (up ? lstr : -lstr) : (up ? -3 : 3) * lstr);
+        } else {
+            return code_nb(g, lcode, l, dir);
+        }
+    };
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     // block of this workgroup (as in k_sweep)
-    const int dim = g.dim, colour = a.colour, half = a.half_last, nb1 = g.nblk[1], nb2 = g.nblk[2];
+    const int dim = gdim, colour = a.colour, half = a.half_last, nb1 = g.nblk[1], nb2 = g.nblk[2];
     const int idx = (int)blockIdx.x;
     const int line = idx / half, i = idx - line * half;
     const int lead0 = dim == 3 ? line / nb1 : line;
@@ -1513,8 +1537,8 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         blk = a.blocks[idx];
         bc = block_coords(g, blk);
     }
-    const int b = g.bpts;
-    const int nd = 2 * g.dim;
+    const int b = CUBE4 ? 64 : g.bpts;
+    const int nd = 2 * gdim;
     const double inner_tol2 = 1e-10;   // FP32: about what FP32 corrections resolve (in norm, 1e-5)
     double rprev = 0.0;
 
@@ -1553,8 +1577,8 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         item[k] = q_it + LPP * k < NT && tid / LPP < b;
         m_it[k] = item[k] ? q_it + LPP * k : 0;
     }
-    const I3 lc_it = local_coords(g, l_it);
-    const I3 gi_it = global_of_local(g, bc, lc_it);
+    const I3 lc_it = local_of(l_it);
+    const I3 gi_it = global_of(bc, lc_it);
     const int gj_it = point_index(g, gi_it);
     int hidx[6], hmask = 0, lcode = 0;
 #pragma unroll
@@ -1562,7 +1586,7 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         const int ax = dir >> 1;
         const bool up = dir & 1;
         const int la = comp(lc_it, ax), ga = comp(gi_it, ax);
-        const int bd = g.bdim[ax], na = g.n[ax];
+        const int bd = bdim(ax), na = g.n[ax];
         const int gstr = ax == 0 ? g.n[1] * g.n[2] : (ax == 1 ? g.n[2] : 1);
         const bool used = dir < nd;
         const bool inside = up ? la + 1 < bd : la > 0;
@@ -1576,7 +1600,7 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         hmask |= (halo ? 1 : 0) << dir;
     }
     const int tp = tid < b ? tid : 0;
-    const I3 gip = global_of_local(g, bc, local_coords(g, tp));
+    const I3 gip = global_of(bc, local_of(tp));
     const int gjp = point_index(g, gip);
 
     // ---- 1b. loads, all in flight together ----
@@ -1631,7 +1655,7 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         for (int r = 0; r < VPT; ++r) {
             const int t = tid + r * THR;
             if (t < bb) {
-                const int j = qdiv_small(t, g.rbp), k = t - j * b;
+                const int j = CUBE4 ? t >> 6 : qdiv_small(t, g.rbp), k = t - j * b;
                 Vs[j * kLdsPad + k] = vr[r];
             }
         }
@@ -1648,10 +1672,10 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
     for (int k = 0; k < IPL; ++k) {
         if (!item[k]) continue;
         const int l = l_it, m = m_it[k];
-        double2 lap = add2(scl2(-2.0 * g.dim, own[k]), halo[k]);
+        double2 lap = add2(scl2(-2.0 * gdim, own[k]), halo[k]);
 #pragma unroll
         for (int dir = 0; dir < 6; ++dir) {
-            const int ln = code_nb(g, lcode, l, dir);
+            const int ln = nb_of(lcode, l, dir);
             lap = add2(lap, scl2(ln >= 0 ? 1.0 : 0.0, cs[(ln >= 0 ? ln : l) * NT + m]));
         }
         const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], own[k]));
@@ -1686,10 +1710,10 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
             double2 lin = make_double2(0.0, 0.0);
 #pragma unroll
             for (int dir = 0; dir < 6; ++dir) {
-                const int ln = code_nb(g, lcode, l, dir);
+                const int ln = nb_of(lcode, l, dir);
                 lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, sgs[ln >= 0 ? ln : l]));
             }
-            const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * g.dim, sg), lin)), scl2(v0s[l], sg));
+            const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * gdim, sg), lin)), scl2(v0s[l], sg));
             r = add2(r, scl2(tos[0], asg));
         }
         if (a.field_on) r = add2(r, scl2(zf * tos[NT + m * NT], sg));
@@ -2083,7 +2107,14 @@ hipError_t launch_sweep(int nt, int mixed, const SweepArgs& a, const double* U, 
         LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, float, true>), grid, threads, 0, st, a, make_ops<NT>(U, W)));
     } else if (mixed && (nt == 8 || nt <= 4)) {
         // two components per lane (for N_t = 5..7 its registers would spill)
-        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_sweep_pair<NT>, grid, dim3(kPairThreads), 0, st, a, make_ops<NT>(U, W)));
+        const LevelGeom& g = a.g;
+        if (g.dim == 3 && g.bdim[0] == 4 && g.bdim[1] == 4 && g.bdim[2] == 4) {
+            LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep_pair<NT, true>), grid, dim3(kPairThreads), 0, st, a,
+                                                   make_ops<NT>(U, W)));
+        } else {
+            LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep_pair<NT, false>), grid, dim3(kPairThreads), 0, st, a,
+                                                   make_ops<NT>(U, W)));
+        }
     } else if (mixed) {
         LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep<NT, float, false>), grid, threads, 0, st, a, make_ops<NT>(U, W)));
     } else if (a.Minv) {

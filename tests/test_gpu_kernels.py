@@ -123,6 +123,10 @@ SWEEP_CASES = [
     dict(shape=(16, 8), n_t=4, block=(4, 4), h=0.3, periodic=True, pulse=PULSE_FOURIER),
     dict(shape=(12, 6), n_t=3, block=(3, 3), h=0.3, potential="random"),
     dict(shape=(16, 16), n_t=4, block=(4, 16), h=0.3, periodic=True),
+    # 3D 4 x 4 x 4 blocks with N_t = 8 and N_t <= 4 (the mixed path's compile-time block
+    # geometry), with a field, and periodic with one block spanning an axis
+    dict(shape=(8, 12, 8), n_t=8, block=(4, 4, 4), h=0.3, pulse=PULSE_BOTH),
+    dict(shape=(4, 8, 8), n_t=4, block=(4, 4, 4), h=0.3, periodic=True),
 ]
 
 
