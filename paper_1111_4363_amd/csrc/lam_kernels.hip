@@ -628,6 +628,93 @@ __global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg,
     *dst = add2(*dst, acc);
 }
 
+// The same interpolation by tiles: a workgroup takes a coarse tile of 2 x 2 x 8
+// points (2 along the used axes but the last, 8 along the last; 1 along unused
+// axes), stages it with a one-point coarse halo in LDS (every component, zero
+// outside a Dirichlet grid, wrapped on a periodic one), and adds the
+// interpolated correction to the fine tile of its children.  Each coarse value
+// is read from memory by the few tiles whose halo holds it, instead of by
+// every fine point that interpolates from it.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_prolong_tile(LevelGeom f, LevelGeom cg, int interp,
+                                                           const double2* __restrict__ cc,
+                                                           const double2* __restrict__ lc,
+                                                           double2* __restrict__ cf, double2* __restrict__ lf,
+                                                           int t1, int t2) {
+    constexpr int NQ = NT + 1;
+    constexpr int HMAX = 4 * 4 * 10;                 // halo points of a 3D tile
+    __shared__ double2 S[HMAX * NQ];
+    const int dim = f.dim;
+    // coarse tile extents and the tile's first coarse point
+    const int ct0 = dim == 1 ? 8 : 2, ct1 = dim == 1 ? 1 : (dim == 2 ? 8 : 2), ct2 = dim == 3 ? 8 : 1;
+    const int bid = (int)blockIdx.x;
+    const int bxy = bid / t2, bz = bid - bxy * t2;
+    const int bx = bxy / t1, by = bxy - bx * t1;
+    const I3 c0{bx * ct0, by * ct1, bz * ct2};
+    // halo extents (one more coarse point on each side of a used axis)
+    const int h0 = ct0 + 2, h1 = dim > 1 ? ct1 + 2 : 1, h2 = dim > 2 ? ct2 + 2 : 1;
+    const int H = h0 * h1 * h2;
+    for (int t = threadIdx.x; t < H * NQ; t += kThreads) {
+        const int hp = t / NQ, q = t - hp * NQ;
+        const int hz = hp % h2, hxy = hp / h2, hy = hxy % h1, hx = hxy / h1;
+        // coarse coordinates of the halo point (axes beyond the rank have extent 1)
+        int cx = c0.x + hx - 1, cy = dim > 1 ? c0.y + hy - 1 : 0, cz = dim > 2 ? c0.z + hz - 1 : 0;
+        bool in = true;
+        // (halo points past a partial tile that no fine point uses may lie more than
+        // one grid length away: reduce fully, so that every load stays in the grid)
+        auto fold = [&](int& v, int n) {
+            if (v < 0 || v >= n) {
+                if (f.periodic) v = ((v % n) + n) % n;
+                else in = false;
+            }
+        };
+        fold(cx, cg.n[0]);
+        fold(cy, cg.n[1]);
+        fold(cz, cg.n[2]);
+        double2 v = make_double2(0.0, 0.0);
+        if (in) {
+            const int J = (cx * cg.n[1] + cy) * cg.n[2] + cz;
+            v = q < NT ? cc[(size_t)J * NT + q] : lc[J];
+        }
+        S[t] = v;
+    }
+    __syncthreads();
+    // fine tile: the children of the coarse tile
+    const int f0 = dim >= 1 ? 2 * ct0 : 1, f1 = dim >= 2 ? 2 * ct1 : 1, f2 = dim >= 3 ? 2 * ct2 : 1;
+    const int F = f0 * f1 * f2;
+    for (int t = threadIdx.x; t < F * NQ; t += kThreads) {
+        const int fp = t / NQ, q = t - fp * NQ;
+        const int lz = fp % f2, lxy = fp / f2, ly = lxy % f1, lx = lxy / f1;
+        const I3 fi{2 * c0.x + lx, dim > 1 ? 2 * c0.y + ly : 0, dim > 2 ? 2 * c0.z + lz : 0};
+        if (fi.x >= f.n[0] || fi.y >= f.n[1] || fi.z >= f.n[2]) continue;
+        // per axis: the parent's halo coordinate, the step to the nearer coarse
+        // neighbour and the two weights (linear: 3/4 and 1/4; constant: 1 and 0)
+        int hp[3], hd[3];
+        double w0[3], w1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int ia = comp(fi, a);
+            const bool used = a < dim;
+            hp[a] = used ? (ia >> 1) - comp(c0, a) + 1 : 0;
+            hd[a] = used ? ((ia & 1) ? 1 : -1) : 0;
+            const bool lin = !interp && used;
+            w0[a] = lin ? 0.75 : 1.0;
+            w1[a] = lin ? 0.25 : 0.0;
+        }
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int cmb = 0; cmb < 8; ++cmb) {
+            const int x = hp[0] + ((cmb & 1) ? hd[0] : 0), y = hp[1] + ((cmb & 2) ? hd[1] : 0),
+                      z = hp[2] + ((cmb & 4) ? hd[2] : 0);
+            const double w = ((cmb & 1) ? w1[0] : w0[0]) * ((cmb & 2) ? w1[1] : w0[1]) * ((cmb & 4) ? w1[2] : w0[2]);
+            acc = add2(acc, scl2(w, S[((x * h1 + y) * h2 + z) * NQ + q]));
+        }
+        const int j = point_index(f, fi);
+        double2* dst = q < NT ? cf + (size_t)j * NT + q : lf + j;
+        *dst = add2(*dst, acc);
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_average_potential(LevelGeom f, LevelGeom cg,
                                                                 const double* __restrict__ vf,
                                                                 double* __restrict__ vc) {
@@ -2072,9 +2159,13 @@ hipError_t launch_restrict(int nt, const LevelGeom& fine, const LevelGeom& coars
 
 hipError_t launch_prolong(int nt, const LevelGeom& fine, const LevelGeom& coarse, int interp, const double2* cc,
                           const double2* lc, double2* cf, double2* lf, hipStream_t st) {
-    const int pw = kThreads / (nt + 1);
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_prolong<NT>, dim3((fine.P + pw - 1) / pw), dim3(kThreads), 0, st, fine,
-                                           coarse, interp, cc, lc, cf, lf));
+    // coarse tiles of 2 x 2 x 8 (8 along the last used axis)
+    const int d = fine.dim;
+    const int ct0 = d == 1 ? 8 : 2, ct1 = d == 1 ? 1 : (d == 2 ? 8 : 2), ct2 = d == 3 ? 8 : 1;
+    const int t0 = (coarse.n[0] + ct0 - 1) / ct0, t1 = (coarse.n[1] + ct1 - 1) / ct1,
+              t2 = (coarse.n[2] + ct2 - 1) / ct2;
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_prolong_tile<NT>, dim3(t0 * t1 * t2), dim3(kThreads), 0, st, fine,
+                                           coarse, interp, cc, lc, cf, lf, t1, t2));
     return hipGetLastError();
 }
 

@@ -86,7 +86,11 @@ def test_block_factor_parity(cfg):
 @pytest.mark.parametrize("cfg", [dict(shape=(16, 24), block=(4, 4), levels=2),
                                  dict(shape=(8, 8, 16), block=(2, 2, 2), levels=3),
                                  dict(shape=(32,), block=(4,), levels=2, periodic=True),
-                                 dict(shape=(16, 8), block=(2, 2), levels=2, periodic=True)],
+                                 dict(shape=(16, 8), block=(2, 2), levels=2, periodic=True),
+                                 # coarse extents that the interpolation's 2 x 8 / 2 x 2 x 8 tiles
+                                 # do not divide (partial tiles), Dirichlet and periodic
+                                 dict(shape=(12, 20), block=(2, 2), levels=2),
+                                 dict(shape=(4, 8, 24), block=(2, 2, 2), levels=2, periodic=True)],
                          ids=lambda c: f"{c['shape']}-L{c['levels']}-p{c.get('periodic', False)}")
 @pytest.mark.parametrize("interp", ["linear", "constant"])
 def test_transfer_parity(cfg, interp):
