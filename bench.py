@@ -411,6 +411,17 @@ def workload_string(cfg, tol):
             f"{1 / cfg['coarse_reduction']:.0e} reduction (at most {cfg['nu_coarse']} sweeps), tol {tol:g}")
 
 
+def sweep_kernel_name(cfg, prec):
+    """The finest-level colour sweep kernel the library launches for this workload
+    (the FP32 shared-factor sweep takes two time components per lane for N_t = 8 and
+    N_t <= 4, with its block geometry fixed at compile time for 4 x 4 x 4 blocks)."""
+    nt = cfg["n_t"]
+    if prec == "mixed" and (nt == 8 or nt <= 4):
+        cube = cfg["dim"] == 3 and cfg["block"] == 4
+        return f"k_sweep_pair<{nt}, {'true' if cube else 'false'}>"
+    return f"k_sweep<{nt}, {'double' if prec == 'fp64' else 'float'}, false>"
+
+
 def roofline_of(cfg, prec, r, traffic):
     import numpy as np
     blocks = (cfg["block"],) * cfg["dim"]
@@ -431,7 +442,7 @@ def roofline_of(cfg, prec, r, traffic):
     mfma_flops = 0.5 * (ncol0 + ncol1) * mfma_per_solve * solves * 2 * 16 * 16 * 4
     mfma_peak = 78.6 if prec == "fp64" else 157.3
     mfma_tf = mfma_flops / (avg * 1e-3) / 1e12 if avg else None
-    kern = f"k_sweep<{cfg['n_t']}, {'double' if prec == 'fp64' else 'float'}, false>"
+    kern = sweep_kernel_name(cfg, prec)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": traffic,

@@ -572,69 +572,19 @@ __global__ __launch_bounds__(kThreads) void k_restrict(LevelGeom f, LevelGeom cg
 }
 
 // ---------------------------------------------------------------------------
-// K5: interpolation of a coarse correction, added into the fine state.
-// interp 0: cell-centred tensor-linear (3/4 parent, 1/4 nearer neighbour per
-// axis; zero outside a Dirichlet grid); 1: piecewise constant.
+// K5: interpolation of a coarse correction, added into the fine state,
+// c_f += I c_c and lambda_f += I lambda_c (Sec. "Multigrid Relaxation", Eq.
+// (correction_fine)).  interp 0: cell-centred tensor-linear (3/4 parent, 1/4
+// nearer neighbour per axis; zero outside a Dirichlet grid); 1: piecewise
+// constant.
+// A workgroup takes a coarse tile of 2 x 2 x 8 points (2 along the used axes
+// but the last, 8 along the last; 1 along unused axes), stages it with a
+// one-point coarse halo in LDS (every component, zero outside a Dirichlet
+// grid, wrapped on a periodic one), and adds the interpolated correction to
+// the fine tile of its children.  Each coarse value is read from memory by
+// the few tiles whose halo holds it, instead of by every fine point that
+// interpolates from it.
 // ---------------------------------------------------------------------------
-template <int NT>
-__global__ __launch_bounds__(kThreads) void k_prolong(LevelGeom f, LevelGeom cg, int interp,
-                                                      const double2* __restrict__ cc,
-                                                      const double2* __restrict__ lc,
-                                                      double2* __restrict__ cf, double2* __restrict__ lf) {
-    // one thread per (fine point, component): components 0..NT-1 of c, then
-    // lambda; a workgroup takes kThreads / NQ consecutive fine points
-    constexpr int NQ = NT + 1;
-    constexpr int PW = kThreads / NQ;
-    const int lp = (int)threadIdx.x / NQ, n = (int)threadIdx.x - lp * NQ;
-    const int j = (int)blockIdx.x * PW + lp;
-    if (lp >= PW || j >= f.P) return;
-    const bool isc = n < NT;
-    const double2* src = isc ? cc + n : lc;
-    double2* dst = isc ? cf + (size_t)j * NT + n : lf + j;
-    const int stride = isc ? NT : 1;
-    const I3 i = point_coords(f, j);
-    // per axis: the parent's coordinate (its index Jp), the index offset to the
-    // nearer coarse neighbour (wrapped on a periodic grid; 0 with weight 0
-    // outside a Dirichlet grid) and the two weights
-    int Jp = 0, dJ[3];
-    double w0[3], w1[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int nc = cg.n[a];
-        const int cst = a == 2 ? 1 : (a == 1 ? cg.n[2] : cg.n[1] * cg.n[2]);
-        const int ia = comp(i, a);
-        const int par = ia >> 1;
-        const int nb = (ia & 1) ? par + 1 : par - 1;
-        const bool inside = (unsigned)nb < (unsigned)nc;
-        const int nbw = inside ? nb : (f.periodic ? (nb < 0 ? nb + nc : nb - nc) : par);
-        const bool lin = !interp && a < f.dim;
-        Jp += par * cst;
-        dJ[a] = (nbw - par) * cst;
-        w0[a] = lin ? 0.75 : 1.0;
-        w1[a] = (lin && (inside || f.periodic)) ? 0.25 : 0.0;
-    }
-    const int ncomb = interp ? 1 : (1 << f.dim);
-    // all loads issued unconditionally (unused combinations: the parent, weight 0),
-    // so that they are in flight together
-    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int cmb = 0; cmb < 8; ++cmb) {
-        const bool use = cmb < ncomb;
-        const int J = Jp + (use ? ((cmb & 1) ? dJ[0] : 0) + ((cmb & 2) ? dJ[1] : 0) + ((cmb & 4) ? dJ[2] : 0) : 0);
-        const double w = use ? ((cmb & 1) ? w1[0] : w0[0]) * ((cmb & 2) ? w1[1] : w0[1]) * ((cmb & 4) ? w1[2] : w0[2])
-                             : 0.0;
-        acc = add2(acc, scl2(w, src[(size_t)J * stride]));
-    }
-    *dst = add2(*dst, acc);
-}
-
-// The same interpolation by tiles: a workgroup takes a coarse tile of 2 x 2 x 8
-// points (2 along the used axes but the last, 8 along the last; 1 along unused
-// axes), stages it with a one-point coarse halo in LDS (every component, zero
-// outside a Dirichlet grid, wrapped on a periodic one), and adds the
-// interpolated correction to the fine tile of its children.  Each coarse value
-// is read from memory by the few tiles whose halo holds it, instead of by
-// every fine point that interpolates from it.
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_prolong_tile(LevelGeom f, LevelGeom cg, int interp,
                                                            const double2* __restrict__ cc,
