@@ -150,8 +150,11 @@ def coarsest_solve(lev, K, b, x, nu_coarse, coarse_reduction=None, direct=False)
 
 
 def reference_vcycle(levels, l, x, b, nu_pre=1, nu_post=1, nu_coarse=2, adjoint=False, coarse_reduction=None,
-                     coarse_direct=False, counts=None):
-    """One V-cycle; counts (a list, optional) receives the coarsest sweeps done."""
+                     coarse_direct=False, counts=None, active=None):
+    """One V-cycle; counts (a list, optional) receives the coarsest sweeps done.
+    active (optional, one flag per subvolume of the finest level): relax the
+    finest level only on those subvolumes (an adaptive tree whose other volumes
+    end on the next level; see composite.py)."""
     lev = levels[l]
     K = operator(lev, adjoint)
     P, n_t = lev.grid.npts, lev.system.n_t
@@ -161,8 +164,11 @@ def reference_vcycle(levels, l, x, b, nu_pre=1, nu_post=1, nu_coarse=2, adjoint=
         if counts is not None:
             counts.append(done)
         return x
+    blocks = lev.blocks
+    if l == 0 and active is not None:
+        blocks = [bl for k, bl in enumerate(lev.blocks) if active[k]]
     for _ in range(nu_pre):
-        x = reference_sweep(K, b, x, lev.blocks, P, n_t)
+        x = reference_sweep(K, b, x, blocks, P, n_t)
     r = b - K @ x
     bc = restrict(lev, r)
     xc = np.zeros_like(bc)
@@ -170,7 +176,7 @@ def reference_vcycle(levels, l, x, b, nu_pre=1, nu_post=1, nu_coarse=2, adjoint=
                           coarse_direct, counts)
     x = x + prolong(lev, xc)
     for _ in range(nu_post):
-        x = reference_sweep(K, b, x, lev.blocks, P, n_t)
+        x = reference_sweep(K, b, x, blocks, P, n_t)
     return x
 
 
