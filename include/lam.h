@@ -72,6 +72,9 @@ extern "C" {
 #define LAM_PULSE_FOURIER       2  /* E = sum_q coef[q-1] sin(q pi t/T) on [0,T] */
 #define LAM_PULSE_SIN2_FOURIER  3  /* sum of the two */
 
+#define LAM_COARSE_REDISCRETISED 0
+#define LAM_COARSE_GALERKIN      1
+
 #define LAM_TF_SHARED 0
 #define LAM_TF_STORED 1
 
@@ -96,6 +99,15 @@ typedef struct {
                          solver's coarse_reduction > 0) */
     int interp;       /* 0: cell-centred tensor-linear interpolation,
                          1: piecewise constant (projection * interpolation = identity) */
+    int coarse_op;    /* LAM_COARSE_REDISCRETISED (0): each coarse level is the step
+                         operator rediscretised on its grid (kinetic coefficient
+                         1/(2 m H^2), H = 2^l h);
+                         LAM_COARSE_GALERKIN (1): the Galerkin product R K I of the finer
+                         level with piecewise-constant I (interp must be 1): the same
+                         operator with the kinetic coefficient 1/(2 m h^2 2^l), halved
+                         per level instead of quartered, the potential averaged over
+                         children and the field at the coarse cell centres (exactly).
+                         Required by the adaptive tree (lam_set_refinement) */
 } lam_grid;
 
 typedef struct {
@@ -343,6 +355,34 @@ int lam_residual_action_noalloc(const lam_grid* grid, const lam_time* time, cons
  * (elements x n_x x n_t <= LAM_PW_MAX_UNKNOWNS).  T_ij is the closed form the
  * paper prints, (j(j+1) - i(i+1))/2 for i > j, i - j even, read as the entry of
  * trial i in test row j. */
+/* The adaptive tree (Sec. "Multigrid Relaxation": the tree of elements need
+ * not subdivide every volume equally; where the function has little detail a
+ * coarse element stands for its children).  The finest level is refined only
+ * on the subvolumes whose flag is nonzero; elsewhere the next level is the
+ * leaf.  Solves then relax the finest level only on those subvolumes (every
+ * coarser level in full) and converge to the composite state
+ *     x = x0 + (corrections on the refined subvolumes) + I (coarse corrections),
+ *     refined rows of b - K x = 0,   R (b - K x) = 0,
+ * with N (the stopping norm, lam_stats resid*) the U-weighted residual norm on
+ * the refined rows plus that of the projected residual on level 1.  With every
+ * flag set it is the ordinary step solution.  Forward solves only (the adjoint
+ * and lam_propagate's step-ahead pipeline run unrefined).
+ *   active: host, one byte per finest-level subvolume, in C order of the
+ *           subvolume coordinates; NULL clears the refinement (every subvolume).
+ * LAM_EINVAL unless levels >= 2 and grid.coarse_op == LAM_COARSE_GALERKIN (with
+ * the rediscretised coarse operator the unrefined region is corrected only
+ * approximately each cycle and the composite iteration converges slowly). */
+int lam_set_refinement(lam_ctx* ctx, const unsigned char* active);
+
+/* Haar detail energy of psi per finest-level subvolume: sum over its points j of
+ * |psi_j - (I R psi)_j|^2, where (I R psi)_j is the average of psi over the 2^d
+ * children of j's parent cell (R: average over children, I: piecewise constant).
+ * The parts I R psi and psi - I R psi are orthogonal (a Haar decomposition);
+ * large details mark where the tree should be refined.
+ *   psi: device, one complex per finest point; detail: host, one double per
+ *   finest subvolume (C order of subvolume coordinates).  Synchronises. */
+int lam_block_detail(lam_ctx* ctx, const lam_c64* psi, double* detail);
+
 #define LAM_PW_ONE           0
 #define LAM_PW_SIMULTANEOUS  1
 #define LAM_PW_INTERGRID     2

@@ -454,6 +454,12 @@ struct lam_ctx {
     int coarse_launch = 0;        // coarsest iterations queued per V-cycle (learned; at most nu_coarse)
     int coarse_sweeps = 0;        // coarsest full sweeps run / V-cycles whose coarsest solve missed its
     int coarse_unmet = 0;         // reduction, since the current call started
+    // adaptive tree: the finest level refined on some subvolumes (lam_set_refinement)
+    bool refined = false;
+    bool refine_off = false;      // lam_adjoint_step solves the unrefined step
+    unsigned char* d_bmask = nullptr;   // one flag per finest subvolume
+    int* d_act[2] = {nullptr, nullptr}; // the refined subvolumes of each colour
+    int nact[2] = {0, 0};
     // profiling of finest-level sweeps
     int prof = 0;                 // record every prof-th finest-level sweep launch (0: off)
     long prof_count = 0;
@@ -650,6 +656,31 @@ int factor_level(lam_ctx* c, Level& L) {
     return LAM_OK;
 }
 
+// Whether solves use the adaptive tree now (forward solves with a refinement set).
+bool refining(const lam_ctx* c) { return c->refined && !c->refine_off && !c->adjoint; }
+
+// Partials of N for the context state into d_partial; *np receives their count.
+// With the adaptive tree: the refined rows of the finest residual plus the
+// projected residual on level 1 (written into level 1's right-hand side, which
+// the next V-cycle overwrites anyway).
+int norm_partials(lam_ctx* c, int* np) {
+    Level& L = c->lv[0];
+    const double2* bg = c->adjoint ? c->d_g : nullptr;
+    const double2* bs = c->adjoint ? nullptr : L.d_bs;
+    const bool comp = refining(c);
+    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, nullptr, bg, bs,
+                           nullptr, nullptr, c->d_partial, np, c->st, nullptr, comp ? c->d_bmask : nullptr));
+    if (comp) {
+        Level& C = c->lv[1];
+        HIPCHK(launch_residual_restrict(c->nt, L.g, C.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam,
+                                        L.d_v0, nullptr, bg, bs, C.d_bc, C.d_bs, C.d_c, C.d_lam, c->st));
+        int np2 = 0;
+        HIPCHK(launch_rhs_norm(c->nt, C.g.P, c->U, C.d_bc, C.d_bs, c->d_partial + *np, &np2, c->st));
+        *np += np2;
+    }
+    return LAM_OK;
+}
+
 int sweep(lam_ctx* c, int l, int colour, const int* skip = nullptr) {
     Level& L = c->lv[l];
     SweepArgs a{};
@@ -659,6 +690,13 @@ int sweep(lam_ctx* c, int l, int colour, const int* skip = nullptr) {
     a.colour = colour;
     a.arith_blocks = (L.g.nblk[L.g.dim - 1] % 2 == 0) ? 1 : 0;
     a.half_last = std::max(1, L.g.nblk[L.g.dim - 1] / 2);
+    int nblk = L.ncol[colour];
+    if (l == 0 && refining(c)) {
+        // adaptive tree: only the refined subvolumes of the colour
+        a.blocks = c->d_act[colour];
+        a.arith_blocks = 0;
+        nblk = c->nact[colour];
+    }
     a.c = L.d_c;
     a.lam = L.d_lam;
     a.v0 = L.d_v0;
@@ -702,7 +740,7 @@ int sweep(lam_ctx* c, int l, int colour, const int* skip = nullptr) {
         }
         HIPCHK(hipEventRecord(c->ev[c->nev], c->st));
     }
-    HIPCHK(launch_sweep(c->nt, L.fp32 ? 1 : 0, a, c->U, c->W, L.ncol[colour], c->st));
+    HIPCHK(launch_sweep(c->nt, L.fp32 ? 1 : 0, a, c->U, c->W, nblk, c->st));
     if (rec) {
         HIPCHK(hipEventRecord(c->ev[c->nev + 1], c->st));
         c->nev += 2;
@@ -790,12 +828,8 @@ int wait_stream(lam_ctx* c) {
 
 // N of the finest level for the context state (synchronises).
 int norm0(lam_ctx* c, double* out) {
-    Level& L = c->lv[0];
-    const double2* bg = c->adjoint ? c->d_g : nullptr;
-    const double2* bs = c->adjoint ? nullptr : L.d_bs;
     int np = 0;
-    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, nullptr, bg, bs, nullptr,
-                           nullptr, c->d_partial, &np, c->st));
+    LAMCHK(norm_partials(c, &np));
     HIPCHK(launch_reduce(c->d_partial, np, 1, c->h_red_dev, c->st));
     LAMCHK(wait_stream(c));
     *out = c->h_red[0];
@@ -823,12 +857,8 @@ int vcycle(lam_ctx* c, int l, int slot = -1) {
 // V-cycles on the context state until sqrt(N/N0) <= tol.
 // Queue N of the finest level for the context state into h_norms[slot] (no wait).
 int queue_norm(lam_ctx* c, int slot) {
-    Level& L = c->lv[0];
-    const double2* bg = c->adjoint ? c->d_g : nullptr;
-    const double2* bs = c->adjoint ? nullptr : L.d_bs;
     int np = 0;
-    HIPCHK(launch_residual(c->nt, L.g, c->U, c->W, c->adjoint, c->field_on, L.d_c, L.d_lam, L.d_v0, nullptr, bg,
-                           bs, nullptr, nullptr, c->d_partial, &np, c->st));
+    LAMCHK(norm_partials(c, &np));
     HIPCHK(launch_reduce(c->d_partial, np, 1, c->h_norms_dev + slot, c->st));
     return LAM_OK;
 }
@@ -961,6 +991,8 @@ int validate(const lam_grid* g, const lam_time* t, const lam_ham* h, const lam_s
     if (g->levels < 1 || g->levels > 16) return LAM_EINVAL;
     if (g->nu_pre < 0 || g->nu_post < 0 || g->nu_coarse < 0) return LAM_EINVAL;
     if (g->interp != 0 && g->interp != 1) return LAM_EINVAL;
+    if (g->coarse_op != LAM_COARSE_REDISCRETISED && g->coarse_op != LAM_COARSE_GALERKIN) return LAM_EINVAL;
+    if (g->coarse_op == LAM_COARSE_GALERKIN && g->interp != 1) return LAM_EINVAL;
     if (h->field_axis < 0 || h->field_axis >= g->dim) return LAM_EINVAL;
     if (h->pulse_kind < LAM_PULSE_NONE || h->pulse_kind > LAM_PULSE_SIN2_FOURIER) return LAM_EINVAL;
     if (h->pulse_kind != LAM_PULSE_NONE && !(h->t_total > 0.0)) return LAM_EINVAL;
@@ -1065,6 +1097,8 @@ void free_ctx(lam_ctx* c) {
     (void)hipFree(c->d_lam_next);
     (void)hipFree(c->d_bs_next);
     for (auto* p : c->d_split) (void)hipFree(p);
+    (void)hipFree(c->d_bmask);
+    for (auto* p : c->d_act) (void)hipFree(p);
     if (c->h_G) (void)hipHostFree(c->h_G);
     for (auto e : c->ev) (void)hipEventDestroy(e);
     delete c;
@@ -1087,7 +1121,10 @@ LevelGeom level_geom(const lam_grid& gr, const lam_ham& ham, int l) {
     g.h = gr.h * std::ldexp(1.0, l);
     g.periodic = gr.periodic;
     g.fax = ham.field_axis;
-    g.kin = 1.0 / (2.0 * ham.mass * g.h * g.h);
+    // rediscretised: 1/(2 m H^2); Galerkin with piecewise-constant interpolation:
+    // the finer level's coefficient halved, 1/(2 m h^2 2^l)
+    g.kin = gr.coarse_op == LAM_COARSE_GALERKIN ? 1.0 / (2.0 * ham.mass * gr.h * gr.h * std::ldexp(1.0, l))
+                                                : 1.0 / (2.0 * ham.mass * g.h * g.h);
     g.bpts = g.bdim[0] * g.bdim[1] * g.bdim[2];
     g.rbp = 1.0f / (float)g.bpts;
     for (int a = 0; a < 3; ++a) {
@@ -1161,7 +1198,9 @@ int build(lam_ctx* c, const double* v0_dev) {
         HIPCHK(launch_average_potential(c->lv[l - 1].g, c->lv[l].g, c->lv[l - 1].d_v0, c->lv[l].d_v0, c->st));
     const int P0 = c->lv[0].g.P;
     c->max_parts = (P0 + kThreads - 1) / kThreads;
-    LAMCHK(dalloc(&c->d_partial, (size_t)residual_blocks(nt, P0)));
+    // norm partials: the finest level's, then (composite norm of the adaptive tree) level 1's
+    LAMCHK(dalloc(&c->d_partial, (size_t)residual_blocks(nt, P0) +
+                                     (gr.levels > 1 ? (size_t)residual_blocks(nt, c->lv[1].g.P) : 0)));
     LAMCHK(dalloc(&c->d_red, 1));
     LAMCHK(dalloc(&c->d_g, (size_t)P0));
     LAMCHK(dalloc(&c->d_cf, (size_t)P0 * nt));
@@ -1635,7 +1674,8 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
             ctx->prep_t = tn;
             ctx->prep_dir = 0;
         }
-        const bool ahead = has_next && alloc_next(ctx);
+        // (the step-ahead start computes the unrefined N0: not with the adaptive tree)
+        const bool ahead = has_next && !ctx->refined && alloc_next(ctx);
         const int next_slot = ctx->solver.max_cycles + 1 + (k & 1);
         bool ready = false;
         lam_stats st{};
@@ -1682,9 +1722,12 @@ int lam_adjoint_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, const lam_c
     ctx->t_factor_ms = 0.0;
     const int sw0 = ctx->sweeps_fine;
     Totals tot;
+    // the adjoint step (forward recomputation included) solves the unrefined step
+    ctx->refine_off = true;
     const int rc = adjoint_split(ctx, t0, 0, reinterpret_cast<const double2*>(psi_in),
                                  reinterpret_cast<const double2*>(g_out), reinterpret_cast<double2*>(g_in), dL_dv0,
                                  dL_dcoef, tot);
+    ctx->refine_off = false;
     set_depth(ctx, 0);
     if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
     if (stats) {
@@ -1695,6 +1738,52 @@ int lam_adjoint_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, const lam_c
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
     }
     return rc;
+}
+
+int lam_set_refinement(lam_ctx* ctx, const unsigned char* active) {
+    if (!ctx) return LAM_EINVAL;
+    if (ctx->L < 2 || ctx->grid.coarse_op != LAM_COARSE_GALERKIN) return LAM_EINVAL;
+    Level& L = ctx->lv[0];
+    if (!active) {
+        ctx->refined = false;
+        return LAM_OK;
+    }
+    const LevelGeom& g = L.g;
+    std::vector<int> col[2];
+    std::vector<unsigned char> mask(L.nblocks);
+    for (int b = 0; b < L.nblocks; ++b) {
+        int bc[3] = {0, 0, 0}, t = b;
+        for (int a = g.dim - 1; a >= 0; --a) {
+            bc[a] = t % g.nblk[a];
+            t /= g.nblk[a];
+        }
+        mask[b] = active[b] ? 1 : 0;
+        if (active[b]) col[(bc[0] + bc[1] + bc[2]) & 1].push_back(b);
+    }
+    // the previous lists may still be read by queued sweeps
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    if (!ctx->d_bmask) LAMCHK(dalloc(&ctx->d_bmask, (size_t)L.nblocks));
+    HIPCHK(hipMemcpy(ctx->d_bmask, mask.data(), mask.size(), hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k) {
+        if (!ctx->d_act[k]) LAMCHK(dalloc(&ctx->d_act[k], (size_t)std::max(1, L.ncol[k])));
+        ctx->nact[k] = (int)col[k].size();
+        if (!col[k].empty())
+            HIPCHK(hipMemcpy(ctx->d_act[k], col[k].data(), sizeof(int) * col[k].size(), hipMemcpyHostToDevice));
+    }
+    ctx->refined = true;
+    return LAM_OK;
+}
+
+int lam_block_detail(lam_ctx* ctx, const lam_c64* psi, double* detail) {
+    if (!ctx || bad_ptr(psi) || bad_ptr(detail)) return LAM_EINVAL;
+    Level& L = ctx->lv[0];
+    double* d = nullptr;
+    LAMCHK(dalloc(&d, (size_t)L.nblocks));
+    hipError_t e = launch_block_detail(L.g, reinterpret_cast<const double2*>(psi), d, ctx->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(detail, d, sizeof(double) * L.nblocks, hipMemcpyDeviceToHost, ctx->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+    (void)hipFree(d);
+    return e == hipSuccess ? LAM_OK : LAM_EHIP;
 }
 
 int lam_restrict(lam_ctx* ctx, int level, const lam_c64* rho_f, const lam_c64* sigma_f, lam_c64* rho_c,

@@ -104,7 +104,18 @@ inline int residual_blocks(int nt, int P) {
 hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const double* W, int adjoint,
                            int field_on, const double2* c, const double2* lam, const double* v0, const double2* bc,
                            const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
-                           int* nparts, hipStream_t st, const int* skip = nullptr);
+                           int* nparts, hipStream_t st, const int* skip = nullptr,
+                           const unsigned char* bmask = nullptr);
+// bmask (may be null): one flag per subvolume of g; the norm partials count only
+// the rows of flagged subvolumes (the residual fields are written in full).
+
+// Partials of sum_j sum_m U_m |rho_jm|^2 + |sigma_j|^2 over P points (as many as
+// residual_blocks(nt, P)).
+hipError_t launch_rhs_norm(int nt, int P, const double* U, const double2* rho, const double2* sig, double* partial,
+                           int* nparts, hipStream_t st);
+
+// Haar detail energy of psi per subvolume of g (blocks of at most 64 points).
+hipError_t launch_block_detail(const LevelGeom& g, const double2* psi, double* out, hipStream_t st);
 
 hipError_t launch_reduce(const double* partial, int nparts, int width, double* out, hipStream_t st);
 

@@ -354,7 +354,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
                                                        const double2* __restrict__ bg,
                                                        const double2* __restrict__ bs,
                                                        double2* __restrict__ rc, double2* __restrict__ rs,
-                                                       double* __restrict__ partial, const int* __restrict__ skip) {
+                                                       double* __restrict__ partial, const int* __restrict__ skip,
+                                                       const unsigned char* __restrict__ bmask) {
     if (skip && *skip) return;
     constexpr int PW = kThreads / NT;  // points per workgroup
     __shared__ double2 cs[PW * NT];
@@ -371,10 +372,16 @@ __global__ __launch_bounds__(kThreads) void k_residual(LevelGeom g, TimeOps<NT> 
                                           cs + (lp < PW ? lp : 0) * NT, tos, &sg);
     if (act) {
         if (rc) rc[(size_t)j * NT + m] = rho;
-        acc += tos[m] * (rho.x * rho.x + rho.y * rho.y);
+        // bmask (one flag per subvolume): the norm counts the rows of flagged subvolumes only
+        double wt = 1.0;
+        if (bmask) {
+            const I3 i = point_coords(g, j);
+            wt = bmask[(i.x / g.bdim[0] * g.nblk[1] + i.y / g.bdim[1]) * g.nblk[2] + i.z / g.bdim[2]] ? 1.0 : 0.0;
+        }
+        acc += wt * tos[m] * (rho.x * rho.x + rho.y * rho.y);
         if (m == 0) {
             if (rs) rs[j] = sg;
-            acc += sg.x * sg.x + sg.y * sg.y;
+            acc += wt * (sg.x * sg.x + sg.y * sg.y);
         }
     }
     if (partial) {
@@ -569,6 +576,58 @@ __global__ __launch_bounds__(kThreads) void k_restrict(LevelGeom f, LevelGeom cg
         bsc[J] = acc;
         if (zl) zl[J] = make_double2(0.0, 0.0);
     }
+}
+
+// Partials of N of a right-hand side held as (rho, sigma) rows, sum_j sum_m U_m
+// |rho_jm|^2 + |sigma_j|^2 (the projected residual of the adaptive tree's
+// composite norm), laid out as k_residual's partials.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_rhs_norm(int P, TimeOps<NT> to, const double2* __restrict__ rho,
+                                                       const double2* __restrict__ sig, double* __restrict__ partial) {
+    constexpr int PW = kThreads / NT;
+    __shared__ double red[kThreads / 64];
+    const int t = threadIdx.x;
+    const int lp = t / NT, m = t - lp * NT;
+    const size_t j = (size_t)blockIdx.x * PW + lp;
+    double acc = 0.0;
+    if (lp < PW && j < (size_t)P) {
+        const double2 r = rho[j * NT + m];
+        double u = to.U[0];
+#pragma unroll
+        for (int k = 1; k < NT; ++k) u = m == k ? to.U[k] : u;
+        acc = u * (r.x * r.x + r.y * r.y);
+        if (m == 0) {
+            const double2 q = sig[j];
+            acc += q.x * q.x + q.y * q.y;
+        }
+    }
+    const double tot = block_sum(acc, red);
+    if (t == 0) partial[blockIdx.x] = tot;
+}
+
+// Haar detail energy per subvolume (one 64-lane workgroup each): sum over its
+// points j of |psi_j - mean of psi over the 2^d children of j's parent cell|^2,
+// reduced in a fixed order.
+__global__ __launch_bounds__(64) void k_block_detail(LevelGeom g, const double2* __restrict__ psi,
+                                                     double* __restrict__ out) {
+    const int blk = blockIdx.x, l = threadIdx.x;
+    double d = 0.0;
+    if (l < g.bpts) {
+        const I3 bc = block_coords(g, blk);
+        const I3 i = global_of_local(g, bc, local_coords(g, l));
+        const int nch = 1 << g.dim;
+        double2 mean = make_double2(0.0, 0.0);
+        for (int ch = 0; ch < nch; ++ch) {
+            const I3 s{(i.x & ~1) | (ch & 1), g.dim > 1 ? ((i.y & ~1) | ((ch >> 1) & 1)) : 0,
+                       g.dim > 2 ? ((i.z & ~1) | ((ch >> 2) & 1)) : 0};
+            mean = add2(mean, psi[point_index(g, s)]);
+        }
+        const double2 p = psi[point_index(g, i)];
+        const double dr = p.x - mean.x / nch, di = p.y - mean.y / nch;
+        d = dr * dr + di * di;
+    }
+    d = wave_sum(d);
+    if (l == 0) out[blk] = d;
 }
 
 // ---------------------------------------------------------------------------
@@ -2056,12 +2115,28 @@ inline int nblk_for(size_t n) { return (int)((n + kThreads - 1) / kThreads); }
 hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const double* W, int adjoint,
                            int field_on, const double2* c, const double2* lam, const double* v0, const double2* bc,
                            const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
-                           int* nparts, hipStream_t st, const int* skip) {
+                           int* nparts, hipStream_t st, const int* skip, const unsigned char* bmask) {
     const int nb = residual_blocks(nt, g.P);
     if (nparts) *nparts = nb;
     LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_residual<NT>, dim3(nb), dim3(kThreads), 0, st, g,
                                            make_ops<NT>(U, W), adjoint, field_on, c, lam, v0, bc, bg, bs, rc,
-                                           rs, partial, skip));
+                                           rs, partial, skip, bmask));
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_norm(int nt, int P, const double* U, const double2* rho, const double2* sig, double* partial,
+                           int* nparts, hipStream_t st) {
+    const int nb = residual_blocks(nt, P);
+    if (nparts) *nparts = nb;
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_rhs_norm<NT>, dim3(nb), dim3(kThreads), 0, st, P,
+                                           make_ops<NT>(U, nullptr), rho, sig, partial));
+    return hipGetLastError();
+}
+
+hipError_t launch_block_detail(const LevelGeom& g, const double2* psi, double* out, hipStream_t st) {
+    const int nblocks = g.nblk[0] * g.nblk[1] * g.nblk[2];
+    if (g.bpts > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_block_detail, dim3(nblocks), dim3(64), 0, st, g, psi, out);
     return hipGetLastError();
 }
 

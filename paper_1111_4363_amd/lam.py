@@ -30,6 +30,7 @@ LAM_MAX_SPLIT = 8
 PULSE = {"none": 0, "sin2": 1, "fourier": 2, "sin2+fourier": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 INTERP = {"linear": 0, "constant": 1}
+COARSE_OP = {"rediscretised": 0, "galerkin": 1}
 TIME_FACTOR = {"shared": 0, "stored": 1}
 
 
@@ -47,7 +48,7 @@ class LamGrid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
                 ("periodic", ctypes.c_int), ("block", ctypes.c_int * 3), ("levels", ctypes.c_int),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("nu_coarse", ctypes.c_int),
-                ("interp", ctypes.c_int)]
+                ("interp", ctypes.c_int), ("coarse_op", ctypes.c_int)]
 
 
 class LamTime(ctypes.Structure):
@@ -114,6 +115,8 @@ SIGNATURES = {
     "lam_level_shape": (_I, [_P, _I, _PI]),
     "lam_block_factor": (_I, [_P, _I, _I, _PD, _PD]),
     "lam_pass_stats": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong)]),
+    "lam_set_refinement": (_I, [_P, _P]),
+    "lam_block_detail": (_I, [_P, _P, _P]),
     "lam_plane_wave_map": (_I, [ctypes.POINTER(LamPWRegime), _I, _PD, _I, _PD, _P, _P, _P]),
     "lam_residual_action_noalloc": (_I, [ctypes.POINTER(LamGrid), ctypes.POINTER(LamTime), ctypes.POINTER(LamHam),
                                          _D, _P, _P, _P, _P, _P, _P, _P]),
@@ -187,7 +190,7 @@ def _pulse_fields(pulse):
 
 
 def _describe(shape, h, v0, n_t, dt, block, levels=1, nu_pre=1, nu_post=1, nu_coarse=2, interp="linear",
-              periodic=False, mass=1.0, field_axis=-1, pulse=None):
+              periodic=False, mass=1.0, field_axis=-1, pulse=None, coarse_op="rediscretised"):
     """The lam_grid, lam_time and lam_ham structs (and the host array the last points to)."""
     shape = tuple(int(s) for s in shape)
     block = tuple(int(b) for b in block)
@@ -204,6 +207,7 @@ def _describe(shape, h, v0, n_t, dt, block, levels=1, nu_pre=1, nu_post=1, nu_co
         g.block[a] = block[a] if a < dim else 1
     g.h, g.periodic, g.levels = float(h), int(bool(periodic)), int(levels)
     g.nu_pre, g.nu_post, g.nu_coarse, g.interp = int(nu_pre), int(nu_post), int(nu_coarse), INTERP[interp]
+    g.coarse_op = COARSE_OP[coarse_op]
     t = LamTime(int(n_t), float(dt))
     kind, e0, omega, t_total, coef = _pulse_fields(pulse)
     carr = (ctypes.c_double * max(1, len(coef)))(*coef)
@@ -259,11 +263,12 @@ class Propagator:
     def __init__(self, shape, h, v0, n_t, dt, block, levels=1, nu_pre=1, nu_post=1, nu_coarse=2,
                  interp="linear", periodic=False, mass=1.0, field_axis=-1, pulse=None,
                  precision="fp64", tol=1e-10, max_cycles=50, n_inner=-1, time_factor="shared", coarse_reduction=0.0,
-                 max_split=0, stream=None):
+                 max_split=0, coarse_op="rediscretised", stream=None):
         lib = load_library()
         v0 = v0.contiguous()
         g, t, ham, self._coef, coef, self.npts = _describe(shape, h, v0, n_t, dt, block, levels, nu_pre, nu_post,
-                                                           nu_coarse, interp, periodic, mass, field_axis, pulse)
+                                                           nu_coarse, interp, periodic, mass, field_axis, pulse,
+                                                           coarse_op)
         self.shape = tuple(int(s) for s in shape)
         self.block = tuple(int(b) for b in block)
         self.n_t, self.dt, self.h = int(n_t), float(dt), float(h)
@@ -363,6 +368,33 @@ class Propagator:
         _check(self._lib.lam_get_state(self._ctx, _ptr(c, torch.complex128), _ptr(lam, torch.complex128)),
                "lam_get_state")
         return c, lam
+
+    def set_refinement(self, active):
+        """lam_set_refinement: refine the finest level only on the subvolumes whose
+        flag is set (host array, one per subvolume in C order of subvolume
+        coordinates); None clears the refinement."""
+        if active is None:
+            _check(self._lib.lam_set_refinement(self._ctx, None), "lam_set_refinement")
+            return
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8).ravel())
+        nblk = 1
+        for s_, b_ in zip(self.shape, self.block):
+            nblk *= s_ // b_
+        if a.size != nblk:
+            raise ValueError(f"one flag per finest subvolume expected ({nblk}), got {a.size}")
+        _check(self._lib.lam_set_refinement(self._ctx, a.ctypes.data_as(ctypes.c_void_p)), "lam_set_refinement")
+
+    def block_detail(self, psi):
+        """lam_block_detail: Haar detail energy of psi per finest subvolume (numpy)."""
+        import numpy as np
+        nblk = 1
+        for s_, b_ in zip(self.shape, self.block):
+            nblk *= s_ // b_
+        out = np.zeros(nblk)
+        _check(self._lib.lam_block_detail(self._ctx, _ptr(psi, torch.complex128, self.npts, "psi"),
+                                          out.ctypes.data_as(ctypes.c_void_p)), "lam_block_detail")
+        return out
 
     def relax_sweep(self, colour, level=0):
         _check(self._lib.lam_relax_sweep(self._ctx, int(level), int(colour)), "lam_relax_sweep")

@@ -51,7 +51,7 @@ def test_struct_layout_matches_c(tmp_path):
 int main(void) {
   printf("lam_grid %zu\nlam_time %zu\nlam_ham %zu\nlam_solver %zu\nlam_stats %zu\n",
          sizeof(lam_grid), sizeof(lam_time), sizeof(lam_ham), sizeof(lam_solver), sizeof(lam_stats));
-  P(lam_grid, h) P(lam_grid, block) P(lam_grid, interp) P(lam_ham, v0) P(lam_ham, coef)
+  P(lam_grid, h) P(lam_grid, block) P(lam_grid, interp) P(lam_grid, coarse_op) P(lam_ham, v0) P(lam_ham, coef)
   P(lam_ham, t_total) P(lam_solver, n_inner) P(lam_solver, time_factor) P(lam_solver, coarse_reduction)
   P(lam_stats, t_solve_ms) P(lam_stats, resid_last) P(lam_stats, coarse_unmet) P(lam_solver, max_split)
   P(lam_stats, substeps) P(lam_stats, split_depth)
@@ -70,6 +70,7 @@ int main(void) {
     assert int(out["lam_grid.h"]) == lam.LamGrid.h.offset
     assert int(out["lam_grid.block"]) == lam.LamGrid.block.offset
     assert int(out["lam_grid.interp"]) == lam.LamGrid.interp.offset
+    assert int(out["lam_grid.coarse_op"]) == lam.LamGrid.coarse_op.offset
     assert int(out["lam_ham.v0"]) == lam.LamHam.v0.offset
     assert int(out["lam_ham.coef"]) == lam.LamHam.coef.offset
     assert int(out["lam_ham.t_total"]) == lam.LamHam.t_total.offset

@@ -21,6 +21,7 @@ def _create(**over):
     g.levels = over.get("levels", 2)
     g.nu_pre, g.nu_post, g.nu_coarse = 1, 1, 2
     g.interp = over.get("interp", 0)
+    g.coarse_op = over.get("coarse_op", 0)
     t = lam.LamTime(over.get("n_t", 4), over.get("dt", 0.05))
     dummy = ctypes.c_double(0.0)
     h = lam.LamHam()
@@ -50,6 +51,7 @@ def _create(**over):
     dict(precision=2), dict(tol=-1.0), dict(n_inner=-2), dict(interp=3), dict(v0=None), dict(time_factor=2),
     dict(n_inner=33), dict(coarse_reduction=-0.1), dict(coarse_reduction=1.0), dict(coarse_reduction=float("nan")),
     dict(max_split=-1), dict(max_split=9),
+    dict(coarse_op=2), dict(coarse_op=1, interp=0),     # Galerkin needs piecewise-constant interpolation
 ])
 def test_invalid_arguments_are_rejected(over):
     assert _create(**over) == lam.LAM_EINVAL
@@ -113,3 +115,10 @@ def _pw(n_x=3, n_t=3, mode=0, kappa=1.0, nu=0.0, nk=4):
                                   dict(kappa=float("inf")), dict(nk=0)])
 def test_plane_wave_map_rejects_invalid_regimes_before_any_device_call(over):
     assert _pw(**over) == lam.LAM_EINVAL
+
+
+def test_adaptive_tree_calls_reject_a_null_context():
+    lib = lam.load_library()
+    assert lib.lam_set_refinement(None, None) == lam.LAM_EINVAL
+    out = (ctypes.c_double * 4)()
+    assert lib.lam_block_detail(None, None, out) == lam.LAM_EINVAL
