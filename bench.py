@@ -308,6 +308,68 @@ def plane_wave_maps(torch, lam, npts=128, kmax=8.0, bases=((3, 3), (4, 4), (6, 6
     return out
 
 
+def adaptive_tree(torch, lam, steps=4, fractions=(1e-10, 1e-8, 1e-6, 1e-4)):
+    """The adaptive tree on the 256^3 workload (mixed path): the hierarchy with
+    piecewise-constant interpolation and Galerkin coarse operators, first
+    unrefined (the reference), then with the finest level refined only on the
+    subvolumes that hold all but a fraction f of the Haar detail energy of psi0
+    (largest details first).  Per f: subvolumes refined, ms per step over the
+    workload's first `steps` steps, V-cycles, and the relative difference of
+    psi after them from the unrefined solution.  The default hierarchy (linear
+    interpolation, rediscretised coarse operators) is timed for comparison."""
+    import numpy as np
+    import workloads as W
+    cfg = W.config("3d_large")
+    v0 = torch.as_tensor(W.potential(cfg), device="cuda")
+    psi0 = torch.as_tensor(W.initial_state(cfg, W.potential(cfg)), device="cuda")
+
+    def make(galerkin):
+        return lam.Propagator(cfg["shape"], cfg["h"], v0, cfg["n_t"], cfg["dt"], (cfg["block"],) * cfg["dim"],
+                              levels=cfg["levels"], nu_coarse=cfg["nu_coarse"],
+                              coarse_reduction=cfg["coarse_reduction"], precision="mixed", tol=1e-10,
+                              max_cycles=60, pulse=pulse_of(cfg), interp="constant" if galerkin else "linear",
+                              coarse_op="galerkin" if galerkin else "rediscretised")
+
+    def run(prop):
+        prop.propagate(psi0.clone(), 1)   # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        psi, st = prop.propagate(psi0.clone(), steps)
+        torch.cuda.synchronize()
+        return psi, (time.perf_counter() - t) / steps * 1e3, st[0]["cycles"] / steps
+
+    rows = []
+    prop = make(False)
+    _, ms, cyc = run(prop)
+    rows.append({"hierarchy": "linear interpolation, rediscretised", "refined": 1.0, "ms_per_step": ms,
+                 "cycles_per_step": cyc, "diff_from_unrefined": None})
+    prop.close()
+    prop = make(True)
+    psi_full, ms, cyc = run(prop)
+    rows.append({"hierarchy": "constant interpolation, Galerkin", "refined": 1.0, "ms_per_step": ms,
+                 "cycles_per_step": cyc, "diff_from_unrefined": 0.0})
+    det = prop.block_detail(psi0)
+    order = np.argsort(det)[::-1]
+    cum = np.cumsum(det[order])
+    nfull = float(torch.linalg.vector_norm(psi_full))
+    for f in fractions:
+        keep = int(np.searchsorted(cum, (1.0 - f) * cum[-1]) + 1)
+        mask = np.zeros(det.size, np.uint8)
+        mask[order[:keep]] = 1
+        prop.set_refinement(mask)
+        psi, ms, cyc = run(prop)
+        diff = float(torch.linalg.vector_norm(psi - psi_full)) / nfull
+        rows.append({"hierarchy": "constant interpolation, Galerkin", "detail_left_out": f,
+                     "refined": keep / det.size, "refined_subvolumes": keep, "ms_per_step": ms,
+                     "cycles_per_step": cyc, "diff_from_unrefined": diff})
+        print(f"[adaptive] f={f:g}: {keep} of {det.size} subvolumes refined, {ms:.2f} ms/step, "
+              f"{cyc:.1f} cycles/step, |psi - psi_unrefined| / |psi_unrefined| = {diff:.2e}", file=sys.stderr,
+              flush=True)
+        prop.set_refinement(None)
+    prop.close()
+    return rows
+
+
 def pulse_of(cfg):
     """The workload's pulse as Propagator arguments (None without a field)."""
     import workloads as W
@@ -476,10 +538,19 @@ def main():
     ap.add_argument("--variants", action="store_true",
                     help="only measure the relaxation variants over groups of 2^d elements (separate, "
                          "simultaneous, intergrid transfer): residual ratio and time per iteration")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="only measure the adaptive tree on the 256^3 workload (Galerkin piecewise-constant "
+                         "hierarchy; finest level refined by Haar detail)")
     ap.add_argument("--plane-wave", action="store_true",
                     help="only compute the Legendre-element plane-wave convergence maps (128 x 128 trial "
                          "waves per regime, basis and mode) and summarise them")
     args = ap.parse_args()
+    if args.adaptive:
+        import torch
+        from paper_1111_4363_amd import lam
+        lam.load_library()
+        print(json.dumps(adaptive_tree(torch, lam)))
+        return
     if args.plane_wave:
         import torch
         from paper_1111_4363_amd import lam
