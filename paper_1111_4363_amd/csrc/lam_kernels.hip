@@ -1549,13 +1549,13 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
 // The FP32 shared-factor colour sweep with two time components per lane: four
 // lanes per point (lane q of a point takes m = q and m = q + 4), so a 64-point
 // block is one wave per SIMD.  The per-point index arithmetic is done once for
-// two components, every wave takes part in the matrix-core steps, and at 168
-// registers three blocks share a compute unit (LDS: under 50 KB each).  The
+// two components, every wave takes part in the matrix-core steps, and at up to
+// 128 registers and under 40 KB of LDS four blocks share a compute unit.  The
 // arithmetic of each item is that of k_sweep<NT, float, false>.  CUBE4: the
 // level is 3D with 4 x 4 x 4 blocks, known at compile time (the block
 // geometry's divisions become shifts and its tests constants).
 template <int NT, bool CUBE4>
-__global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, TimeOps<NT> to) {
+__global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, TimeOps<NT> to) {
     using BT = float;
     using C = cx<BT>;
     // a finished coarsest-level solve: the rest of its launches do nothing
@@ -1571,18 +1571,17 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
     constexpr int LPP = 4, IPL = 2;                          // lanes per point, items per lane
     static_assert(kMaxNT <= LPP * IPL && kMaxB * LPP == THR && NW == 4, "every residual item has a lane");
     __shared__ BT Vs[kMaxB * kLdsPad];
-    __shared__ double2 cs[kMaxB * NT];
+    __shared__ double2 cs[(kMaxB + 1) * NT];   // row kMaxB: zeros (absent neighbours)
     __shared__ double2 ls[kMaxB];
-    __shared__ double v0s[kMaxB];
-    __shared__ double zs[kMaxB];
     __shared__ int gidx[kMaxB];
-    __shared__ C rs[kMaxB * NQ];   // local residual
+    __shared__ C sgr[kMaxB];       // constraint residual of each point
     __shared__ C rh[kMaxB * NQ];   // per-mode solutions
     __shared__ C xb[kMaxB * NQ];   // reduced right-hand side, then the correction V y
     __shared__ BT tfs[TFR];        // shared time factor of this direction: E1, E3 real forms, lam
     __shared__ BT es[kMaxB];
-    __shared__ double2 sgs[kMaxB];  // constraint residual per point
-    __shared__ double tos[NT + NT * NT];   // the time operators U, W (indexed per lane, so staged here)
+    __shared__ double2 sgs[kMaxB + 1];  // constraint residual per point (row kMaxB: zero)
+    __shared__ double tos[NT];             // the time operator U (indexed per lane, so staged here)
+    __shared__ double2 tcs[NT * NT];       // per (m, n): W_mn and the 0/1 pattern of the Q coupling
     __shared__ double red[NW];
     __shared__ double rnorm_sh;
 
@@ -1606,17 +1605,6 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
     };
     auto global_of = [&](const I3& blk3, const I3& lc) {
         return I3{blk3.x * bdim(0) + lc.x, blk3.y * bdim(1) + lc.y, blk3.z * bdim(2) + lc.z};
-    };
-    auto nb_of = [&](int lcode, int l, int dir) {
-        if constexpr (CUBE4) {
-            const int ax = dir >> 1;
-            const bool up = dir & 1;
-            const int lstr = ax == 0 ? 16 : (ax == 1 ? 4 : 1);
-            const int code = (lcode >> (2 * dir)) & 3;
-            return code == 0 ? -1 : l + (code == 1 ? (up ? lstr : -lstr) : (up ? -3 : 3) * lstr);
-        } else {
-            return code_nb(g, lcode, l, dir);
-        }
     };
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -1676,7 +1664,14 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
     const I3 lc_it = local_of(l_it);
     const I3 gi_it = global_of(bc, lc_it);
     const int gj_it = point_index(g, gi_it);
-    int hidx[6], hmask = 0, lcode = 0;
+    // neighbours: nrow[dir] is the in-block neighbour's row in LDS (the zero row
+    // kMaxB when there is none); the halo comes from HBM, one load per direction,
+    // or with CUBE4 one per axis (a point of a 4-wide block lies on at most one of
+    // the block's two faces across an axis)
+    constexpr int NH = CUBE4 ? 3 : 6;
+    int hidx[NH], nrow[6], hmask = 0;
+#pragma unroll
+    for (int s = 0; s < NH; ++s) hidx[s] = gj_it;
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) {
         const int ax = dir >> 1;
@@ -1684,28 +1679,31 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         const int la = comp(lc_it, ax), ga = comp(gi_it, ax);
         const int bd = bdim(ax), na = g.n[ax];
         const int gstr = ax == 0 ? g.n[1] * g.n[2] : (ax == 1 ? g.n[2] : 1);
+        const int lstr = ax == 0 ? bdim(1) * bdim(2) : (ax == 1 ? bdim(2) : 1);
         const bool used = dir < nd;
         const bool inside = up ? la + 1 < bd : la > 0;
         const bool self_wrap = g.periodic && g.nblk[ax] == 1;
         const bool edge = up ? ga + 1 >= na : ga == 0;
         const int gstep = up ? gstr : -gstr;
-        lcode |= (!used ? 0 : (inside ? 1 : (self_wrap ? 2 : 0))) << (2 * dir);
+        const int lstep = inside ? (up ? lstr : -lstr) : (up ? -1 : 1) * (bd - 1) * lstr;
+        nrow[dir] = used && (inside || self_wrap) ? l_it + lstep : kMaxB;
         const bool halo = used && !inside && !self_wrap && (!edge || g.periodic);
         const int hw = edge ? gj_it - (up ? 1 : -1) * (na - 1) * gstr : gj_it + gstep;
-        hidx[dir] = halo ? hw : gj_it;
-        hmask |= (halo ? 1 : 0) << dir;
+        const int s = CUBE4 ? ax : dir;
+        hidx[s] = halo ? hw : hidx[s];
+        hmask |= (halo ? 1 : 0) << s;
     }
     const int tp = tid < b ? tid : 0;
     const I3 gip = global_of(bc, local_of(tp));
     const int gjp = point_index(g, gip);
 
     // ---- 1b. loads, all in flight together ----
-    double2 own[IPL], hv[IPL][6], rhsv[IPL];
+    double2 own[IPL], hv[IPL][NH], rhsv[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         own[k] = a.c[(size_t)gj_it * NT + m_it[k]];
 #pragma unroll
-        for (int dir = 0; dir < 6; ++dir) hv[k][dir] = a.c[(size_t)hidx[dir] * NT + m_it[k]];
+        for (int s = 0; s < NH; ++s) hv[k][s] = a.c[(size_t)hidx[s] * NT + m_it[k]];
     }
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
@@ -1713,12 +1711,19 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
                                   : (a.bg ? a.bg + gj_it : a.c + (size_t)gj_it * NT + m_it[k]);
         rhsv[k] = scl2((a.bc || a.bg) ? 1.0 : 0.0, *rbp);
     }
-    const double v0p = a.v0[gjp];
+    const double v0l = a.v0[gj_it];   // the point's potential (each of its lanes loads it)
     const double2 lp = a.lam[gjp];
     // the point's constraint right-hand side (lane q = 0 holds m = 0)
     const double2 sgv = scl2((a.bs && q_it == 0) ? 1.0 : 0.0, (a.bs ? a.bs : a.lam)[gj_it]);
     // ---- 1c. consume into LDS; sigma = bs - sum_n s_n c_n as a sum over the point's lanes ----
-    if (tid < NT + NT * NT) tos[tid] = tov;
+    if (tid < NT) tos[tid] = tov;
+    if (iw >= 0 && iw < NT * NT) {
+        const int mm = iw / NT, nn = iw - mm * NT;
+        const bool cpl = a.adjoint ? (nn < mm && ((mm - nn) & 1)) : (nn > mm && ((nn - mm) & 1));
+        tcs[iw] = make_double2(tov, cpl ? 1.0 : 0.0);
+    }
+    if (tid < NT) cs[kMaxB * NT + tid] = make_double2(0.0, 0.0);
+    if (tid == NT) sgs[kMaxB] = make_double2(0.0, 0.0);
     {
         double pr = 0.0, pi = 0.0;
 #pragma unroll
@@ -1730,19 +1735,22 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         const double sr = group_sum<LPP>(pr), si = group_sum<LPP>(pi);
         if (tid / LPP < b && q_it == 0) sgs[l_it] = make_double2(sgv.x - sr, sgv.y - si);
     }
-    double2 halo[IPL];
+    // the parts of (H c) at the item that need no other in-block point:
+    // -kin (halo - 2 d c) + V0 c (the in-block neighbours are added from LDS)
+    double2 pre[IPL];
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
-        halo[k] = make_double2(0.0, 0.0);
+        double2 halo = scl2(-2.0 * gdim, own[k]);
 #pragma unroll
-        for (int dir = 0; dir < 6; ++dir) halo[k] = add2(halo[k], scl2((hmask >> dir) & 1 ? 1.0 : 0.0, hv[k][dir]));
+        for (int s = 0; s < NH; ++s) halo = add2(halo, scl2((hmask >> s) & 1 ? 1.0 : 0.0, hv[k][s]));
+        pre[k] = add2(scl2(-g.kin, halo), scl2(v0l, own[k]));
+        // formed here, so that the halo values need no registers past the barrier
+        asm volatile("" : "+v"(pre[k].x), "+v"(pre[k].y));
         if (item[k]) cs[l_it * NT + m_it[k]] = own[k];
     }
     if (tid < b) {
         gidx[tid] = gjp;
-        v0s[tid] = v0p;
         ls[tid] = lp;
-        zs[tid] = zcoord(g, gip);
         es[tid] = ep;
     }
     {
@@ -1764,26 +1772,25 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
     __syncthreads();
 
     // ---- 2. local residual (FP64) and the reduced right-hand side (see k_sweep) ----
+    const double zl = zcoord(g, gi_it);   // the point's coordinate along the field
+    double rloc = 0.0;                    // squared local residual of this lane's rows (as stored)
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         if (!item[k]) continue;
         const int l = l_it, m = m_it[k];
-        double2 lap = add2(scl2(-2.0 * gdim, own[k]), halo[k]);
+        double2 nbs = cs[nrow[0] * NT + m];
 #pragma unroll
-        for (int dir = 0; dir < 6; ++dir) {
-            const int ln = nb_of(lcode, l, dir);
-            lap = add2(lap, scl2(ln >= 0 ? 1.0 : 0.0, cs[(ln >= 0 ? ln : l) * NT + m]));
-        }
-        const double2 hc = add2(scl2(-g.kin, lap), scl2(v0s[l], own[k]));
+        for (int dir = 1; dir < 6; ++dir) nbs = add2(nbs, cs[nrow[dir] * NT + m]);
+        const double2 hc = add2(pre[k], scl2(-g.kin, nbs));
         double2 tq = make_double2(0.0, 0.0);
         double2 wc = make_double2(0.0, 0.0);
         if (a.field_on) {
 #pragma unroll
             for (int n = 0; n < NT; ++n) {
                 const double2 cn = cs[l * NT + n];
-                const bool cpl = a.adjoint ? (n < m && ((m - n) & 1)) : (n > m && ((n - m) & 1));
-                tq = add2(tq, scl2(cpl ? 1.0 : 0.0, cn));
-                wc = add2(wc, scl2(tos[NT + m * NT + n], cn));
+                const double2 wq = tcs[m * NT + n];
+                tq = add2(tq, scl2(wq.y, cn));
+                wc = add2(wc, scl2(wq.x, cn));
             }
         } else {
 #pragma unroll
@@ -1795,33 +1802,33 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
         }
         const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
         const double sm = (m & 1) ? -1.0 : 1.0;
-        double2 row = sub2(sub2(tim, scl2(tos[m], hc)), scl2(zs[l], wc));
+        double2 row = sub2(sub2(tim, scl2(tos[m], hc)), scl2(zl, wc));
         row = add2(row, scl2(sm, ls[l]));
         const double2 rho = sub2(rhsv[k], row);
-        rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
+        const C rhof = C{(BT)rho.x, (BT)rho.y};
+        rloc += (double)rhof.r * rhof.r + (double)rhof.i * rhof.i;
         const double2 sg = sgs[l];
-        if (m == 0) rs[l * NQ + NT] = C{(BT)sg.x, (BT)sg.y};
+        if (m == 0) {
+            const C sgf = C{(BT)sg.x, (BT)sg.y};
+            sgr[l] = sgf;
+            rloc += (double)sgf.r * sgf.r + (double)sgf.i * sgf.i;
+        }
         double2 r = rho;
         if (m == 0) {
             double2 lin = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int dir = 0; dir < 6; ++dir) {
-                const int ln = nb_of(lcode, l, dir);
-                lin = add2(lin, scl2(ln >= 0 ? 1.0 : 0.0, sgs[ln >= 0 ? ln : l]));
-            }
-            const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * gdim, sg), lin)), scl2(v0s[l], sg));
+            for (int dir = 0; dir < 6; ++dir) lin = add2(lin, sgs[nrow[dir]]);
+            const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * gdim, sg), lin)), scl2(v0l, sg));
             r = add2(r, scl2(tos[0], asg));
         }
-        if (a.field_on) r = add2(r, scl2(zf * tos[NT + m * NT], sg));
+        if (a.field_on) r = add2(r, scl2(zf * tcs[m * NT].x, sg));
         if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
         xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
     }
     __syncthreads();
     double r0n = 0.0;
     if (a.n_inner > 0) {
-        double loc = 0.0;
-        for (int t = tid; t < b * NQ; t += THR) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
-        const double tot = block_sum(loc, red);
+        const double tot = block_sum(rloc, red);
         if (tid == 0) rnorm_sh = tot;
         __syncthreads();
         r0n = rnorm_sh;
@@ -1858,7 +1865,7 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
                 pi += sm * x[k].i;
             }
             const BT sr = group_sum<LPP>(pr), si = group_sum<LPP>(pi);
-            const C sg = rs[l_it * NQ + NT];
+            const C sg = sgr[l_it];
 #pragma unroll
             for (int k = 0; k < IPL; ++k) dv[k] = m_it[k] > 0 ? x[k] : C{sg.r - sr, sg.i - si};
             dl = x[0];   // used by the lane holding m = 0 only
@@ -1898,11 +1905,10 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_sweep_pair(SweepArgs a, Tim
             C wd = C{0, 0};
             if (a.field_on) {
 #pragma unroll 1
-                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tos[NT + m * NT + n], rh[l * NQ + n]);
+                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tcs[m * NT + n].x, rh[l * NQ + n]);
             }
-            const C rn = rmul((BT)(zs[l] - zf), wd);
-            rs[l * NQ + m] = rn;
-            if (m == 0) rs[l * NQ + NT] = C{0, 0};
+            const C rn = rmul((BT)(zl - zf), wd);
+            if (m == 0) sgr[l] = C{0, 0};
             xb[l * NQ + m] = rn;
             loc += (double)rn.r * rn.r + (double)rn.i * rn.i;
         }
