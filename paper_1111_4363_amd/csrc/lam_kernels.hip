@@ -86,17 +86,20 @@ __device__ __forceinline__ typename Mfma<T>::acc_t tile_gemm(const T* __restrict
     // columns past NCOL only feed result columns that are never stored: read column NCOL-1
     const int cc = col < NCOL ? col : NCOL - 1;
     if (b == kMaxB) {
-        // full block: every operand in range; two halves of eight MFMA steps,
-        // each half's loads issued together with offsets folded into the LDS instructions
+        // full block: every operand in range.  Step s takes K index p = 16 kq + s
+        // from lane group kq, so the four groups of a step read V rows (or columns)
+        // 16 apart: distinct LDS banks with the padded row stride.  Two halves of
+        // eight steps, each half's loads issued together, offsets folded into the
+        // LDS instructions.
 #pragma unroll 1
-        for (int kh = 0; kh < kMaxB; kh += kMaxB / 2) {
-            const T* va = TRANS ? Vs + kh * kLdsPad + m : Vs + m * kLdsPad + kh;
-            const T* vb = in + kh * LD + cc;
+        for (int sh = 0; sh < kMaxB / 4; sh += kMaxB / 8) {
+            const int p0 = 16 * kq + sh;
+            const T* va = TRANS ? Vs + p0 * kLdsPad + m : Vs + m * kLdsPad + p0;
+            const T* vb = in + p0 * LD + cc;
 #pragma unroll
-            for (int kk = 0; kk < kMaxB / 8; ++kk) {
-                const int p = 4 * kk + kq;
-                const T av = TRANS ? va[p * kLdsPad] : va[p];
-                acc = Mfma<T>::step(av, vb[p * LD], acc);
+            for (int s = 0; s < kMaxB / 8; ++s) {
+                const T av = TRANS ? va[s * kLdsPad] : va[s];
+                acc = Mfma<T>::step(av, vb[s * LD], acc);
             }
         }
         return acc;
@@ -1042,11 +1045,12 @@ __device__ __forceinline__ void mode_chain(const T* __restrict__ Vs, const T* __
     const int jc = j < nc ? j : nc - 1;
     if (b == kMaxB) {
         // one base address per operand, steps at compile-time offsets (folded into
-        // the LDS instructions, so no per-step address registers)
-        const T* rb = R + kq * ld + jc;
-        const T* vb = Vs + kq * kLdsPad + mode;
+        // the LDS instructions, so no per-step address registers); step st takes
+        // point p = 16 kq + st from lane group kq (V rows 16 apart: distinct banks)
+        const T* rb = R + 16 * kq * ld + jc;
+        const T* vb = Vs + 16 * kq * kLdsPad + mode;
 #pragma unroll
-        for (int st = 0; st < kMaxB / 4; ++st) x = Mfma<T>::step(rb[4 * st * ld] * fc, vb[4 * st * kLdsPad], x);
+        for (int st = 0; st < kMaxB / 4; ++st) x = Mfma<T>::step(rb[st * ld] * fc, vb[st * kLdsPad], x);
     } else {
         for (int st = 0; 4 * st < b; ++st) {
             const int p = 4 * st + kq;
@@ -1571,7 +1575,12 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
     constexpr int LPP = 4, IPL = 2;                          // lanes per point, items per lane
     static_assert(kMaxNT <= LPP * IPL && kMaxB * LPP == THR && NW == 4, "every residual item has a lane");
     __shared__ BT Vs[kMaxB * kLdsPad];
-    __shared__ double2 cs[(kMaxB + 1) * NT];   // row kMaxB: zeros (absent neighbours)
+    __shared__ double2 cs[(kMaxB + 1) * NT];   // row kMaxB: zeros (absent neighbours); layout csx
+    // Slot of (point l, component m) in cs: with N_t = 8 the components of row l are
+    // permuted by (l / 2) mod 8, so that both the 64 lanes reading one component of
+    // 16 points and the 16 point groups reading one component each spread over all
+    // LDS banks (128-byte rows would otherwise meet in two bank groups).
+    auto csx = [](int l, int m) { return l * NT + (NT == 8 ? m ^ ((l >> 1) & 7) : m); };
     __shared__ double2 ls[kMaxB];
     __shared__ int gidx[kMaxB];
     __shared__ C sgr[kMaxB];       // constraint residual of each point
@@ -1581,7 +1590,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
     __shared__ BT es[kMaxB];
     __shared__ double2 sgs[kMaxB + 1];  // constraint residual per point (row kMaxB: zero)
     __shared__ double tos[NT];             // the time operator U (indexed per lane, so staged here)
-    __shared__ double2 tcs[NT * NT];       // per (m, n): W_mn and the 0/1 pattern of the Q coupling
+    __shared__ double2 tcs[NT * NT];       // at n NT + m: W_mn and the 0/1 pattern of the Q coupling
     __shared__ double red[NW];
     __shared__ double rnorm_sh;
 
@@ -1720,7 +1729,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
     if (iw >= 0 && iw < NT * NT) {
         const int mm = iw / NT, nn = iw - mm * NT;
         const bool cpl = a.adjoint ? (nn < mm && ((mm - nn) & 1)) : (nn > mm && ((nn - mm) & 1));
-        tcs[iw] = make_double2(tov, cpl ? 1.0 : 0.0);
+        tcs[nn * NT + mm] = make_double2(tov, cpl ? 1.0 : 0.0);
     }
     if (tid < NT) cs[kMaxB * NT + tid] = make_double2(0.0, 0.0);
     if (tid == NT) sgs[kMaxB] = make_double2(0.0, 0.0);
@@ -1746,7 +1755,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
         pre[k] = add2(scl2(-g.kin, halo), scl2(v0l, own[k]));
         // formed here, so that the halo values need no registers past the barrier
         asm volatile("" : "+v"(pre[k].x), "+v"(pre[k].y));
-        if (item[k]) cs[l_it * NT + m_it[k]] = own[k];
+        if (item[k]) cs[csx(l_it, m_it[k])] = own[k];
     }
     if (tid < b) {
         gidx[tid] = gjp;
@@ -1778,17 +1787,17 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
     for (int k = 0; k < IPL; ++k) {
         if (!item[k]) continue;
         const int l = l_it, m = m_it[k];
-        double2 nbs = cs[nrow[0] * NT + m];
+        double2 nbs = cs[csx(nrow[0], m)];
 #pragma unroll
-        for (int dir = 1; dir < 6; ++dir) nbs = add2(nbs, cs[nrow[dir] * NT + m]);
+        for (int dir = 1; dir < 6; ++dir) nbs = add2(nbs, cs[csx(nrow[dir], m)]);
         const double2 hc = add2(pre[k], scl2(-g.kin, nbs));
         double2 tq = make_double2(0.0, 0.0);
         double2 wc = make_double2(0.0, 0.0);
         if (a.field_on) {
 #pragma unroll
             for (int n = 0; n < NT; ++n) {
-                const double2 cn = cs[l * NT + n];
-                const double2 wq = tcs[m * NT + n];
+                const double2 cn = cs[csx(l, n)];
+                const double2 wq = tcs[n * NT + m];
                 tq = add2(tq, scl2(wq.y, cn));
                 wc = add2(wc, scl2(wq.x, cn));
             }
@@ -1797,7 +1806,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
             for (int kk = 0; kk < (NT + 1) / 2; ++kk) {
                 const int n = a.adjoint ? m - 1 - 2 * kk : m + 1 + 2 * kk;
                 const bool in = n >= 0 && n < NT;
-                tq = add2(tq, scl2(in ? 1.0 : 0.0, cs[l * NT + (in ? n : m)]));
+                tq = add2(tq, scl2(in ? 1.0 : 0.0, cs[csx(l, in ? n : m)]));
             }
         }
         const double2 tim = a.adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
@@ -1821,7 +1830,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
             const double2 asg = add2(scl2(g.kin, sub2(scl2(2.0 * gdim, sg), lin)), scl2(v0l, sg));
             r = add2(r, scl2(tos[0], asg));
         }
-        if (a.field_on) r = add2(r, scl2(zf * tcs[m * NT].x, sg));
+        if (a.field_on) r = add2(r, scl2(zf * tcs[m].x, sg));
         if (a.adjoint && (m & 1)) r = add2(r, make_double2(-2.0 * sg.y, 2.0 * sg.x));
         xb[l * NQ + m] = C{(BT)r.x, (BT)r.y};
     }
@@ -1876,7 +1885,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
             for (int k = 0; k < IPL; ++k) {
                 if (!item[k]) continue;
                 const int l = l_it, m = m_it[k];
-                a.c[(size_t)gj_it * NT + m] = add2(cs[l * NT + m], make_double2((double)dv[k].r, (double)dv[k].i));
+                a.c[(size_t)gj_it * NT + m] = add2(cs[csx(l, m)], make_double2((double)dv[k].r, (double)dv[k].i));
                 if (m == 0) a.lam[gj_it] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
             }
             if (a.passes && tid == 0)
@@ -1889,7 +1898,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
         for (int k = 0; k < IPL; ++k) {
             if (!item[k]) continue;
             const int l = l_it, m = m_it[k];
-            cs[l * NT + m] = add2(cs[l * NT + m], make_double2((double)dv[k].r, (double)dv[k].i));
+            cs[csx(l, m)] = add2(cs[csx(l, m)], make_double2((double)dv[k].r, (double)dv[k].i));
             if (m == 0) ls[l] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
             rh[l * NQ + m] = dv[k];
         }
@@ -1905,7 +1914,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
             C wd = C{0, 0};
             if (a.field_on) {
 #pragma unroll 1
-                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tcs[m * NT + n].x, rh[l * NQ + n]);
+                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tcs[n * NT + m].x, rh[l * NQ + n]);
             }
             const C rn = rmul((BT)(zl - zf), wd);
             if (m == 0) sgr[l] = C{0, 0};
@@ -1925,7 +1934,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
                 if (a.passes && tid == 0) a.passes[blk] = (unsigned char)(pass | (solved ? 0 : 0x80));
                 for (int t = tid; t < b * NT; t += THR) {
                     const int l = t / NT, n = t - l * NT;
-                    a.c[(size_t)gidx[l] * NT + n] = cs[t];
+                    a.c[(size_t)gidx[l] * NT + n] = cs[csx(l, n)];
                 }
                 for (int l = tid; l < b; l += THR) a.lam[gidx[l]] = ls[l];
                 break;
