@@ -136,8 +136,8 @@ typedef struct {
                          at one dipole coordinate zf, the centre of its slab of
                          subvolumes along the field axis; the corrections remove the
                          rest, (z - zf) W, point by point.  Each subvolume stops once its
-                         own residual fell by 1e-13 in FP64, 1e-5 in FP32, or stops
-                         improving (lam_pass_stats counts both) */
+                         own residual fell by inner_tol, or stops improving
+                         (lam_pass_stats counts both) */
     int time_factor;  /* how each mode's time system is solved inside a sweep:
                          LAM_TF_SHARED (0): one factor shared by all modes (the n_t x n_t
                          system left after each point's continuity row eliminates c_0,
@@ -165,6 +165,12 @@ typedef struct {
                          and the deepest halving used.  Forward steps (lam_solve_step,
                          lam_propagate) and adjoint steps (lam_adjoint_step, which splits
                          the same way its forward recomputation does) */
+    double inner_tol; /* the inner corrections of a subvolume stop once its own residual
+                         norm fell by this factor; 0 = the precision's default: 1e-13 in
+                         FP64 (an exact subvolume solve), 1e-2 in FP32 (the field defect
+                         left below 1% of the local residual does not change the V-cycle
+                         rate, and each further correction costs a whole block solve;
+                         1e-5 makes the FP32 solve exact to its precision).  0 <= inner_tol < 1 */
 } lam_solver;
 
 typedef struct {

@@ -730,6 +730,10 @@ int sweep(lam_ctx* c, int l, int colour, const int* skip = nullptr) {
     a.passes = L.d_passes;
     a.adjoint = c->adjoint;
     a.n_inner = c->n_inner;
+    {
+        const double tol = c->solver.inner_tol > 0.0 ? c->solver.inner_tol : (L.fp32 ? 1e-2 : 1e-13);
+        a.inner_tol2 = tol * tol;
+    }
     a.field_on = c->field_on ? 1 : 0;
     const bool rec = c->prof > 0 && l == 0 && (c->prof_count++ % c->prof) == 0;
     if (rec) {
@@ -1002,6 +1006,7 @@ int validate(const lam_grid* g, const lam_time* t, const lam_ham* h, const lam_s
     if (s->max_cycles < 0 || !(s->tol >= 0.0) || s->n_inner < -1 || s->n_inner > LAM_MAX_INNER) return LAM_EINVAL;
     if (!(s->coarse_reduction >= 0.0 && s->coarse_reduction < 1.0)) return LAM_EINVAL;
     if (s->max_split < 0 || s->max_split > LAM_MAX_SPLIT) return LAM_EINVAL;
+    if (!(s->inner_tol >= 0.0 && s->inner_tol < 1.0)) return LAM_EINVAL;
     if (s->time_factor != LAM_TF_SHARED && s->time_factor != LAM_TF_STORED) return LAM_EINVAL;
     long bpts = 1;
     for (int a = 0; a < g->dim; ++a) {

@@ -69,6 +69,8 @@ struct SweepArgs {
     int adjoint;
     int n_inner;
     int field_on;             // W (the field's time matrix) is nonzero this step
+    double inner_tol2;        // inner passes stop once the block's residual norm fell by
+                              // this factor squared
 };
 
 // Control of the iterated coarsest-level solve (device memory): the norm N of

@@ -1118,11 +1118,38 @@ __device__ __forceinline__ float dpp_move(float v) {
 }
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-    static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1, 2, 4 or 8 lanes");
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1, 2, 4, 8 or 16 lanes");
     if constexpr (G >= 2) v += dpp_move<0xB1>(v);    // quad_perm (1, 0, 3, 2)
     if constexpr (G >= 4) v += dpp_move<0x4E>(v);    // quad_perm (2, 3, 0, 1)
     if constexpr (G >= 8) v += dpp_move<0x141>(v);   // row_half_mirror
+    if constexpr (G >= 16) v += dpp_move<0x140>(v);  // row_mirror
     return v;
+}
+
+// Sum over the wave, the same value in every lane: the sums of the four rows of
+// 16 lanes by DPP, then read from lanes 0, 16, 32 and 48 and added in that order.
+// Every lane of the wave must be active.
+__device__ __forceinline__ double wave_total(double v) {
+    const long long u = __double_as_longlong(group_sum<16>(v));
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)u, 16 * r);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), 16 * r);
+        t += __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
+    return t;
+}
+
+// The value of lane s of each quad (s < 4), in every lane of the quad.
+template <typename T>
+__device__ __forceinline__ cx<T> quad_bcast(const cx<T>& v, int s) {
+    switch (s) {
+        case 0: return cx<T>{dpp_move<0x00>(v.r), dpp_move<0x00>(v.i)};   // quad_perm (0, 0, 0, 0)
+        case 1: return cx<T>{dpp_move<0x55>(v.r), dpp_move<0x55>(v.i)};   // quad_perm (1, 1, 1, 1)
+        case 2: return cx<T>{dpp_move<0xAA>(v.r), dpp_move<0xAA>(v.i)};   // quad_perm (2, 2, 2, 2)
+        default: return cx<T>{dpp_move<0xFF>(v.r), dpp_move<0xFF>(v.i)};  // quad_perm (3, 3, 3, 3)
+    }
 }
 
 // Waves per SIMD the sweep is compiled for: the shared-factor variants fit 128
@@ -1195,10 +1222,10 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     const int b = g.bpts;
     const int nd = 2 * g.dim;
     constexpr bool shared_tf = !STORED;
-    // inner passes stop once the block's own residual fell below this fraction (in norm)
-    // (FP64: 1e-13; FP32: 1e-5, about what FP32 corrections can resolve), or once a pass
-    // gains less than a factor 4 (the corrections have reached their rounding floor)
-    const double inner_tol2 = sizeof(BT) == 8 ? 1e-26 : 1e-10;
+    // inner passes stop once the block's own residual fell by the solver's factor (in
+    // norm), or once a pass gains less than a factor 4 (the corrections have reached
+    // their rounding floor)
+    const double inner_tol2 = a.inner_tol2;
     double rprev = 0.0;
 
     // ---- 1. the block's eigenvectors and time factor record first: they depend on
@@ -1582,7 +1609,6 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
     // LDS banks (128-byte rows would otherwise meet in two bank groups).
     auto csx = [](int l, int m) { return l * NT + (NT == 8 ? m ^ ((l >> 1) & 7) : m); };
     __shared__ double2 ls[kMaxB];
-    __shared__ int gidx[kMaxB];
     __shared__ C sgr[kMaxB];       // constraint residual of each point
     __shared__ C rh[kMaxB * NQ];   // per-mode solutions
     __shared__ C xb[kMaxB * NQ];   // reduced right-hand side, then the correction V y
@@ -1591,8 +1617,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
     __shared__ double2 sgs[kMaxB + 1];  // constraint residual per point (row kMaxB: zero)
     __shared__ double tos[NT];             // the time operator U (indexed per lane, so staged here)
     __shared__ double2 tcs[NT * NT];       // at n NT + m: W_mn and the 0/1 pattern of the Q coupling
-    __shared__ double red[NW];
-    __shared__ double rnorm_sh;
+    __shared__ double2 red2[NW];    // per wave: an inner pass's residual norm and the initial one
 
     {
         // touch every 64-byte line of the sweep arguments at once (see k_sweep)
@@ -1632,7 +1657,7 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
     }
     const int b = CUBE4 ? 64 : g.bpts;
     const int nd = 2 * gdim;
-    const double inner_tol2 = 1e-10;   // FP32: about what FP32 corrections resolve (in norm, 1e-5)
+    const double inner_tol2 = a.inner_tol2;   // inner passes: see k_sweep
     double rprev = 0.0;
 
     // ---- 1. eigenvectors and the slab's time factor record (see k_sweep) ----
@@ -1758,7 +1783,6 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
         if (item[k]) cs[csx(l_it, m_it[k])] = own[k];
     }
     if (tid < b) {
-        gidx[tid] = gjp;
         ls[tid] = lp;
         es[tid] = ep;
     }
@@ -1836,13 +1860,6 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
     }
     __syncthreads();
     double r0n = 0.0;
-    if (a.n_inner > 0) {
-        const double tot = block_sum(rloc, red);
-        if (tid == 0) rnorm_sh = tot;
-        __syncthreads();
-        r0n = rnorm_sh;
-        __syncthreads();
-    }
 
     for (int pass = 0; pass <= a.n_inner; ++pass) {
         // ---- 3a + 3b. into the block eigenbasis and the per-mode solve, one wave per
@@ -1879,67 +1896,76 @@ __global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, Tim
             for (int k = 0; k < IPL; ++k) dv[k] = m_it[k] > 0 ? x[k] : C{sg.r - sr, sg.i - si};
             dl = x[0];   // used by the lane holding m = 0 only
         }
-        if (last) {
-            // the last possible pass writes the updated state straight to HBM
+        // the updated state goes straight to HBM, before the pass check: the block
+        // owns its points during the launch, so when another pass follows (rarely)
+        // its result simply overwrites this one
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            if (!item[k]) continue;
+            const int l = l_it, m = m_it[k];
+            a.c[(size_t)gj_it * NT + m] = add2(cs[csx(l, m)], make_double2((double)dv[k].r, (double)dv[k].i));
+            if (m == 0) a.lam[gj_it] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
+        }
+        // inner pass check (see k_sweep): the next local residual would be
+        // (z_l - zf) (W delta_l)_m on row (l, m) and 0 on the constraint rows; its
+        // norm against the initial one decides (uniformly: every thread sums the
+        // same wave partials after one barrier) whether the block is done
+        bool done = last;
+        unsigned char pbyte = (unsigned char)(pass | ((a.n_inner > 0 && a.field_on) ? 0x80 : 0));
+        C rn[IPL];
+        if (!last) {
+            // delta of every component of the point, from the point's four lanes
+            // (lane q holds components q and q + 4)
+            C dn[NT];
+#pragma unroll
+            for (int n = 0; n < NT; ++n) dn[n] = quad_bcast(dv[n >> 2], n & 3);
+            double loc = 0.0;
 #pragma unroll
             for (int k = 0; k < IPL; ++k) {
-                if (!item[k]) continue;
-                const int l = l_it, m = m_it[k];
-                a.c[(size_t)gj_it * NT + m] = add2(cs[csx(l, m)], make_double2((double)dv[k].r, (double)dv[k].i));
-                if (m == 0) a.lam[gj_it] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
+                const int m = m_it[k];
+                C wd = C{0, 0};
+                if (a.field_on) {
+#pragma unroll
+                    for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tcs[n * NT + m].x, dn[n]);
+                }
+                rn[k] = item[k] ? rmul((BT)(zl - zf), wd) : C{0, 0};
+                loc += (double)rn[k].r * rn[k].r + (double)rn[k].i * rn[k].i;
             }
-            if (a.passes && tid == 0)
-                a.passes[blk] = (unsigned char)(pass | ((a.n_inner > 0 && a.field_on) ? 0x80 : 0));
+            const double ws = wave_total(loc), w0 = pass == 0 ? wave_total(rloc) : 0.0;
+            if (lane == 0) red2[wave] = make_double2(ws, w0);
+            __syncthreads();
+            double rnt = 0.0, r0t = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const double2 v = red2[w];
+                rnt += v.x;
+                r0t += v.y;
+            }
+            if (pass == 0) r0n = r0t;
+            // the same in every lane: taken as a scalar, so the branches below are uniform
+            const bool solved = __builtin_amdgcn_readfirstlane(rnt <= inner_tol2 * r0n ? 1 : 0) != 0;
+            done = solved || __builtin_amdgcn_readfirstlane(rnt > 0.0625 * (pass > 0 ? rprev : r0n) ? 1 : 0) != 0;
+            rprev = rnt;
+            pbyte = (unsigned char)(pass | (solved ? 0 : 0x80));
+        }
+        if (done) {
+            if (a.passes && tid == 0) a.passes[blk] = pbyte;
             break;
         }
-        // inner pass (see k_sweep): the state stays in LDS, the new local residual is
-        // (z_l - zf) (W delta_l)_m on row (l, m) and 0 on the constraint rows
+        // another pass: the state stays in LDS and the new local residual is the
+        // right-hand side
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
             if (!item[k]) continue;
             const int l = l_it, m = m_it[k];
             cs[csx(l, m)] = add2(cs[csx(l, m)], make_double2((double)dv[k].r, (double)dv[k].i));
-            if (m == 0) ls[l] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
-            rh[l * NQ + m] = dv[k];
-        }
-        // a point's lanes are one group inside a wave
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double loc = 0.0;
-#pragma unroll
-        for (int k = 0; k < IPL; ++k) {
-            if (!item[k]) continue;
-            const int l = l_it, m = m_it[k];
-            C wd = C{0, 0};
-            if (a.field_on) {
-#pragma unroll 1
-                for (int n = 0; n < NT; ++n) wd = wd + rmul((BT)tcs[n * NT + m].x, rh[l * NQ + n]);
+            if (m == 0) {
+                ls[l] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
+                sgr[l] = C{0, 0};
             }
-            const C rn = rmul((BT)(zl - zf), wd);
-            if (m == 0) sgr[l] = C{0, 0};
-            xb[l * NQ + m] = rn;
-            loc += (double)rn.r * rn.r + (double)rn.i * rn.i;
+            xb[l * NQ + m] = rn[k];
         }
-        {
-            const double tot = block_sum(loc, red);
-            if (tid == 0) rnorm_sh = tot;
-            __syncthreads();
-            const double rn = rnorm_sh;
-            const bool solved = rn <= inner_tol2 * r0n;
-            const bool done = solved || rn > 0.0625 * (pass > 0 ? rprev : r0n);
-            rprev = rn;
-            __syncthreads();
-            if (done) {
-                if (a.passes && tid == 0) a.passes[blk] = (unsigned char)(pass | (solved ? 0 : 0x80));
-                for (int t = tid; t < b * NT; t += THR) {
-                    const int l = t / NT, n = t - l * NT;
-                    a.c[(size_t)gidx[l] * NT + n] = cs[csx(l, n)];
-                }
-                for (int l = tid; l < b; l += THR) a.lam[gidx[l]] = ls[l];
-                break;
-            }
-        }
+        __syncthreads();
     }
 }
 

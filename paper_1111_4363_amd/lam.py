@@ -65,7 +65,7 @@ class LamHam(ctypes.Structure):
 class LamSolver(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_cycles", ctypes.c_int),
                 ("n_inner", ctypes.c_int), ("time_factor", ctypes.c_int), ("coarse_reduction", ctypes.c_double),
-                ("max_split", ctypes.c_int)]
+                ("max_split", ctypes.c_int), ("inner_tol", ctypes.c_double)]
 
 
 class LamPWRegime(ctypes.Structure):
@@ -263,7 +263,7 @@ class Propagator:
     def __init__(self, shape, h, v0, n_t, dt, block, levels=1, nu_pre=1, nu_post=1, nu_coarse=2,
                  interp="linear", periodic=False, mass=1.0, field_axis=-1, pulse=None,
                  precision="fp64", tol=1e-10, max_cycles=50, n_inner=-1, time_factor="shared", coarse_reduction=0.0,
-                 max_split=0, coarse_op="rediscretised", stream=None):
+                 max_split=0, coarse_op="rediscretised", inner_tol=0.0, stream=None):
         lib = load_library()
         v0 = v0.contiguous()
         g, t, ham, self._coef, coef, self.npts = _describe(shape, h, v0, n_t, dt, block, levels, nu_pre, nu_post,
@@ -275,7 +275,7 @@ class Propagator:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.n_coef = len(coef)
         s = LamSolver(PRECISION[precision], float(tol), int(max_cycles), int(n_inner), TIME_FACTOR[time_factor],
-                      float(coarse_reduction), int(max_split))
+                      float(coarse_reduction), int(max_split), float(inner_tol))
         self.levels = int(levels)
         self.precision = precision
         # what the context holds (the autograd function restores its own inputs)

@@ -53,7 +53,7 @@ int main(void) {
          sizeof(lam_grid), sizeof(lam_time), sizeof(lam_ham), sizeof(lam_solver), sizeof(lam_stats));
   P(lam_grid, h) P(lam_grid, block) P(lam_grid, interp) P(lam_grid, coarse_op) P(lam_ham, v0) P(lam_ham, coef)
   P(lam_ham, t_total) P(lam_solver, n_inner) P(lam_solver, time_factor) P(lam_solver, coarse_reduction)
-  P(lam_stats, t_solve_ms) P(lam_stats, resid_last) P(lam_stats, coarse_unmet) P(lam_solver, max_split)
+  P(lam_stats, t_solve_ms) P(lam_stats, resid_last) P(lam_stats, coarse_unmet) P(lam_solver, max_split) P(lam_solver, inner_tol)
   P(lam_stats, substeps) P(lam_stats, split_depth)
   return 0;
 }
@@ -81,6 +81,7 @@ int main(void) {
     assert int(out["lam_solver.coarse_reduction"]) == lam.LamSolver.coarse_reduction.offset
     assert int(out["lam_stats.coarse_unmet"]) == lam.LamStats.coarse_unmet.offset
     assert int(out["lam_solver.max_split"]) == lam.LamSolver.max_split.offset
+    assert int(out["lam_solver.inner_tol"]) == lam.LamSolver.inner_tol.offset
     assert int(out["lam_stats.substeps"]) == lam.LamStats.substeps.offset
     assert int(out["lam_stats.split_depth"]) == lam.LamStats.split_depth.offset
 

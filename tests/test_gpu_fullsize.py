@@ -48,7 +48,10 @@ def neighbourhood(grid, pts):
     return sorted(out)
 
 
-def setup(name, precision="fp64"):
+EXACT_TOL = {"fp64": 0.0, "mixed": 1e-5}
+
+
+def setup(name, precision="fp64", inner_tol=0.0):
     import torch
     from paper_1111_4363_amd import lam
     cfg = W.config(name)
@@ -65,7 +68,7 @@ def setup(name, precision="fp64"):
     prop = lam.Propagator(cfg["shape"], cfg["h"], torch.as_tensor(v0, device=dev), cfg["n_t"], cfg["dt"],
                           (cfg["block"],) * cfg["dim"], levels=cfg["levels"], nu_coarse=cfg["nu_coarse"],
                           coarse_reduction=cfg["coarse_reduction"],
-                          pulse=pulse, precision=precision, tol=1e-10, max_cycles=60)
+                          pulse=pulse, precision=precision, tol=1e-10, max_cycles=60, inner_tol=inner_tol)
     grid = G.Grid(cfg["shape"], cfg["h"])
     return cfg, v0, psi0, pulse, prop, grid, dev
 
@@ -104,7 +107,8 @@ def test_fullsize_sweep_sampled_blocks(name, precision):
     (FP64: 1e-11 of the correction; mixed, FP32 local solves: 1e-4, as in the
     small-size sweep parity); the other colour's points are left untouched."""
     import torch
-    cfg, v0, psi0, pulse, prop, grid, dev = setup(name, precision)
+    # exact subvolume solves (FP32: corrections of the field defect to 1e-5)
+    cfg, v0, psi0, pulse, prop, grid, dev = setup(name, precision, EXACT_TOL[precision])
     note(f"full-size sweep {name} {precision} {cfg['shape']}")
     nt, P = cfg["n_t"], grid.npts
     c, lam_ = W.random_state_device(P, nt, 12, dev, scale=0.1)
@@ -157,7 +161,8 @@ def test_fullsize_adjoint_sweep_sampled_blocks(name, precision):
     residual rows (FP64: 1e-11 of the correction; mixed: 1e-4); the other
     colour's points untouched.  Also: every subvolume's local system solved."""
     import torch
-    cfg, v0, psi0, pulse, prop, grid, dev = setup(name, precision)
+    # exact subvolume solves (FP32: corrections of the field defect to 1e-5)
+    cfg, v0, psi0, pulse, prop, grid, dev = setup(name, precision, EXACT_TOL[precision])
     note(f"full-size adjoint sweep {name} {precision} {cfg['shape']}")
     nt, P = cfg["n_t"], grid.npts
     mu_c, mu_l = W.random_state_device(P, nt, 21, dev, scale=0.1)
@@ -227,7 +232,7 @@ def test_fullsize_step_converges(name, precision):
          f"finest inner passes max={passes} unsolved={unsolved}")
     assert st["resid"] <= 1e-10 * st["resid0"]
     # every finest subvolume's local system solved; with the field's full time matrix in
-    # the slab factor, at most 3 corrections (FP64, to 1e-13) or 1 (FP32, to 1e-5)
+    # the slab factor, at most 3 corrections (FP64, to 1e-13) or 1 (FP32, to 1e-2)
     assert unsolved == 0
     assert passes <= (3 if precision == "fp64" else 1)
     c_t, l_t = prop.get_state()

@@ -33,7 +33,7 @@ def _create(**over):
     h.n_coef = over.get("n_coef", 0)
     s = lam.LamSolver(over.get("precision", 0), over.get("tol", 1e-10), over.get("max_cycles", 10),
                       over.get("n_inner", -1), over.get("time_factor", 0), over.get("coarse_reduction", 0.0),
-                      over.get("max_split", 0))
+                      over.get("max_split", 0), over.get("inner_tol", 0.0))
     out = ctypes.c_void_p()
     return lib.lam_create(ctypes.byref(g), ctypes.byref(t), ctypes.byref(h), ctypes.byref(s), None,
                           ctypes.byref(out))
@@ -50,7 +50,7 @@ def _create(**over):
     dict(field_axis=2), dict(pulse_kind=7), dict(pulse_kind=1, t_total=0.0), dict(n_coef=3),
     dict(precision=2), dict(tol=-1.0), dict(n_inner=-2), dict(interp=3), dict(v0=None), dict(time_factor=2),
     dict(n_inner=33), dict(coarse_reduction=-0.1), dict(coarse_reduction=1.0), dict(coarse_reduction=float("nan")),
-    dict(max_split=-1), dict(max_split=9),
+    dict(max_split=-1), dict(max_split=9), dict(inner_tol=-1e-3), dict(inner_tol=1.0), dict(inner_tol=float("nan")),
     dict(coarse_op=2), dict(coarse_op=1, interp=0),     # Galerkin needs piecewise-constant interpolation
 ])
 def test_invalid_arguments_are_rejected(over):
