@@ -271,6 +271,57 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return tot;
 }
 
+// Sum over aligned groups of G consecutive lanes (G = 1, 2, 4 or 8), returned
+// in every lane of the group: DPP moves within a quad (lanes ^ 1, ^ 2), then
+// between the two quads of a group of eight (row_half_mirror).  Every lane of
+// the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1, 2, 4, 8 or 16 lanes");
+    if constexpr (G >= 2) v += dpp_move<0xB1>(v);    // quad_perm (1, 0, 3, 2)
+    if constexpr (G >= 4) v += dpp_move<0x4E>(v);    // quad_perm (2, 3, 0, 1)
+    if constexpr (G >= 8) v += dpp_move<0x141>(v);   // row_half_mirror
+    if constexpr (G >= 16) v += dpp_move<0x140>(v);  // row_mirror
+    return v;
+}
+
+// Sum over the wave, the same value in every lane: the sums of the four rows of
+// 16 lanes by DPP, then read from lanes 0, 16, 32 and 48 and added in that order.
+// Every lane of the wave must be active.
+__device__ __forceinline__ double wave_total(double v) {
+    const long long u = __double_as_longlong(group_sum<16>(v));
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)u, 16 * r);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), 16 * r);
+        t += __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
+    return t;
+}
+
+// The value of lane s of each quad (s < 4), in every lane of the quad.
+template <typename T>
+__device__ __forceinline__ cx<T> quad_bcast(const cx<T>& v, int s) {
+    switch (s) {
+        case 0: return cx<T>{dpp_move<0x00>(v.r), dpp_move<0x00>(v.i)};   // quad_perm (0, 0, 0, 0)
+        case 1: return cx<T>{dpp_move<0x55>(v.r), dpp_move<0x55>(v.i)};   // quad_perm (1, 1, 1, 1)
+        case 2: return cx<T>{dpp_move<0xAA>(v.r), dpp_move<0xAA>(v.i)};   // quad_perm (2, 2, 2, 2)
+        default: return cx<T>{dpp_move<0xFF>(v.r), dpp_move<0xFF>(v.i)};  // quad_perm (3, 3, 3, 3)
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K1: action residual of the step system (or its adjoint) + norm partials.
 // One thread per (point, time component), kThreads / NT points per workgroup,
@@ -473,6 +524,235 @@ __global__ __launch_bounds__(kThreads) void k_residual_restrict(LevelGeom f, Lev
             }
         }
     }
+}
+
+// K1 and K1+K4 on 3D levels: a workgroup takes an 8 x 8 tile of the (y, z)
+// plane, four lanes per point (lane q holds the time components q and q + 4,
+// like the pair sweep), and marches along x over a range of planes.  A point's
+// neighbours across x stay in the registers of its lanes (previous, current and
+// next plane); the current plane and its one-point halo in y and z sit in LDS
+// (two buffers, one barrier per plane).  Each coefficient is read 1.5 times
+// (own plane + halo) instead of once per stencil neighbour, and the work of a
+// point (addresses, potential, multiplier, right-hand sides, the constraint
+// row) is shared by its two components.  The arithmetic of each item is that
+// of residual_item (the constraint sum taken over the point's lanes);
+// RESTRICT: the residual is averaged over the 2 x 2 x 2 children of each
+// coarse point (planes 2X and 2X + 1 of the range) as in k_residual_restrict,
+// else the norm partial of the workgroup.
+constexpr int kMarchTY = 8, kMarchTZ = 8;
+
+template <int NT, bool RESTRICT>
+__global__ __launch_bounds__(kThreads, 3) void k_residual_march(
+    LevelGeom g, LevelGeom cg, TimeOps<NT> to, int adjoint, int field_on, const double2* __restrict__ c,
+    const double2* __restrict__ lam, const double* __restrict__ v0, const double2* __restrict__ bc,
+    const double2* __restrict__ bg, const double2* __restrict__ bs, double2* __restrict__ rc,
+    double2* __restrict__ rs, double* __restrict__ partial, const int* __restrict__ skip,
+    const unsigned char* __restrict__ bmask, double2* __restrict__ bcc, double2* __restrict__ bsc,
+    double2* __restrict__ zc, double2* __restrict__ zl, int tiles_y, int tiles_z, int xs) {
+    if (skip && *skip) return;
+    constexpr int TY = kMarchTY, TZ = kMarchTZ, HZ = TZ + 2, HP = (TY + 2) * HZ;
+    constexpr int NQ = NT + 1, IPL = 2;
+    constexpr int NHALO = 2 * TZ + 2 * TY;   // halo points of a plane tile (no corners)
+    static_assert(TY * TZ * 4 == kThreads && NHALO * 8 == kThreads, "four lanes per point, one halo item per thread");
+    __shared__ double2 pl[2][HP * NT];
+    __shared__ double2 rb[RESTRICT ? 2 : 1][RESTRICT ? TY * TZ * NQ : 1];
+    __shared__ double tos[NT + NT * NT];
+    __shared__ double red[kThreads / 64];
+    const int t = threadIdx.x;
+    const int q = t & 3, pz = (t >> 2) & (TZ - 1), py = t >> 5;
+    bool item[IPL];
+    int mi[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+        item[k] = q + 4 * k < NT;
+        mi[k] = item[k] ? q + 4 * k : 0;
+    }
+    const int bid = (int)blockIdx.x;
+    const int q0 = bid / tiles_z, tzi = bid - q0 * tiles_z;
+    const int xr = q0 / tiles_y, tyi = q0 - xr * tiles_y;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const size_t sx = (size_t)n1 * n2;
+    const int y = tyi * TY + py, z = tzi * TZ + pz;
+    const int jyz = y * n2 + z;
+    const int x0 = xr * xs, x1 = min(n0, x0 + xs);
+    // this thread's halo item: point hp of the halo ring, component hm
+    const int hp = t >> 3, hm = t & 7;
+    int hy, hz;
+    if (hp < TZ) { hy = -1; hz = hp; }
+    else if (hp < 2 * TZ) { hy = TY; hz = hp - TZ; }
+    else if (hp < 2 * TZ + TY) { hy = hp - 2 * TZ; hz = -1; }
+    else { hy = hp - 2 * TZ - TY; hz = TZ; }
+    int gy = tyi * TY + hy, gz = tzi * TZ + hz;
+    bool hval = hm < NT;
+    if (gy < 0 || gy >= n1) { gy += gy < 0 ? n1 : -n1; hval = hval && g.periodic; }
+    if (gz < 0 || gz >= n2) { gz += gz < 0 ? n2 : -n2; hval = hval && g.periodic; }
+    const int hmc = hm < NT ? hm : 0;
+    const int hj = gy * n2 + gz;
+    const int hslot = ((hy + 1) * HZ + (hz + 1)) * NT + hmc;
+    const int oslot = ((py + 1) * HZ + (pz + 1)) * NT;
+    // plane x (one past either end: wrapped, or zero under Dirichlet)
+    auto plane = [&](int x, bool& ok) {
+        ok = true;
+        if (x < 0) { x += n0; ok = g.periodic; }
+        else if (x >= n0) { x -= n0; ok = g.periodic; }
+        return x;
+    };
+    auto load_own = [&](int x, double2* v) {
+        bool ok;
+        const int xx = plane(x, ok);
+        const double2* src = c + ((size_t)xx * sx + jyz) * NT;
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) v[k] = scl2(ok && item[k] ? 1.0 : 0.0, src[mi[k]]);
+    };
+    auto load_halo = [&](int x) {
+        bool ok;
+        const int xx = plane(x, ok);
+        return scl2(ok && hval ? 1.0 : 0.0, c[((size_t)xx * sx + hj) * NT + hmc]);
+    };
+    if (t < NT + NT * NT) tos[t] = t < NT ? to.U[t] : to.W[t - NT];
+    double2 cprev[IPL], ccur[IPL], cnext[IPL];
+    load_own(x0 - 1, cprev);
+    load_own(x0, ccur);
+    {
+        const double2 h0 = load_halo(x0);
+#pragma unroll
+        for (int k = 0; k < IPL; ++k)
+            if (item[k]) pl[0][oslot + mi[k]] = ccur[k];
+        if (hm < NT) pl[0][hslot] = h0;
+    }
+    __syncthreads();
+    double u_m[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) u_m[k] = tos[mi[k]];
+    double acc = 0.0;
+    double2 cacc = make_double2(0.0, 0.0);
+    for (int x = x0; x < x1; ++x) {
+        const int b = (x - x0) & 1;
+        // the next plane, and this plane's point data
+        load_own(x + 1, cnext);
+        const double2 hnext = load_halo(x + 1);
+        const size_t j = (size_t)x * sx + jyz;
+        const double vj = v0[j];
+        const double2 lj = lam[j];
+        double2 rhs[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            const double2* rbp = bc ? bc + j * NT + mi[k] : (bg ? bg + j : c + j * NT + mi[k]);
+            rhs[k] = scl2((bc || bg) ? 1.0 : 0.0, *rbp);
+        }
+        const double2 sgb = scl2(bs ? 1.0 : 0.0, (bs ? bs : lam)[j]);
+        const double2* P = pl[b] + oslot;
+        // the constraint residual of the point: bs - sum_n (-1)^n c_n over its lanes
+        double2 sg;
+        {
+            double2 part = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k < IPL; ++k)
+                part = add2(part, scl2(item[k] ? ((mi[k] & 1) ? 1.0 : -1.0) : 0.0, ccur[k]));
+            sg = add2(sgb, make_double2(group_sum<4>(part.x), group_sum<4>(part.y)));
+        }
+        const double zf = field_on ? zcoord(g, I3{x, y, z}) : 0.0;
+        double2 rho[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            const int m = mi[k];
+            double2 lap = add2(scl2(-6.0, ccur[k]), add2(cprev[k], cnext[k]));
+            lap = add2(lap, add2(P[-HZ * NT + m], P[HZ * NT + m]));
+            lap = add2(lap, add2(P[-NT + m], P[NT + m]));
+            double2 tq = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int kk = 0; kk < (NT + 1) / 2; ++kk) {
+                const int n = adjoint ? m - 1 - 2 * kk : m + 1 + 2 * kk;
+                const bool in = n >= 0 && n < NT;
+                tq = add2(tq, scl2(in ? 1.0 : 0.0, P[in ? n : m]));
+            }
+            const double2 tim = adjoint ? make_double2(2.0 * tq.y, -2.0 * tq.x) : make_double2(-2.0 * tq.y, 2.0 * tq.x);
+            const double2 hc = add2(scl2(-g.kin, lap), scl2(vj, ccur[k]));
+            double2 row = sub2(tim, scl2(u_m[k], hc));
+            if (field_on) {
+                double2 wc = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) wc = add2(wc, scl2(tos[NT + m * NT + n], P[n]));
+                row = sub2(row, scl2(zf, wc));
+            }
+            row = add2(row, scl2((m & 1) ? -1.0 : 1.0, lj));
+            rho[k] = sub2(rhs[k], row);
+        }
+        if constexpr (RESTRICT) {
+            double2* R = rb[b] + (py * TZ + pz) * NQ;
+#pragma unroll
+            for (int k = 0; k < IPL; ++k)
+                if (item[k]) R[mi[k]] = rho[k];
+            if (q == 0) R[NT] = sg;
+        } else {
+            double wt = 1.0;
+            if (bmask)
+                wt = bmask[((x / g.bdim[0]) * g.nblk[1] + y / g.bdim[1]) * g.nblk[2] + z / g.bdim[2]] ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) {
+                if (!item[k]) continue;
+                if (rc) rc[j * NT + mi[k]] = rho[k];
+                acc += wt * u_m[k] * (rho[k].x * rho[k].x + rho[k].y * rho[k].y);
+            }
+            if (q == 0) {
+                if (rs) rs[j] = sg;
+                acc += wt * (sg.x * sg.x + sg.y * sg.y);
+            }
+        }
+        // the next plane into the other buffer
+#pragma unroll
+        for (int k = 0; k < IPL; ++k)
+            if (item[k]) pl[b ^ 1][oslot + mi[k]] = cnext[k];
+        if (hm < NT) pl[b ^ 1][hslot] = hnext;
+        __syncthreads();
+        if constexpr (RESTRICT) {
+            // coarse points of the tile: 4 x 4, NQ values each (threads < 16 NQ)
+            if (t < (TY / 2) * (TZ / 2) * NQ) {
+                const int cp = t / NQ, qq = t - cp * NQ;
+                const int cy = cp / (TZ / 2), cz = cp - cy * (TZ / 2);
+                const double2* R = rb[b];
+                double2 s4 = add2(R[((2 * cy) * TZ + 2 * cz) * NQ + qq], R[((2 * cy) * TZ + 2 * cz + 1) * NQ + qq]);
+                s4 = add2(s4, add2(R[((2 * cy + 1) * TZ + 2 * cz) * NQ + qq], R[((2 * cy + 1) * TZ + 2 * cz + 1) * NQ + qq]));
+                cacc = add2(cacc, s4);
+                if (x & 1) {
+                    const int J = ((x >> 1) * cg.n[1] + (tyi * TY >> 1) + cy) * cg.n[2] + (tzi * TZ >> 1) + cz;
+                    const double2 v = scl2(0.125, cacc);
+                    if (qq < NT) {
+                        bcc[(size_t)J * NT + qq] = v;
+                        zc[(size_t)J * NT + qq] = make_double2(0.0, 0.0);
+                    } else {
+                        bsc[J] = v;
+                        zl[J] = make_double2(0.0, 0.0);
+                    }
+                    cacc = make_double2(0.0, 0.0);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; ++k) {
+            cprev[k] = ccur[k];
+            ccur[k] = cnext[k];
+        }
+    }
+    if constexpr (!RESTRICT) {
+        if (partial) {
+            const double tot = block_sum(acc, red);
+            if (t == 0) partial[bid] = tot;
+        }
+    }
+}
+
+// Whether a level takes the marching residual: 3D, the (y, z) plane tiled by
+// 8 x 8 exactly and an even x extent (pairs of planes restrict together).
+// Planes per workgroup: long ranges on large levels, short ones on small levels
+// (enough workgroups to fill the device).
+inline bool march_fits(const LevelGeom& g) {
+    return g.dim == 3 && g.n[1] % kMarchTY == 0 && g.n[2] % kMarchTZ == 0 && g.n[0] % 2 == 0;
+}
+inline int march_planes(const LevelGeom& g) { return g.n[0] >= 128 ? 16 : (g.n[0] >= 32 ? 8 : 2); }
+inline int march_blocks(const LevelGeom& g) {
+    const int xs = march_planes(g);
+    return (g.n[1] / kMarchTY) * (g.n[2] / kMarchTZ) * ((g.n[0] + xs - 1) / xs);
 }
 
 // Sum of the partials in a fixed order (one 1024-thread workgroup, four
@@ -1098,57 +1378,6 @@ __device__ __forceinline__ void mode_chain(const T* __restrict__ Vs, const T* __
             const int row = Mfma<T>::row(lane, r);
             if (row < nc) Z[mode * ld + row] = z[r];
         }
-    }
-}
-
-// Sum over aligned groups of G consecutive lanes (G = 1, 2, 4 or 8), returned
-// in every lane of the group: DPP moves within a quad (lanes ^ 1, ^ 2), then
-// between the two quads of a group of eight (row_half_mirror).  Every lane of
-// the wave must be active.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-template <int G, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1, 2, 4, 8 or 16 lanes");
-    if constexpr (G >= 2) v += dpp_move<0xB1>(v);    // quad_perm (1, 0, 3, 2)
-    if constexpr (G >= 4) v += dpp_move<0x4E>(v);    // quad_perm (2, 3, 0, 1)
-    if constexpr (G >= 8) v += dpp_move<0x141>(v);   // row_half_mirror
-    if constexpr (G >= 16) v += dpp_move<0x140>(v);  // row_mirror
-    return v;
-}
-
-// Sum over the wave, the same value in every lane: the sums of the four rows of
-// 16 lanes by DPP, then read from lanes 0, 16, 32 and 48 and added in that order.
-// Every lane of the wave must be active.
-__device__ __forceinline__ double wave_total(double v) {
-    const long long u = __double_as_longlong(group_sum<16>(v));
-    double t = 0.0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)u, 16 * r);
-        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), 16 * r);
-        t += __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-    }
-    return t;
-}
-
-// The value of lane s of each quad (s < 4), in every lane of the quad.
-template <typename T>
-__device__ __forceinline__ cx<T> quad_bcast(const cx<T>& v, int s) {
-    switch (s) {
-        case 0: return cx<T>{dpp_move<0x00>(v.r), dpp_move<0x00>(v.i)};   // quad_perm (0, 0, 0, 0)
-        case 1: return cx<T>{dpp_move<0x55>(v.r), dpp_move<0x55>(v.i)};   // quad_perm (1, 1, 1, 1)
-        case 2: return cx<T>{dpp_move<0xAA>(v.r), dpp_move<0xAA>(v.i)};   // quad_perm (2, 2, 2, 2)
-        default: return cx<T>{dpp_move<0xFF>(v.r), dpp_move<0xFF>(v.i)};  // quad_perm (3, 3, 3, 3)
     }
 }
 
@@ -2157,6 +2386,15 @@ hipError_t launch_residual(int nt, const LevelGeom& g, const double* U, const do
                            int field_on, const double2* c, const double2* lam, const double* v0, const double2* bc,
                            const double2* bg, const double2* bs, double2* rc, double2* rs, double* partial,
                            int* nparts, hipStream_t st, const int* skip, const unsigned char* bmask) {
+    if (march_fits(g)) {
+        const int nb = march_blocks(g);
+        if (nparts) *nparts = nb;
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_residual_march<NT, false>), dim3(nb), dim3(kThreads), 0, st, g,
+                                               g, make_ops<NT>(U, W), adjoint, field_on, c, lam, v0, bc, bg, bs, rc,
+                                               rs, partial, skip, bmask, nullptr, nullptr, nullptr, nullptr,
+                                               g.n[1] / kMarchTY, g.n[2] / kMarchTZ, march_planes(g)));
+        return hipGetLastError();
+    }
     const int nb = residual_blocks(nt, g.P);
     if (nparts) *nparts = nb;
     LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_residual<NT>, dim3(nb), dim3(kThreads), 0, st, g,
@@ -2203,6 +2441,14 @@ hipError_t launch_residual_restrict(int nt, const LevelGeom& fine, const LevelGe
                                     const double2* lam, const double* v0, const double2* bc, const double2* bg,
                                     const double2* bs, double2* bcc, double2* bsc, double2* zero_c,
                                     double2* zero_l, hipStream_t st) {
+    if (march_fits(fine)) {
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_residual_march<NT, true>), dim3(march_blocks(fine)),
+                                               dim3(kThreads), 0, st, fine, coarse, make_ops<NT>(U, W), adjoint,
+                                               field_on, c, lam, v0, bc, bg, bs, nullptr, nullptr, nullptr, nullptr,
+                                               nullptr, bcc, bsc, zero_c, zero_l, fine.n[1] / kMarchTY,
+                                               fine.n[2] / kMarchTZ, march_planes(fine)));
+        return hipGetLastError();
+    }
     const int sl = 6 - fine.dim;
     const int e0 = fine.dim == 1 ? (1 << sl) : 2, e1 = fine.dim == 1 ? 1 : (fine.dim == 2 ? (1 << sl) : 2);
     const int e2 = fine.dim == 3 ? (1 << sl) : 1;
