@@ -1809,13 +1809,14 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
 // The FP32 shared-factor colour sweep with two time components per lane: four
 // lanes per point (lane q of a point takes m = q and m = q + 4), so a 64-point
 // block is one wave per SIMD.  The per-point index arithmetic is done once for
-// two components, every wave takes part in the matrix-core steps, and at up to
-// 128 registers and under 40 KB of LDS four blocks share a compute unit.  The
+// two components, every wave takes part in the matrix-core steps, and with
+// CUBE4 (up to 128 registers and under 40 KB of LDS) four blocks share a compute
+// unit, otherwise three (the general block geometry takes up to 168).  The
 // arithmetic of each item is that of k_sweep<NT, float, false>.  CUBE4: the
 // level is 3D with 4 x 4 x 4 blocks, known at compile time (the block
 // geometry's divisions become shifts and its tests constants).
 template <int NT, bool CUBE4>
-__global__ __launch_bounds__(kPairThreads, 4) void k_sweep_pair(SweepArgs a, TimeOps<NT> to) {
+__global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(SweepArgs a, TimeOps<NT> to) {
     using BT = float;
     using C = cx<BT>;
     // a finished coarsest-level solve: the rest of its launches do nothing
