@@ -1406,7 +1406,6 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __shared__ double2 ls[kMaxB];
     __shared__ double v0s[kMaxB];
     __shared__ double zs[kMaxB];
-    __shared__ int gidx[kMaxB];
     __shared__ C rs[kMaxB * NQ];   // local residual
     __shared__ C rh[kMaxB * NQ];   // per-mode solutions (stored path: V^T r first)
     __shared__ C xb[kMaxB * NQ];   // reduced right-hand side (shared factor), then the correction V y
@@ -1414,8 +1413,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __shared__ BT es[kMaxB];
     __shared__ double2 sgs[kMaxB];  // constraint residual per point (shared factor)
     __shared__ double tos[NT + NT * NT];   // the time operators U, W (indexed per lane, so staged here)
-    __shared__ double red[kSweepThreads / 64];
-    __shared__ double rnorm_sh;
+    __shared__ double2 red2[kSweepThreads / 64];   // per wave: a pass's residual norm and the initial one
 
     {
         // touch every 64-byte line of the sweep arguments at once, so that the later
@@ -1552,7 +1550,6 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     for (int dir = 0; dir < 6; ++dir) halo = add2(halo, scl2((hmask >> dir) & 1 ? 1.0 : 0.0, hv[dir]));
     if (item) cs[l_it * NT + m_it] = own;
     if (tid < b) {
-        gidx[tid] = gjp;
         v0s[tid] = v0p;
         ls[tid] = lp;
         zs[tid] = zcoord(g, gip);
@@ -1579,6 +1576,7 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     __syncthreads();
 
     // ---- 2. local residual (FP64); the item (l, 0) also takes the constraint row of point l ----
+    double rloc = 0.0;   // squared local residual of this lane's rows (as stored)
     if (item) {
         const int l = l_it, m = m_it;
         double2 lap = add2(scl2(-2.0 * g.dim, own), halo);
@@ -1616,10 +1614,14 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         double2 row = sub2(sub2(tim, scl2(tos[m], hc)), scl2(zs[l], wc));
         row = add2(row, scl2(sm, ls[l]));
         const double2 rho = sub2(rhsv, row);
-        rs[l * NQ + m] = C{(BT)rho.x, (BT)rho.y};
+        const C rhof = C{(BT)rho.x, (BT)rho.y};
+        rs[l * NQ + m] = rhof;
+        rloc = (double)rhof.r * rhof.r + (double)rhof.i * rhof.i;
         if (m == 0) {
             if constexpr (shared_tf) sgl = sgs[l];   // the same rounding as the reduced system
-            rs[l * NQ + NT] = C{(BT)sgl.x, (BT)sgl.y};
+            const C sgf = C{(BT)sgl.x, (BT)sgl.y};
+            rs[l * NQ + NT] = sgf;
+            rloc += (double)sgf.r * sgf.r + (double)sgf.i * sgf.i;
         }
         if constexpr (shared_tf) {
             // right-hand side of the reduced system (dc_0 eliminated): rho - sigma K(e) e_0
@@ -1646,15 +1648,6 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     }
     __syncthreads();
     double r0n = 0.0;
-    if (a.n_inner > 0) {
-        double loc = 0.0;
-        for (int t = tid; t < b * NQ; t += kSweepThreads) loc += (double)rs[t].r * rs[t].r + (double)rs[t].i * rs[t].i;
-        const double tot = block_sum(loc, red);
-        if (tid == 0) rnorm_sh = tot;
-        __syncthreads();
-        r0n = rnorm_sh;
-        __syncthreads();
-    }
 
     const C* Mi = static_cast<const C*>(a.Minv);
     for (int pass = 0; pass <= a.n_inner; ++pass) {
@@ -1740,13 +1733,15 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
                 dl = x;
             }
         }
+        // the updated state goes straight to HBM, before the pass check: the block
+        // owns its points during the launch, so when another pass follows its
+        // result simply overwrites this one
+        if (item) {
+            const int l = l_it, m = m_it;
+            a.c[(size_t)gj_it * NT + m] = add2(cs[l * NT + m], make_double2((double)dv.r, (double)dv.i));
+            if (m == 0) a.lam[gj_it] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
+        }
         if (last) {
-            // the last possible pass writes the updated state straight to HBM
-            if (item) {
-                const int l = l_it, m = m_it;
-                a.c[(size_t)gj_it * NT + m] = add2(cs[l * NT + m], make_double2((double)dv.r, (double)dv.i));
-                if (m == 0) a.lam[gj_it] = add2(ls[l], make_double2((double)dl.r, (double)dl.i));
-            }
             // the cap was reached: with a field the last correction is left unchecked
             if (a.passes && tid == 0)
                 a.passes[blk] = (unsigned char)(pass | ((a.n_inner > 0 && a.field_on) ? 0x80 : 0));
@@ -1783,23 +1778,26 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
             loc = (double)rn.r * rn.r + (double)rn.i * rn.i;
         }
         {
-            // stop the defect corrections once the local system is solved
-            const double tot = block_sum(loc, red);
-            if (tid == 0) rnorm_sh = tot;
+            // stop the defect corrections once the local system is solved: the wave
+            // partials of this pass's norm (and, on the first pass, of the initial
+            // one) summed by every thread after one barrier, the same in every lane
+            const double ws = wave_total(loc), w0 = pass == 0 ? wave_total(rloc) : 0.0;
+            if (lane == 0) red2[wave] = make_double2(ws, w0);
             __syncthreads();
-            const double rn = rnorm_sh;
-            const bool solved = rn <= inner_tol2 * r0n;
-            const bool done = solved || rn > 0.0625 * (pass > 0 ? rprev : r0n);
+            double rn = 0.0, r0t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kSweepThreads / 64; ++w) {
+                const double2 v = red2[w];
+                rn += v.x;
+                r0t += v.y;
+            }
+            if (pass == 0) r0n = r0t;
+            const bool solved = __builtin_amdgcn_readfirstlane(rn <= inner_tol2 * r0n ? 1 : 0) != 0;
+            const bool done =
+                solved || __builtin_amdgcn_readfirstlane(rn > 0.0625 * (pass > 0 ? rprev : r0n) ? 1 : 0) != 0;
             rprev = rn;
-            __syncthreads();
             if (done) {
                 if (a.passes && tid == 0) a.passes[blk] = (unsigned char)(pass | (solved ? 0 : 0x80));
-                // ---- 5. write back (after an early stop of the passes) ----
-                for (int t = tid; t < b * NT; t += kSweepThreads) {
-                    const int l = t / NT, n = t - l * NT;
-                    a.c[(size_t)gidx[l] * NT + n] = cs[t];
-                }
-                for (int l = tid; l < b; l += kSweepThreads) a.lam[gidx[l]] = ls[l];
                 break;
             }
         }
