@@ -733,6 +733,14 @@ int sweep(lam_ctx* c, int l, int colour, const int* skip = nullptr) {
     {
         const double tol = c->solver.inner_tol > 0.0 ? c->solver.inner_tol : (L.fp32 ? 1e-2 : 1e-13);
         a.inner_tol2 = tol * tol;
+        // ||W||_2 <= max_m sum_n |W_mn| for the symmetric field matrix
+        double wb = 0.0;
+        for (int m = 0; m < c->nt && c->field_on; ++m) {
+            double r = 0.0;
+            for (int n = 0; n < c->nt; ++n) r += std::fabs(c->W[m * c->nt + n]);
+            wb = std::max(wb, r);
+        }
+        a.wbound2 = wb * wb;
     }
     a.field_on = c->field_on ? 1 : 0;
     const bool rec = c->prof > 0 && l == 0 && (c->prof_count++ % c->prof) == 0;

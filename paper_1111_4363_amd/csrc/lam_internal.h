@@ -71,6 +71,8 @@ struct SweepArgs {
     int field_on;             // W (the field's time matrix) is nonzero this step
     double inner_tol2;        // inner passes stop once the block's residual norm fell by
                               // this factor squared
+    double wbound2;           // square of an upper bound of the 2-norm of W (its largest
+                              // absolute row sum; W is symmetric), 0 without a field
 };
 
 // Control of the iterated coarsest-level solve (device memory): the norm N of

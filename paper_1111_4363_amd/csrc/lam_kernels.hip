@@ -1845,7 +1845,8 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
     __shared__ double2 sgs[kMaxB + 1];  // constraint residual per point (row kMaxB: zero)
     __shared__ double tos[NT];             // the time operator U (indexed per lane, so staged here)
     __shared__ double2 tcs[NT * NT];       // at n NT + m: W_mn and the 0/1 pattern of the Q coupling
-    __shared__ double2 red2[NW];    // per wave: an inner pass's residual norm and the initial one
+    __shared__ double2 red2[NW];    // per wave: the bound of an inner pass's residual norm and the initial one
+    __shared__ double red3[NW];     // per wave: an inner pass's residual norm
 
     {
         // touch every 64-byte line of the sweep arguments at once (see k_sweep)
@@ -2142,6 +2143,31 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
         unsigned char pbyte = (unsigned char)(pass | ((a.n_inner > 0 && a.field_on) ? 0x80 : 0));
         C rn[IPL];
         if (!last) {
+            // first a bound: ||(z - zf) W delta||^2 <= sum_l (z_l - zf)^2 ||W||^2 ||delta_l||^2;
+            // when it already meets the tolerance the block is solved (as the exact
+            // defect below would find), else the exact defect decides
+            {
+                double bl = 0.0;
+#pragma unroll
+                for (int k = 0; k < IPL; ++k)
+                    if (item[k]) bl += (double)dv[k].r * dv[k].r + (double)dv[k].i * dv[k].i;
+                bl *= (zl - zf) * (zl - zf);
+                const double wb = wave_total(bl), w0 = pass == 0 ? wave_total(rloc) : 0.0;
+                if (lane == 0) red2[wave] = make_double2(wb, w0);
+                __syncthreads();
+                double bt = 0.0, r0t = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const double2 v = red2[w];
+                    bt += v.x;
+                    r0t += v.y;
+                }
+                if (pass == 0) r0n = r0t;
+                if (__builtin_amdgcn_readfirstlane(a.wbound2 * bt <= inner_tol2 * r0n ? 1 : 0) != 0) {
+                    if (a.passes && tid == 0) a.passes[blk] = (unsigned char)pass;
+                    break;
+                }
+            }
             // delta of every component of the point, from the point's four lanes
             // (lane q holds components q and q + 4)
             C dn[NT];
@@ -2159,17 +2185,12 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
                 rn[k] = item[k] ? rmul((BT)(zl - zf), wd) : C{0, 0};
                 loc += (double)rn[k].r * rn[k].r + (double)rn[k].i * rn[k].i;
             }
-            const double ws = wave_total(loc), w0 = pass == 0 ? wave_total(rloc) : 0.0;
-            if (lane == 0) red2[wave] = make_double2(ws, w0);
+            const double ws = wave_total(loc);
+            if (lane == 0) red3[wave] = ws;
             __syncthreads();
-            double rnt = 0.0, r0t = 0.0;
+            double rnt = 0.0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const double2 v = red2[w];
-                rnt += v.x;
-                r0t += v.y;
-            }
-            if (pass == 0) r0n = r0t;
+            for (int w = 0; w < NW; ++w) rnt += red3[w];
             // the same in every lane: taken as a scalar, so the branches below are uniform
             const bool solved = __builtin_amdgcn_readfirstlane(rnt <= inner_tol2 * r0n ? 1 : 0) != 0;
             done = solved || __builtin_amdgcn_readfirstlane(rnt > 0.0625 * (pass > 0 ? rprev : r0n) ? 1 : 0) != 0;
