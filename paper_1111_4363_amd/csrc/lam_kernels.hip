@@ -1935,6 +1935,28 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
     int hidx[NH], nrow[6], hmask = 0;
 #pragma unroll
     for (int s = 0; s < NH; ++s) hidx[s] = gj_it;
+    if constexpr (CUBE4) {
+        // whether the block's low / high face across an axis has a halo, and the
+        // offset to it, are the same for the whole block; a point only asks
+        // whether it lies on that face
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int la = comp(lc_it, ax), bax = comp(bc, ax), nba = g.nblk[ax], na = g.n[ax];
+            const int gstr = ax == 0 ? g.n[1] * g.n[2] : (ax == 1 ? g.n[2] : 1);
+            const int lstr = ax == 0 ? 16 : (ax == 1 ? 4 : 1);
+            const bool self_wrap = g.periodic && nba == 1;
+            const bool lo_ok = !self_wrap && (bax > 0 || g.periodic);
+            const bool hi_ok = !self_wrap && (bax < nba - 1 || g.periodic);
+            const int lo_off = bax > 0 ? -gstr : (na - 1) * gstr;
+            const int hi_off = bax < nba - 1 ? gstr : -(na - 1) * gstr;
+            const bool at_lo = la == 0, at_hi = la == 3;
+            const bool halo = (at_lo && lo_ok) || (at_hi && hi_ok);
+            hidx[ax] = gj_it + (halo ? (at_lo ? lo_off : hi_off) : 0);
+            hmask |= (halo ? 1 : 0) << ax;
+            nrow[2 * ax] = !at_lo ? l_it - lstr : (self_wrap ? l_it + 3 * lstr : kMaxB);
+            nrow[2 * ax + 1] = !at_hi ? l_it + lstr : (self_wrap ? l_it - 3 * lstr : kMaxB);
+        }
+    } else
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) {
         const int ax = dir >> 1;
