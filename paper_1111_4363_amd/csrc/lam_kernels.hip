@@ -1259,10 +1259,11 @@ __global__ __launch_bounds__(64) void k_mode_factor(LevelGeom g, TimeOps<NT> to,
 //   3. delta = V (M_r(e_k)^{-1} (V^T r)) per mode k   [K_UU^{-1} r in factored
 //      form]: V^T r, the per-mode solve E3 (I - e diag(lam))^{-1} E1 chained in
 //      the registers of one wave per 16 modes, then V (.) on the matrix cores;
-//   4. (field steps) the new local residual is the frozen field's defect of
-//      delta, point by point; repeat 3 until the block's residual fell by 1e-13
-//      (FP64) / 1e-5 (FP32) or stops improving, at most n_inner times;
-//   5. write c_U += delta_c, lambda_U += delta_lambda.
+//   4. write c_U += delta_c, lambda_U += delta_lambda;
+//   5. (field steps) the new local residual is the frozen field's defect of
+//      delta, point by point; repeat 3 and 4 until the block's residual fell by
+//      the solver's inner tolerance (default 1e-13 in FP64, 1e-2 in FP32) or
+//      stops improving, at most n_inner times.
 // BT is the precision of the factors and of step 3 (double, or float for the
 // mixed path); the state and the residual of step 2 are always FP64.
 // ---------------------------------------------------------------------------
@@ -2058,13 +2059,20 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
     // ---- 2. local residual (FP64) and the reduced right-hand side (see k_sweep) ----
     const double zl = zcoord(g, gi_it);   // the point's coordinate along the field
     double rloc = 0.0;                    // squared local residual of this lane's rows (as stored)
+    // slots of the in-block neighbours' component m_it[0]; with N_t = 8 component
+    // m_it[0] + 4 sits at slot ^ 4 (the row permutation changes the index by an xor)
+    int nbs0[6];
+#pragma unroll
+    for (int dir = 0; dir < 6; ++dir) nbs0[dir] = csx(nrow[dir], m_it[0]);
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
         if (!item[k]) continue;
         const int l = l_it, m = m_it[k];
-        double2 nbs = cs[csx(nrow[0], m)];
+        // m = m_it[0] + 4 k (with N_t <= 4 the second item is idle: its reads stay in row)
+        const int sx = (k == 0 || NT != 8) ? 0 : 4;
+        double2 nbs = cs[nbs0[0] ^ sx];
 #pragma unroll
-        for (int dir = 1; dir < 6; ++dir) nbs = add2(nbs, cs[csx(nrow[dir], m)]);
+        for (int dir = 1; dir < 6; ++dir) nbs = add2(nbs, cs[nbs0[dir] ^ sx]);
         const double2 hc = add2(pre[k], scl2(-g.kin, nbs));
         double2 tq = make_double2(0.0, 0.0);
         double2 wc = make_double2(0.0, 0.0);
