@@ -927,7 +927,7 @@ __global__ __launch_bounds__(64) void k_block_detail(LevelGeom g, const double2*
 // the few tiles whose halo holds it, instead of by every fine point that
 // interpolates from it.
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int D>
 __global__ __launch_bounds__(kThreads) void k_prolong_tile(LevelGeom f, LevelGeom cg, int interp,
                                                            const double2* __restrict__ cc,
                                                            const double2* __restrict__ lc,
@@ -936,7 +936,9 @@ __global__ __launch_bounds__(kThreads) void k_prolong_tile(LevelGeom f, LevelGeo
     constexpr int NQ = NT + 1;
     constexpr int HMAX = 4 * 4 * 10;                 // halo points of a 3D tile
     __shared__ double2 S[HMAX * NQ];
-    const int dim = f.dim;
+    // D > 0: the rank at compile time (tile extents and the index quotients below
+    // become constants); D = 0: the level's rank
+    const int dim = D > 0 ? D : f.dim;
     // coarse tile extents and the tile's first coarse point
     const int ct0 = dim == 1 ? 8 : 2, ct1 = dim == 1 ? 1 : (dim == 2 ? 8 : 2), ct2 = dim == 3 ? 8 : 1;
     const int bid = (int)blockIdx.x;
@@ -2526,8 +2528,13 @@ hipError_t launch_prolong(int nt, const LevelGeom& fine, const LevelGeom& coarse
     const int ct0 = d == 1 ? 8 : 2, ct1 = d == 1 ? 1 : (d == 2 ? 8 : 2), ct2 = d == 3 ? 8 : 1;
     const int t0 = (coarse.n[0] + ct0 - 1) / ct0, t1 = (coarse.n[1] + ct1 - 1) / ct1,
               t2 = (coarse.n[2] + ct2 - 1) / ct2;
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_prolong_tile<NT>, dim3(t0 * t1 * t2), dim3(kThreads), 0, st, fine,
-                                           coarse, interp, cc, lc, cf, lf, t1, t2));
+    if (d == 3) {
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_prolong_tile<NT, 3>), dim3(t0 * t1 * t2), dim3(kThreads), 0, st,
+                                               fine, coarse, interp, cc, lc, cf, lf, t1, t2));
+    } else {
+        LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_prolong_tile<NT, 0>), dim3(t0 * t1 * t2), dim3(kThreads), 0, st,
+                                               fine, coarse, interp, cc, lc, cf, lf, t1, t2));
+    }
     return hipGetLastError();
 }
 
