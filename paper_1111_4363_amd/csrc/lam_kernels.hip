@@ -1903,8 +1903,9 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
         const int bb = b * b;
 #pragma unroll
         for (int r = 0; r < VPT; ++r) {
+            // CUBE4: b = 64, every entry in range (one base address, constant offsets)
             const int t = tid + r * THR;
-            vr[r] = Vg[t < bb ? t : bb - 1];
+            vr[r] = Vg[CUBE4 ? t : (t < bb ? t : bb - 1)];
         }
     }
     BT tr[TPT];
@@ -2040,13 +2041,18 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
         ls[tid] = lp;
         es[tid] = ep;
     }
-    {
+    if constexpr (CUBE4) {
+        // row tid / 64 + 4 r, column tid % 64: one base address, constant offsets
+        BT* vrow = Vs + (tid >> 6) * kLdsPad + (tid & 63);
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) vrow[r * (THR / 64) * kLdsPad] = vr[r];
+    } else {
         const int bb = b * b;
 #pragma unroll
         for (int r = 0; r < VPT; ++r) {
             const int t = tid + r * THR;
             if (t < bb) {
-                const int j = CUBE4 ? t >> 6 : qdiv_small(t, g.rbp), k = t - j * b;
+                const int j = qdiv_small(t, g.rbp), k = t - j * b;
                 Vs[j * kLdsPad + k] = vr[r];
             }
         }
