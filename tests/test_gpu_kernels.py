@@ -30,6 +30,11 @@ RESIDUAL_CASES = [
     dict(shape=(16, 8), n_t=4, block=(4, 4), periodic=True, pulse=PULSE_BOTH),
     dict(shape=(20,), n_t=1, block=(4,), mass=1.7, potential="random"),
     dict(shape=(6, 10), n_t=5, block=(2, 2), field_axis=0, pulse=PULSE_SIN2),
+    # 3D grids whose (y, z) plane tiles by 8 x 8 with an even x extent (the residual
+    # that marches along x): ragged x ranges, periodic, each field axis, odd N_t
+    dict(shape=(6, 8, 16), n_t=8, block=(2, 2, 2), pulse=PULSE_BOTH, field_axis=1),
+    dict(shape=(8, 16, 8), n_t=3, block=(4, 4, 4), periodic=True, pulse=PULSE_FOURIER, field_axis=0),
+    dict(shape=(34, 8, 8), n_t=5, block=(2, 2, 2), pulse=PULSE_SIN2),
 ]
 
 

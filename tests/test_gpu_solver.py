@@ -31,6 +31,8 @@ PULSE_FOURIER = dict(kind="fourier", t_total=0.4, coef=[0.03, -0.02, 0.05])
     dict(shape=(16, 24), n_t=4, block=(4, 4), levels=2, h=0.2, pulse=PULSE_FOURIER),
     dict(shape=(8, 8, 12), n_t=3, block=(2, 2, 2), levels=2, h=0.3, interp="constant"),
     dict(shape=(40,), n_t=5, block=(4,), levels=2, h=0.3, potential="random"),
+    # the residual-restriction that marches along x, periodic, with a field
+    dict(shape=(8, 16, 16), n_t=8, block=(2, 2, 2), levels=2, h=0.3, periodic=True, pulse=PULSE_FOURIER),
 ], ids=lambda c: f"{c['shape']}-L{c['levels']}")
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_vcycle_parity(cfg, adjoint):
