@@ -1810,14 +1810,15 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
 // The FP32 shared-factor colour sweep with two time components per lane: four
 // lanes per point (lane q of a point takes m = q and m = q + 4), so a 64-point
 // block is one wave per SIMD.  The per-point index arithmetic is done once for
-// two components, every wave takes part in the matrix-core steps, and with
-// CUBE4 (up to 128 registers and under 40 KB of LDS) four blocks share a compute
-// unit, otherwise three (the general block geometry takes up to 168).  The
-// arithmetic of each item is that of k_sweep<NT, float, false>.  CUBE4: the
-// level is 3D with 4 x 4 x 4 blocks, known at compile time (the block
-// geometry's divisions become shifts and its tests constants).
-template <int NT, bool CUBE4>
-__global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(SweepArgs a, TimeOps<NT> to) {
+// two components, every wave takes part in the matrix-core steps, and with a
+// block geometry fixed at compile time (up to 128 registers and under 40 KB of
+// LDS) four blocks share a compute unit, otherwise three (the general geometry
+// takes up to 168).  The arithmetic of each item is that of k_sweep<NT, float,
+// false>.  GEO: 3 = a 3D level with 4 x 4 x 4 blocks, 2 = a 2D level with 8 x 8
+// blocks, both known at compile time (the block geometry's divisions become
+// shifts and its tests constants); 0 = the level's block geometry.
+template <int NT, int GEO>
+__global__ __launch_bounds__(kPairThreads, GEO != 0 ? 4 : 3) void k_sweep_pair(SweepArgs a, TimeOps<NT> to) {
     using BT = float;
     using C = cx<BT>;
     // a finished coarsest-level solve: the rest of its launches do nothing
@@ -1861,12 +1862,15 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
         asm volatile("" ::"s"(t));
     }
     const LevelGeom& g = a.g;
-    // the block geometry (compile-time for CUBE4): extents, local coordinates of
-    // block point l, global coordinates, in-block neighbour from its 2-bit code
-    const int gdim = CUBE4 ? 3 : g.dim;
-    auto bdim = [&](int ax) { return CUBE4 ? 4 : g.bdim[ax]; };
+    // the block geometry (compile-time when FIX): rank, extents, local
+    // coordinates of block point l, global coordinates
+    constexpr bool FIX = GEO != 0;
+    constexpr int FE = GEO == 3 ? 4 : 8;   // extent per used axis of a fixed geometry
+    const int gdim = FIX ? GEO : g.dim;
+    auto bdim = [&](int ax) { return FIX ? (ax < GEO ? FE : 1) : g.bdim[ax]; };
     auto local_of = [&](int l) {
-        if constexpr (CUBE4) return I3{l >> 4, (l >> 2) & 3, l & 3};
+        if constexpr (GEO == 3) return I3{l >> 4, (l >> 2) & 3, l & 3};
+        else if constexpr (GEO == 2) return I3{l >> 3, l & 7, 0};
         else return local_coords(g, l);
     };
     auto global_of = [&](const I3& blk3, const I3& lc) {
@@ -1887,7 +1891,7 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
         blk = a.blocks[idx];
         bc = block_coords(g, blk);
     }
-    const int b = CUBE4 ? 64 : g.bpts;
+    const int b = FIX ? 64 : g.bpts;
     const int nd = 2 * gdim;
     const double inner_tol2 = a.inner_tol2;   // inner passes: see k_sweep
     double rprev = 0.0;
@@ -1903,9 +1907,9 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
         const int bb = b * b;
 #pragma unroll
         for (int r = 0; r < VPT; ++r) {
-            // CUBE4: b = 64, every entry in range (one base address, constant offsets)
+            // FIX: b = 64, every entry in range (one base address, constant offsets)
             const int t = tid + r * THR;
-            vr[r] = Vg[CUBE4 ? t : (t < bb ? t : bb - 1)];
+            vr[r] = Vg[FIX ? t : (t < bb ? t : bb - 1)];
         }
     }
     BT tr[TPT];
@@ -1933,32 +1937,34 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
     const int gj_it = point_index(g, gi_it);
     // neighbours: nrow[dir] is the in-block neighbour's row in LDS (the zero row
     // kMaxB when there is none); the halo comes from HBM, one load per direction,
-    // or with CUBE4 one per axis (a point of a 4-wide block lies on at most one of
-    // the block's two faces across an axis)
-    constexpr int NH = CUBE4 ? 3 : 6;
+    // or with FIX one per axis (a point of a 4- or 8-wide block lies on at most one
+    // of the block's two faces across an axis)
+    constexpr int NH = FIX ? GEO : 6;
     int hidx[NH], nrow[6], hmask = 0;
 #pragma unroll
     for (int s = 0; s < NH; ++s) hidx[s] = gj_it;
-    if constexpr (CUBE4) {
+    if constexpr (FIX) {
         // whether the block's low / high face across an axis has a halo, and the
         // offset to it, are the same for the whole block; a point only asks
         // whether it lies on that face
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
+        for (int dir = 2 * GEO; dir < 6; ++dir) nrow[dir] = kMaxB;
+#pragma unroll
+        for (int ax = 0; ax < GEO; ++ax) {
             const int la = comp(lc_it, ax), bax = comp(bc, ax), nba = g.nblk[ax], na = g.n[ax];
             const int gstr = ax == 0 ? g.n[1] * g.n[2] : (ax == 1 ? g.n[2] : 1);
-            const int lstr = ax == 0 ? 16 : (ax == 1 ? 4 : 1);
+            const int lstr = GEO == 3 ? (ax == 0 ? 16 : (ax == 1 ? 4 : 1)) : (ax == 0 ? 8 : 1);
             const bool self_wrap = g.periodic && nba == 1;
             const bool lo_ok = !self_wrap && (bax > 0 || g.periodic);
             const bool hi_ok = !self_wrap && (bax < nba - 1 || g.periodic);
             const int lo_off = bax > 0 ? -gstr : (na - 1) * gstr;
             const int hi_off = bax < nba - 1 ? gstr : -(na - 1) * gstr;
-            const bool at_lo = la == 0, at_hi = la == 3;
+            const bool at_lo = la == 0, at_hi = la == FE - 1;
             const bool halo = (at_lo && lo_ok) || (at_hi && hi_ok);
             hidx[ax] = gj_it + (halo ? (at_lo ? lo_off : hi_off) : 0);
             hmask |= (halo ? 1 : 0) << ax;
-            nrow[2 * ax] = !at_lo ? l_it - lstr : (self_wrap ? l_it + 3 * lstr : kMaxB);
-            nrow[2 * ax + 1] = !at_hi ? l_it + lstr : (self_wrap ? l_it - 3 * lstr : kMaxB);
+            nrow[2 * ax] = !at_lo ? l_it - lstr : (self_wrap ? l_it + (FE - 1) * lstr : kMaxB);
+            nrow[2 * ax + 1] = !at_hi ? l_it + lstr : (self_wrap ? l_it - (FE - 1) * lstr : kMaxB);
         }
     } else
 #pragma unroll
@@ -1978,7 +1984,7 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
         nrow[dir] = used && (inside || self_wrap) ? l_it + lstep : kMaxB;
         const bool halo = used && !inside && !self_wrap && (!edge || g.periodic);
         const int hw = edge ? gj_it - (up ? 1 : -1) * (na - 1) * gstr : gj_it + gstep;
-        const int s = CUBE4 ? ax : dir;
+        const int s = FIX ? ax : dir;
         hidx[s] = halo ? hw : hidx[s];
         hmask |= (halo ? 1 : 0) << s;
     }
@@ -2041,7 +2047,7 @@ __global__ __launch_bounds__(kPairThreads, CUBE4 ? 4 : 3) void k_sweep_pair(Swee
         ls[tid] = lp;
         es[tid] = ep;
     }
-    if constexpr (CUBE4) {
+    if constexpr (FIX) {
         // row tid / 64 + 4 r, column tid % 64: one base address, constant offsets
         BT* vrow = Vs + (tid >> 6) * kLdsPad + (tid & 63);
 #pragma unroll
@@ -2575,10 +2581,13 @@ hipError_t launch_sweep(int nt, int mixed, const SweepArgs& a, const double* U, 
         // two components per lane (for N_t = 5..7 its registers would spill)
         const LevelGeom& g = a.g;
         if (g.dim == 3 && g.bdim[0] == 4 && g.bdim[1] == 4 && g.bdim[2] == 4) {
-            LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep_pair<NT, true>), grid, dim3(kPairThreads), 0, st, a,
+            LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep_pair<NT, 3>), grid, dim3(kPairThreads), 0, st, a,
+                                                   make_ops<NT>(U, W)));
+        } else if (g.dim == 2 && g.bdim[0] == 8 && g.bdim[1] == 8) {
+            LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep_pair<NT, 2>), grid, dim3(kPairThreads), 0, st, a,
                                                    make_ops<NT>(U, W)));
         } else {
-            LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep_pair<NT, false>), grid, dim3(kPairThreads), 0, st, a,
+            LAM_DISPATCH_NT(nt, hipLaunchKernelGGL((k_sweep_pair<NT, 0>), grid, dim3(kPairThreads), 0, st, a,
                                                    make_ops<NT>(U, W)));
         }
     } else if (mixed) {

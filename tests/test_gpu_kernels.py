@@ -136,6 +136,9 @@ SWEEP_CASES = [
     # geometry), with a field, and periodic with one block spanning an axis
     dict(shape=(8, 12, 8), n_t=8, block=(4, 4, 4), h=0.3, pulse=PULSE_BOTH),
     dict(shape=(4, 8, 8), n_t=4, block=(4, 4, 4), h=0.3, periodic=True),
+    # 2D 8 x 8 blocks (the other compile-time geometry), with a field, and periodic
+    dict(shape=(32, 16), n_t=8, block=(8, 8), h=0.2, pulse=PULSE_SIN2, field_axis=0),
+    dict(shape=(16, 32), n_t=4, block=(8, 8), h=0.25, periodic=True, pulse=PULSE_BOTH),
 ]
 
 
