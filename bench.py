@@ -476,11 +476,12 @@ def workload_string(cfg, tol):
 def sweep_kernel_name(cfg, prec):
     """The finest-level colour sweep kernel the library launches for this workload
     (the FP32 shared-factor sweep takes two time components per lane for N_t = 8 and
-    N_t <= 4, with its block geometry fixed at compile time for 4 x 4 x 4 blocks)."""
+    N_t <= 4, with its block geometry fixed at compile time for 4 x 4 x 4 blocks in
+    3D (3) and 8 x 8 blocks in 2D (2), else 0)."""
     nt = cfg["n_t"]
     if prec == "mixed" and (nt == 8 or nt <= 4):
-        cube = cfg["dim"] == 3 and cfg["block"] == 4
-        return f"k_sweep_pair<{nt}, {'true' if cube else 'false'}>"
+        geo = 3 if (cfg["dim"] == 3 and cfg["block"] == 4) else (2 if (cfg["dim"] == 2 and cfg["block"] == 8) else 0)
+        return f"k_sweep_pair<{nt}, {geo}>"
     return f"k_sweep<{nt}, {'double' if prec == 'fp64' else 'float'}, false>"
 
 
