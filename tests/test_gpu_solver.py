@@ -165,6 +165,41 @@ def test_solve_step_parity(cfg, precision):
     prop.close()
 
 
+@pytest.mark.parametrize("cfg", [SOLVE_CASES[3], SOLVE_CASES[4]], ids=lambda c: f"{c['shape']}-L{c['levels']}")
+def test_fp32_defect_tolerance_leaves_the_step_unchanged(cfg):
+    """The mixed path's FP32 subvolume solves with the default field-defect
+    tolerance (1e-2) and with exact FP32 solves (inner_tol = 1e-5): the same
+    V-cycle count, both within 1e-8 of the oracle's direct step, and the exact
+    setting does take correction passes in a V-cycle's sweeps (so the two runs
+    differ inside)."""
+    cfg = dict(cfg)
+    nu_coarse = cfg.pop("nu_coarse")
+    case = Case(**cfg)
+    note(f"defect tolerance {case}")
+    t0 = 0.15
+    sysm = kkt.StepSystem(case.grid, case.v0, case.n_t, case.dt, t0, case.field)
+    x_ref = kkt.solve_direct(sysm.K, kkt.rhs(sysm, case.psi0))
+    c_ref, _ = kkt.split(x_ref, case.npts, case.n_t)
+    runs = []
+    for tol in (0.0, 1e-5):
+        prop = case.prop(precision="mixed", tol=1e-10, max_cycles=40, nu_coarse=nu_coarse, inner_tol=tol)
+        passes = []
+        c0 = np.concatenate([case.psi0[:, None], np.zeros((case.npts, case.n_t - 1), complex)], 1)
+        prop.set_state(t0, t_c(case.psi0), t_c(c0.ravel()), t_c(np.zeros(case.npts, complex)))
+        prop.vcycle()
+        hist, _ = prop.pass_stats(0)
+        passes.append(sum(k * c for k, c in enumerate(hist)))
+        _, st = prop.solve_step(t0, t_c(case.psi0))
+        cg, _ = prop.get_state()
+        runs.append((st["cycles"], n(cg).reshape(-1, case.n_t), passes[0]))
+        prop.close()
+    note(f"cycles {runs[0][0]} / {runs[1][0]}, passes in a V-cycle's last sweep {runs[0][2]} / {runs[1][2]}")
+    assert runs[0][0] == runs[1][0]
+    for cycles, cg, _ in runs:
+        assert np.abs(cg - c_ref).max() <= 1e-8 * np.abs(c_ref).max()
+    assert runs[1][2] > 0
+
+
 def test_multi_step_propagation_matches_direct_steps():
     case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=PULSE_FOURIER)
     note(f"propagate 8 steps {case}")
