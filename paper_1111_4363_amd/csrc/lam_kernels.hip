@@ -1471,10 +1471,16 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
     {
         const BT* Vg = static_cast<const BT*>(a.V) + (size_t)blk * b * b;
         const int bb = b * b;
+        if (b == kMaxB) {
+            // full blocks: every entry in range (one base address, constant offsets)
 #pragma unroll
-        for (int r = 0; r < VPT; ++r) {
-            const int t = tid + r * kSweepThreads;
-            vr[r] = Vg[t < bb ? t : bb - 1];
+            for (int r = 0; r < VPT; ++r) vr[r] = Vg[tid + r * kSweepThreads];
+        } else {
+#pragma unroll
+            for (int r = 0; r < VPT; ++r) {
+                const int t = tid + r * kSweepThreads;
+                vr[r] = Vg[t < bb ? t : bb - 1];
+            }
         }
     }
     BT tr[TPT];
@@ -1558,7 +1564,12 @@ __global__ __launch_bounds__(kSweepThreads, (sweep_waves_per_simd<BT, STORED>())
         zs[tid] = zcoord(g, gip);
         es[tid] = ep;
     }
-    {
+    if (b == kMaxB) {
+        // row tid / 64 + 8 r, column tid % 64
+        BT* vrow = Vs + (tid >> 6) * kLdsPad + (tid & 63);
+#pragma unroll
+        for (int r = 0; r < VPT; ++r) vrow[r * (kSweepThreads / 64) * kLdsPad] = vr[r];
+    } else {
         const int bb = b * b;
 #pragma unroll
         for (int r = 0; r < VPT; ++r) {
