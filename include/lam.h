@@ -200,7 +200,8 @@ typedef struct {
 int lam_create(const lam_grid* grid, const lam_time* time, const lam_ham* ham,
                const lam_solver* solver, void* hip_stream, lam_ctx** out);
 
-/* Release every device buffer of the context.  Accepts NULL. */
+/* Release every device buffer of the context.  Accepts NULL.  Resource
+ * management only: no passage of the paper. */
 int lam_destroy(lam_ctx* ctx);
 
 /* Replace the Fourier pulse amplitudes (host array of n_coef values, n_coef
@@ -211,7 +212,11 @@ int lam_destroy(lam_ctx* ctx);
  * a loaded state keeps its step. */
 int lam_set_pulse(lam_ctx* ctx, int n_coef, const double* coef);
 
-/* Replace V0 (device, one FP64 per finest point) and refactor every level. */
+/* Replace V0 (device, one FP64 per finest point) and refactor every level:
+ * the static part of the local potential of the Hamiltonian (Sec. "Review of
+ * the Least Action Principle"), averaged over children on coarser levels
+ * (Sec. "Multigrid Relaxation"); every subvolume factor of Sec. "Iterative
+ * relaxation to the least action solution" depends on it. */
 int lam_set_potential(lam_ctx* ctx, const double* v0);
 
 /* Action residual of a forward step at time t0, Eq. (actionresidual) extended
@@ -224,22 +229,29 @@ int lam_residual_action(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_
                         const lam_c64* lam, lam_c64* rho, lam_c64* sigma, double* norm);
 
 /* Same for the adjoint system K^H mu = E^H g of a step at t0 (E: end-of-step
- * evaluation psi_j = sum_n c_jn, so E^H g puts g_j on every row (j, n)).
+ * evaluation psi_j = sum_n c_jn, so E^H g puts g_j on every row (j, n)): the
+ * conjugate transpose of the step system of Eq. (stationaryphase) and its
+ * initial-condition rows (Sec. "Review of the Least Action Principle").
  * g: device (P); mu_c (P*n_t), mu_lam (P): device inputs. */
 int lam_residual_adjoint(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c,
                          const lam_c64* mu_lam, lam_c64* rho, lam_c64* sigma, double* norm);
 
 /* Load a forward state into the context: step time t0, initial wavefunction
  * psi0 (P), coefficients c (P*n_t) and multipliers lam (P), all device.
- * Subsequent lam_relax_sweep / lam_vcycle act on the system K x = (0, psi0). */
+ * Subsequent lam_relax_sweep / lam_vcycle act on the system K x = (0, psi0):
+ * the stationarity rows of Eq. (stationaryphase) and the initial-condition
+ * rows of one step (Sec. "Review of the Least Action Principle"). */
 int lam_set_state(lam_ctx* ctx, double t0, const lam_c64* psi0, const lam_c64* c,
                   const lam_c64* lam);
 
-/* Load an adjoint state: subsequent sweeps / V-cycles act on K^H mu = E^H g. */
+/* Load an adjoint state: subsequent sweeps / V-cycles act on K^H mu = E^H g,
+ * the conjugate-transposed step system (as for lam_residual_adjoint). */
 int lam_set_adjoint_state(lam_ctx* ctx, double t0, const lam_c64* g, const lam_c64* mu_c,
                           const lam_c64* mu_lam);
 
-/* Copy the finest-level state (c: P*n_t, lam: P; device) out of the context. */
+/* Copy the finest-level state (c: P*n_t, lam: P; device) out of the context:
+ * the time-expansion coefficients c_jn and multipliers of the step system
+ * (Sec. "Review of the Least Action Principle"). */
 int lam_get_state(lam_ctx* ctx, lam_c64* c, lam_c64* lam);
 
 /* One colour of subvolume relaxation of the context state on the finest
@@ -319,12 +331,15 @@ int lam_restrict(lam_ctx* ctx, int level, const lam_c64* rho_f, const lam_c64* s
 int lam_prolong_add(lam_ctx* ctx, int level, const lam_c64* c_c, const lam_c64* lam_c,
                     lam_c64* c_f, lam_c64* lam_f);
 
-/* Points per axis of a level (n[3], host). */
+/* Points per axis of a level (n[3], host): each coarser level doubles the
+ * spacing (Sec. "Multigrid Relaxation"). */
 int lam_level_shape(const lam_ctx* ctx, int level, int* n);
 
 /* Subvolume factor of block `block` on `level`: eigenvectors (host, bpts*bpts,
  * row-major [point][mode]) and eigenvalues (host, bpts) of the real symmetric
- * spatial block operator T_U + diag(V0_U).  For tests of the block factor. */
+ * spatial block operator T_U + diag(V0_U), the factor that turns each
+ * subvolume solve of Sec. "Iterative relaxation to the least action solution"
+ * into independent time systems.  For tests of the block factor. */
 int lam_block_factor(const lam_ctx* ctx, int level, int block, double* vecs, double* vals);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -347,20 +362,6 @@ int lam_residual_action_noalloc(const lam_grid* grid, const lam_time* time, cons
                                 const lam_c64* psi0, const lam_c64* c, const lam_c64* lam, lam_c64* rho,
                                 lam_c64* sigma, double* norm, void* hip_stream);
 
-/* ---- The plane-wave relaxation experiment in the Legendre element basis ----
- * Sec. "Implementation with Legendre Polynomials" (element matrices O, U, Q, T,
- * transfers, continuity) and Sec. "Convergence" (the experiment).  A regime is
- * the dimensionless element operator of Eq. (leastaction_dimensionless),
- *   i O_ij Q_nm - 2 kappa T_ij U_nm - nu O_ij U_nm,
- * on n_x x n_t Legendre functions per element (1..8 each), and a relaxation mode:
- *   LAM_PW_ONE           one element [-1, 1];
- *   LAM_PW_SIMULTANEOUS  two elements [-1, 0], [0, 1] relaxed at once;
- *   LAM_PW_INTERGRID     two elements: the parent element's correction (Galerkin
- *                        problem of Eq. (residual_rough), Eq. (correction_fine)),
- *                        then each element with its interface held fixed.
- * (elements x n_x x n_t <= LAM_PW_MAX_UNKNOWNS).  T_ij is the closed form the
- * paper prints, (j(j+1) - i(i+1))/2 for i > j, i - j even, read as the entry of
- * trial i in test row j. */
 /* The adaptive tree (Sec. "Multigrid Relaxation": the tree of elements need
  * not subdivide every volume equally; where the function has little detail a
  * coarse element stands for its children).  The finest level is refined only
@@ -389,6 +390,20 @@ int lam_set_refinement(lam_ctx* ctx, const unsigned char* active);
  *   finest subvolume (C order of subvolume coordinates).  Synchronises. */
 int lam_block_detail(lam_ctx* ctx, const lam_c64* psi, double* detail);
 
+/* ---- The plane-wave relaxation experiment in the Legendre element basis ----
+ * Sec. "Implementation with Legendre Polynomials" (element matrices O, U, Q, T,
+ * transfers, continuity) and Sec. "Convergence" (the experiment).  A regime is
+ * the dimensionless element operator of Eq. (leastaction_dimensionless),
+ *   i O_ij Q_nm - 2 kappa T_ij U_nm - nu O_ij U_nm,
+ * on n_x x n_t Legendre functions per element (1..8 each), and a relaxation mode:
+ *   LAM_PW_ONE           one element [-1, 1];
+ *   LAM_PW_SIMULTANEOUS  two elements [-1, 0], [0, 1] relaxed at once;
+ *   LAM_PW_INTERGRID     two elements: the parent element's correction (Galerkin
+ *                        problem of Eq. (residual_rough), Eq. (correction_fine)),
+ *                        then each element with its interface held fixed.
+ * (elements x n_x x n_t <= LAM_PW_MAX_UNKNOWNS).  T_ij is the closed form the
+ * paper prints, (j(j+1) - i(i+1))/2 for i > j, i - j even, read as the entry of
+ * trial i in test row j. */
 #define LAM_PW_ONE           0
 #define LAM_PW_SIMULTANEOUS  1
 #define LAM_PW_INTERGRID     2
@@ -420,11 +435,14 @@ int lam_plane_wave_map(const lam_pw_regime* regime, int nk, const double* k, int
  * took p inner corrections (0 without field) and in hist[LAM_MAX_INNER + 1]
  * the number whose last solve stopped with its local residual above the
  * tolerance (pass limit reached, or corrections that stopped improving).
+ * The inner corrections take the time-dependent field term of the block
+ * system (the V_ijnm term of Eq. (stationaryphase)) into account by repeated
+ * solves with the field-free factor.
  * Synchronises the stream.  For measurements and tests. */
 int lam_pass_stats(lam_ctx* ctx, int level, long long* hist);
 
 /* Timing of finest-level sweep launches with HIP events on the context
- * stream.  enable = k > 0 starts recording (clearing previous records) the
+ * stream (measurement only: no passage of the paper).  enable = k > 0 starts recording (clearing previous records) the
  * 1st, (k+1)-th, (2k+1)-th ... finest-level sweep launch: a sample, since each
  * event record costs a few microseconds of stream time; 0 stops; negative is
  * LAM_EINVAL.  lam_profile_read returns the number of recorded launches and
@@ -433,6 +451,8 @@ int lam_pass_stats(lam_ctx* ctx, int level, long long* hist);
 int lam_profile(lam_ctx* ctx, int enable);
 int lam_profile_read(lam_ctx* ctx, int* launches, double* total_ms);
 
+/* Text of a LAM_* return code (static storage; unknown codes give a generic
+ * text).  No passage of the paper. */
 const char* lam_strerror(int code);
 
 #ifdef __cplusplus
