@@ -166,11 +166,15 @@ typedef struct {
                          lam_propagate) and adjoint steps (lam_adjoint_step, which splits
                          the same way its forward recomputation does) */
     double inner_tol; /* the inner corrections of a subvolume stop once its own residual
-                         norm fell by this factor; 0 = the precision's default: 1e-13 in
-                         FP64 (an exact subvolume solve), 1e-2 in FP32 (the field defect
-                         left below 1% of the local residual does not change the V-cycle
-                         rate, and each further correction costs a whole block solve;
-                         1e-5 makes the FP32 solve exact to its precision).  0 <= inner_tol < 1 */
+                         norm fell by this factor; 0 = the default, 1e-2 in both precisions:
+                         the V-cycles converge to the same step solution whatever the
+                         tolerance (the relaxation is their smoother, the FP64 residual
+                         decides when to stop), a field defect left below 1% of the local
+                         residual does not change their rate, and each further correction
+                         costs a whole block solve.  Exact subvolume solves, the
+                         relaxation as the paper defines it (Sec. "Iterative relaxation to
+                         the least action solution"): 1e-13 in FP64, 1e-5 in FP32 (exact to
+                         its precision).  0 <= inner_tol < 1 */
 } lam_solver;
 
 typedef struct {

@@ -731,7 +731,7 @@ int sweep(lam_ctx* c, int l, int colour, const int* skip = nullptr) {
     a.adjoint = c->adjoint;
     a.n_inner = c->n_inner;
     {
-        const double tol = c->solver.inner_tol > 0.0 ? c->solver.inner_tol : (L.fp32 ? 1e-2 : 1e-13);
+        const double tol = c->solver.inner_tol > 0.0 ? c->solver.inner_tol : 1e-2;
         a.inner_tol2 = tol * tol;
         // ||W||_2 <= max_m sum_n |W_mn| for the symmetric field matrix
         double wb = 0.0;

@@ -1264,7 +1264,7 @@ __global__ __launch_bounds__(64) void k_mode_factor(LevelGeom g, TimeOps<NT> to,
 //   4. write c_U += delta_c, lambda_U += delta_lambda;
 //   5. (field steps) the new local residual is the frozen field's defect of
 //      delta, point by point; repeat 3 and 4 until the block's residual fell by
-//      the solver's inner tolerance (default 1e-13 in FP64, 1e-2 in FP32) or
+//      the solver's inner tolerance (default 1e-2; 1e-13 for an exact solve) or
 //      stops improving, at most n_inner times.
 // BT is the precision of the factors and of step 3 (double, or float for the
 // mixed path); the state and the residual of step 2 are always FP64.

@@ -11,7 +11,7 @@ Transfers: averages and interpolation weights are exact binary fractions, so
 import numpy as np
 import pytest
 
-from gpu_util import Case, EPS, field_fn, n, note, rounding_bound, t_c
+from gpu_util import Case, EPS, EXACT_INNER_TOL, field_fn, n, note, rounding_bound, t_c
 from oracle import adjoint as A
 from oracle import grid as G
 from oracle import kkt, relax
@@ -168,7 +168,7 @@ def test_sweep_parity(cfg, adjoint, precision, time_factor):
     x = kkt.join(c, lam)
     # exact subvolume solves: FP32 corrections of the field defect to 1e-5
     prop = case.prop(precision=precision, n_inner=(6 if case.field is not None else -1), time_factor=time_factor,
-                     inner_tol=(1e-5 if precision == "mixed" else 0.0))
+                     inner_tol=EXACT_INNER_TOL[precision])
     if adjoint:
         prop.set_adjoint_state(t0, t_c(case.psi0), t_c(c), t_c(lam))
     else:

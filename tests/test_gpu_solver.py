@@ -11,7 +11,7 @@ direct K^H solve.
 import numpy as np
 import pytest
 
-from gpu_util import Case, n, note, t_c, t_r
+from gpu_util import EXACT_INNER_TOL, Case, n, note, t_c, t_r
 from oracle import adjoint as A
 from oracle import kkt, relax
 
@@ -166,37 +166,38 @@ def test_solve_step_parity(cfg, precision):
 
 
 @pytest.mark.parametrize("cfg", [SOLVE_CASES[3], SOLVE_CASES[4]], ids=lambda c: f"{c['shape']}-L{c['levels']}")
-def test_fp32_defect_tolerance_leaves_the_step_unchanged(cfg):
-    """The mixed path's FP32 subvolume solves with the default field-defect
-    tolerance (1e-2) and with exact FP32 solves (inner_tol = 1e-5): the same
-    V-cycle count, both within 1e-8 of the oracle's direct step, and the exact
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_defect_tolerance_leaves_the_step_unchanged(cfg, precision):
+    """Subvolume solves with the default field-defect tolerance (1e-2) and exact
+    ones (inner_tol 1e-13 in FP64, 1e-5 in FP32): the same V-cycle count, both
+    within the precision's bound of the oracle's direct step, and the exact
     setting does take correction passes in a V-cycle's sweeps (so the two runs
     differ inside)."""
     cfg = dict(cfg)
     nu_coarse = cfg.pop("nu_coarse")
     case = Case(**cfg)
-    note(f"defect tolerance {case}")
+    note(f"defect tolerance {precision} {case}")
     t0 = 0.15
     sysm = kkt.StepSystem(case.grid, case.v0, case.n_t, case.dt, t0, case.field)
     x_ref = kkt.solve_direct(sysm.K, kkt.rhs(sysm, case.psi0))
     c_ref, _ = kkt.split(x_ref, case.npts, case.n_t)
     runs = []
-    for tol in (0.0, 1e-5):
-        prop = case.prop(precision="mixed", tol=1e-10, max_cycles=40, nu_coarse=nu_coarse, inner_tol=tol)
-        passes = []
+    for tol in (0.0, EXACT_INNER_TOL[precision]):
+        prop = case.prop(precision=precision, tol=1e-10, max_cycles=40, nu_coarse=nu_coarse, inner_tol=tol)
         c0 = np.concatenate([case.psi0[:, None], np.zeros((case.npts, case.n_t - 1), complex)], 1)
         prop.set_state(t0, t_c(case.psi0), t_c(c0.ravel()), t_c(np.zeros(case.npts, complex)))
         prop.vcycle()
         hist, _ = prop.pass_stats(0)
-        passes.append(sum(k * c for k, c in enumerate(hist)))
+        passes = sum(k * c for k, c in enumerate(hist))
         _, st = prop.solve_step(t0, t_c(case.psi0))
         cg, _ = prop.get_state()
-        runs.append((st["cycles"], n(cg).reshape(-1, case.n_t), passes[0]))
+        runs.append((st["cycles"], n(cg).reshape(-1, case.n_t), passes))
         prop.close()
     note(f"cycles {runs[0][0]} / {runs[1][0]}, passes in a V-cycle's last sweep {runs[0][2]} / {runs[1][2]}")
     assert runs[0][0] == runs[1][0]
+    target = 1e-10 if precision == "fp64" else 1e-8
     for cycles, cg, _ in runs:
-        assert np.abs(cg - c_ref).max() <= 1e-8 * np.abs(c_ref).max()
+        assert np.abs(cg - c_ref).max() <= target * np.abs(c_ref).max()
     assert runs[1][2] > 0
 
 
