@@ -2276,18 +2276,23 @@ __global__ __launch_bounds__(kPairThreads, GEO != 0 ? 4 : 3) void k_sweep_pair(S
 // ---------------------------------------------------------------------------
 // K11: step I/O and the adjoint right-hand side.
 // ---------------------------------------------------------------------------
+// Initial guess c_j0 = psi_j (s_0 = T_0(t0) = 1), c_jn = 0 (n >= 1),
+// lambda = 0: one thread per (point, component), so the stores of c are
+// coalesced.
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_init_forward(int P, const double2* __restrict__ psi,
                                                            double2* __restrict__ c, double2* __restrict__ lam,
                                                            double2* __restrict__ bs) {
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    if (j >= P) return;
+    const size_t k = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= (size_t)P * NT) return;
+    const size_t j = k / NT;
+    const int m = (int)(k - j * NT);
     const double2 p = psi[j];
-    c[(size_t)j * NT] = p;  // s_0 = T_0(t0) = 1
-#pragma unroll
-    for (int n = 1; n < NT; ++n) c[(size_t)j * NT + n] = make_double2(0.0, 0.0);
-    lam[j] = make_double2(0.0, 0.0);
-    bs[j] = p;
+    c[k] = m == 0 ? p : make_double2(0.0, 0.0);
+    if (m == 0) {
+        lam[j] = make_double2(0.0, 0.0);
+        bs[j] = p;
+    }
 }
 
 // Zero state (the adjoint solve starts from mu = 0).
@@ -2312,74 +2317,76 @@ __global__ __launch_bounds__(kThreads) void k_end_eval(int P, const double2* __r
     psi[j] = acc;
 }
 
-// End of one step and start of the next in one pass, with the norm N0 of the
-// next step's initial state: psi = x(t0 + dt) as in k_end_eval, the next
-// initial state from it as in k_init_forward, written to a second set of
-// buffers (c is left as it is), and per-workgroup partials of N0.  For that
-// state the constraint residual vanishes exactly (c_j0 = psi_j) and the time
-// couplings see zero coefficients, so row (j, m) holds U_0 (H psi)_j for m = 0
-// plus z_j W_m0 psi_j (the next step's field; zero without one).
-// H psi = sum_n H c_n by linearity, so one thread per (point, component)
-// applies the stencil to its component (coalesced, as in k_residual) and the
-// workgroup sums over the components in LDS.
+// End of one step and start of the next: psi = x(t0 + dt) as in k_end_eval
+// (the components summed in the same order), and the next initial state from
+// it as in k_init_forward, written to a second set of buffers (c is left as it
+// is).  One thread per (point, component), so every load and store is
+// coalesced; the components of a point meet in LDS.
 template <int NT>
-__global__ __launch_bounds__(kThreads) void k_advance(LevelGeom g, TimeOps<NT> to, int field_on,
-                                                      const double2* __restrict__ c,
-                                                      const double* __restrict__ v0, double2* __restrict__ psi,
-                                                      double2* __restrict__ cn, double2* __restrict__ lamn,
-                                                      double2* __restrict__ bsn, double* __restrict__ partial) {
+__global__ __launch_bounds__(kThreads) void k_advance(int P, const double2* __restrict__ c,
+                                                      double2* __restrict__ psi, double2* __restrict__ cn,
+                                                      double2* __restrict__ lamn, double2* __restrict__ bsn) {
     constexpr int PW = kThreads / NT;  // points per workgroup
     __shared__ double2 cs[PW * NT];
-    __shared__ double2 hs[PW * NT];
-    __shared__ double red[kThreads / 64];
     const int t = threadIdx.x;
     const int lp = t / NT, m = t - lp * NT;
-    const size_t jw = (size_t)blockIdx.x * PW + lp;
-    const bool act = lp < PW && jw < (size_t)g.P;
-    const int j = act ? (int)jw : 0;
-    const I3 i = point_coords(g, j);
-    const double2 own = c[(size_t)j * NT + m];
-    int nbq[6];
-    nbq[0] = neighbour_of<0, -1>(g, i, j);
-    nbq[1] = neighbour_of<0, 1>(g, i, j);
-    nbq[2] = g.dim > 1 ? neighbour_of<1, -1>(g, i, j) : -1;
-    nbq[3] = g.dim > 1 ? neighbour_of<1, 1>(g, i, j) : -1;
-    nbq[4] = g.dim > 2 ? neighbour_of<2, -1>(g, i, j) : -1;
-    nbq[5] = g.dim > 2 ? neighbour_of<2, 1>(g, i, j) : -1;
-    double2 nbv[6];
-#pragma unroll
-    for (int dir = 0; dir < 6; ++dir) nbv[dir] = c[(size_t)(nbq[dir] >= 0 ? nbq[dir] : j) * NT + m];
-    const double vj = v0[j];
-    double2 lap = scl2(-2.0 * g.dim, own);
-#pragma unroll
-    for (int dir = 0; dir < 6; ++dir) lap = add2(lap, scl2(nbq[dir] >= 0 ? 1.0 : 0.0, nbv[dir]));
-    const double2 hc = add2(scl2(-g.kin, lap), scl2(vj, own));
-    if (lp < PW) {
-        cs[t] = own;
-        hs[t] = hc;
-    }
+    const size_t j = (size_t)blockIdx.x * PW + lp;
+    const bool act = lp < PW && j < (size_t)P;
+    if (act) cs[t] = c[j * NT + m];
     __syncthreads();
-    double acc = 0.0;
-    if (act) {
-        // psi in the order of k_end_eval
-        double2 ps = make_double2(0.0, 0.0), hp = make_double2(0.0, 0.0);
+    if (!act) return;
+    double2 ps = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            ps = add2(ps, cs[lp * NT + n]);
-            hp = add2(hp, hs[lp * NT + n]);
+    for (int n = 0; n < NT; ++n) ps = add2(ps, cs[lp * NT + n]);
+    cn[j * NT + m] = m == 0 ? ps : make_double2(0.0, 0.0);
+    if (m == 0) {
+        psi[j] = ps;
+        lamn[j] = make_double2(0.0, 0.0);
+        bsn[j] = ps;
+    }
+}
+
+// Per-workgroup partials of the norm N0 of the initial state k_advance
+// writes (c_j0 = psi_j, the other components and lambda zero).  Its
+// constraint rows vanish exactly and the time couplings see zero
+// coefficients, so row (j, m) holds U_0 (H psi)_j for m = 0 plus
+// z_j W_m0 psi_j (the next step's field; zero without one), and
+// N0 = sum_jm U_m |row_jm|^2.  One thread per point.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void k_initial_norm(LevelGeom g, TimeOps<NT> to, int field_on,
+                                                           const double2* __restrict__ psi,
+                                                           const double* __restrict__ v0,
+                                                           double* __restrict__ partial) {
+    __shared__ double red[kThreads / 64];
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    double acc = 0.0;
+    if (j < g.P) {
+        const I3 i = point_coords(g, j);
+        int nbq[6];
+        nbq[0] = neighbour_of<0, -1>(g, i, j);
+        nbq[1] = neighbour_of<0, 1>(g, i, j);
+        nbq[2] = g.dim > 1 ? neighbour_of<1, -1>(g, i, j) : -1;
+        nbq[3] = g.dim > 1 ? neighbour_of<1, 1>(g, i, j) : -1;
+        nbq[4] = g.dim > 2 ? neighbour_of<2, -1>(g, i, j) : -1;
+        nbq[5] = g.dim > 2 ? neighbour_of<2, 1>(g, i, j) : -1;
+        const double2 own = psi[j];
+        double2 nbv[6];
+#pragma unroll
+        for (int dir = 0; dir < 6; ++dir) nbv[dir] = psi[nbq[dir] >= 0 ? nbq[dir] : j];
+        double2 lap = scl2(-2.0 * g.dim, own);
+#pragma unroll
+        for (int dir = 0; dir < 6; ++dir) lap = add2(lap, scl2(nbq[dir] >= 0 ? 1.0 : 0.0, nbv[dir]));
+        const double2 hp = add2(scl2(-g.kin, lap), scl2(v0[j], own));
+        const double zj = field_on ? zcoord(g, i) : 0.0;
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+            double2 r = scl2(zj * to.W[m * NT], own);
+            if (m == 0) r = add2(scl2(to.U[0], hp), r);
+            acc += to.U[m] * (r.x * r.x + r.y * r.y);
         }
-        cn[(size_t)j * NT + m] = m == 0 ? ps : make_double2(0.0, 0.0);
-        double2 r = scl2(field_on ? zcoord(g, i) * to.W[m * NT] : 0.0, ps);
-        if (m == 0) {
-            psi[j] = ps;
-            lamn[j] = make_double2(0.0, 0.0);
-            bsn[j] = ps;
-            r = add2(scl2(to.U[0], hp), r);
-        }
-        acc = to.U[m] * (r.x * r.x + r.y * r.y);
     }
     const double tot = block_sum(acc, red);
-    if (t == 0) partial[blockIdx.x] = tot;
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(kThreads) void k_copy_c2(const double2* __restrict__ src, double2* __restrict__ dst,
@@ -2613,8 +2620,8 @@ hipError_t launch_sweep(int nt, int mixed, const SweepArgs& a, const double* U, 
 
 hipError_t launch_init_forward(int nt, int P, const double2* psi, double2* c, double2* lam, double2* bs,
                                hipStream_t st) {
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_init_forward<NT>, dim3(nblk_for(P)), dim3(kThreads), 0, st, P, psi,
-                                           c, lam, bs));
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_init_forward<NT>, dim3(nblk_for((size_t)P * nt)), dim3(kThreads), 0,
+                                           st, P, psi, c, lam, bs));
     return hipGetLastError();
 }
 
@@ -2632,10 +2639,15 @@ hipError_t launch_end_eval(int nt, int P, const double2* c, double2* psi, hipStr
 hipError_t launch_advance(int nt, const LevelGeom& g, const double* U, const double* W, const double2* c,
                           const double* v0, double2* psi, double2* cn, double2* lamn, double2* bsn,
                           double* partial, int* nparts, hipStream_t st) {
-    const int nb = residual_blocks(nt, g.P);
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_advance<NT>, dim3(residual_blocks(nt, g.P)), dim3(kThreads), 0, st,
+                                           g.P, c, psi, cn, lamn, bsn));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // at most residual_blocks(nt, P) partials, the capacity of a residual launch's
+    const int nb = nblk_for(g.P);
     if (nparts) *nparts = nb;
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_advance<NT>, dim3(nb), dim3(kThreads), 0, st, g, make_ops<NT>(U, W),
-                                           W ? 1 : 0, c, v0, psi, cn, lamn, bsn, partial));
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_initial_norm<NT>, dim3(nb), dim3(kThreads), 0, st, g,
+                                           make_ops<NT>(U, W), W ? 1 : 0, psi, v0, partial));
     return hipGetLastError();
 }
 

@@ -343,8 +343,8 @@ def test_native_propagate_queued_next_step(pulse, precision):
     assert st[0]["resid"] <= 1e-12 * st[0]["resid0"] * 1.0001
     cg, _ = prop.get_state()
     assert np.abs(n(cg).reshape(-1, case.n_t).sum(axis=1) - n(psi_native)).max() <= 1e-14 * ref
-    # the last step's N0 came from the queued-ahead pass (H psi summed over the
-    # components): the same as the residual of that step's initial guess
+    # the last step's N0 came from the queued-ahead pass (H applied to the end
+    # state psi): the same as the residual of that step's initial guess
     psi_prev, _ = prop.propagate(t_c(case.psi0), K - 1)
     _, st1 = prop.solve_step((K - 1) * case.dt, psi_prev)
     assert abs(st[0]["resid0_last"] - st1["resid0"]) <= 1e-9 * st1["resid0"]
