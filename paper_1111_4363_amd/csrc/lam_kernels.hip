@@ -552,9 +552,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_residual_march(
     if (skip && *skip) return;
     constexpr int TY = kMarchTY, TZ = kMarchTZ, HZ = TZ + 2, HP = (TY + 2) * HZ;
     constexpr int NQ = NT + 1, IPL = 2;
+    // LDS slot stride of a point: odd in units of 16 bytes, so that the 16 points of
+    // a wave reading one component spread over the banks (an even stride puts
+    // them in a few bank groups)
+    constexpr int NTP = NT | 1;
     constexpr int NHALO = 2 * TZ + 2 * TY;   // halo points of a plane tile (no corners)
     static_assert(TY * TZ * 4 == kThreads && NHALO * 8 == kThreads, "four lanes per point, one halo item per thread");
-    __shared__ double2 pl[2][HP * NT];
+    __shared__ double2 pl[2][HP * NTP];
     __shared__ double2 rb[RESTRICT ? 2 : 1][RESTRICT ? TY * TZ * NQ : 1];
     __shared__ double tos[NT + NT * NT];
     __shared__ double red[kThreads / 64];
@@ -588,8 +592,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_residual_march(
     if (gz < 0 || gz >= n2) { gz += gz < 0 ? n2 : -n2; hval = hval && g.periodic; }
     const int hmc = hm < NT ? hm : 0;
     const int hj = gy * n2 + gz;
-    const int hslot = ((hy + 1) * HZ + (hz + 1)) * NT + hmc;
-    const int oslot = ((py + 1) * HZ + (pz + 1)) * NT;
+    const int hslot = ((hy + 1) * HZ + (hz + 1)) * NTP + hmc;
+    const int oslot = ((py + 1) * HZ + (pz + 1)) * NTP;
     // plane x (one past either end: wrapped, or zero under Dirichlet)
     auto plane = [&](int x, bool& ok) {
         ok = true;
@@ -657,8 +661,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_residual_march(
         for (int k = 0; k < IPL; ++k) {
             const int m = mi[k];
             double2 lap = add2(scl2(-6.0, ccur[k]), add2(cprev[k], cnext[k]));
-            lap = add2(lap, add2(P[-HZ * NT + m], P[HZ * NT + m]));
-            lap = add2(lap, add2(P[-NT + m], P[NT + m]));
+            lap = add2(lap, add2(P[-HZ * NTP + m], P[HZ * NTP + m]));
+            lap = add2(lap, add2(P[-NTP + m], P[NTP + m]));
             double2 tq = make_double2(0.0, 0.0);
 #pragma unroll
             for (int kk = 0; kk < (NT + 1) / 2; ++kk) {
