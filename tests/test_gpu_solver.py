@@ -321,11 +321,10 @@ def test_native_propagate_matches_stepwise_and_edge_cases():
 @pytest.mark.parametrize("pulse", [None, dict(kind="sin2", e0=0.05, omega=0.057, t_total=0.1)],
                          ids=["no-field", "field-ends-mid-run"])
 def test_native_propagate_queued_next_step(pulse, precision):
-    """Steps without a field have the next step's start queued ahead of each
-    wait (spare buffers swapped in when the step has converged).  Against the
-    oracle's direct steps and the step-by-step path: a run with no field, and
-    one whose pulse ends with the second step (the first two steps keep the
-    plain path); the in-place form; the context state after the run is the last
+    """Each step's successor has its start queued ahead of each wait (spare
+    buffers swapped in when the step has converged).  Against the oracle's
+    direct steps and the step-by-step path: a run with no field, and one whose
+    pulse ends with the second step; the in-place form; the context state after the run is the last
     step's, and an adjoint step on the same context (its state buffers swapped
     by the runs) matches the oracle's direct adjoint; a tiny max_cycles stops
     the run at its first step with that step's result."""
@@ -399,6 +398,34 @@ def test_queued_step_across_grids(cfg):
     _, st1 = prop.solve_step((K - 1) * case.dt, seq[-2])
     assert abs(st[0]["resid0_last"] - st1["resid0"]) <= 1e-9 * st1["resid0"]
     prop.close()
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(shape=(16, 16), n_t=8, block=(4, 4), levels=2, h=0.3, field_axis=0),
+    dict(shape=(8, 8, 8), n_t=6, block=(4, 4, 4), levels=2, h=0.3, field_axis=2, periodic=True),
+], ids=lambda c: f"{c['shape']}-axis{c['field_axis']}")
+def test_queued_field_step_has_the_initial_norm_of_its_guess(cfg):
+    """Field steps also take the queued-ahead start: the N0 of the last step of
+    a run inside the pulse (formed from the end state psi with that step's
+    field) equals the plain residual norm of the same initial guess."""
+    pulse = dict(kind="sin2", e0=0.2, omega=0.9, t_total=1.0)
+    case = Case(pulse=pulse, **cfg)
+    note(f"queued field step {case}")
+    K = 4
+    t_start = 0.3
+    prop = case.prop(tol=1e-12, max_cycles=60)
+    psi_native, st = prop.propagate(t_c(case.psi0), K, t_start)
+    seq, _ = prop.propagate(t_c(case.psi0), K, t_start, keep=True)
+    ref = np.abs(n(seq[-1])).max()
+    assert np.abs(n(psi_native) - n(seq[-1])).max() <= 1e-10 * ref
+    _, st1 = prop.solve_step(t_start + (K - 1) * case.dt, seq[-2])
+    assert abs(st[0]["resid0_last"] - st1["resid0"]) <= 1e-9 * st1["resid0"]
+    prop.close()
+    # the field term matters here: without it the same guess has another N0
+    plain = Case(**cfg).prop(tol=1e-12, max_cycles=60)
+    _, st0 = plain.solve_step(t_start + (K - 1) * case.dt, seq[-2])
+    assert abs(st0["resid0"] - st1["resid0"]) > 1e-6 * st1["resid0"]
+    plain.close()
 
 
 def test_sweep_profiling_samples_every_kth_launch():
