@@ -2402,45 +2402,69 @@ __global__ __launch_bounds__(kThreads) void k_copy_c2(const double2* __restrict_
 // ---------------------------------------------------------------------------
 // K10: gradients from the forward solution c and the adjoint solution mu.
 //   dv0[j] += 2 Re sum_m conj(mu_jm) U_mm c_jm
-//   Gpart[wg][m][n] = sum_{j in wg} z_j conj(mu_jm) c_jn
+//   Gpart[wg][m][n] = sum over the points the workgroup visits of z_j conj(mu_jm) c_jn
+// One thread per (point slot, m) in a grid-stride loop over the points: the
+// thread keeps row m of its points' products in registers (the threads of a
+// point all read its row of c, the same cache lines); the thread with m = 0
+// also reads the point's row of mu and updates dv0.  The workgroup sums its
+// point slots at the end, once, through LDS.
 // ---------------------------------------------------------------------------
+constexpr int kGradBlocks = 1024;   // workgroups of a gradient launch (at most)
+
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_gradients(LevelGeom g, TimeOps<NT> to,
                                                         const double2* __restrict__ cf,
                                                         const double2* __restrict__ mu,
                                                         double* __restrict__ dv0, double2* __restrict__ Gpart) {
-    __shared__ double red[kThreads / 64];
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    const bool on = j < g.P;
-    double2 cj[NT], mj[NT];
-    double z = 0.0;
-    if (on) {
-        z = zcoord(g, point_coords(g, j));
-        double acc = 0.0;
+    constexpr int PW = kThreads / NT;  // point slots per workgroup
+    __shared__ double2 part[kThreads];
+    const int t = threadIdx.x;
+    const int ps = t / NT, m = t - ps * NT;
+    const bool slot = ps < PW;
+    const bool want_g = Gpart != nullptr;
+    double2 acc[NT];
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            cj[n] = cf[(size_t)j * NT + n];
-            mj[n] = mu[(size_t)j * NT + n];
-            acc += to.U[n] * (mj[n].x * cj[n].x + mj[n].y * cj[n].y);
+    for (int n = 0; n < NT; ++n) acc[n] = make_double2(0.0, 0.0);
+    const size_t stride = (size_t)gridDim.x * PW;
+    for (size_t j = (size_t)blockIdx.x * PW + ps; slot && j < (size_t)g.P; j += stride) {
+        const double2* cj = cf + j * NT;
+        const double2* mj = mu + j * NT;
+        double2 cr[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) cr[n] = cj[n];
+        const double2 mm = mj[m];
+        if (want_g) {
+            // z conj(mu_m) c_n
+            const double z = zcoord(g, point_coords(g, (int)j));
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                acc[n].x += z * (mm.x * cr[n].x + mm.y * cr[n].y);
+                acc[n].y += z * (mm.x * cr[n].y - mm.y * cr[n].x);
+            }
         }
-        dv0[j] += 2.0 * acc;
-    } else {
+        if (m == 0) {
+            double a = 0.0;
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            cj[n] = make_double2(0.0, 0.0);
-            mj[n] = make_double2(0.0, 0.0);
+            for (int n = 0; n < NT; ++n) {
+                const double2 mn = n == 0 ? mm : mj[n];
+                a += to.U[n] * (mn.x * cr[n].x + mn.y * cr[n].y);
+            }
+            dv0[j] += 2.0 * a;
         }
     }
-    if (!Gpart) return;
-    for (int m = 0; m < NT; ++m)
-        for (int n = 0; n < NT; ++n) {
-            // z conj(mu_m) c_n
-            const double gr = z * (mj[m].x * cj[n].x + mj[m].y * cj[n].y);
-            const double gim = z * (mj[m].x * cj[n].y - mj[m].y * cj[n].x);
-            const double tr = block_sum(gr, red);
-            const double ti = block_sum(gim, red);
-            if (threadIdx.x == 0) Gpart[(size_t)blockIdx.x * NT * NT + m * NT + n] = make_double2(tr, ti);
+    if (!want_g) return;
+    // column n of the workgroup's sums: the threads m < NT add up the point slots
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        if (slot) part[t] = acc[n];
+        __syncthreads();
+        if (t < NT) {
+            double2 sum = make_double2(0.0, 0.0);
+            for (int p = 0; p < PW; ++p) sum = add2(sum, part[p * NT + t]);
+            Gpart[(size_t)blockIdx.x * NT * NT + t * NT + n] = sum;
         }
+        __syncthreads();
+    }
 }
 
 template <int NT>
@@ -2663,7 +2687,8 @@ hipError_t launch_copy_c2(const double2* src, double2* dst, size_t n, hipStream_
 
 hipError_t launch_gradients(int nt, const LevelGeom& g, const double* U, const double2* cfwd, const double2* mu,
                             double* dv0, double2* Gpart, int* nparts, hipStream_t st) {
-    const int nb = nblk_for(g.P);
+    // at most one workgroup per kThreads points: the partial buffer holds that many
+    const int nb = std::min(nblk_for(g.P), kGradBlocks);
     if (nparts) *nparts = nb;
     LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_gradients<NT>, dim3(nb), dim3(kThreads), 0, st, g,
                                            make_ops<NT>(U, nullptr), cfwd, mu, dv0, Gpart));
