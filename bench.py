@@ -454,6 +454,20 @@ def run_precision(args, precision, v0_t, psi0_t, cfg, torch, lam, adjoint_steps=
             g, _ = prop.adjoint_step(t_k, psi, g, dv0, dcoef)
         torch.cuda.synchronize()
         out["adjoint_ms_per_step"] = (time.perf_counter() - t_b) / adjoint_steps * 1e3
+        # the same backward steps from a stored forward solution (lam_adjoint_step_stored:
+        # the adjoint solve and the gradients only; a caller keeps P N_t complex values per step)
+        t_last = (args.steps - 1) * cfg["dt"]
+        prop.solve_step(t_last, psi)
+        c_fwd, _ = prop.get_state()
+        g = (psi / torch.sqrt(torch.sum(torch.abs(psi) ** 2))).contiguous()
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        for k in range(adjoint_steps):
+            t_k = (args.steps - 1 - k) * cfg["dt"]
+            g, _ = prop.adjoint_step_stored(t_k, c_fwd, g, dv0, dcoef)
+        torch.cuda.synchronize()
+        out["adjoint_stored_ms_per_step"] = (time.perf_counter() - t_b) / adjoint_steps * 1e3
+        del c_fwd
     prop.close()
     return out
 

@@ -324,6 +324,24 @@ int lam_propagate(lam_ctx* ctx, double t0, int n_steps, const lam_c64* psi_in, l
 int lam_adjoint_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, const lam_c64* g_out,
                      lam_c64* g_in, double* dL_dv0, double* dL_dcoef, lam_stats* stats);
 
+/* Backward pass of one step from its stored forward solution: the adjoint solve
+ * and gradients of lam_adjoint_step (the same conjugate-transposed step system
+ * of Sec. "Review of the Least Action Principle", the same relaxation and
+ * V-cycles), without recomputing the forward solve.  For callers that keep the
+ * forward coefficients of every step instead of only the step-boundary
+ * wavefunctions: P*n_t complex values per step (2.1 GB at 256^3 with n_t = 8),
+ * which the HBM of one GPU holds for tens of steps.
+ *   c_fwd: device (P*n_t), the converged coefficients of the forward step at
+ *          t0 (lam_get_state after that step's lam_solve_step), read during the
+ *          call only;
+ *   g_out, g_in, dL_dv0, dL_dcoef, stats: as for lam_adjoint_step.
+ * A step whose forward solve was split (lam_stats.substeps > 1) has no single
+ * set of coefficients: its backward pass is lam_adjoint_step.  Synchronises
+ * the stream.  Errors: LAM_EINVAL (pointers), LAM_ENOCONV (g_in and the
+ * gradients written) or LAM_EDIVERGED from the adjoint solve, LAM_EHIP. */
+int lam_adjoint_step_stored(lam_ctx* ctx, double t0, const lam_c64* c_fwd, const lam_c64* g_out,
+                            lam_c64* g_in, double* dL_dv0, double* dL_dcoef, lam_stats* stats);
+
 /* Grid transfers on caller buffers; `level` is the fine level (0..levels-2).
  * lam_restrict: coarse (rho, sigma) = average of the 2^d children of the fine
  * (rho, sigma) (projection of Eq. (residual_rough)).

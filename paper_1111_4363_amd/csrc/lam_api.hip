@@ -1357,6 +1357,9 @@ int forward_halves(lam_ctx* c, double t0, int depth, const double2* psi_in, doub
 // it did going forward): g_in = the adjoint state at the step's start for
 // g_out at its end, gradients accumulated.  A split step's adjoint runs
 // through its halves in reverse, with the state between them recomputed.
+int adjoint_gradients(lam_ctx* c, double t0, int depth, const double2* cf, const double2* g_out, double2* g_in,
+                      double* dL_dv0, double* dL_dcoef, Totals& tot);
+
 int adjoint_split(lam_ctx* c, double t0, int depth, const double2* psi_in, const double2* g_out, double2* g_in,
                   double* dL_dv0, double* dL_dcoef, Totals& tot) {
     set_depth(c, depth);
@@ -1388,14 +1391,30 @@ int adjoint_split(lam_ctx* c, double t0, int depth, const double2* psi_in, const
         return adjoint_split(c, t0, depth + 1, psi_in, gmid, g_in, dL_dv0, dL_dcoef, tot);
     }
     if (rc != LAM_OK) return rc;
+    // the adjoint solve overwrites the state: the forward solution moves aside
     HIPCHK(launch_copy_c2(L.d_c, c->d_cf, P * nt, c->st));
+    return adjoint_gradients(c, t0, depth, c->d_cf, g_out, g_in, dL_dv0, dL_dcoef, tot);
+}
+
+// The adjoint solve of the step [t0, t0 + dt / 2^depth) and its gradients, for
+// the converged forward coefficients cf of that step (device, P n_t, read only):
+// g_in = the adjoint state at the step's start for g_out at its end, dL_dv0 and
+// dL_dcoef accumulated.  The depth must already be set.
+int adjoint_gradients(lam_ctx* c, double t0, int depth, const double2* cf, const double2* g_out, double2* g_in,
+                      double* dL_dv0, double* dL_dcoef, Totals& tot) {
+    Level& L = c->lv[0];
+    const int nt = c->nt;
+    const size_t P = L.g.P;
+    c->have_state = 1;
+    c->state_t0 = t0;
+    c->state_depth = depth;
     // 2. adjoint solve K^H mu = E^H g_out from mu = 0
     LAMCHK(set_step(c, t0, 1));
     HIPCHK(launch_copy_c2(g_out, c->d_g, P, c->st));
     HIPCHK(launch_init_zero(nt, (int)P, L.d_c, L.d_lam, c->st));
     c->adjoint = 1;
     lam_stats st{};
-    rc = solve_loop(c, &st);
+    const int rc = solve_loop(c, &st);
     tot.work(st);
     if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
     tot.accept(st, depth);
@@ -1403,7 +1422,7 @@ int adjoint_split(lam_ctx* c, double t0, int depth, const double2* psi_in, const
     int np = 0;
     const bool want_coef = dL_dcoef && !c->coef.empty() &&
                            (c->ham.pulse_kind == LAM_PULSE_FOURIER || c->ham.pulse_kind == LAM_PULSE_SIN2_FOURIER);
-    HIPCHK(launch_gradients(nt, L.g, c->U, c->d_cf, L.d_c, dL_dv0, want_coef ? c->d_Gpart : nullptr, &np, c->st));
+    HIPCHK(launch_gradients(nt, L.g, c->U, cf, L.d_c, dL_dv0, want_coef ? c->d_Gpart : nullptr, &np, c->st));
     HIPCHK(launch_copy_c2(L.d_lam, g_in, P, c->st));
     if (want_coef) {
         HIPCHK(launch_reduce_c2(c->d_Gpart, np, nt * nt, c->d_G, c->st));
@@ -1742,6 +1761,30 @@ int lam_adjoint_step(lam_ctx* ctx, double t0, const lam_c64* psi_in, const lam_c
                                  dL_dcoef, tot);
     ctx->refine_off = false;
     set_depth(ctx, 0);
+    if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
+    if (stats) {
+        *stats = tot.s;
+        stats->sweeps_fine = ctx->sweeps_fine - sw0;
+        stats->t_factor_ms = ctx->t_factor_ms;
+        stats->t_solve_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_a).count();
+    }
+    return rc;
+}
+
+int lam_adjoint_step_stored(lam_ctx* ctx, double t0, const lam_c64* c_fwd, const lam_c64* g_out, lam_c64* g_in,
+                            double* dL_dv0, double* dL_dcoef, lam_stats* stats) {
+    if (!ctx || bad_ptr(c_fwd) || bad_ptr(g_out) || bad_ptr(g_in) || bad_ptr(dL_dv0)) return LAM_EINVAL;
+    const auto t_a = std::chrono::steady_clock::now();
+    ctx->t_factor_ms = 0.0;
+    const int sw0 = ctx->sweeps_fine;
+    Totals tot;
+    ctx->refine_off = true;
+    set_depth(ctx, 0);
+    const int rc = adjoint_gradients(ctx, t0, 0, reinterpret_cast<const double2*>(c_fwd),
+                                     reinterpret_cast<const double2*>(g_out), reinterpret_cast<double2*>(g_in), dL_dv0,
+                                     dL_dcoef, tot);
+    ctx->refine_off = false;
     if (rc != LAM_OK && rc != LAM_ENOCONV) return rc;
     if (stats) {
         *stats = tot.s;

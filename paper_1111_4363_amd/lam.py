@@ -110,6 +110,7 @@ SIGNATURES = {
     "lam_solve_step": (_I, [_P, _D, _P, _P, ctypes.POINTER(LamStats)]),
     "lam_propagate": (_I, [_P, _D, _I, _P, _P, ctypes.POINTER(LamStats)]),
     "lam_adjoint_step": (_I, [_P, _D, _P, _P, _P, _P, _PD, ctypes.POINTER(LamStats)]),
+    "lam_adjoint_step_stored": (_I, [_P, _D, _P, _P, _P, _P, _PD, ctypes.POINTER(LamStats)]),
     "lam_restrict": (_I, [_P, _I, _P, _P, _P, _P]),
     "lam_prolong_add": (_I, [_P, _I, _P, _P, _P, _P]),
     "lam_level_shape": (_I, [_P, _I, _PI]),
@@ -281,6 +282,7 @@ class Propagator:
         # what the context holds (the autograd function restores its own inputs)
         self._v0_held = v0.detach().clone()
         self._coef_held = list(coef)
+        self.refined = False   # a refinement set by set_refinement
         h_ctx = ctypes.c_void_p()
         _check(lib.lam_create(ctypes.byref(g), ctypes.byref(t), ctypes.byref(ham), ctypes.byref(s),
                               _stream_handle(self.stream), ctypes.byref(h_ctx)), "lam_create")
@@ -375,6 +377,7 @@ class Propagator:
         coordinates); None clears the refinement."""
         if active is None:
             _check(self._lib.lam_set_refinement(self._ctx, None), "lam_set_refinement")
+            self.refined = False
             return
         import numpy as np
         a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8).ravel())
@@ -384,6 +387,7 @@ class Propagator:
         if a.size != nblk:
             raise ValueError(f"one flag per finest subvolume expected ({nblk}), got {a.size}")
         _check(self._lib.lam_set_refinement(self._ctx, a.ctypes.data_as(ctypes.c_void_p)), "lam_set_refinement")
+        self.refined = True
 
     def block_detail(self, psi):
         """lam_block_detail: Haar detail energy of psi per finest subvolume (numpy)."""
@@ -433,6 +437,25 @@ class Propagator:
                                           _ptr(dv0, torch.float64, P, "dv0"),
                                           arr if dcoef is not None else None, ctypes.byref(st)),
                "lam_adjoint_step")
+        if dcoef is not None:
+            for q in range(nc):
+                dcoef[q] = arr[q]
+        return g_in, st.as_dict()
+
+    def adjoint_step_stored(self, t0, c_fwd, g_out, dv0, dcoef=None):
+        """As adjoint_step, from the step's converged forward coefficients c_fwd
+        (get_state after its solve_step) instead of a recomputed forward solve."""
+        P, nt = self.npts, self.n_t
+        g_in = self._new(P)
+        st = LamStats()
+        nc = self.n_coef
+        arr = (ctypes.c_double * max(1, nc))(*(dcoef if dcoef is not None else [0.0] * nc))
+        _check(self._lib.lam_adjoint_step_stored(self._ctx, float(t0), _ptr(c_fwd, torch.complex128, P * nt, "c_fwd"),
+                                                 _ptr(g_out, torch.complex128, P, "g_out"),
+                                                 _ptr(g_in, torch.complex128, P, "g_in"),
+                                                 _ptr(dv0, torch.float64, P, "dv0"),
+                                                 arr if dcoef is not None else None, ctypes.byref(st)),
+               "lam_adjoint_step_stored")
         if dcoef is not None:
             for q in range(nc):
                 dcoef[q] = arr[q]
@@ -521,22 +544,38 @@ class LeastActionPropagate(torch.autograd.Function):
     """psi_K = F_{K-1}( ... F_0(psi_0)) with one least-action solve per step.
 
     Inputs: psi0 (complex128, device), v0 (float64, device) and coef
-    (float64, host or device; the Fourier amplitudes of the pulse).  Only the
-    step-boundary wavefunctions are kept; backward recomputes each step's
-    forward solve from its checkpoint and solves the adjoint step system with
-    the same relaxation and multigrid machinery (lam_adjoint_step).
+    (float64, host or device; the Fourier amplitudes of the pulse).  With
+    store=False only the step-boundary wavefunctions are kept, and backward
+    recomputes each step's forward solve from its checkpoint before it solves
+    the adjoint step system with the same relaxation and multigrid machinery
+    (lam_adjoint_step).  With store=True the forward coefficients of every step
+    are kept as well (P n_t complex values per step, in device memory), and
+    backward solves only the adjoint systems (lam_adjoint_step_stored); steps
+    whose forward solve was split, or solved on the adaptive tree, keep the
+    recomputing form.
     """
 
     @staticmethod
-    def forward(ctx, psi0, v0, coef, prop, n_steps, t_start):
+    def forward(ctx, psi0, v0, coef, prop, n_steps, t_start, store=False):
         ctx.v0 = v0.detach().contiguous().clone()
         ctx.coef = [float(a) for a in coef.detach().cpu().tolist()] if prop.n_coef else []
         prop.hold(ctx.v0, ctx.coef)
-        psis, _ = prop.propagate(psi0.detach().contiguous(), int(n_steps), float(t_start), keep=True)
+        n_steps, t_start = int(n_steps), float(t_start)
+        stored = [None] * n_steps
+        if store:
+            psis = [psi0.detach().contiguous()]
+            for k in range(n_steps):
+                psi, st = prop.solve_step(t_start + k * prop.dt, psis[-1])
+                psis.append(psi)
+                if st["substeps"] == 1 and not prop.refined:
+                    stored[k] = prop.get_state()[0]
+        else:
+            psis, _ = prop.propagate(psi0.detach().contiguous(), n_steps, t_start, keep=True)
         ctx.prop = prop
-        ctx.n_steps = int(n_steps)
-        ctx.t_start = float(t_start)
+        ctx.n_steps = n_steps
+        ctx.t_start = t_start
         ctx.checkpoints = psis[:-1]
+        ctx.stored = stored
         ctx.coef_device = coef.device
         return psis[-1].clone()
 
@@ -551,11 +590,18 @@ class LeastActionPropagate(torch.autograd.Function):
         dv0 = torch.zeros(prop.npts, dtype=torch.float64, device=prop.device)
         dcoef = [0.0] * prop.n_coef
         for k in reversed(range(ctx.n_steps)):
-            g, _ = prop.adjoint_step(ctx.t_start + k * prop.dt, ctx.checkpoints[k], g, dv0, dcoef)
+            t_k = ctx.t_start + k * prop.dt
+            if ctx.stored[k] is not None:
+                g, _ = prop.adjoint_step_stored(t_k, ctx.stored[k], g, dv0, dcoef)
+            else:
+                g, _ = prop.adjoint_step(t_k, ctx.checkpoints[k], g, dv0, dcoef)
         grad_psi0 = 2.0 * g
         grad_coef = torch.tensor(dcoef, dtype=torch.float64, device=ctx.coef_device)
-        return grad_psi0, dv0, grad_coef, None, None, None
+        return grad_psi0, dv0, grad_coef, None, None, None, None
 
 
-def propagate_differentiable(prop, psi0, v0, coef, n_steps, t_start=0.0):
-    return LeastActionPropagate.apply(psi0, v0, coef, prop, n_steps, t_start)
+def propagate_differentiable(prop, psi0, v0, coef, n_steps, t_start=0.0, store=False):
+    """psi_K of n_steps least-action steps, differentiable in psi0, v0 and coef;
+    store=True keeps every step's forward coefficients for the backward pass
+    (LeastActionPropagate)."""
+    return LeastActionPropagate.apply(psi0, v0, coef, prop, n_steps, t_start, store)

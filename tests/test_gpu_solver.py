@@ -235,6 +235,71 @@ def test_adjoint_step_parity(precision):
     prop.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adjoint_step_from_the_stored_forward_solution(precision):
+    """lam_adjoint_step_stored with the forward step's converged coefficients:
+    the oracle's adjoint state and gradients to the precision's bound (as the
+    recomputing adjoint step), and agreement with lam_adjoint_step."""
+    import torch
+    case = Case(shape=(16, 16), h=0.25, n_t=6, block=(4, 4), levels=2, pulse=PULSE_FOURIER)
+    note(f"stored adjoint step {precision} {case}")
+    t0 = 0.1
+    sysm = kkt.StepSystem(case.grid, case.v0, case.n_t, case.dt, t0, case.field)
+    x = kkt.solve_direct(sysm.K, kkt.rhs(sysm, case.psi0))
+    g_out = case.rng.normal(size=case.npts) + 1j * case.rng.normal(size=case.npts)
+    mu = A.adjoint_solve(sysm, A.adjoint_rhs(sysm, g_out))
+    from oracle import timebasis as tb
+    basis = [tb.fourier_basis_function(q, PULSE_FOURIER["t_total"]) for q in (1, 2, 3)]
+    g_in_ref, dv0_ref, da_ref = A.step_gradients(sysm, x, mu, basis)
+    prop = case.prop(precision=precision, tol=1e-12, max_cycles=60)
+    prop.solve_step(t0, t_c(case.psi0))
+    c_fwd, _ = prop.get_state()
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    res = []
+    for stored in (True, False):
+        dv0 = torch.zeros(case.npts, dtype=torch.float64, device="cuda")
+        dcoef = [0.0, 0.0, 0.0]
+        if stored:
+            g_in, st = prop.adjoint_step_stored(t0, c_fwd, t_c(g_out), dv0, dcoef)
+            assert st["sweeps_fine"] == 2 * st["cycles"]   # no forward solve inside
+        else:
+            g_in, st = prop.adjoint_step(t0, t_c(case.psi0), t_c(g_out), dv0, dcoef)
+        assert np.abs(n(g_in) - g_in_ref).max() <= tol * np.abs(g_in_ref).max()
+        assert np.abs(n(dv0) - dv0_ref).max() <= tol * np.abs(dv0_ref).max()
+        assert np.abs(np.array(dcoef) - da_ref).max() <= tol * np.abs(da_ref).max()
+        res.append((n(g_in), n(dv0), np.array(dcoef)))
+    for a_, b_ in zip(res[0], res[1]):
+        assert np.abs(a_ - b_).max() <= tol * np.abs(b_).max()
+    prop.close()
+
+
+def test_autograd_with_stored_forward_states_matches_the_recomputing_one():
+    """propagate_differentiable(store=True) keeps each step's forward
+    coefficients and runs only the adjoint solves backward: the same
+    gradients (psi0, V0, pulse amplitudes) as the recomputing form, 1e-10."""
+    import torch
+    from paper_1111_4363_amd import lam
+    case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=None)
+    n_steps, T = 5, 5 * case.dt
+    coef = np.array([0.3, -0.2, 0.25, 0.1])
+    pulse = dict(kind="fourier", t_total=T, coef=list(coef))
+    note(f"autograd stored vs recomputed {case}")
+    prop = case.prop(pulse=pulse, tol=1e-13, max_cycles=80)
+    g_t = t_c(case.psi0)
+    grads = []
+    for store in (False, True):
+        psi0 = t_c(case.psi0).requires_grad_(True)
+        v0 = t_r(case.v0).requires_grad_(True)
+        cf = torch.tensor(coef, dtype=torch.float64, requires_grad=True)
+        psiK = lam.propagate_differentiable(prop, psi0, v0, cf, n_steps, store=store)
+        ov = torch.sum(torch.conj(g_t) * psiK)
+        (ov * torch.conj(ov)).real.backward()
+        grads.append((n(psi0.grad), n(v0.grad), cf.grad.numpy().copy()))
+    for a_, b_ in zip(grads[0], grads[1]):
+        assert np.abs(a_ - b_).max() <= 1e-10 * np.abs(a_).max()
+    prop.close()
+
+
 def test_autograd_gradients_match_finite_differences():
     """Loss = population of the grid ground state after K steps; gradients with
     respect to the pulse amplitudes and sampled V0 points against central
