@@ -122,3 +122,9 @@ def test_adaptive_tree_calls_reject_a_null_context():
     assert lib.lam_set_refinement(None, None) == lam.LAM_EINVAL
     out = (ctypes.c_double * 4)()
     assert lib.lam_block_detail(None, None, out) == lam.LAM_EINVAL
+
+
+def test_adjoint_calls_reject_a_null_context():
+    lib = lam.load_library()
+    for fn in (lib.lam_adjoint_step, lib.lam_adjoint_step_stored):
+        assert fn(None, 0.0, None, None, None, None, None, None) == lam.LAM_EINVAL
