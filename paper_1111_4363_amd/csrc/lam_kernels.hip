@@ -2303,11 +2303,11 @@ __global__ __launch_bounds__(kThreads) void k_init_forward(int P, const double2*
 template <int NT>
 __global__ __launch_bounds__(kThreads) void k_init_zero(int P, double2* __restrict__ c,
                                                         double2* __restrict__ lam) {
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    if (j >= P) return;
-#pragma unroll
-    for (int n = 0; n < NT; ++n) c[(size_t)j * NT + n] = make_double2(0.0, 0.0);
-    lam[j] = make_double2(0.0, 0.0);
+    // one thread per (point, component): coalesced stores of c
+    const size_t k = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= (size_t)P * NT) return;
+    c[k] = make_double2(0.0, 0.0);
+    if (k % NT == 0) lam[k / NT] = make_double2(0.0, 0.0);
 }
 
 template <int NT>
@@ -2403,64 +2403,75 @@ __global__ __launch_bounds__(kThreads) void k_copy_c2(const double2* __restrict_
 // K10: gradients from the forward solution c and the adjoint solution mu.
 //   dv0[j] += 2 Re sum_m conj(mu_jm) U_mm c_jm
 //   Gpart[wg][m][n] = sum over the points the workgroup visits of z_j conj(mu_jm) c_jn
-// One thread per (point slot, m) in a grid-stride loop over the points: the
-// thread keeps row m of its points' products in registers (the threads of a
-// point all read its row of c, the same cache lines); the thread with m = 0
-// also reads the point's row of mu and updates dv0.  The workgroup sums its
-// point slots at the end, once, through LDS.
+// One thread per (point slot, m) in a grid-stride loop over rounds of
+// kThreads / NT points: each thread loads its own c_jm and mu_jm (every load
+// coalesced), the round's rows of c and the dV0 terms meet in LDS, and the
+// thread keeps row m of its points' products in registers.  The workgroup
+// sums its point slots at the end, once, through LDS.
 // ---------------------------------------------------------------------------
-constexpr int kGradBlocks = 1024;   // workgroups of a gradient launch (at most)
+constexpr int kGradBlocks = 1536;   // workgroups of a gradient launch (at most): six per CU
 
 template <int NT>
-__global__ __launch_bounds__(kThreads) void k_gradients(LevelGeom g, TimeOps<NT> to,
-                                                        const double2* __restrict__ cf,
-                                                        const double2* __restrict__ mu,
-                                                        double* __restrict__ dv0, double2* __restrict__ Gpart) {
+__global__ __launch_bounds__(kThreads, 6) void k_gradients(LevelGeom g, TimeOps<NT> to,
+                                                           const double2* __restrict__ cf,
+                                                           const double2* __restrict__ mu,
+                                                           double* __restrict__ dv0, double2* __restrict__ Gpart) {
     constexpr int PW = kThreads / NT;  // point slots per workgroup
-    __shared__ double2 part[kThreads];
+    __shared__ double2 cs[kThreads];   // the round's rows of c; at the end the slot sums
+    __shared__ double us[kThreads];    // the round's dV0 terms U_m Re(conj(mu_jm) c_jm)
     const int t = threadIdx.x;
     const int ps = t / NT, m = t - ps * NT;
     const bool slot = ps < PW;
     const bool want_g = Gpart != nullptr;
+    double um = 0.0;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) um = n == m ? to.U[n] : um;
     double2 acc[NT];
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[n] = make_double2(0.0, 0.0);
     const size_t stride = (size_t)gridDim.x * PW;
-    for (size_t j = (size_t)blockIdx.x * PW + ps; slot && j < (size_t)g.P; j += stride) {
-        const double2* cj = cf + j * NT;
-        const double2* mj = mu + j * NT;
-        double2 cr[NT];
+    for (size_t base = (size_t)blockIdx.x * PW; base < (size_t)g.P; base += stride) {
+        const size_t j = base + ps;
+        const bool on = slot && j < (size_t)g.P;
+        double2 cm = make_double2(0.0, 0.0), mm = make_double2(0.0, 0.0);
+        if (on) {
+            cm = cf[j * NT + m];
+            mm = mu[j * NT + m];
+        }
+        if (slot) {
+            cs[t] = cm;
+            us[t] = um * (mm.x * cm.x + mm.y * cm.y);
+        }
+        __syncthreads();
+        if (on) {
+            if (want_g) {
+                // z conj(mu_m) c_n
+                const double z = zcoord(g, point_coords(g, (int)j));
 #pragma unroll
-        for (int n = 0; n < NT; ++n) cr[n] = cj[n];
-        const double2 mm = mj[m];
-        if (want_g) {
-            // z conj(mu_m) c_n
-            const double z = zcoord(g, point_coords(g, (int)j));
+                for (int n = 0; n < NT; ++n) {
+                    const double2 cn = cs[ps * NT + n];
+                    acc[n].x += z * (mm.x * cn.x + mm.y * cn.y);
+                    acc[n].y += z * (mm.x * cn.y - mm.y * cn.x);
+                }
+            }
+            if (m == 0) {
+                double a = 0.0;
 #pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                acc[n].x += z * (mm.x * cr[n].x + mm.y * cr[n].y);
-                acc[n].y += z * (mm.x * cr[n].y - mm.y * cr[n].x);
+                for (int n = 0; n < NT; ++n) a += us[ps * NT + n];
+                dv0[j] += 2.0 * a;
             }
         }
-        if (m == 0) {
-            double a = 0.0;
-#pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const double2 mn = n == 0 ? mm : mj[n];
-                a += to.U[n] * (mn.x * cr[n].x + mn.y * cr[n].y);
-            }
-            dv0[j] += 2.0 * a;
-        }
+        __syncthreads();
     }
     if (!want_g) return;
     // column n of the workgroup's sums: the threads m < NT add up the point slots
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
-        if (slot) part[t] = acc[n];
+        if (slot) cs[t] = acc[n];
         __syncthreads();
         if (t < NT) {
             double2 sum = make_double2(0.0, 0.0);
-            for (int p = 0; p < PW; ++p) sum = add2(sum, part[p * NT + t]);
+            for (int p = 0; p < PW; ++p) sum = add2(sum, cs[p * NT + t]);
             Gpart[(size_t)blockIdx.x * NT * NT + t * NT + n] = sum;
         }
         __syncthreads();
@@ -2654,7 +2665,8 @@ hipError_t launch_init_forward(int nt, int P, const double2* psi, double2* c, do
 }
 
 hipError_t launch_init_zero(int nt, int P, double2* c, double2* lam, hipStream_t st) {
-    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_init_zero<NT>, dim3(nblk_for(P)), dim3(kThreads), 0, st, P, c, lam));
+    LAM_DISPATCH_NT(nt, hipLaunchKernelGGL(k_init_zero<NT>, dim3(nblk_for((size_t)P * nt)), dim3(kThreads), 0, st, P,
+                                           c, lam));
     return hipGetLastError();
 }
 
