@@ -273,18 +273,23 @@ def test_adjoint_step_from_the_stored_forward_solution(precision):
     prop.close()
 
 
-def test_autograd_with_stored_forward_states_matches_the_recomputing_one():
+@pytest.mark.parametrize("cfg,precision", [
+    (dict(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2), "fp64"),
+    (dict(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2), "mixed"),
+    (dict(shape=(8, 8, 16), h=0.3, n_t=8, block=(4, 4, 4), levels=2, field_axis=2), "mixed"),
+], ids=["2d-fp64", "2d-mixed", "3d-mixed"])
+def test_autograd_with_stored_forward_states_matches_the_recomputing_one(cfg, precision):
     """propagate_differentiable(store=True) keeps each step's forward
     coefficients and runs only the adjoint solves backward: the same
     gradients (psi0, V0, pulse amplitudes) as the recomputing form, 1e-10."""
     import torch
     from paper_1111_4363_amd import lam
-    case = Case(shape=(32, 32), h=0.2, n_t=8, block=(8, 8), levels=2, pulse=None)
+    case = Case(pulse=None, **cfg)
     n_steps, T = 5, 5 * case.dt
     coef = np.array([0.3, -0.2, 0.25, 0.1])
     pulse = dict(kind="fourier", t_total=T, coef=list(coef))
-    note(f"autograd stored vs recomputed {case}")
-    prop = case.prop(pulse=pulse, tol=1e-13, max_cycles=80)
+    note(f"autograd stored vs recomputed {precision} {case}")
+    prop = case.prop(pulse=pulse, tol=1e-13, max_cycles=80, precision=precision)
     g_t = t_c(case.psi0)
     grads = []
     for store in (False, True):
